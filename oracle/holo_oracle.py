@@ -1,0 +1,397 @@
+"""FP64 CPU oracle for the joint object-and-probe holotomography gradient.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this module.  The product path (the HIP library
+and its Python binding) never calls it and shares no code with it.
+
+Everything here is the plain, slow definition of what the GPU path computes,
+written in NumPy complex128/float64 so that a reader can check it against the
+paper by eye:
+
+  * Sec. 2, Eq. (8)   cone-beam forward model with probe: the field on the
+                      detector for sample plane j is D_{zeta_j/m~_j^2}(
+                      D_{omega_j}(q) . M_{1/m~_j}(psi)), after the rescaling
+                      of the data by m0^2 M_{1/m0} (Eq. 9 text).
+  * Sec. 2, Eq. (10)  the amplitude functional F2 with the reference term.
+  * Sec. 2, Eq. (11)  and the display after it: the gradients with respect to
+                      psi_k and q, including the adjoint L* = S_-t M*_{1/m~}
+                      (conj(D_omega q) . D_{-zeta/m~^2}(.)).
+  * Sec. 5, Eq. (17)  the joint model psi_k = exp(2 pi i/nu R_k u).
+  * Sec. 2, Eq. (14)  R_k, the Radon transform at angle theta_k.
+  * Appendix A, the Fresnel kernel P_Z and D_Z psi = psi * P_Z.
+
+Dimensionless units (one length unit = one detector pixel after the data
+rescaling):  the Fresnel number of the first plane is N_F0 = Delta^2 /
+(lambda zeta_0), every propagation distance is a multiple rho of zeta_0, and
+kappa = 2 pi Delta / nu turns the voxel-unit ray sum of u into a phase.
+
+Readings of points the paper leaves open (each one is listed with its reason
+in the design notes of the repository):
+  R1 R is Joseph's ray-driven discretisation: unit steps along the dominant
+     axis, linear interpolation across it, path factor 1/max(|cos|,|sin|),
+     zero outside the grid.  Voxel (ix, iy) sits at (ix - W/2, iy - W/2); bin i
+     sits at s = i - W/2 with s = x cos(theta) + y sin(theta).
+  R2 D_rho is the FFT transfer function exp(-i pi rho |k|^2 / N_F0) on the
+     unpadded periodic H x W grid; the constant e^{ikZ}/(i lambda Z) is
+     dropped, so D is unitary and D_a D_b = D_{a+b}.
+  R3 M_{1/m~} S_t is bilinear sampling at src = c + m~ (x - c) - t about the
+     grid centre c = n/2; outside the psi grid the transmission is 1 (free
+     space), i.e. M(psi) = 1 + B(psi - 1).
+  R4 v/|v| := 0 where |v| = 0.
+  R5 Gradient convention g = dF/dRe + i dF/dIm (the paper's 2 L*(...)).
+     The object gradient of the joint model follows by the chain rule:
+     g_u = sum_k R_k^T(-i kappa conj(psi_k) g_psi_k).
+  R6 Data are given directly as amplitudes a = sqrt(d~) on the computational
+     grid (the m0^2 M_{1/m0} rescaling is the identity there).
+
+Array layouts (the same ones the C ABI uses):
+  u, g_u      (W, W, H) complex  -- u[y, x, z], z (detector row) last
+  q, g_q      (H, W) complex
+  amp         (n_angles, n_dist, H, W) float
+  amp_ref     (H, W) float
+  frames v, w (n_angles, n_dist, H, W) complex
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+
+# ---------------------------------------------------------------------------
+# Geometry
+# ---------------------------------------------------------------------------
+
+def distances(m0: float, mag_rel: Sequence[float]):
+    """Dimensionless propagation distances of Eq. (8) / Theorem A.3.
+
+    With z_0 the first sample plane, m~_j = z_j / z_0 and m0 = Z / z_0:
+      zeta_j / m~_j^2 (object-to-detector step)  ->  rho_det_j
+      omega_j = (z_j - z_0) / m~_j (probe step)  ->  rho_probe_j
+    both divided by zeta_0 = z_0 (Z - z_0) / Z, so the reference image is the
+    probe propagated by rho = 1.
+    """
+    m = np.asarray(mag_rel, dtype=np.float64)
+    rho_det = (m0 - m) / (m * (m0 - 1.0))
+    rho_probe = m0 * (m - 1.0) / (m * (m0 - 1.0))
+    return rho_det, rho_probe
+
+
+@dataclass
+class Geometry:
+    """Parameters of one gradient evaluation (dimensionless, see module doc)."""
+    H: int                      # detector rows = volume slices (z)
+    W: int                      # detector columns = in-plane volume edge
+    theta: np.ndarray           # (n_angles,) radians
+    mag_rel: np.ndarray         # (n_dist,) m~_j = z_j / z_0, mag_rel[0] = 1
+    m0: float = 300.0           # Z / z_0
+    fresnel0: float = 0.01      # N_F0 of the first plane
+    kappa: float = 4667.35      # phase per unit u per voxel of path
+    shift: Optional[np.ndarray] = None   # (n_angles, n_dist, 2) = (t_y, t_x) px
+
+    def __post_init__(self):
+        self.theta = np.asarray(self.theta, dtype=np.float64)
+        self.mag_rel = np.asarray(self.mag_rel, dtype=np.float64)
+        if self.shift is not None:
+            self.shift = np.asarray(self.shift, dtype=np.float64)
+
+    @property
+    def n_angles(self):
+        return len(self.theta)
+
+    @property
+    def n_dist(self):
+        return len(self.mag_rel)
+
+    def t(self, k, j):
+        if self.shift is None:
+            return 0.0, 0.0
+        return float(self.shift[k, j, 0]), float(self.shift[k, j, 1])
+
+
+# ---------------------------------------------------------------------------
+# Fresnel propagation (Appendix A: D_Z psi = psi * P_Z)
+# ---------------------------------------------------------------------------
+
+def transfer(n: int, rho: float, fresnel0: float) -> np.ndarray:
+    """1-D factor of the Fresnel transfer function along an axis of length n.
+
+    The Fourier transform of P_Z (with e^{-2 pi i x f}) is, up to the dropped
+    constant, exp(-i pi lambda Z |f|^2); with f = k / (n Delta) and
+    Z = rho zeta_0 this is exp(-i pi rho k^2 / (N_F0 n^2)).
+    """
+    k = np.fft.fftfreq(n) * n
+    return np.exp(-1j * np.pi * rho * k * k / (fresnel0 * n * n))
+
+
+def propagate(f: np.ndarray, rho: float, fresnel0: float) -> np.ndarray:
+    """D_rho f on the last two axes (reading R2)."""
+    H, W = f.shape[-2:]
+    h = transfer(H, rho, fresnel0)[:, None] * transfer(W, rho, fresnel0)[None, :]
+    return np.fft.ifft2(np.fft.fft2(f) * h)
+
+
+# ---------------------------------------------------------------------------
+# Radon transform R_k (Eq. 14), Joseph discretisation (reading R1)
+# ---------------------------------------------------------------------------
+
+def _joseph_taps(W: int, theta: float, step: int):
+    """Taps of all rays for one step of the walk along the dominant axis.
+
+    Returns (axis, idx0, w, scale): for bin i the ray crosses line `step` of
+    the dominant axis at fractional index f_i = idx0_i + w_i of the other axis.
+    axis = 0: the walk is along y (|cos| >= |sin|) and the taps index x.
+    axis = 1: the walk is along x and the taps index y.
+    """
+    c = W / 2.0
+    C, S = np.cos(theta), np.sin(theta)
+    s = np.arange(W, dtype=np.float64) - c
+    if abs(C) >= abs(S):
+        f = c + (s - (step - c) * S) / C
+        axis, scale = 0, 1.0 / abs(C)
+    else:
+        f = c + (s - (step - c) * C) / S
+        axis, scale = 1, 1.0 / abs(S)
+    i0 = np.floor(f).astype(np.int64)
+    return axis, i0, f - i0, scale
+
+
+def radon(u: np.ndarray, theta: float) -> np.ndarray:
+    """p[z, i] = R_theta u: ray sums of every slice z at one angle.
+
+    u is (W, W, H) = u[y, x, z]; the result is (H, W) = p[z, bin].
+    """
+    W, W2, H = u.shape
+    assert W == W2
+    pt = np.zeros((W, H), dtype=np.result_type(u.dtype, np.float64))
+    for step in range(W):
+        axis, i0, w, scale = _joseph_taps(W, theta, step)
+        for idx, wt in ((i0, 1.0 - w), (i0 + 1, w)):
+            ok = (idx >= 0) & (idx < W)
+            if not ok.any():
+                continue
+            if axis == 0:
+                vals = u[step, idx[ok], :]
+            else:
+                vals = u[idx[ok], step, :]
+            pt[ok, :] += (wt[ok] * scale)[:, None] * vals
+    return pt.T.copy()
+
+
+def radon_T(p: np.ndarray, theta: float, W: int) -> np.ndarray:
+    """Literal transpose of `radon`: scatter each ray sum back with the same
+    interpolation weights.  p is (H, W) = p[z, bin]; returns (W, W, H)."""
+    H = p.shape[0]
+    g = np.zeros((W, W, H), dtype=np.result_type(p.dtype, np.float64))
+    pt = p.T
+    for step in range(W):
+        axis, i0, w, scale = _joseph_taps(W, theta, step)
+        for idx, wt in ((i0, 1.0 - w), (i0 + 1, w)):
+            ok = (idx >= 0) & (idx < W)
+            if not ok.any():
+                continue
+            sel = idx[ok]
+            # Consecutive bins are >= 1 index apart along a step (the slope
+            # is 1/max(|cos|,|sin|) >= 1), so `sel` holds no repeated index
+            # and a plain fancy-index += is an exact scatter-add.
+            assert np.all(np.diff(sel) != 0)
+            contrib = (wt[ok] * scale)[:, None] * pt[ok, :]
+            if axis == 0:
+                g[step, sel, :] += contrib
+            else:
+                g[sel, step, :] += contrib
+    return g
+
+
+# ---------------------------------------------------------------------------
+# Demagnification and shift M_{1/m~} S_t (reading R3)
+# ---------------------------------------------------------------------------
+
+def interp_matrix(n: int, mag: float, shift: float) -> np.ndarray:
+    """Dense n x n linear-interpolation matrix of one axis:
+    (B1 f)[i] = f sampled at c + mag (i - c) - shift, taps outside dropped."""
+    c = n / 2.0
+    src = c + mag * (np.arange(n, dtype=np.float64) - c) - shift
+    i0 = np.floor(src).astype(np.int64)
+    w = src - i0
+    B = np.zeros((n, n))
+    for idx, wt in ((i0, 1.0 - w), (i0 + 1, w)):
+        ok = (idx >= 0) & (idx < n)
+        B[np.nonzero(ok)[0], idx[ok]] += wt[ok]
+    return B
+
+
+def resample(f: np.ndarray, mag: float, ty: float = 0.0, tx: float = 0.0):
+    """B f: bilinear sampling of an (H, W) frame (separable)."""
+    H, W = f.shape
+    return interp_matrix(H, mag, ty) @ f @ interp_matrix(W, mag, tx).T
+
+
+def resample_T(g: np.ndarray, mag: float, ty: float = 0.0, tx: float = 0.0):
+    """B^T g, the exact transpose of `resample`."""
+    H, W = g.shape
+    return interp_matrix(H, mag, ty).T @ g @ interp_matrix(W, mag, tx)
+
+
+def transmit(psi: np.ndarray, mag: float, ty: float = 0.0, tx: float = 0.0):
+    """M_{1/m~} S_t psi with free space (transmission 1) outside the grid."""
+    return 1.0 + resample(psi - 1.0, mag, ty, tx)
+
+
+# ---------------------------------------------------------------------------
+# The joint model and its objective/gradient
+# ---------------------------------------------------------------------------
+
+def transmittance(u: np.ndarray, theta: float, kappa: float) -> np.ndarray:
+    """psi_k = exp(i kappa R_k u) (Sec. 5, Eq. 17)."""
+    return np.exp(1j * kappa * radon(u, theta))
+
+
+def probes(q: np.ndarray, geom: Geometry):
+    """Q_j = D_{rho_probe_j} q: the probe at sample plane j (Eq. 8)."""
+    _, rho_p = distances(geom.m0, geom.mag_rel)
+    return [propagate(q, r, geom.fresnel0) for r in rho_p]
+
+
+def _residual(v: np.ndarray, a: np.ndarray):
+    """(|v| - a)^2 summed, and r = 2 (v - a v/|v|) (Eq. 11, reading R4)."""
+    av = np.abs(v)
+    unit = np.divide(v, av, out=np.zeros_like(v), where=av > 0)
+    return float(np.sum((av - a) ** 2)), 2.0 * (v - a * unit)
+
+
+def forward(u: np.ndarray, q: np.ndarray, geom: Geometry, ks=None) -> np.ndarray:
+    """Detector fields v_kj of Eq. (17) for the angles `ks` (default: all)."""
+    ks = range(geom.n_angles) if ks is None else ks
+    rho_d, _ = distances(geom.m0, geom.mag_rel)
+    Q = probes(q, geom)
+    out = np.zeros((len(ks), geom.n_dist, geom.H, geom.W), dtype=np.complex128)
+    for a, k in enumerate(ks):
+        psi = transmittance(u, geom.theta[k], geom.kappa)
+        for j in range(geom.n_dist):
+            phi = transmit(psi, geom.mag_rel[j], *geom.t(k, j))
+            out[a, j] = propagate(Q[j] * phi, rho_d[j], geom.fresnel0)
+    return out
+
+
+def reference_term(q: np.ndarray, amp_ref: np.ndarray, fresnel0: float):
+    """|| |D_1 q| - sqrt(d~r) ||^2 and its probe gradient D_{-1}(r_ref)."""
+    P = propagate(q, 1.0, fresnel0)
+    F, r = _residual(P, amp_ref)
+    return F, propagate(r, -1.0, fresnel0)
+
+
+def objective(u, q, amp, amp_ref, geom: Geometry) -> float:
+    """F(u, q) = F2(psi_k = exp(i kappa R_k u), q), Eq. (10) with Eq. (17)."""
+    v = forward(u, q, geom)
+    F = float(np.sum((np.abs(v) - amp) ** 2))
+    return F + reference_term(q, amp_ref, geom.fresnel0)[0]
+
+
+def gradient(u, q, amp, amp_ref, geom: Geometry, with_reference=True):
+    """F, g_u, g_q of the joint objective.
+
+    Per angle: forward to v_kj, residual r_kj (Eq. 11), w_kj = D_{-rho}(r_kj)
+    (D* = D_{-z}), probe part conj(phi_kj) w_kj (display after Eq. 11),
+    object part B^T(conj(Q_j) w_kj) (L* of Eq. 11), chain rule through the
+    exponential and R^T (reading R5).
+    """
+    rho_d, rho_p = distances(geom.m0, geom.mag_rel)
+    Q = probes(q, geom)
+    F = 0.0
+    G = [np.zeros((geom.H, geom.W), np.complex128) for _ in range(geom.n_dist)]
+    g_u = np.zeros(u.shape, np.complex128)
+    for k in range(geom.n_angles):
+        psi = transmittance(u, geom.theta[k], geom.kappa)
+        g_psi = np.zeros_like(psi)
+        for j in range(geom.n_dist):
+            ty, tx = geom.t(k, j)
+            phi = transmit(psi, geom.mag_rel[j], ty, tx)
+            v = propagate(Q[j] * phi, rho_d[j], geom.fresnel0)
+            Fk, r = _residual(v, amp[k, j])
+            F += Fk
+            w = propagate(r, -rho_d[j], geom.fresnel0)
+            G[j] += np.conj(phi) * w
+            g_psi += resample_T(np.conj(Q[j]) * w, geom.mag_rel[j], ty, tx)
+        h = -1j * geom.kappa * np.conj(psi) * g_psi
+        g_u += radon_T(h, geom.theta[k], geom.W)
+    g_q = sum(propagate(G[j], -rho_p[j], geom.fresnel0) for j in range(geom.n_dist))
+    if with_reference:
+        Fr, gr = reference_term(q, amp_ref, geom.fresnel0)
+        F += Fr
+        g_q = g_q + gr
+    return F, g_u, g_q
+
+
+def adjoint(u, q, w_frames, geom: Geometry, ks=None):
+    """J^H w for J = d v / d(u, q) over the angles `ks`: (g_u, g_q).
+
+    v is holomorphic in (u, q), so this is the vector-Jacobian product of a
+    complex-linear map; with w = r it reproduces the gradient without the
+    reference term.
+    """
+    ks = range(geom.n_angles) if ks is None else ks
+    rho_d, rho_p = distances(geom.m0, geom.mag_rel)
+    Q = probes(q, geom)
+    G = [np.zeros((geom.H, geom.W), np.complex128) for _ in range(geom.n_dist)]
+    g_u = np.zeros(u.shape, np.complex128)
+    for a, k in enumerate(ks):
+        psi = transmittance(u, geom.theta[k], geom.kappa)
+        g_psi = np.zeros_like(psi)
+        for j in range(geom.n_dist):
+            ty, tx = geom.t(k, j)
+            phi = transmit(psi, geom.mag_rel[j], ty, tx)
+            wb = propagate(w_frames[a, j], -rho_d[j], geom.fresnel0)
+            G[j] += np.conj(phi) * wb
+            g_psi += resample_T(np.conj(Q[j]) * wb, geom.mag_rel[j], ty, tx)
+        g_u += radon_T(-1j * geom.kappa * np.conj(psi) * g_psi, geom.theta[k], geom.W)
+    g_q = sum(propagate(G[j], -rho_p[j], geom.fresnel0) for j in range(geom.n_dist))
+    return g_u, g_q
+
+
+# ---------------------------------------------------------------------------
+# Single-angle multi-distance retrieval (psi is the unknown; Eq. 10, N_theta=1)
+# ---------------------------------------------------------------------------
+
+def holo2d_forward(psi, q, mag_rel, m0, fresnel0):
+    rho_d, rho_p = distances(m0, mag_rel)
+    return np.stack([
+        propagate(propagate(q, rho_p[j], fresnel0) * transmit(psi, mag_rel[j]),
+                  rho_d[j], fresnel0)
+        for j in range(len(mag_rel))])
+
+
+def holo2d_gradient(psi, q, amp, amp_ref, mag_rel, m0, fresnel0):
+    """F2 of one projection with its own probe: F, g_psi, g_q (Eq. 10/11)."""
+    rho_d, rho_p = distances(m0, mag_rel)
+    F = 0.0
+    g_psi = np.zeros(psi.shape, np.complex128)
+    g_q = np.zeros(q.shape, np.complex128)
+    for j in range(len(mag_rel)):
+        Qj = propagate(q, rho_p[j], fresnel0)
+        phi = transmit(psi, mag_rel[j])
+        v = propagate(Qj * phi, rho_d[j], fresnel0)
+        Fj, r = _residual(v, amp[j])
+        F += Fj
+        w = propagate(r, -rho_d[j], fresnel0)
+        g_psi += resample_T(np.conj(Qj) * w, mag_rel[j])
+        g_q += propagate(np.conj(phi) * w, -rho_p[j], fresnel0)
+    Fr, gr = reference_term(q, amp_ref, fresnel0)
+    return F + Fr, g_psi, g_q + gr
+
+
+# ---------------------------------------------------------------------------
+# Error metric used by the parity tests
+# ---------------------------------------------------------------------------
+
+def rel_err(x, ref) -> float:
+    """||x - ref||_2 / ||ref||_2 in float64 (0 if both are zero)."""
+    x = np.asarray(x, dtype=np.complex128)
+    ref = np.asarray(ref, dtype=np.complex128)
+    den = np.linalg.norm(ref.ravel())
+    num = np.linalg.norm((x - ref).ravel())
+    if den == 0.0:
+        return float(num)
+    return float(num / den)
