@@ -45,7 +45,7 @@ in the design notes of the repository):
      grid (the m0^2 M_{1/m0} rescaling is the identity there).
 
 Array layouts (the same ones the C ABI uses):
-  u, g_u      (W, W, H) complex  -- u[y, x, z], z (detector row) last
+  u, g_u      (H, W, W) complex  -- u[z, y, x], z = detector row = slice
   q, g_q      (H, W) complex
   amp         (n_angles, n_dist, H, W) float
   amp_ref     (H, W) float
@@ -161,11 +161,11 @@ def _joseph_taps(W: int, theta: float, step: int):
 def radon(u: np.ndarray, theta: float) -> np.ndarray:
     """p[z, i] = R_theta u: ray sums of every slice z at one angle.
 
-    u is (W, W, H) = u[y, x, z]; the result is (H, W) = p[z, bin].
+    u is (H, W, W) = u[z, y, x]; the result is (H, W) = p[z, bin].
     """
-    W, W2, H = u.shape
+    H, W, W2 = u.shape
     assert W == W2
-    pt = np.zeros((W, H), dtype=np.result_type(u.dtype, np.float64))
+    p = np.zeros((H, W), dtype=np.result_type(u.dtype, np.float64))
     for step in range(W):
         axis, i0, w, scale = _joseph_taps(W, theta, step)
         for idx, wt in ((i0, 1.0 - w), (i0 + 1, w)):
@@ -173,19 +173,18 @@ def radon(u: np.ndarray, theta: float) -> np.ndarray:
             if not ok.any():
                 continue
             if axis == 0:
-                vals = u[step, idx[ok], :]
+                vals = u[:, step, idx[ok]]
             else:
-                vals = u[idx[ok], step, :]
-            pt[ok, :] += (wt[ok] * scale)[:, None] * vals
-    return pt.T.copy()
+                vals = u[:, idx[ok], step]
+            p[:, ok] += (wt[ok] * scale)[None, :] * vals
+    return p
 
 
 def radon_T(p: np.ndarray, theta: float, W: int) -> np.ndarray:
     """Literal transpose of `radon`: scatter each ray sum back with the same
-    interpolation weights.  p is (H, W) = p[z, bin]; returns (W, W, H)."""
+    interpolation weights.  p is (H, W) = p[z, bin]; returns (H, W, W)."""
     H = p.shape[0]
-    g = np.zeros((W, W, H), dtype=np.result_type(p.dtype, np.float64))
-    pt = p.T
+    g = np.zeros((H, W, W), dtype=np.result_type(p.dtype, np.float64))
     for step in range(W):
         axis, i0, w, scale = _joseph_taps(W, theta, step)
         for idx, wt in ((i0, 1.0 - w), (i0 + 1, w)):
@@ -197,11 +196,11 @@ def radon_T(p: np.ndarray, theta: float, W: int) -> np.ndarray:
             # is 1/max(|cos|,|sin|) >= 1), so `sel` holds no repeated index
             # and a plain fancy-index += is an exact scatter-add.
             assert np.all(np.diff(sel) != 0)
-            contrib = (wt[ok] * scale)[:, None] * pt[ok, :]
+            contrib = (wt[ok] * scale)[None, :] * p[:, ok]
             if axis == 0:
-                g[step, sel, :] += contrib
+                g[:, step, sel] += contrib
             else:
-                g[sel, step, :] += contrib
+                g[:, sel, step] += contrib
     return g
 
 

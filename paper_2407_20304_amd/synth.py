@@ -114,14 +114,14 @@ def ellipsoid_params(W: int, H: int, seed: int, n: int = 10, delta_max: float = 
 
 def ellipsoid_volume(W: int, H: int, seed: int, device="cpu", n: int = 10,
                      delta_max: float = 1e-5):
-    """Complex volume u = delta + i beta, shape (W, W, H) = u[y, x, z].
+    """Complex volume u = delta + i beta, shape (H, W, W) = u[z, y, x].
 
     Voxel (ix, iy, iz) sits at (ix - W/2, iy - W/2, iz - H/2); a voxel takes the
     value of the last ellipsoid (in drawing order) that contains its position.
     Returns a torch complex64 tensor on `device`.
     """
     import torch
-    vol = torch.zeros((W, W, H), dtype=torch.complex64, device=device)
+    vol = torch.zeros((H, W, W), dtype=torch.complex64, device=device)
     for (cx, cy, cz, ax, ay, az, rot, delta) in ellipsoid_params(W, H, seed, n, delta_max):
         r = max(ax, ay)
         y0, y1 = max(0, int(math.floor(W / 2 + cy - r))), min(W, int(math.ceil(W / 2 + cy + r)) + 1)
@@ -137,9 +137,9 @@ def ellipsoid_volume(W: int, H: int, seed: int, device="cpu", n: int = 10,
         xr = X * c + Y * s
         yr = -X * s + Y * c
         inplane = (xr / ax) ** 2 + (yr / ay) ** 2               # (ny, nx)
-        inside = inplane[:, :, None] + ((Zc / az) ** 2)[None, None, :] <= 1.0
+        inside = inplane[None, :, :] + ((Zc / az) ** 2)[:, None, None] <= 1.0
         val = torch.tensor(complex(delta, delta / 100.0), dtype=torch.complex64, device=device)
-        block = vol[y0:y1, x0:x1, z0:z1]
+        block = vol[z0:z1, y0:y1, x0:x1]
         block[inside] = val
     return vol
 

@@ -123,7 +123,7 @@ def footprint_radon(u, theta):
     half-width h = max(|cos|, |sin|) and height 1/h centred on its projection
     s = x cos + y sin -- the closed form of linear interpolation along unit
     steps of the dominant axis."""
-    W, _, H = u.shape
+    H, W, _ = u.shape
     c = W / 2
     C, S = math.cos(theta), math.sin(theta)
     h = max(abs(C), abs(S))
@@ -134,33 +134,33 @@ def footprint_radon(u, theta):
             for i in range(W):
                 wt = max(0.0, 1.0 - abs((i - c) - q) / h) / h
                 if wt:
-                    p[:, i] += wt * u[iy, ix, :]
+                    p[:, i] += wt * u[:, iy, ix]
     return p
 
 
 @pytest.mark.parametrize("theta", [0.0, 0.3, math.pi / 4, 1.1, 2.0, 2.9])
 def test_radon_matches_brute_force_footprint(theta):
     rng = np.random.default_rng(3)
-    u = crandn(rng, 12, 12, 3)
+    u = crandn(rng, 3, 12, 12)
     np.testing.assert_allclose(O.radon(u, theta), footprint_radon(u, theta), atol=1e-12)
 
 
 def test_radon_axis_sums():
     rng = np.random.default_rng(4)
-    u = crandn(rng, 16, 16, 5)
+    u = crandn(rng, 5, 16, 16)
     # theta = 0: bins along x, rays along y
-    np.testing.assert_allclose(O.radon(u, 0.0), u.sum(axis=0).T, atol=1e-12)
+    np.testing.assert_allclose(O.radon(u, 0.0), u.sum(axis=1), atol=1e-12)
     # theta = pi/2: bins along y, rays along x
-    np.testing.assert_allclose(O.radon(u, math.pi / 2), u.sum(axis=1).T, atol=1e-12)
+    np.testing.assert_allclose(O.radon(u, math.pi / 2), u.sum(axis=2), atol=1e-12)
 
 
 def test_radon_point_voxel_lands_on_its_projection():
     # A single voxel at (x, y) = (5, -7) lands on the two bins around
     # s = x cos + y sin, the nearer one taking the larger weight.
     W = 32
-    u = np.zeros((W, W, 1))
+    u = np.zeros((1, W, W))
     ix, iy = 21, 9
-    u[iy, ix, 0] = 1.0
+    u[0, iy, ix] = 1.0
     for theta in (0.2, 0.9, 1.7, 2.6):
         p = O.radon(u, theta)[0].real
         s = (ix - W / 2) * math.cos(theta) + (iy - W / 2) * math.sin(theta)
@@ -176,9 +176,9 @@ def test_radon_uniform_ball_chords():
     # A centred ball of radius r: every ray at offset s through slice z
     # crosses 2 sqrt(r^2 - s^2 - z^2) voxels, at every angle.
     W, H, r = 96, 9, 40.0
-    y = np.arange(W)[:, None, None] - W / 2
-    x = np.arange(W)[None, :, None] - W / 2
-    z = np.arange(H)[None, None, :] - H / 2
+    z = np.arange(H)[:, None, None] - H / 2
+    y = np.arange(W)[None, :, None] - W / 2
+    x = np.arange(W)[None, None, :] - W / 2
     u = ((x ** 2 + y ** 2 + (z * 4.0) ** 2) <= r * r).astype(float)
     s = np.arange(W) - W / 2
     for theta in (0.0, 0.35, math.pi / 4, 1.3, 2.2):
@@ -197,7 +197,7 @@ def test_radon_uniform_ball_chords():
 @pytest.mark.parametrize("theta", [0.1, math.pi / 4, 1.9, 3.0])
 def test_radon_adjoint(theta):
     rng = np.random.default_rng(5)
-    u = crandn(rng, 20, 20, 4)
+    u = crandn(rng, 4, 20, 20)
     p = crandn(rng, 4, 20)
     lhs = np.vdot(p, O.radon(u, theta))
     rhs = np.vdot(O.radon_T(p, theta, 20), u)
@@ -256,7 +256,7 @@ def tiny_problem(seed=10, W=16, H=8, n_angles=3, shifts=True):
     sh = rng.uniform(-1.5, 1.5, (n_angles, 4, 2)) if shifts else None
     geom = O.Geometry(H=H, W=W, theta=theta, mag_rel=[1.0, 1.08, 1.25, 1.5],
                       m0=300.0, fresnel0=0.05, kappa=40.0, shift=sh)
-    u = 1e-3 * (rng.uniform(0, 1, (W, W, H)) + 0.01j * rng.uniform(0, 1, (W, W, H)))
+    u = 1e-3 * (rng.uniform(0, 1, (H, W, W)) + 0.01j * rng.uniform(0, 1, (H, W, W)))
     q = (1 + 0.1 * crandn(rng, H, W))
     amp = np.abs(1 + 0.2 * crandn(rng, n_angles, 4, H, W))
     amp_ref = np.abs(1 + 0.2 * crandn(rng, H, W))
@@ -314,7 +314,7 @@ def test_plane_wave_probe_reduces_to_parallel_beam():
     W, H = 16, 8
     geom = O.Geometry(H=H, W=W, theta=[0.7], mag_rel=[1.0, 1.0], m0=300.0,
                       fresnel0=0.05, kappa=30.0)
-    u = 1e-3 * crandn(rng, W, W, H)
+    u = 1e-3 * crandn(rng, H, W, W)
     v = O.forward(u, np.ones((H, W), complex), geom)
     psi = np.exp(1j * 30.0 * O.radon(u, 0.7))
     rd, _ = O.distances(300.0, [1.0])
