@@ -1,0 +1,155 @@
+/*
+ * holo.h -- C ABI of the MI355X holotomography gradient library (libholo.so).
+ *
+ * The library evaluates the joint object-and-probe holotomography objective
+ * and its gradients on one AMD Instinct MI355X (gfx950):
+ *
+ *   psi_k  = exp(i kappa R_k u)                     joint model, Sec. 5 Eq. (17)
+ *   phi_kj = M_{1/m~_j} S_{t_kj}(psi_k)             demagnify + shift, Sec. 2 Eq. (8)-(9)
+ *   Q_j    = D_{rho_probe_j}(q)                     probe at plane j, Eq. (8)
+ *   v_kj   = D_{rho_det_j}(Q_j . phi_kj)            detector field, Eq. (8) / Thm A.3
+ *   F(u,q) = sum_kj || |v_kj| - a_kj ||^2
+ *          + || |D_1 q| - a_ref ||^2                amplitude functional F2, Eq. (10)
+ *
+ * and the gradients of Eq. (11) and the display after it, extended to u by the
+ * chain rule through exp and R.  Everything is dimensionless: lengths are
+ * detector pixels after the data rescaling d~ = m0^2 M_{1/m0} d (Eq. 9 text),
+ * distances are multiples of zeta_0 = z_0 (Z - z_0) / Z, and
+ *   rho_det_j   = zeta_j / (m~_j^2 zeta_0) = (m0 - m~_j) / (m~_j (m0 - 1)),
+ *   rho_probe_j = omega_j / zeta_0         = m0 (m~_j - 1) / (m~_j (m0 - 1)),
+ * with m~_j = z_j / z_0 and m0 = Z / z_0 (Thm A.3).  D_rho is the Fresnel
+ * transfer function exp(-i pi rho (kx^2/W^2 + ky^2/H^2) / N_F0) applied by FFT
+ * on the unpadded periodic H x W grid (Appendix A, kernel P_Z); it is unitary
+ * and D_rho^H = D_{-rho}.
+ *
+ * Discretisations (the paper names the operators but not their grids):
+ *   R_k  Joseph ray sums: unit steps along the dominant axis of the ray,
+ *        linear interpolation across it, path factor 1/max(|cos|,|sin|).
+ *        Voxel (ix, iy) sits at (ix - W/2, iy - W/2); bin i sits at
+ *        s = i - W/2 with s = x cos(theta) + y sin(theta).
+ *   M S  bilinear sampling at src = c + m~ (x - c) - t (c = n/2 per axis);
+ *        outside the psi grid the transmission is 1 (free space).
+ *   |v|=0  the residual uses v/|v| := 0.
+ *
+ * Gradient convention: g = dF/dRe + i dF/dIm (the paper's 2 L*(...)); this is
+ * also PyTorch's convention for the gradient of a real loss.
+ *
+ * Memory layouts (all device pointers, row-major, complex = interleaved
+ * float re/im, i.e. the layout of torch.complex64):
+ *   u, g_u    [H][W][W]                      u[z][y][x], z = detector row
+ *   q, g_q    [H][W]
+ *   amp       [n_angles][n_dist][H][W] float  a_kj = sqrt(d~_kj)
+ *   amp_ref   [H][W] float                    a_ref = sqrt(d~r)
+ *   v, w      [k1-k0][n_dist][H][W]           detector-plane frames
+ *
+ * Sizes: H and W must each be one of 64, 128, 192, 256, 384, 512, 1024,
+ * 2048 (FFT lengths 2^a and 3*2^a handled in LDS), and 1 <= n_dist <= 8.
+ *
+ * Ownership and execution: every device buffer, including the workspace, is
+ * owned by the caller.  A call validates its arguments on the host, returns a
+ * non-OK status before enqueueing anything if they are wrong, and otherwise
+ * enqueues kernels on `stream` (a hipStream_t; NULL = the default stream) and
+ * returns without synchronising.  Outputs are overwritten, never
+ * accumulated.  Scalars (F) are written to device memory as double.  The
+ * plan's first compute call uploads small constant tables to the current
+ * device (one hipMalloc owned by the plan, freed by holo_plan_destroy); later
+ * calls on that plan must use the same device.  A plan may be used by one
+ * stream at a time.  Device faults surface at the caller's synchronisation.
+ */
+#ifndef HOLO_H
+#define HOLO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { float re, im; } holo_c64;
+
+typedef enum {
+  HOLO_OK = 0,
+  HOLO_ERR_INVALID_ARGUMENT = 1,   /* NULL pointer, bad range, bad geometry  */
+  HOLO_ERR_UNSUPPORTED_SIZE = 2,   /* H or W not a supported FFT length     */
+  HOLO_ERR_WORKSPACE_TOO_SMALL = 3,
+  HOLO_ERR_HIP = 4,                /* a HIP runtime call or launch failed   */
+  HOLO_ERR_OUT_OF_HOST_MEMORY = 5
+} holo_status;
+
+/* Geometry of one reconstruction problem (all host memory, copied by
+ * holo_plan_create; the caller may free it afterwards). */
+typedef struct {
+  int32_t det_rows;        /* H: detector rows = volume slices z            */
+  int32_t det_cols;        /* W: detector columns = in-plane volume edge    */
+  int32_t n_angles;        /* N_theta >= 1                                  */
+  int32_t n_dist;          /* N_z, number of sample planes, 1..8            */
+  const double* theta;     /* [n_angles] projection angles, radians         */
+  const double* mag_rel;   /* [n_dist] m~_j = z_j / z_0 >= 1 (plane 0 = 1)  */
+  double m0;               /* Z / z_0 > 1 (Table 1: 300)                    */
+  double fresnel0;         /* N_F0 = Delta^2 / (lambda zeta_0) > 0          */
+  double kappa;            /* 2 pi Delta / lambda: phase per unit u per voxel */
+  const float* shift;      /* [n_angles][n_dist][2] = (t_y, t_x) sample
+                              shifts in pixels (Eq. 9), or NULL for none   */
+  int32_t chunk;           /* angles per chunk of the frame stages; 0 = 64  */
+} holo_geom;
+
+typedef struct holo_plan holo_plan;
+
+/* Validate `geom` and build the host-side plan (no device work).
+ * Errors: INVALID_ARGUMENT (NULL, n_angles < 1, n_dist outside 1..8,
+ * m0 <= 1, fresnel0 <= 0, non-finite values, mag_rel < 1), UNSUPPORTED_SIZE. */
+holo_status holo_plan_create(const holo_geom* geom, holo_plan** out);
+
+/* Free a plan and its device tables.  NULL is accepted. */
+holo_status holo_plan_destroy(holo_plan* plan);
+
+/* Bytes of device workspace every compute call of this plan needs. */
+holo_status holo_workspace_bytes(const holo_plan* plan, size_t* bytes);
+
+/* Forward model: v_kj for the angles k0 <= k < k1 (Eq. 8 with Eq. 17). */
+holo_status holo_fwd(holo_plan* plan, const holo_c64* u, const holo_c64* q,
+                     int32_t k0, int32_t k1, holo_c64* v,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of the linearised forward model: (g_u, g_q) = J^H w with
+ * J = d v / d(u, q) over the angles k0 <= k < k1 (v is holomorphic in u and
+ * q, so this is the vector-Jacobian product).  Either output may be NULL. */
+holo_status holo_adj(holo_plan* plan, const holo_c64* u, const holo_c64* q,
+                     int32_t k0, int32_t k1, const holo_c64* w,
+                     holo_c64* g_u, holo_c64* g_q,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* Objective F(u, q) of Eq. (10) over all angles, written to F_dev[0]. */
+holo_status holo_objective(holo_plan* plan, const holo_c64* u, const holo_c64* q,
+                           const float* amp, const float* amp_ref, double* F_dev,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* Objective and gradients in one sweep.  F_dev, g_u and g_q may each be
+ * NULL; with g_u == NULL the R^T sweep is skipped. */
+holo_status holo_grad(holo_plan* plan, const holo_c64* u, const holo_c64* q,
+                      const float* amp, const float* amp_ref,
+                      double* F_dev, holo_c64* g_u, holo_c64* g_q,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* holo_grad with g_q = NULL: gradient with respect to the object only. */
+holo_status holo_grad_object(holo_plan* plan, const holo_c64* u, const holo_c64* q,
+                             const float* amp, const float* amp_ref,
+                             double* F_dev, holo_c64* g_u,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/* holo_grad with g_u = NULL: gradient with respect to the probe only (the
+ * forward ray sums still run; the R^T sweep does not). */
+holo_status holo_grad_probe(holo_plan* plan, const holo_c64* u, const holo_c64* q,
+                            const float* amp, const float* amp_ref,
+                            double* F_dev, holo_c64* g_q,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/* Message describing the last non-OK status returned on this thread. */
+const char* holo_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOLO_H */

@@ -1,0 +1,182 @@
+// In-LDS complex FFT of one line per thread group, for gfx950.
+//
+// Stockham autosort formulation: for each radix-R stage with P = product of
+// the radices already applied, butterfly i (0 <= i < N/R) reads
+// x[i + j N/R], multiplies input j by W_{PR}^{j (i mod P)}, applies an R-point
+// DFT and writes output j to y[(i / P) P R + (i mod P) + j P].  Input and
+// output are in natural order, so the transfer-function multiply in between
+// indexes frequencies directly.  Each stage reads all its inputs into
+// registers, synchronises, and writes in place, so one LDS line per transform
+// suffices.
+//
+// Lengths are 2^a (radices 8, then 4 or 2) and 3 * 2^a (one radix-3 stage
+// first).  Twiddles come from a table tw[m] = exp(-2 pi i m / N) built in
+// double precision on the host and staged in LDS by the caller.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace holo {
+
+__host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+__host__ __device__ constexpr int pow2_floor(int n) { return n <= 1 ? 1 : 2 * pow2_floor(n / 2); }
+
+__host__ __device__ constexpr int fft_has3(int N) { return N % 3 == 0 ? 1 : 0; }
+__host__ __device__ constexpr int fft_log2m(int N) { return ilog2(fft_has3(N) ? N / 3 : N); }
+
+__host__ __device__ constexpr int fft_nstages(int N) {
+  return fft_has3(N) +
+         (fft_log2m(N) % 3 == 0 ? fft_log2m(N) / 3
+          : fft_log2m(N) % 3 == 2 ? fft_log2m(N) / 3 + 1
+          : (fft_log2m(N) >= 3 ? fft_log2m(N) / 3 + 1 : 1));
+}
+
+// Radix of stage t of the power-of-two part (2^L): 8 ... 8 then {}, {4},
+// {4, 4} or {2}.
+__host__ __device__ constexpr int fft_radix_pow2(int L, int t) {
+  return (L % 3 == 0) ? 8
+         : (L % 3 == 2) ? (t < L / 3 ? 8 : 4)
+         : (L >= 3 ? (t < L / 3 - 1 ? 8 : 4) : 2);
+}
+
+// Radix of stage s of an N-point transform (one radix-3 stage first).
+__host__ __device__ constexpr int fft_radix(int N, int s) {
+  return (fft_has3(N) && s == 0) ? 3 : fft_radix_pow2(fft_log2m(N), s - fft_has3(N));
+}
+
+__host__ __device__ constexpr int fft_pstride(int N, int s) {
+  return s == 0 ? 1 : fft_pstride(N, s - 1) * fft_radix(N, s - 1);
+}
+
+// Threads that share one line in the row kernels: a power of two near N/8.
+__host__ __device__ constexpr int fft_row_threads(int N) { return pow2_floor(N / 8); }
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ float2 mul_mi(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+template <int R, bool INV> struct Dft;
+
+template <bool INV> struct Dft<2, INV> {
+  __device__ __forceinline__ static void run(float2* v) {
+    float2 a = v[0];
+    v[0] = cadd(a, v[1]);
+    v[1] = csub(a, v[1]);
+  }
+};
+
+template <bool INV> struct Dft<3, INV> {
+  __device__ __forceinline__ static void run(float2* v) {
+    const float s3 = 0.86602540378443864676f;  // sin(2 pi / 3)
+    float2 t = cadd(v[1], v[2]);
+    float2 d = csub(v[1], v[2]);
+    float2 m = make_float2(v[0].x - 0.5f * t.x, v[0].y - 0.5f * t.y);
+    float2 jd = mul_mi<INV>(d);  // -i d (forward) / +i d (inverse)
+    v[0] = cadd(v[0], t);
+    v[1] = make_float2(m.x + s3 * jd.x, m.y + s3 * jd.y);
+    v[2] = make_float2(m.x - s3 * jd.x, m.y - s3 * jd.y);
+  }
+};
+
+template <bool INV> struct Dft<4, INV> {
+  __device__ __forceinline__ static void run(float2* v) {
+    float2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+    float2 a2 = cadd(v[1], v[3]), a3 = mul_mi<INV>(csub(v[1], v[3]));
+    v[0] = cadd(a0, a2);
+    v[2] = csub(a0, a2);
+    v[1] = cadd(a1, a3);
+    v[3] = csub(a1, a3);
+  }
+};
+
+template <bool INV> struct Dft<8, INV> {
+  __device__ __forceinline__ static void run(float2* v) {
+    const float r = 0.70710678118654752440f;
+    float2 e[4] = {v[0], v[2], v[4], v[6]};
+    float2 o[4] = {v[1], v[3], v[5], v[7]};
+    Dft<4, INV>::run(e);
+    Dft<4, INV>::run(o);
+    // o_k *= exp(-+ 2 pi i k / 8)
+    float2 t1 = INV ? make_float2(r * (o[1].x - o[1].y), r * (o[1].x + o[1].y))
+                    : make_float2(r * (o[1].x + o[1].y), r * (o[1].y - o[1].x));
+    float2 t2 = mul_mi<INV>(o[2]);
+    float2 t3 = INV ? make_float2(-r * (o[3].x + o[3].y), r * (o[3].x - o[3].y))
+                    : make_float2(r * (o[3].y - o[3].x), -r * (o[3].x + o[3].y));
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], t1);
+    v[5] = csub(e[1], t1);
+    v[2] = cadd(e[2], t2);
+    v[6] = csub(e[2], t2);
+    v[3] = cadd(e[3], t3);
+    v[7] = csub(e[3], t3);
+  }
+};
+
+// One Stockham stage on `line` (LDS), executed by TL threads (thread lt).
+template <int N, int TL, int R, int P, bool INV>
+__device__ __forceinline__ void fft_stage(float2* line, const float2* tw, int lt) {
+  constexpr int NB = N / R;
+  constexpr int IT = (NB + TL - 1) / TL;
+  float2 v[IT][R];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int i = lt + it * TL;
+    if (NB % TL == 0 || i < NB) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) v[it][j] = line[i + j * NB];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int i = lt + it * TL;
+    if (NB % TL == 0 || i < NB) {
+      const int k = i % P;
+      if (P > 1) {
+#pragma unroll
+        for (int j = 1; j < R; ++j) {
+          float2 w = tw[j * k * (N / (P * R))];
+          if (INV) w.y = -w.y;
+          v[it][j] = cmul(v[it][j], w);
+        }
+      }
+      Dft<R, INV>::run(v[it]);
+      const int base = (i - k) * R + k;
+#pragma unroll
+      for (int j = 0; j < R; ++j) line[base + j * P] = v[it][j];
+    }
+  }
+  __syncthreads();
+}
+
+template <int N, int TL, bool INV, int S>
+__device__ __forceinline__ void fft_stages(float2* line, const float2* tw, int lt) {
+  if constexpr (S < fft_nstages(N)) {
+    fft_stage<N, TL, fft_radix(N, S), fft_pstride(N, S), INV>(line, tw, lt);
+    fft_stages<N, TL, INV, S + 1>(line, tw, lt);
+  }
+}
+
+// Unnormalised DFT of `line` (forward: exp(-2 pi i jk/N); INV: exp(+...)).
+// All threads of the workgroup must call it (it synchronises); the line must
+// be fully written before the call.
+template <int N, int TL, bool INV>
+__device__ __forceinline__ void fft(float2* line, const float2* tw, int lt) {
+  __syncthreads();
+  fft_stages<N, TL, INV, 0>(line, tw, lt);
+}
+
+}  // namespace holo

@@ -1,0 +1,460 @@
+// Host runtime and C ABI of libholo.so (see include/holo.h).
+//
+// A plan holds the validated geometry, the transfer-function and twiddle
+// tables (built in double precision on the host), the per-angle ray-sum
+// constants and the workspace layout.  A compute call enqueues, on the
+// caller's stream:
+//   probe stage      Q_j = D_{rho_probe_j} q; reference field D_1 q, its cost
+//                    and gradient D_{-1}(r_ref)
+//   per angle chunk  ray sums + exp -> psi; pass A (rows) -> pass B (columns,
+//                    residual) -> pass C (rows, probe gradient) -> pass D
+//                    (transpose of the demagnification, chain rule) -> h
+//   after the chunks R^T over all angles -> g_u;  g_q = sum_j D_{-rho_probe_j}
+//                    G_j + reference gradient;  F = sum of double partials
+#include "../../include/holo.h"
+#include "holo_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace holo;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+holo_status fail(holo_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+enum Mode { kFwd, kAdj, kObj, kGrad };
+
+}  // namespace
+
+struct holo_plan {
+  int H = 0, W = 0, n_angles = 0, nd = 0, chunk = 64;
+  double m0 = 0, fresnel0 = 0, kappa = 0;
+  std::vector<double> theta, mag;
+  std::vector<float> shift;                 // empty = no shifts
+  std::vector<double> ang;                  // [n_angles][kAngleStride]
+  std::vector<float2> twW, twH, chirpW, chirpH;
+  bool any_xwalk = false;
+  // workspace layout (byte offsets)
+  size_t off_Q = 0, off_G = 0, off_P = 0, off_uT = 0, off_psi = 0, off_X = 0, off_S = 0,
+         off_F = 0, ws_bytes = 0, n_fpart = 0;
+  // device tables (lazily uploaded on the first compute call)
+  void* d_tables = nullptr;
+  int device = -1;
+  size_t off_twW = 0, off_twH = 0, off_chW = 0, off_chH = 0, off_ang = 0, off_shift = 0;
+};
+
+static void build_chirp(std::vector<float2>& out, int n, const std::vector<double>& rhos,
+                        double fresnel0) {
+  // exp(-i pi rho k^2 / (N_F0 n^2)) / n with k the signed integer frequency
+  out.resize(rhos.size() * (size_t)n);
+  for (size_t r = 0; r < rhos.size(); ++r) {
+    for (int i = 0; i < n; ++i) {
+      const double k = (2 * i < n) ? i : i - n;
+      // phase in turns, reduced before the trigonometric evaluation
+      double turns = -0.5 * rhos[r] * k * k / (fresnel0 * (double)n * (double)n);
+      turns -= std::floor(turns);
+      const double ph = 2.0 * M_PI * turns;
+      out[r * n + i] = make_float2((float)(std::cos(ph) / n), (float)(std::sin(ph) / n));
+    }
+  }
+}
+
+static void build_twiddles(std::vector<float2>& out, int n) {
+  out.resize(n);
+  for (int m = 0; m < n; ++m) {
+    const double ph = -2.0 * M_PI * (double)m / (double)n;
+    out[m] = make_float2((float)std::cos(ph), (float)std::sin(ph));
+  }
+}
+
+static bool is_finite(double x) { return std::isfinite(x); }
+
+extern "C" holo_status holo_plan_create(const holo_geom* geom, holo_plan** out) {
+  if (!out) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_create: out is NULL");
+  *out = nullptr;
+  if (!geom) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_create: geom is NULL");
+  const holo_geom& G = *geom;
+  if (G.n_angles < 1) return fail(HOLO_ERR_INVALID_ARGUMENT, "n_angles must be >= 1");
+  if (G.n_dist < 1 || G.n_dist > kMaxDist)
+    return fail(HOLO_ERR_INVALID_ARGUMENT, "n_dist must be in 1..8");
+  if (!G.theta || !G.mag_rel) return fail(HOLO_ERR_INVALID_ARGUMENT, "theta/mag_rel is NULL");
+  if (!fft_size_supported(G.det_rows) || !fft_size_supported(G.det_cols))
+    return fail(HOLO_ERR_UNSUPPORTED_SIZE,
+                "det_rows and det_cols must each be one of 64,128,192,256,384,512,1024,2048 (got " +
+                    std::to_string(G.det_rows) + "x" + std::to_string(G.det_cols) + ")");
+  if (!(is_finite(G.m0) && G.m0 > 1.0)) return fail(HOLO_ERR_INVALID_ARGUMENT, "m0 must be finite and > 1");
+  if (!(is_finite(G.fresnel0) && G.fresnel0 > 0.0))
+    return fail(HOLO_ERR_INVALID_ARGUMENT, "fresnel0 must be finite and > 0");
+  if (!is_finite(G.kappa)) return fail(HOLO_ERR_INVALID_ARGUMENT, "kappa must be finite");
+  if (G.chunk < 0) return fail(HOLO_ERR_INVALID_ARGUMENT, "chunk must be >= 0");
+  for (int j = 0; j < G.n_dist; ++j)
+    if (!(is_finite(G.mag_rel[j]) && G.mag_rel[j] >= 1.0))
+      return fail(HOLO_ERR_INVALID_ARGUMENT, "mag_rel[j] must be finite and >= 1");
+  for (int k = 0; k < G.n_angles; ++k)
+    if (!is_finite(G.theta[k])) return fail(HOLO_ERR_INVALID_ARGUMENT, "theta must be finite");
+  if (G.shift) {
+    for (size_t i = 0; i < (size_t)G.n_angles * G.n_dist * 2; ++i)
+      if (!std::isfinite(G.shift[i])) return fail(HOLO_ERR_INVALID_ARGUMENT, "shift must be finite");
+  }
+
+  holo_plan* P = new (std::nothrow) holo_plan();
+  if (!P) return fail(HOLO_ERR_OUT_OF_HOST_MEMORY, "holo_plan_create: out of host memory");
+  try {
+    P->H = G.det_rows;
+    P->W = G.det_cols;
+    P->n_angles = G.n_angles;
+    P->nd = G.n_dist;
+    P->chunk = G.chunk > 0 ? G.chunk : 64;
+    if (P->chunk > P->n_angles) P->chunk = P->n_angles;
+    P->m0 = G.m0;
+    P->fresnel0 = G.fresnel0;
+    P->kappa = G.kappa;
+    P->theta.assign(G.theta, G.theta + G.n_angles);
+    P->mag.assign(G.mag_rel, G.mag_rel + G.n_dist);
+    if (G.shift) P->shift.assign(G.shift, G.shift + (size_t)G.n_angles * G.n_dist * 2);
+
+    // Per-angle ray constants.  Walk along y when |cos| >= |sin|: the ray of
+    // bin i crosses row `step` at x = c + ((i - c) - (step - c) sin) / cos;
+    // otherwise walk along x with the roles of the axes exchanged.
+    const double c = P->W / 2.0;
+    P->ang.resize((size_t)P->n_angles * kAngleStride);
+    for (int k = 0; k < P->n_angles; ++k) {
+      const double C = std::cos(P->theta[k]), S = std::sin(P->theta[k]);
+      double* a = &P->ang[(size_t)k * kAngleStride];
+      a[kCos] = C;
+      a[kSin] = S;
+      const double h = std::fmax(std::fabs(C), std::fabs(S));
+      a[kInvH] = 1.0 / h;
+      a[kScale] = 1.0 / h;
+      if (std::fabs(C) >= std::fabs(S)) {
+        a[kBranch] = 0.0;
+        a[kB] = 1.0 / C;
+        a[kD] = -S / C;
+        a[kA] = c - c / C + c * S / C;
+      } else {
+        a[kBranch] = 1.0;
+        a[kB] = 1.0 / S;
+        a[kD] = -C / S;
+        a[kA] = c - c / S + c * C / S;
+        P->any_xwalk = true;
+      }
+    }
+
+    // Transfer-function tables: detector steps, probe steps, reference.
+    std::vector<double> rhos(chirp_rows(P->nd));
+    for (int j = 0; j < P->nd; ++j) {
+      const double m = P->mag[j];
+      rhos[chirp_det(j)] = (P->m0 - m) / (m * (P->m0 - 1.0));
+      rhos[chirp_probe(P->nd, j)] = P->m0 * (m - 1.0) / (m * (P->m0 - 1.0));
+    }
+    rhos[chirp_ref(P->nd)] = 1.0;
+    build_chirp(P->chirpW, P->W, rhos, P->fresnel0);
+    build_chirp(P->chirpH, P->H, rhos, P->fresnel0);
+    build_twiddles(P->twW, P->W);
+    build_twiddles(P->twH, P->H);
+
+    // Workspace layout.
+    const size_t fr = (size_t)P->H * P->W * sizeof(float2);
+    size_t o = 0;
+    P->off_Q = o;   o = align_up(o + fr * P->nd);
+    P->off_G = o;   o = align_up(o + fr * P->nd);
+    P->off_P = o;   o = align_up(o + fr);
+    P->off_uT = o;  o = align_up(o + (P->any_xwalk ? fr * P->W : 0));
+    P->off_psi = o; o = align_up(o + fr * P->chunk);
+    P->off_X = o;   o = align_up(o + fr * P->chunk * P->nd);
+    P->off_S = o;   o = align_up(o + fr * P->n_angles);
+    const size_t tiles = (size_t)P->W / cols_per_wg(P->H);
+    P->n_fpart = tiles * (1 + (size_t)P->n_angles * P->nd);
+    P->off_F = o;   o = align_up(o + P->n_fpart * sizeof(double));
+    P->ws_bytes = o;
+
+    // Device table layout.
+    size_t t = 0;
+    P->off_twW = t;   t = align_up(t + P->twW.size() * sizeof(float2));
+    P->off_twH = t;   t = align_up(t + P->twH.size() * sizeof(float2));
+    P->off_chW = t;   t = align_up(t + P->chirpW.size() * sizeof(float2));
+    P->off_chH = t;   t = align_up(t + P->chirpH.size() * sizeof(float2));
+    P->off_ang = t;   t = align_up(t + P->ang.size() * sizeof(double));
+    P->off_shift = t; t = align_up(t + P->shift.size() * sizeof(float));
+  } catch (const std::bad_alloc&) {
+    delete P;
+    return fail(HOLO_ERR_OUT_OF_HOST_MEMORY, "holo_plan_create: out of host memory");
+  }
+  *out = P;
+  return HOLO_OK;
+}
+
+extern "C" holo_status holo_plan_destroy(holo_plan* P) {
+  if (!P) return HOLO_OK;
+  if (P->d_tables) {
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (cur != P->device) (void)hipSetDevice(P->device);
+    (void)hipFree(P->d_tables);
+    if (cur != P->device && cur >= 0) (void)hipSetDevice(cur);
+  }
+  delete P;
+  return HOLO_OK;
+}
+
+extern "C" holo_status holo_workspace_bytes(const holo_plan* P, size_t* bytes) {
+  if (!P || !bytes) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_workspace_bytes: NULL argument");
+  *bytes = P->ws_bytes;
+  return HOLO_OK;
+}
+
+extern "C" const char* holo_last_error(void) { return g_last_error.c_str(); }
+
+namespace {
+
+holo_status hip_fail(hipError_t e, const char* where) {
+  return fail(HOLO_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HOLO_HIP(call)                                  \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);   \
+  } while (0)
+
+holo_status ensure_tables(holo_plan* P) {
+  int dev = -1;
+  HOLO_HIP(hipGetDevice(&dev));
+  if (P->d_tables) {
+    if (dev != P->device)
+      return fail(HOLO_ERR_INVALID_ARGUMENT, "plan tables live on device " + std::to_string(P->device) +
+                                                 ", current device is " + std::to_string(dev));
+    return HOLO_OK;
+  }
+  const size_t bytes = P->off_shift + align_up(P->shift.size() * sizeof(float)) + 256;
+  void* d = nullptr;
+  HOLO_HIP(hipMalloc(&d, bytes));
+  char* b = (char*)d;
+  auto put = [&](size_t off, const void* src, size_t n) -> hipError_t {
+    return n ? hipMemcpy(b + off, src, n, hipMemcpyHostToDevice) : hipSuccess;
+  };
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = put(P->off_twW, P->twW.data(), P->twW.size() * sizeof(float2));
+  if (e == hipSuccess) e = put(P->off_twH, P->twH.data(), P->twH.size() * sizeof(float2));
+  if (e == hipSuccess) e = put(P->off_chW, P->chirpW.data(), P->chirpW.size() * sizeof(float2));
+  if (e == hipSuccess) e = put(P->off_chH, P->chirpH.data(), P->chirpH.size() * sizeof(float2));
+  if (e == hipSuccess) e = put(P->off_ang, P->ang.data(), P->ang.size() * sizeof(double));
+  if (e == hipSuccess) e = put(P->off_shift, P->shift.data(), P->shift.size() * sizeof(float));
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return hip_fail(e, "uploading plan tables");
+  }
+  P->d_tables = d;
+  P->device = dev;
+  return HOLO_OK;
+}
+
+DevGeom make_geom(const holo_plan* P) {
+  DevGeom g;
+  g.H = P->H;
+  g.W = P->W;
+  g.nd = P->nd;
+  g.n_angles = P->n_angles;
+  g.cH = P->H / 2.0;
+  g.cW = P->W / 2.0;
+  for (int j = 0; j < kMaxDist; ++j) g.mag[j] = j < P->nd ? P->mag[j] : 1.0;
+  g.kappa = (float)P->kappa;
+  const char* b = (const char*)P->d_tables;
+  g.twW = (const float2*)(b + P->off_twW);
+  g.twH = (const float2*)(b + P->off_twH);
+  g.chirpW = (const float2*)(b + P->off_chW);
+  g.chirpH = (const float2*)(b + P->off_chH);
+  g.shift = P->shift.empty() ? nullptr : (const float*)(b + P->off_shift);
+  return g;
+}
+
+holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_, int k0, int k1,
+                const holo_c64* w_in_, holo_c64* v_out_, const float* amp, const float* amp_ref,
+                double* F, holo_c64* gu_, holo_c64* gq_, void* ws, size_t ws_bytes, void* stream_) {
+  const float2* u = (const float2*)u_;
+  const float2* q = (const float2*)q_;
+  const float2* w_in = (const float2*)w_in_;
+  float2* v_out = (float2*)v_out_;
+  float2* gu = (float2*)gu_;
+  float2* gq = (float2*)gq_;
+  hipStream_t st = (hipStream_t)stream_;
+
+  if (!ws) return fail(HOLO_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  if (ws_bytes < P->ws_bytes)
+    return fail(HOLO_ERR_WORKSPACE_TOO_SMALL, "workspace needs " + std::to_string(P->ws_bytes) +
+                                                  " bytes, got " + std::to_string(ws_bytes));
+  holo_status ts = ensure_tables(P);
+  if (ts != HOLO_OK) return ts;
+
+  const DevGeom g = make_geom(P);
+  const int H = P->H, W = P->W, nd = P->nd;
+  const size_t HW = (size_t)H * W;
+  char* wsb = (char*)ws;
+  float2* Q = (float2*)(wsb + P->off_Q);
+  float2* Gacc = (float2*)(wsb + P->off_G);
+  float2* Pref = (float2*)(wsb + P->off_P);
+  float2* uT = (float2*)(wsb + P->off_uT);
+  float2* psi = (float2*)(wsb + P->off_psi);
+  float2* X = (float2*)(wsb + P->off_X);
+  float2* S = (float2*)(wsb + P->off_S);
+  double* Fpart = (double*)(wsb + P->off_F);
+  const double* d_ang = (const double*)((const char*)P->d_tables + P->off_ang);
+  const int tiles = W / cols_per_wg(H);
+
+  const bool want_F = (mode == kObj || mode == kGrad) && F;
+  const bool want_gq = (mode == kAdj || mode == kGrad) && gq;
+  const bool want_gu = (mode == kAdj || mode == kGrad) && gu;
+  const bool with_ref = (mode == kObj || mode == kGrad);
+
+  // Probe stage.
+  {
+    PropJobs rj{}, cj{};
+    for (int j = 0; j < nd; ++j) {
+      rj.job[rj.n++] = PropJob{q, Q + j * HW, nullptr, chirp_probe(nd, j), 0, 0};
+      cj.job[cj.n++] = PropJob{Q + j * HW, Q + j * HW, nullptr, chirp_probe(nd, j), 0, 0};
+    }
+    if (with_ref) {
+      rj.job[rj.n++] = PropJob{q, Pref, nullptr, chirp_ref(nd), 0, 0};
+      cj.job[cj.n++] = PropJob{Pref, Pref, amp_ref, chirp_ref(nd), 0, 0};
+    }
+    HOLO_HIP(launch_rows_prop(g, rj, st));
+    HOLO_HIP(launch_cols_prop(g, cj, Fpart, st));
+    if (with_ref && want_gq) {
+      PropJobs r2{}, c2{};
+      r2.job[r2.n++] = PropJob{Pref, Pref, nullptr, chirp_ref(nd), 1, 0};
+      c2.job[c2.n++] = PropJob{Pref, Pref, nullptr, chirp_ref(nd), 1, 0};
+      HOLO_HIP(launch_rows_prop(g, r2, st));
+      HOLO_HIP(launch_cols_prop(g, c2, Fpart, st));
+    }
+  }
+  bool xwalk = false;
+  for (int k = k0; k < k1; ++k) xwalk |= P->ang[(size_t)k * kAngleStride + kBranch] != 0.0;
+  if (xwalk) HOLO_HIP(launch_transpose_xy(g, u, uT, st));
+  if (want_gq) HOLO_HIP(launch_fill_zero(Gacc, nd * HW, st));
+
+  const bool frames_back = want_gq || want_gu;
+  for (int c0 = k0; c0 < k1; c0 += P->chunk) {
+    const int Kc = std::min(P->chunk, k1 - c0);
+    HOLO_HIP(launch_radon_fwd(g, u, uT, psi, d_ang + (size_t)c0 * kAngleStride, Kc, st));
+    double* Fc = Fpart + (size_t)tiles * (1 + (size_t)(c0 - k0) * nd);
+    switch (mode) {
+      case kFwd: {
+        float2* v = v_out + (size_t)(c0 - k0) * nd * HW;
+        HOLO_HIP(launch_pass_a(g, psi, Q, v, c0, Kc, st));
+        HOLO_HIP(launch_pass_b(g, kColFwd, nullptr, v, nullptr, nullptr, Kc, st));
+        break;
+      }
+      case kObj:
+      case kGrad: {
+        HOLO_HIP(launch_pass_a(g, psi, Q, X, c0, Kc, st));
+        const float* a = amp + (size_t)c0 * nd * HW;
+        HOLO_HIP(launch_pass_b(g, frames_back ? kColGrad : kColObj, nullptr, X, a, Fc, Kc, st));
+        break;
+      }
+      case kAdj: {
+        const float2* w = w_in + (size_t)(c0 - k0) * nd * HW;
+        HOLO_HIP(launch_pass_b(g, kColAdj, w, X, nullptr, nullptr, Kc, st));
+        break;
+      }
+    }
+    if ((mode == kGrad || mode == kAdj) && frames_back) {
+      HOLO_HIP(launch_pass_c(g, X, psi, Q, Gacc, want_gq ? 1 : 0, c0, Kc, st));
+      if (want_gu) HOLO_HIP(launch_pass_d(g, X, psi, S + (size_t)(c0 - k0) * HW, c0, Kc, st));
+    }
+  }
+  if (want_gu) HOLO_HIP(launch_radon_adj(g, S, gu, d_ang + (size_t)k0 * kAngleStride, k1 - k0, st));
+  if (want_gq) {
+    PropJobs rj{}, cj{};
+    for (int j = 0; j < nd; ++j) {
+      rj.job[rj.n++] = PropJob{Gacc + j * HW, Gacc + j * HW, nullptr, chirp_probe(nd, j), 1, 0};
+      cj.job[cj.n++] = PropJob{Gacc + j * HW, Gacc + j * HW, nullptr, chirp_probe(nd, j), 1, 0};
+    }
+    HOLO_HIP(launch_rows_prop(g, rj, st));
+    HOLO_HIP(launch_cols_prop(g, cj, Fpart, st));
+    HOLO_HIP(launch_sum_frames(Gacc, nd, with_ref ? Pref : nullptr, gq, HW, st));
+  }
+  if (want_F) {
+    const size_t n = (size_t)tiles * (1 + (size_t)(k1 - k0) * nd);
+    HOLO_HIP(launch_reduce_sum(Fpart, n, F, st));
+  }
+  return HOLO_OK;
+}
+
+holo_status check_common(holo_plan* P, const holo_c64* u, const holo_c64* q, const char* fn) {
+  if (!P) return fail(HOLO_ERR_INVALID_ARGUMENT, std::string(fn) + ": plan is NULL");
+  if (!u || !q) return fail(HOLO_ERR_INVALID_ARGUMENT, std::string(fn) + ": u or q is NULL");
+  return HOLO_OK;
+}
+
+}  // namespace
+
+extern "C" holo_status holo_fwd(holo_plan* P, const holo_c64* u, const holo_c64* q, int32_t k0,
+                                int32_t k1, holo_c64* v, void* ws, size_t ws_bytes, void* stream) {
+  holo_status s = check_common(P, u, q, "holo_fwd");
+  if (s != HOLO_OK) return s;
+  if (!v) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_fwd: v is NULL");
+  if (k0 < 0 || k1 > P->n_angles || k0 >= k1)
+    return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_fwd: need 0 <= k0 < k1 <= n_angles");
+  return run(P, kFwd, u, q, k0, k1, nullptr, v, nullptr, nullptr, nullptr, nullptr, nullptr, ws,
+             ws_bytes, stream);
+}
+
+extern "C" holo_status holo_adj(holo_plan* P, const holo_c64* u, const holo_c64* q, int32_t k0,
+                                int32_t k1, const holo_c64* w, holo_c64* g_u, holo_c64* g_q,
+                                void* ws, size_t ws_bytes, void* stream) {
+  holo_status s = check_common(P, u, q, "holo_adj");
+  if (s != HOLO_OK) return s;
+  if (!w) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_adj: w is NULL");
+  if (k0 < 0 || k1 > P->n_angles || k0 >= k1)
+    return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_adj: need 0 <= k0 < k1 <= n_angles");
+  return run(P, kAdj, u, q, k0, k1, w, nullptr, nullptr, nullptr, nullptr, g_u, g_q, ws, ws_bytes,
+             stream);
+}
+
+extern "C" holo_status holo_objective(holo_plan* P, const holo_c64* u, const holo_c64* q,
+                                      const float* amp, const float* amp_ref, double* F, void* ws,
+                                      size_t ws_bytes, void* stream) {
+  holo_status s = check_common(P, u, q, "holo_objective");
+  if (s != HOLO_OK) return s;
+  if (!amp || !amp_ref || !F)
+    return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_objective: amp, amp_ref or F is NULL");
+  return run(P, kObj, u, q, 0, P->n_angles, nullptr, nullptr, amp, amp_ref, F, nullptr, nullptr, ws,
+             ws_bytes, stream);
+}
+
+extern "C" holo_status holo_grad(holo_plan* P, const holo_c64* u, const holo_c64* q,
+                                 const float* amp, const float* amp_ref, double* F, holo_c64* g_u,
+                                 holo_c64* g_q, void* ws, size_t ws_bytes, void* stream) {
+  holo_status s = check_common(P, u, q, "holo_grad");
+  if (s != HOLO_OK) return s;
+  if (!amp || !amp_ref) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_grad: amp or amp_ref is NULL");
+  return run(P, kGrad, u, q, 0, P->n_angles, nullptr, nullptr, amp, amp_ref, F, g_u, g_q, ws,
+             ws_bytes, stream);
+}
+
+extern "C" holo_status holo_grad_object(holo_plan* P, const holo_c64* u, const holo_c64* q,
+                                        const float* amp, const float* amp_ref, double* F,
+                                        holo_c64* g_u, void* ws, size_t ws_bytes, void* stream) {
+  if (!g_u) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_grad_object: g_u is NULL");
+  return holo_grad(P, u, q, amp, amp_ref, F, g_u, nullptr, ws, ws_bytes, stream);
+}
+
+extern "C" holo_status holo_grad_probe(holo_plan* P, const holo_c64* u, const holo_c64* q,
+                                       const float* amp, const float* amp_ref, double* F,
+                                       holo_c64* g_q, void* ws, size_t ws_bytes, void* stream) {
+  if (!g_q) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_grad_probe: g_q is NULL");
+  return holo_grad(P, u, q, amp, amp_ref, F, nullptr, g_q, ws, ws_bytes, stream);
+}

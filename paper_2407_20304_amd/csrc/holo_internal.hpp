@@ -1,0 +1,89 @@
+// Internal interface between the host runtime (holo_api.cpp) and the HIP
+// kernels (holo_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace holo {
+
+constexpr int kMaxDist = 8;
+// Per-angle constants (double): see AngleCols.
+constexpr int kAngleStride = 8;
+enum AngleCols {
+  kCos = 0,     // cos(theta)
+  kSin = 1,     // sin(theta)
+  kInvH = 2,    // 1 / max(|cos|, |sin|)  (footprint half-width h = max(...))
+  kBranch = 3,  // 0: walk along y, taps along x;  1: walk along x, taps along y
+  kA = 4,       // tap position f = A + bin * B + step * D (fractional index)
+  kB = 5,
+  kD = 6,
+  kScale = 7    // path length per step, 1 / max(|cos|, |sin|)
+};
+
+// Geometry and device tables as the kernels see them.
+struct DevGeom {
+  int H, W, nd;
+  int n_angles;              // angles of the plan (shift table stride)
+  double cH, cW;             // grid centres H/2, W/2
+  double mag[kMaxDist];      // m~_j
+  float kappa;
+  const float2* twW;         // [W]  exp(-2 pi i m / W)
+  const float2* twH;         // [H]
+  const float2* chirpW;      // [3 nd + 1][W] transfer factors, times 1/W
+  const float2* chirpH;      // [3 nd + 1][H] transfer factors, times 1/H
+  const float* shift;        // [n_angles][nd][2] (t_y, t_x) or nullptr
+};
+
+// Transfer-function table rows: detector step of plane j, probe step of
+// plane j, and the reference step rho = 1.
+__host__ __device__ inline int chirp_det(int j) { return j; }
+__host__ __device__ inline int chirp_probe(int nd, int j) { return nd + j; }
+__host__ __device__ inline int chirp_ref(int nd) { return 2 * nd; }
+__host__ __device__ inline int chirp_rows(int nd) { return 2 * nd + 1; }
+
+// One propagation job of the probe-side kernels (rows or columns).
+struct PropJob {
+  const float2* src;
+  float2* dst;
+  const float* amp;          // non-null: replace the field by the residual
+  int chirp;                 // table row
+  int conj;                  // 1: use the conjugate transfer (D_{-rho})
+  int fslot;                 // index into Fpart for the residual's cost
+};
+constexpr int kMaxJobs = 12;
+struct PropJobs {
+  PropJob job[kMaxJobs];
+  int n;
+};
+
+enum ColMode { kColFwd = 0, kColObj = 1, kColGrad = 2, kColAdj = 3 };
+
+// Launch geometry helpers shared by host and device.
+int rows_per_wg(int W);      // lines of W handled by one 256-thread workgroup
+int cols_per_wg(int H);      // columns of length H per workgroup
+bool fft_size_supported(int n);
+constexpr int kRadonZ = 16;  // slices per thread in the ray-sum kernels
+
+// Launchers (all asynchronous on `st`; return hipSuccess or the launch error).
+hipError_t launch_rows_prop(const DevGeom& g, const PropJobs& jobs, hipStream_t st);
+hipError_t launch_cols_prop(const DevGeom& g, const PropJobs& jobs, double* Fpart, hipStream_t st);
+hipError_t launch_pass_a(const DevGeom& g, const float2* psi, const float2* Q, float2* X,
+                         int k_first, int Kc, hipStream_t st);
+hipError_t launch_pass_b(const DevGeom& g, int mode, const float2* src, float2* X,
+                         const float* amp, double* Fpart, int Kc, hipStream_t st);
+hipError_t launch_pass_c(const DevGeom& g, float2* X, const float2* psi, const float2* Q,
+                         float2* G, int accumulate, int k_first, int Kc, hipStream_t st);
+hipError_t launch_pass_d(const DevGeom& g, const float2* X, const float2* psi, float2* S,
+                         int k_first, int Kc, hipStream_t st);
+hipError_t launch_radon_fwd(const DevGeom& g, const float2* u, const float2* uT, float2* psi,
+                            const double* ang, int Kc, hipStream_t st);
+hipError_t launch_radon_adj(const DevGeom& g, const float2* S, float2* gu, const double* ang,
+                            int K, hipStream_t st);
+hipError_t launch_transpose_xy(const DevGeom& g, const float2* u, float2* uT, hipStream_t st);
+hipError_t launch_fill_zero(float2* p, size_t n, hipStream_t st);
+hipError_t launch_sum_frames(const float2* G, int nd, const float2* extra, float2* out,
+                             size_t n, hipStream_t st);
+hipError_t launch_reduce_sum(const double* parts, size_t n, double* out, hipStream_t st);
+
+}  // namespace holo

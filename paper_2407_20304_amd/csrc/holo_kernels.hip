@@ -1,0 +1,729 @@
+// HIP kernels of the holotomography gradient for gfx950 (MI355X).
+//
+// Frame stages (detector-plane work, HBM-bound):
+//   pass A  rows:    phi = 1 + B(psi - 1), x = Q_j phi, row FFT * transfer * IFFT
+//   pass B  columns: column FFT * transfer * IFFT -> v, residual and cost,
+//                    column FFT * conj(transfer) * IFFT
+//   pass C  rows:    row FFT * conj(transfer) * IFFT -> w,
+//                    G_j += conj(phi) w (probe gradient), X := conj(Q_j) w
+//   pass D  pixels:  g_psi = sum_j B^T X_j (gather), h = -i kappa conj(psi) g_psi
+// Ray sums (VALU-bound):
+//   radon_fwd  Joseph ray sums over all slices at once (lanes = bins, each
+//              thread owns kRadonZ slices), fused exp(i kappa p) epilogue
+//   radon_adj  transpose as a triangle-footprint gather over all angles
+//              (lanes = a 16 x 16 voxel tile, each thread owns kRadonZ slices)
+// Positions and interpolation weights are formed in double precision; field
+// arithmetic is single precision; costs and long ray/angle sums are carried
+// in double.
+#include "holo_internal.hpp"
+#include "fft_lds.hpp"
+
+namespace holo {
+
+typedef float f4a8 __attribute__((ext_vector_type(4), aligned(8)));
+
+constexpr int kThreads = 256;
+
+__host__ __device__ constexpr int rows_tl(int W) { return fft_row_threads(W); }
+__host__ __device__ constexpr int rows_lpw(int W) { return kThreads / fft_row_threads(W); }
+__host__ __device__ constexpr int cols_tc(int H) { return H >= 2048 ? 4 : (H >= 1024 ? 8 : 16); }
+
+int rows_per_wg(int W) { return rows_lpw(W); }
+int cols_per_wg(int H) { return cols_tc(H); }
+bool fft_size_supported(int n) {
+  switch (n) {
+    case 64: case 128: case 192: case 256: case 384: case 512: case 1024: case 2048:
+      return true;
+    default:
+      return false;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Demagnification / shift taps (bilinear, free space outside)
+// ---------------------------------------------------------------------------
+
+// Sample position of output index idx along one axis: c + m (idx - c) - t.
+// The forward resample and its transpose call this same function, so both
+// see bit-identical positions and weights.
+__device__ __forceinline__ double src_pos(double c, double m, double t, int idx) {
+  return c + m * ((double)idx - c) - t;
+}
+
+struct AxisTaps {
+  int i0, i1;      // clamped in-range indices
+  float w0, w1;    // weights (0 for taps outside the grid)
+};
+
+__device__ __forceinline__ AxisTaps fwd_taps(double c, double m, double t, int idx, int n) {
+  double sp = src_pos(c, m, t, idx);
+  double fl = floor(sp);
+  int i0 = (int)fl;
+  float w = (float)(sp - fl);
+  AxisTaps a;
+  bool v0 = (i0 >= 0) && (i0 < n);
+  bool v1 = (i0 + 1 >= 0) && (i0 + 1 < n);
+  a.w0 = v0 ? 1.0f - w : 0.0f;
+  a.w1 = v1 ? w : 0.0f;
+  a.i0 = v0 ? i0 : 0;
+  a.i1 = v1 ? i0 + 1 : 0;
+  return a;
+}
+
+// phi = 1 + sum of bilinear taps of (psi - 1) inside the grid.
+__device__ __forceinline__ float2 sample_phi(const float2* __restrict__ psik, int W,
+                                             const AxisTaps& ty, const AxisTaps& tx) {
+  float2 a = psik[(size_t)ty.i0 * W + tx.i0];
+  float2 b = psik[(size_t)ty.i0 * W + tx.i1];
+  float2 c = psik[(size_t)ty.i1 * W + tx.i0];
+  float2 d = psik[(size_t)ty.i1 * W + tx.i1];
+  float w00 = ty.w0 * tx.w0, w01 = ty.w0 * tx.w1, w10 = ty.w1 * tx.w0, w11 = ty.w1 * tx.w1;
+  float re = w00 * (a.x - 1.0f) + w01 * (b.x - 1.0f) + w10 * (c.x - 1.0f) + w11 * (d.x - 1.0f);
+  float im = w00 * a.y + w01 * b.y + w10 * c.y + w11 * d.y;
+  return make_float2(1.0f + re, im);
+}
+
+// Destination indices whose sample position lies within one pixel of source
+// index `idx`, with the weight the forward resample gave to `idx` (taps of
+// the transpose).  Three candidates cover every such index; unused ones get
+// weight 0 and a clamped in-range index.
+struct AdjTaps {
+  int d[3];
+  float w[3];
+};
+
+__device__ __forceinline__ AdjTaps adj_taps(double c, double m, double t, int idx, int n) {
+  const double pre = ((double)idx - c + t) / m + c;
+  const int d0 = (int)floor(pre) - 1;
+  AdjTaps a;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int d = d0 + e;
+    const bool ok = (d >= 0) && (d < n);
+    const double sp = src_pos(c, m, t, d);
+    const double fl = floor(sp);
+    const int i0 = (int)fl;
+    const float w = (float)(sp - fl);
+    const float wt = (i0 == idx) ? 1.0f - w : ((i0 + 1 == idx) ? w : 0.0f);
+    a.d[e] = ok ? d : 0;
+    a.w[e] = ok ? wt : 0.0f;
+  }
+  return a;
+}
+
+__device__ __forceinline__ void shift_of(const DevGeom& g, int kglob, int j, double& ty, double& tx) {
+  if (g.shift) {
+    const float* s = g.shift + ((size_t)kglob * g.nd + j) * 2;
+    ty = (double)s[0];
+    tx = (double)s[1];
+  } else {
+    ty = 0.0;
+    tx = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row kernels (lines of length W along the detector columns)
+// ---------------------------------------------------------------------------
+
+template <int W>
+__global__ __launch_bounds__(kThreads) void k_pass_a(const float2* __restrict__ psi,
+                                                     const float2* __restrict__ Q,
+                                                     float2* __restrict__ X, DevGeom g,
+                                                     int k_first) {
+  constexpr int TL = rows_tl(W), LPW = rows_lpw(W), E = W / TL;
+  __shared__ float2 s_tw[W];
+  __shared__ float2 s_line[LPW][W];
+  const int line = threadIdx.x / TL, lt = threadIdx.x % TL;
+  const int z = blockIdx.x * LPW + line;
+  const int f = blockIdx.y;
+  const int k = f / g.nd, j = f % g.nd;
+  for (int i = threadIdx.x; i < W; i += kThreads) s_tw[i] = g.twW[i];
+
+  double ty, tx;
+  shift_of(g, k_first + k, j, ty, tx);
+  const double m = g.mag[j];
+  const AxisTaps tyt = fwd_taps(g.cH, m, ty, z, g.H);
+  const float2* psik = psi + (size_t)k * g.H * W;
+  const float2* Qrow = Q + ((size_t)j * g.H + z) * W;
+  float2* L = s_line[line];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int s = lt + e * TL;
+    const AxisTaps txt = fwd_taps(g.cW, m, tx, s, W);
+    L[s] = cmul(Qrow[s], sample_phi(psik, W, tyt, txt));
+  }
+  fft<W, TL, false>(L, s_tw, lt);
+  const float2* ch = g.chirpW + (size_t)chirp_det(j) * W;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int s = lt + e * TL;
+    L[s] = cmul(L[s], ch[s]);
+  }
+  fft<W, TL, true>(L, s_tw, lt);
+  float2* out = X + ((size_t)f * g.H + z) * W;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int s = lt + e * TL;
+    out[s] = L[s];
+  }
+}
+
+template <int W>
+__global__ __launch_bounds__(kThreads) void k_pass_c(float2* __restrict__ X,
+                                                     const float2* __restrict__ psi,
+                                                     const float2* __restrict__ Q,
+                                                     float2* __restrict__ G, DevGeom g,
+                                                     int accumulate, int k_first, int Kc) {
+  constexpr int TL = rows_tl(W), LPW = rows_lpw(W), E = W / TL;
+  __shared__ float2 s_tw[W];
+  __shared__ float2 s_line[LPW][W];
+  const int line = threadIdx.x / TL, lt = threadIdx.x % TL;
+  const int z = blockIdx.x * LPW + line;
+  const int j = blockIdx.y;
+  for (int i = threadIdx.x; i < W; i += kThreads) s_tw[i] = g.twW[i];
+  const double m = g.mag[j];
+  const float2* Qrow = Q + ((size_t)j * g.H + z) * W;
+  const float2* ch = g.chirpW + (size_t)chirp_det(j) * W;
+  float2* L = s_line[line];
+  float2 gacc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) gacc[e] = make_float2(0.f, 0.f);
+
+  for (int k = 0; k < Kc; ++k) {
+    float2* row = X + (((size_t)k * g.nd + j) * g.H + z) * W;
+#pragma unroll
+    for (int e = 0; e < E; ++e) L[lt + e * TL] = row[lt + e * TL];
+    fft<W, TL, false>(L, s_tw, lt);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int s = lt + e * TL;
+      L[s] = cmulc(L[s], ch[s]);
+    }
+    fft<W, TL, true>(L, s_tw, lt);
+    double ty, tx;
+    shift_of(g, k_first + k, j, ty, tx);
+    const AxisTaps tyt = fwd_taps(g.cH, m, ty, z, g.H);
+    const float2* psik = psi + (size_t)k * g.H * W;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int s = lt + e * TL;
+      const float2 w = L[s];
+      if (accumulate) {
+        const AxisTaps txt = fwd_taps(g.cW, m, tx, s, W);
+        const float2 phi = sample_phi(psik, W, tyt, txt);
+        const float2 t = cmulc(w, phi);  // conj(phi) w
+        gacc[e].x += t.x;
+        gacc[e].y += t.y;
+      }
+      row[s] = cmulc(w, Qrow[s]);        // conj(Q_j) w
+    }
+  }
+  if (accumulate) {
+    float2* grow = G + ((size_t)j * g.H + z) * W;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int s = lt + e * TL;
+      float2 v = grow[s];
+      grow[s] = make_float2(v.x + gacc[e].x, v.y + gacc[e].y);
+    }
+  }
+}
+
+template <int W>
+__global__ __launch_bounds__(kThreads) void k_rows_prop(PropJobs jobs, DevGeom g) {
+  constexpr int TL = rows_tl(W), LPW = rows_lpw(W), E = W / TL;
+  __shared__ float2 s_tw[W];
+  __shared__ float2 s_line[LPW][W];
+  const int line = threadIdx.x / TL, lt = threadIdx.x % TL;
+  const int z = blockIdx.x * LPW + line;
+  const PropJob& jb = jobs.job[blockIdx.y];
+  for (int i = threadIdx.x; i < W; i += kThreads) s_tw[i] = g.twW[i];
+  const float2* in = jb.src + (size_t)z * W;
+  float2* L = s_line[line];
+#pragma unroll
+  for (int e = 0; e < E; ++e) L[lt + e * TL] = in[lt + e * TL];
+  fft<W, TL, false>(L, s_tw, lt);
+  const float2* ch = g.chirpW + (size_t)jb.chirp * W;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int s = lt + e * TL;
+    L[s] = jb.conj ? cmulc(L[s], ch[s]) : cmul(L[s], ch[s]);
+  }
+  fft<W, TL, true>(L, s_tw, lt);
+  float2* out = jb.dst + (size_t)z * W;
+#pragma unroll
+  for (int e = 0; e < E; ++e) out[lt + e * TL] = L[lt + e * TL];
+}
+
+// ---------------------------------------------------------------------------
+// Column kernels (lines of length H along the detector rows)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void block_sum_store(double v, double* out) {
+  __shared__ double red[kThreads];
+  red[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int o = kThreads / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+// r = 2 (v - a v/|v|) in place (v/|v| := 0 at |v| = 0); returns (|v| - a)^2.
+__device__ __forceinline__ double residual(float2& v, float a) {
+  const float av = sqrtf(v.x * v.x + v.y * v.y);
+  const double d = (double)av - (double)a;
+  const float sc = av > 0.0f ? 2.0f * (1.0f - a / av) : 2.0f;
+  v = make_float2(sc * v.x, sc * v.y);
+  return d * d;
+}
+
+template <int H, int MODE>
+__global__ __launch_bounds__(kThreads) void k_pass_b(const float2* __restrict__ src,
+                                                     float2* __restrict__ X,
+                                                     const float* __restrict__ amp,
+                                                     double* __restrict__ Fpart, DevGeom g) {
+  constexpr int TC = cols_tc(H), TLc = kThreads / TC;
+  __shared__ float2 s_tw[H];
+  __shared__ float2 s_col[TC][H + 1];
+  const int c = threadIdx.x / TLc, lt = threadIdx.x % TLc;
+  const int W = g.W;
+  const int s0 = blockIdx.x * TC;
+  const int f = blockIdx.y;
+  const int j = f % g.nd;
+  for (int i = threadIdx.x; i < H; i += kThreads) s_tw[i] = g.twH[i];
+  const float2* in = (MODE == kColAdj ? src : X) + (size_t)f * H * W + s0;
+  for (int i = threadIdx.x; i < H * TC; i += kThreads) {
+    const int zz = i / TC, cc = i % TC;
+    s_col[cc][zz] = in[(size_t)zz * W + cc];
+  }
+  float2* L = s_col[c];
+  const float2* ch = g.chirpH + (size_t)chirp_det(j) * H;
+  if (MODE != kColAdj) {
+    fft<H, TLc, false>(L, s_tw, lt);
+    for (int zz = lt; zz < H; zz += TLc) L[zz] = cmul(L[zz], ch[zz]);
+    fft<H, TLc, true>(L, s_tw, lt);
+    __syncthreads();
+  }
+  if (MODE == kColObj || MODE == kColGrad) {
+    double acc = 0.0;
+    const float* a = amp + (size_t)f * H * W + s0;
+    for (int i = threadIdx.x; i < H * TC; i += kThreads) {
+      const int zz = i / TC, cc = i % TC;
+      float2 v = s_col[cc][zz];
+      acc += residual(v, a[(size_t)zz * W + cc]);
+      s_col[cc][zz] = v;
+    }
+    block_sum_store(acc, Fpart + (size_t)f * gridDim.x + blockIdx.x);
+  }
+  if (MODE == kColGrad || MODE == kColAdj) {
+    fft<H, TLc, false>(L, s_tw, lt);
+    for (int zz = lt; zz < H; zz += TLc) L[zz] = cmulc(L[zz], ch[zz]);
+    fft<H, TLc, true>(L, s_tw, lt);
+    __syncthreads();
+  }
+  if (MODE != kColObj) {
+    float2* out = X + (size_t)f * H * W + s0;
+    for (int i = threadIdx.x; i < H * TC; i += kThreads) {
+      const int zz = i / TC, cc = i % TC;
+      out[(size_t)zz * W + cc] = s_col[cc][zz];
+    }
+  }
+}
+
+template <int H>
+__global__ __launch_bounds__(kThreads) void k_cols_prop(PropJobs jobs, double* __restrict__ Fpart,
+                                                        DevGeom g) {
+  constexpr int TC = cols_tc(H), TLc = kThreads / TC;
+  __shared__ float2 s_tw[H];
+  __shared__ float2 s_col[TC][H + 1];
+  const int c = threadIdx.x / TLc, lt = threadIdx.x % TLc;
+  const int W = g.W;
+  const int s0 = blockIdx.x * TC;
+  const PropJob& jb = jobs.job[blockIdx.y];
+  for (int i = threadIdx.x; i < H; i += kThreads) s_tw[i] = g.twH[i];
+  const float2* in = jb.src + s0;
+  for (int i = threadIdx.x; i < H * TC; i += kThreads) {
+    const int zz = i / TC, cc = i % TC;
+    s_col[cc][zz] = in[(size_t)zz * W + cc];
+  }
+  float2* L = s_col[c];
+  const float2* ch = g.chirpH + (size_t)jb.chirp * H;
+  fft<H, TLc, false>(L, s_tw, lt);
+  for (int zz = lt; zz < H; zz += TLc) L[zz] = jb.conj ? cmulc(L[zz], ch[zz]) : cmul(L[zz], ch[zz]);
+  fft<H, TLc, true>(L, s_tw, lt);
+  __syncthreads();
+  if (jb.amp) {
+    double acc = 0.0;
+    const float* a = jb.amp + s0;
+    for (int i = threadIdx.x; i < H * TC; i += kThreads) {
+      const int zz = i / TC, cc = i % TC;
+      float2 v = s_col[cc][zz];
+      acc += residual(v, a[(size_t)zz * W + cc]);
+      s_col[cc][zz] = v;
+    }
+    block_sum_store(acc, Fpart + (size_t)jb.fslot * gridDim.x + blockIdx.x);
+    __syncthreads();
+  }
+  float2* out = jb.dst + s0;
+  for (int i = threadIdx.x; i < H * TC; i += kThreads) {
+    const int zz = i / TC, cc = i % TC;
+    out[(size_t)zz * W + cc] = s_col[cc][zz];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass D: transpose of the demagnification, summed over planes, and the
+// chain rule through psi = exp(i kappa p).
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kThreads) void k_pass_d(const float2* __restrict__ X,
+                                                     const float2* __restrict__ psi,
+                                                     float2* __restrict__ S, DevGeom g,
+                                                     int k_first) {
+  const int H = g.H, W = g.W;
+  const int p = blockIdx.x * kThreads + threadIdx.x;
+  if (p >= H * W) return;
+  const int z = p / W, s = p % W;
+  const int k = blockIdx.y;
+  float ax = 0.f, ay = 0.f;
+  for (int j = 0; j < g.nd; ++j) {
+    double ty, tx;
+    shift_of(g, k_first + k, j, ty, tx);
+    const double m = g.mag[j];
+    const AdjTaps rz = adj_taps(g.cH, m, ty, z, H);
+    const AdjTaps rs = adj_taps(g.cW, m, tx, s, W);
+    const float2* Xj = X + ((size_t)k * g.nd + j) * H * W;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const float wt = rz.w[a] * rs.w[b];
+        if (wt != 0.0f) {
+          const float2 v = Xj[(size_t)rz.d[a] * W + rs.d[b]];
+          ax += wt * v.x;
+          ay += wt * v.y;
+        }
+      }
+    }
+  }
+  const float2 ps = psi[((size_t)k * H + z) * W + s];
+  // conj(psi) g
+  const float cx = ps.x * ax + ps.y * ay;
+  const float cy = ps.x * ay - ps.y * ax;
+  // -i kappa (cx + i cy) = kappa cy - i kappa cx
+  S[((size_t)k * H + z) * W + s] = make_float2(g.kappa * cy, -g.kappa * cx);
+}
+
+// ---------------------------------------------------------------------------
+// Joseph ray sums and their transpose
+// ---------------------------------------------------------------------------
+
+// Forward: lanes are 64 consecutive bins, each thread owns kRadonZ slices.
+// Taps (t0, t0 + 1) are adjacent along the tap axis, so one 16-byte load
+// fetches both; angles that walk along x read the x/y-transposed volume.
+__global__ __launch_bounds__(64) void k_radon_fwd(const float2* __restrict__ u,
+                                                  const float2* __restrict__ uT,
+                                                  float2* __restrict__ psi, DevGeom g,
+                                                  const double* __restrict__ ang) {
+  constexpr int ZL = kRadonZ;
+  const int W = g.W, H = g.H;
+  const int s = blockIdx.x * 64 + threadIdx.x;
+  const int z0 = blockIdx.y * ZL;
+  const int k = blockIdx.z;
+  const double* a = ang + (size_t)k * kAngleStride;
+  const double A = a[kA], B = a[kB], D = a[kD];
+  const float2* vol = (a[kBranch] != 0.0) ? uT : u;
+  const size_t WW = (size_t)W * W;
+  const char* vbase = (const char*)(vol + (size_t)z0 * WW);
+  const double fA = A + (double)s * B;
+
+  float ax[ZL], ay[ZL];
+  double ox[ZL], oy[ZL];
+#pragma unroll
+  for (int i = 0; i < ZL; ++i) { ax[i] = ay[i] = 0.f; ox[i] = oy[i] = 0.0; }
+
+  for (int step = 0; step < W; ++step) {
+    const double fpos = fA + (double)step * D;
+    const double fl = floor(fpos);
+    const int t0 = (int)fl;
+    const float w = (float)(fpos - fl);
+    float w0 = 1.0f - w, w1 = w;
+    int tc = t0;
+    if (t0 < 0) {            // only tap t0 + 1 = 0 may be inside
+      w0 = (t0 == -1) ? w : 0.0f;
+      w1 = 0.0f;
+      tc = 0;
+    } else if (t0 >= W - 1) {  // only tap t0 = W - 1 may be inside
+      w1 = (t0 == W - 1) ? 1.0f - w : 0.0f;
+      w0 = 0.0f;
+      tc = W - 2;
+    }
+    const char* p = vbase + ((size_t)step * W + tc) * sizeof(float2);
+#pragma unroll
+    for (int i = 0; i < ZL; ++i) {
+      const f4a8 v = *(const f4a8*)(p + (size_t)i * WW * sizeof(float2));
+      ax[i] += w0 * v.x + w1 * v.z;
+      ay[i] += w0 * v.y + w1 * v.w;
+    }
+    if ((step & 31) == 31) {
+#pragma unroll
+      for (int i = 0; i < ZL; ++i) {
+        ox[i] += (double)ax[i];
+        oy[i] += (double)ay[i];
+        ax[i] = ay[i] = 0.f;
+      }
+    }
+  }
+  const double scale = a[kScale];
+  const double kap = (double)g.kappa;
+  const double twopi = 6.283185307179586476925;
+#pragma unroll
+  for (int i = 0; i < ZL; ++i) {
+    const double px = (ox[i] + (double)ax[i]) * scale;
+    const double py = (oy[i] + (double)ay[i]) * scale;
+    double ph = kap * px;
+    ph -= twopi * rint(ph / twopi);
+    float sn, cs;
+    sincosf((float)ph, &sn, &cs);
+    const float mag = expf((float)(-kap * py));
+    psi[((size_t)k * H + z0 + i) * W + s] = make_float2(mag * cs, mag * sn);
+  }
+}
+
+// Transpose: lanes cover a 16 x 16 voxel tile, each thread owns kRadonZ
+// slices and loops over all angles.  A voxel projecting to fractional bin
+// q takes max(0, 1 - |i - q| / h) / h of bin i (h = max(|cos|, |sin|)),
+// which is exactly the weight Joseph's interpolation gave it.
+__global__ __launch_bounds__(kThreads) void k_radon_adj(const float2* __restrict__ S,
+                                                        float2* __restrict__ gu, DevGeom g,
+                                                        const double* __restrict__ ang,
+                                                        int K) {
+  constexpr int ZL = kRadonZ;
+  const int W = g.W, H = g.H;
+  const int x = blockIdx.x * 16 + (threadIdx.x & 15);
+  const int y = blockIdx.y * 16 + (threadIdx.x >> 4);
+  const int z0 = blockIdx.z * ZL;
+  const double X = (double)x - g.cW, Y = (double)y - g.cW;
+  const size_t HW = (size_t)H * W;
+
+  float ax[ZL], ay[ZL];
+  double ox[ZL], oy[ZL];
+#pragma unroll
+  for (int i = 0; i < ZL; ++i) { ax[i] = ay[i] = 0.f; ox[i] = oy[i] = 0.0; }
+
+  for (int k = 0; k < K; ++k) {
+    const double* a = ang + (size_t)k * kAngleStride;
+    const double invh = a[kInvH];
+    const double q = g.cW + X * a[kCos] + Y * a[kSin];
+    const double fl = floor(q);
+    const int s0 = (int)fl;
+    const double fr = q - fl;
+    float w0 = (float)(fmax(0.0, 1.0 - fr * invh) * invh);
+    float w1 = (float)(fmax(0.0, 1.0 - (1.0 - fr) * invh) * invh);
+    int sc = s0;
+    if (s0 < 0) {
+      w0 = (s0 == -1) ? w1 : 0.0f;
+      w1 = 0.0f;
+      sc = 0;
+    } else if (s0 >= W - 1) {
+      w1 = (s0 == W - 1) ? w0 : 0.0f;
+      w0 = 0.0f;
+      sc = W - 2;
+    }
+    const char* p = (const char*)(S + (size_t)k * HW + (size_t)z0 * W + sc);
+#pragma unroll
+    for (int i = 0; i < ZL; ++i) {
+      const f4a8 v = *(const f4a8*)(p + (size_t)i * W * sizeof(float2));
+      ax[i] += w0 * v.x + w1 * v.z;
+      ay[i] += w0 * v.y + w1 * v.w;
+    }
+    if ((k & 31) == 31) {
+#pragma unroll
+      for (int i = 0; i < ZL; ++i) {
+        ox[i] += (double)ax[i];
+        oy[i] += (double)ay[i];
+        ax[i] = ay[i] = 0.f;
+      }
+    }
+  }
+  const size_t WW = (size_t)W * W;
+#pragma unroll
+  for (int i = 0; i < ZL; ++i) {
+    gu[(size_t)(z0 + i) * WW + (size_t)y * W + x] =
+        make_float2((float)(ox[i] + (double)ax[i]), (float)(oy[i] + (double)ay[i]));
+  }
+}
+
+// uT[z][x][y] = u[z][y][x]
+__global__ __launch_bounds__(kThreads) void k_transpose_xy(const float2* __restrict__ u,
+                                                           float2* __restrict__ uT, int W) {
+  __shared__ float2 tile[32][33];
+  const size_t zoff = (size_t)blockIdx.z * W * W;
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) tile[r][tx] = u[zoff + (size_t)(by + r) * W + bx + tx];
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) uT[zoff + (size_t)(bx + r) * W + by + tx] = tile[tx][r];
+}
+
+__global__ void k_fill_zero(float2* __restrict__ p, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = make_float2(0.f, 0.f);
+}
+
+__global__ void k_sum_frames(const float2* __restrict__ G, int nd, const float2* __restrict__ extra,
+                             float2* __restrict__ out, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) {
+    float2 acc = extra ? extra[i] : make_float2(0.f, 0.f);
+    for (int j = 0; j < nd; ++j) {
+      const float2 v = G[(size_t)j * n + i];
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    out[i] = acc;
+  }
+}
+
+// Deterministic single-workgroup sum of double partials.
+__global__ __launch_bounds__(kThreads) void k_reduce_sum(const double* __restrict__ parts, size_t n,
+                                                         double* __restrict__ out) {
+  double acc = 0.0;
+  for (size_t i = threadIdx.x; i < n; i += kThreads) acc += parts[i];
+  block_sum_store(acc, out);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+#define HOLO_FOR_SIZES(X) X(64) X(128) X(192) X(256) X(384) X(512) X(1024) X(2048)
+
+hipError_t launch_rows_prop(const DevGeom& g, const PropJobs& jobs, hipStream_t st) {
+  if (jobs.n == 0) return hipSuccess;
+  const dim3 grid(g.H / rows_per_wg(g.W), jobs.n);
+  switch (g.W) {
+#define CASE(N) case N: k_rows_prop<N><<<grid, kThreads, 0, st>>>(jobs, g); break;
+    HOLO_FOR_SIZES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cols_prop(const DevGeom& g, const PropJobs& jobs, double* Fpart, hipStream_t st) {
+  if (jobs.n == 0) return hipSuccess;
+  const dim3 grid(g.W / cols_per_wg(g.H), jobs.n);
+  switch (g.H) {
+#define CASE(N) case N: k_cols_prop<N><<<grid, kThreads, 0, st>>>(jobs, Fpart, g); break;
+    HOLO_FOR_SIZES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_a(const DevGeom& g, const float2* psi, const float2* Q, float2* X,
+                         int k_first, int Kc, hipStream_t st) {
+  const dim3 grid(g.H / rows_per_wg(g.W), Kc * g.nd);
+  switch (g.W) {
+#define CASE(N) case N: k_pass_a<N><<<grid, kThreads, 0, st>>>(psi, Q, X, g, k_first); break;
+    HOLO_FOR_SIZES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_b(const DevGeom& g, int mode, const float2* src, float2* X,
+                         const float* amp, double* Fpart, int Kc, hipStream_t st) {
+  const dim3 grid(g.W / cols_per_wg(g.H), Kc * g.nd);
+  switch (g.H) {
+#define CASE(N)                                                                               \
+  case N:                                                                                     \
+    switch (mode) {                                                                           \
+      case kColFwd: k_pass_b<N, kColFwd><<<grid, kThreads, 0, st>>>(src, X, amp, Fpart, g); break; \
+      case kColObj: k_pass_b<N, kColObj><<<grid, kThreads, 0, st>>>(src, X, amp, Fpart, g); break; \
+      case kColGrad: k_pass_b<N, kColGrad><<<grid, kThreads, 0, st>>>(src, X, amp, Fpart, g); break; \
+      case kColAdj: k_pass_b<N, kColAdj><<<grid, kThreads, 0, st>>>(src, X, amp, Fpart, g); break; \
+      default: return hipErrorInvalidValue;                                                   \
+    }                                                                                         \
+    break;
+    HOLO_FOR_SIZES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_c(const DevGeom& g, float2* X, const float2* psi, const float2* Q,
+                         float2* G, int accumulate, int k_first, int Kc, hipStream_t st) {
+  const dim3 grid(g.H / rows_per_wg(g.W), g.nd);
+  switch (g.W) {
+#define CASE(N) \
+  case N: k_pass_c<N><<<grid, kThreads, 0, st>>>(X, psi, Q, G, g, accumulate, k_first, Kc); break;
+    HOLO_FOR_SIZES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_d(const DevGeom& g, const float2* X, const float2* psi, float2* S,
+                         int k_first, int Kc, hipStream_t st) {
+  const dim3 grid((g.H * g.W + kThreads - 1) / kThreads, Kc);
+  k_pass_d<<<grid, kThreads, 0, st>>>(X, psi, S, g, k_first);
+  return hipGetLastError();
+}
+
+hipError_t launch_radon_fwd(const DevGeom& g, const float2* u, const float2* uT, float2* psi,
+                            const double* ang, int Kc, hipStream_t st) {
+  const dim3 grid(g.W / 64, g.H / kRadonZ, Kc);
+  k_radon_fwd<<<grid, 64, 0, st>>>(u, uT, psi, g, ang);
+  return hipGetLastError();
+}
+
+hipError_t launch_radon_adj(const DevGeom& g, const float2* S, float2* gu, const double* ang,
+                            int K, hipStream_t st) {
+  const dim3 grid(g.W / 16, g.W / 16, g.H / kRadonZ);
+  k_radon_adj<<<grid, kThreads, 0, st>>>(S, gu, g, ang, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_xy(const DevGeom& g, const float2* u, float2* uT, hipStream_t st) {
+  const dim3 grid(g.W / 32, g.W / 32, g.H);
+  k_transpose_xy<<<grid, kThreads, 0, st>>>(u, uT, g.W);
+  return hipGetLastError();
+}
+
+static unsigned grid_for(size_t n) {
+  size_t b = (n + kThreads - 1) / kThreads;
+  if (b > 65536) b = 65536;
+  if (b == 0) b = 1;
+  return (unsigned)b;
+}
+
+hipError_t launch_fill_zero(float2* p, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  k_fill_zero<<<grid_for(n), kThreads, 0, st>>>(p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_frames(const float2* G, int nd, const float2* extra, float2* out, size_t n,
+                             hipStream_t st) {
+  k_sum_frames<<<grid_for(n), kThreads, 0, st>>>(G, nd, extra, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_sum(const double* parts, size_t n, double* out, hipStream_t st) {
+  k_reduce_sum<<<1, kThreads, 0, st>>>(parts, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace holo

@@ -1,0 +1,280 @@
+"""Python binding of libholo.so (C ABI in include/holo.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Tensors are PyTorch CUDA/HIP tensors; their device pointers and the
+current stream are handed to the library.  If the library is not built, every
+call raises HoloError -- there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_size_t, c_void_p
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libholo.so")
+
+# Every symbol declared in include/holo.h.
+EXPORTS = (
+    "holo_plan_create", "holo_plan_destroy", "holo_workspace_bytes",
+    "holo_fwd", "holo_adj", "holo_objective", "holo_grad",
+    "holo_grad_object", "holo_grad_probe", "holo_last_error",
+)
+
+STATUS = {0: "HOLO_OK", 1: "HOLO_ERR_INVALID_ARGUMENT", 2: "HOLO_ERR_UNSUPPORTED_SIZE",
+          3: "HOLO_ERR_WORKSPACE_TOO_SMALL", 4: "HOLO_ERR_HIP", 5: "HOLO_ERR_OUT_OF_HOST_MEMORY"}
+
+
+class HoloError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (STATUS.get(status, status), message))
+        self.status = status
+
+
+class holo_geom(ctypes.Structure):
+    _fields_ = [
+        ("det_rows", c_int32), ("det_cols", c_int32),
+        ("n_angles", c_int32), ("n_dist", c_int32),
+        ("theta", POINTER(c_double)), ("mag_rel", POINTER(c_double)),
+        ("m0", c_double), ("fresnel0", c_double), ("kappa", c_double),
+        ("shift", POINTER(c_float)), ("chunk", c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libholo.so (raises HoloError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise HoloError(-1, "libholo.so is not built (run paper_2407_20304_amd/build.py)")
+    L = ctypes.CDLL(LIB_PATH)
+    P = c_void_p
+    L.holo_plan_create.argtypes = [POINTER(holo_geom), POINTER(c_void_p)]
+    L.holo_plan_destroy.argtypes = [P]
+    L.holo_workspace_bytes.argtypes = [P, POINTER(c_size_t)]
+    L.holo_fwd.argtypes = [P, P, P, c_int32, c_int32, P, P, c_size_t, P]
+    L.holo_adj.argtypes = [P, P, P, c_int32, c_int32, P, P, P, P, c_size_t, P]
+    L.holo_objective.argtypes = [P, P, P, P, P, P, P, c_size_t, P]
+    L.holo_grad.argtypes = [P, P, P, P, P, P, P, P, P, c_size_t, P]
+    L.holo_grad_object.argtypes = [P, P, P, P, P, P, P, P, c_size_t, P]
+    L.holo_grad_probe.argtypes = [P, P, P, P, P, P, P, P, c_size_t, P]
+    for name in EXPORTS[:-1]:
+        getattr(L, name).restype = c_int32
+    L.holo_last_error.restype = c_char_p
+    L.holo_last_error.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != 0:
+        raise HoloError(status, lib().holo_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A holo_plan plus the workspace it needs (allocated with torch)."""
+
+    def __init__(self, H: int, W: int, theta: Sequence[float], mag_rel: Sequence[float],
+                 m0: float, fresnel0: float, kappa: float, shift=None, chunk: int = 0):
+        self.H, self.W = int(H), int(W)
+        self._theta = np.ascontiguousarray(theta, dtype=np.float64)
+        self._mag = np.ascontiguousarray(mag_rel, dtype=np.float64)
+        self.n_angles, self.n_dist = len(self._theta), len(self._mag)
+        self._shift = None if shift is None else np.ascontiguousarray(shift, dtype=np.float32)
+        if self._shift is not None and self._shift.shape != (self.n_angles, self.n_dist, 2):
+            raise ValueError("shift must have shape (n_angles, n_dist, 2)")
+        g = holo_geom()
+        g.det_rows, g.det_cols = self.H, self.W
+        g.n_angles, g.n_dist = self.n_angles, self.n_dist
+        g.theta = self._theta.ctypes.data_as(POINTER(c_double))
+        g.mag_rel = self._mag.ctypes.data_as(POINTER(c_double))
+        g.m0, g.fresnel0, g.kappa = float(m0), float(fresnel0), float(kappa)
+        g.shift = (self._shift.ctypes.data_as(POINTER(c_float)) if self._shift is not None
+                   else POINTER(c_float)())
+        g.chunk = int(chunk)
+        h = c_void_p()
+        _check(lib().holo_plan_create(ctypes.byref(g), ctypes.byref(h)))
+        self._h = h
+        n = c_size_t()
+        _check(lib().holo_workspace_bytes(h, ctypes.byref(n)))
+        self.workspace_bytes = int(n.value)
+        self._ws = None
+
+    @classmethod
+    def for_workload(cls, wl, theta=None, shift=None):
+        return cls(wl.H, wl.W, wl.theta if theta is None else theta, wl.mag_rel, wl.m0,
+                   wl.fresnel0, wl.kappa, shift=shift, chunk=wl.chunk)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().holo_plan_destroy(self._h)
+            self._h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, device):
+        import torch
+        if self._ws is None or self._ws.device != torch.device(device):
+            self._ws = torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=device)
+        return self._ws
+
+    # -- argument checks (shapes, dtypes, devices) -------------------------
+    def _vol(self, t, name):
+        import torch
+        if t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous() \
+                or tuple(t.shape) != (self.H, self.W, self.W):
+            raise ValueError("%s must be a contiguous complex64 GPU tensor of shape (H, W, W)" % name)
+        return t
+
+    def _frame(self, t, name, dtype=None):
+        import torch
+        dtype = torch.complex64 if dtype is None else dtype
+        if t.dtype != dtype or not t.is_cuda or not t.is_contiguous() \
+                or tuple(t.shape) != (self.H, self.W):
+            raise ValueError("%s must be a contiguous %s GPU tensor of shape (H, W)" % (name, dtype))
+        return t
+
+    def _frames(self, t, n, name, dtype=None):
+        import torch
+        dtype = torch.complex64 if dtype is None else dtype
+        if t.dtype != dtype or not t.is_cuda or not t.is_contiguous() \
+                or tuple(t.shape) != (n, self.n_dist, self.H, self.W):
+            raise ValueError("%s must be a contiguous %s GPU tensor of shape (%d, n_dist, H, W)"
+                             % (name, dtype, n))
+        return t
+
+    # -- entry points with the C ABI's names ------------------------------
+    def holo_fwd(self, u, q, k0=0, k1=None, v=None, stream=None):
+        import torch
+        k1 = self.n_angles if k1 is None else k1
+        self._vol(u, "u"), self._frame(q, "q")
+        if v is None:
+            v = torch.empty((k1 - k0, self.n_dist, self.H, self.W), dtype=torch.complex64,
+                            device=u.device)
+        self._frames(v, k1 - k0, "v")
+        ws = self.workspace(u.device)
+        _check(lib().holo_fwd(self._h, _ptr(u), _ptr(q), int(k0), int(k1), _ptr(v),
+                              _ptr(ws), c_size_t(ws.numel()), _stream(stream)))
+        return v
+
+    def holo_adj(self, u, q, w, k0=0, k1=None, g_u=None, g_q=None, want_u=True, want_q=True,
+                 stream=None):
+        import torch
+        k1 = self.n_angles if k1 is None else k1
+        self._vol(u, "u"), self._frame(q, "q"), self._frames(w, k1 - k0, "w")
+        if want_u and g_u is None:
+            g_u = torch.empty_like(u)
+        if want_q and g_q is None:
+            g_q = torch.empty_like(q)
+        ws = self.workspace(u.device)
+        _check(lib().holo_adj(self._h, _ptr(u), _ptr(q), int(k0), int(k1), _ptr(w),
+                              _ptr(g_u if want_u else None), _ptr(g_q if want_q else None),
+                              _ptr(ws), c_size_t(ws.numel()), _stream(stream)))
+        return g_u, g_q
+
+    def holo_objective(self, u, q, amp, amp_ref, F=None, stream=None):
+        import torch
+        self._check_data(u, q, amp, amp_ref)
+        if F is None:
+            F = torch.empty((1,), dtype=torch.float64, device=u.device)
+        ws = self.workspace(u.device)
+        _check(lib().holo_objective(self._h, _ptr(u), _ptr(q), _ptr(amp), _ptr(amp_ref), _ptr(F),
+                                    _ptr(ws), c_size_t(ws.numel()), _stream(stream)))
+        return F
+
+    def holo_grad(self, u, q, amp, amp_ref, F=None, g_u=None, g_q=None, want_F=True,
+                  want_u=True, want_q=True, stream=None):
+        import torch
+        self._check_data(u, q, amp, amp_ref)
+        if want_F and F is None:
+            F = torch.empty((1,), dtype=torch.float64, device=u.device)
+        if want_u and g_u is None:
+            g_u = torch.empty_like(u)
+        if want_q and g_q is None:
+            g_q = torch.empty_like(q)
+        ws = self.workspace(u.device)
+        _check(lib().holo_grad(self._h, _ptr(u), _ptr(q), _ptr(amp), _ptr(amp_ref),
+                               _ptr(F if want_F else None), _ptr(g_u if want_u else None),
+                               _ptr(g_q if want_q else None), _ptr(ws), c_size_t(ws.numel()),
+                               _stream(stream)))
+        return (F if want_F else None), (g_u if want_u else None), (g_q if want_q else None)
+
+    def holo_grad_object(self, u, q, amp, amp_ref, stream=None):
+        F, g_u, _ = self.holo_grad(u, q, amp, amp_ref, want_q=False, stream=stream)
+        return F, g_u
+
+    def holo_grad_probe(self, u, q, amp, amp_ref, stream=None):
+        F, _, g_q = self.holo_grad(u, q, amp, amp_ref, want_u=False, stream=stream)
+        return F, g_q
+
+    def _check_data(self, u, q, amp, amp_ref):
+        import torch
+        self._vol(u, "u"), self._frame(q, "q")
+        self._frames(amp, self.n_angles, "amp", torch.float32)
+        self._frame(amp_ref, "amp_ref", torch.float32)
+
+
+def _make_autograd():
+    import torch
+
+    class HoloLoss(torch.autograd.Function):
+        """F(u, q) as a differentiable scalar.
+
+        Forward and backward share one sweep: the forward call runs holo_grad
+        and keeps g_u and g_q; backward scales them by the incoming gradient.
+        """
+
+        @staticmethod
+        def forward(ctx, u, q, amp, amp_ref, plan):
+            need_u, need_q = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+            F, g_u, g_q = plan.holo_grad(u.detach(), q.detach(), amp, amp_ref,
+                                         want_u=need_u, want_q=need_q)
+            ctx.save_for_backward(*(t for t in (g_u, g_q) if t is not None))
+            ctx.have = (g_u is not None, g_q is not None)
+            return F[0]
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            saved = list(ctx.saved_tensors)
+            g_u = saved.pop(0) if ctx.have[0] else None
+            g_q = saved.pop(0) if ctx.have[1] else None
+            s = grad_out.to(torch.float32)
+            return (None if g_u is None else g_u * s, None if g_q is None else g_q * s,
+                    None, None, None)
+
+    return HoloLoss
+
+
+_HoloLoss = None
+
+
+def holo_loss(u, q, amp, amp_ref, plan):
+    """Differentiable objective F(u, q) (a 0-dim float64 tensor)."""
+    global _HoloLoss
+    if _HoloLoss is None:
+        _HoloLoss = _make_autograd()
+    return _HoloLoss.apply(u, q, amp, amp_ref, plan)

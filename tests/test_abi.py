@@ -1,0 +1,95 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects bad arguments on the host before any device
+work (plan creation is host-only)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2407_20304_amd import holo
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "holo.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(holo.LIB_PATH),
+                                reason="libholo.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(holo_\w+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(holo.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(holo.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def make_plan(**kw):
+    args = dict(H=64, W=64, theta=np.linspace(0, np.pi, 10, endpoint=False),
+                mag_rel=[1.0, 1.08, 1.25, 1.5], m0=300.0, fresnel0=0.01, kappa=4667.35)
+    args.update(kw)
+    return holo.Plan(**args)
+
+
+def test_plan_and_workspace_size():
+    p = make_plan(chunk=4)
+    # frames: Q, G (4 each), reference, transposed volume, psi chunk, X chunk,
+    # sinogram; all complex64 64 x 64
+    fr = 64 * 64 * 8
+    assert p.workspace_bytes >= fr * (4 + 4 + 1 + 64 + 4 + 16 + 10)
+    p.close()
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(H=100), 2), (dict(W=7 * 64), 2), (dict(H=32), 2), (dict(W=4096), 2),
+    (dict(m0=1.0), 1), (dict(m0=float("nan")), 1), (dict(fresnel0=0.0), 1),
+    (dict(mag_rel=[1.0, 0.9]), 1), (dict(mag_rel=[1.0] * 9), 1), (dict(mag_rel=[]), 1),
+    (dict(theta=[]), 1), (dict(theta=[0.0, float("inf")]), 1), (dict(kappa=float("inf")), 1),
+    (dict(chunk=-1), 1),
+])
+def test_plan_rejects_bad_geometry(kw, status):
+    with pytest.raises(holo.HoloError) as e:
+        make_plan(**kw)
+    assert e.value.status == status
+    assert holo.lib().holo_last_error().decode()
+
+
+def test_plan_rejects_non_finite_shift():
+    sh = np.zeros((10, 4, 2), np.float32)
+    sh[3, 2, 1] = np.nan
+    with pytest.raises(holo.HoloError) as e:
+        make_plan(shift=sh)
+    assert e.value.status == 1
+
+
+def test_null_arguments_return_invalid_argument():
+    L = holo.lib()
+    assert L.holo_plan_create(None, None) == 1
+    p = make_plan()
+    n = ctypes.c_size_t()
+    assert L.holo_workspace_bytes(None, ctypes.byref(n)) == 1
+    # compute calls validate on the host before touching the device
+    buf = ctypes.c_void_p(1)
+    assert L.holo_fwd(p._h, None, buf, 0, 1, buf, buf, 1 << 40, None) == 1
+    assert L.holo_fwd(p._h, buf, buf, 0, 11, buf, buf, 1 << 40, None) == 1
+    assert L.holo_fwd(p._h, buf, buf, 3, 3, buf, buf, 1 << 40, None) == 1
+    assert L.holo_adj(p._h, buf, buf, 0, 1, None, buf, buf, buf, 1 << 40, None) == 1
+    assert L.holo_objective(p._h, buf, buf, None, buf, buf, buf, 1 << 40, None) == 1
+    assert L.holo_grad(None, buf, buf, buf, buf, buf, buf, buf, buf, 1 << 40, None) == 1
+    assert L.holo_grad_object(p._h, buf, buf, buf, buf, buf, None, buf, 1 << 40, None) == 1
+    assert L.holo_grad_probe(p._h, buf, buf, buf, buf, buf, None, buf, 1 << 40, None) == 1
+    # workspace checks come before any device work as well
+    assert L.holo_grad(p._h, buf, buf, buf, buf, buf, buf, buf, None, 1 << 40, None) == 1
+    assert L.holo_grad(p._h, buf, buf, buf, buf, buf, buf, buf, buf, 16, None) == 3
+    assert L.holo_plan_destroy(None) == 0
+    p.close()

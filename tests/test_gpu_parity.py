@@ -1,0 +1,136 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerance: 1e-5 relative L2 error on the objective and on each gradient and
+field, the bar the single-precision path is held to."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import holo_oracle as O
+from tests import problems as PB
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2407_20304_amd import holo
+    holo.lib()
+
+
+def rel(x, ref):
+    return O.rel_err(x, ref)
+
+
+# ---------------------------------------------------------------------------
+# Propagation alone: u = 0 gives psi = 1, phi = 1 and v_kj = D_1 q exactly.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("H,W", [(64, 64), (128, 256), (192, 192), (384, 128), (256, 512),
+                                 (1024, 1024), (512, 2048), (2048, 64)])
+def test_zero_object_fields_are_the_propagated_probe(H, W):
+    import torch
+    say("zero-object fwd", H, W)
+    from paper_2407_20304_amd import synth
+    q = synth.probe(H, W, 77)
+    theta = np.array([0.1, 1.2, 2.0])
+    from paper_2407_20304_amd import holo
+    plan = holo.Plan(H, W, theta, synth.MAG_REL, synth.M0, synth.FRESNEL0, synth.KAPPA)
+    u = torch.zeros((H, W, W), dtype=torch.complex64, device="cuda")
+    v = plan.holo_fwd(u, torch.from_numpy(q).cuda()).cpu().numpy()
+    ref = O.propagate(PB.c128(q), 1.0, synth.FRESNEL0)
+    for k in range(3):
+        for j in range(4):
+            assert rel(v[k, j], ref) < TOL, (k, j, rel(v[k, j], ref))
+
+
+# ---------------------------------------------------------------------------
+# Forward model, adjoint, objective, gradient
+# ---------------------------------------------------------------------------
+
+SMALL = dict(H=64, W=64, n_angles=12, config=0, shifts=True, chunk=5)
+
+
+@pytest.fixture(scope="module")
+def small():
+    return PB.make_problem(**SMALL)
+
+
+def test_fwd_parity(small):
+    say("fwd parity 64^3, 12 angles, shifts, chunk 5")
+    u, q, _, _ = PB.to_gpu(small)
+    plan = PB.gpu_plan(small)
+    v = plan.holo_fwd(u, q, 2, 11).cpu().numpy()
+    ref = O.forward(PB.c128(small.u), PB.c128(small.q), small.geom, ks=range(2, 11))
+    assert rel(v, ref) < TOL, rel(v, ref)
+
+
+def test_adj_parity(small):
+    import torch
+    say("adj parity 64^3")
+    u, q, _, _ = PB.to_gpu(small)
+    plan = PB.gpu_plan(small)
+    rng = np.random.default_rng(5)
+    w = (rng.standard_normal((7, 4, 64, 64)) + 1j * rng.standard_normal((7, 4, 64, 64))).astype(np.complex64)
+    gu, gq = plan.holo_adj(u, q, torch.from_numpy(w).cuda(), 3, 10)
+    ru, rq = O.adjoint(PB.c128(small.u), PB.c128(small.q), PB.c128(w), small.geom, ks=range(3, 10))
+    assert rel(gu.cpu().numpy(), ru) < TOL, rel(gu.cpu().numpy(), ru)
+    assert rel(gq.cpu().numpy(), rq) < TOL, rel(gq.cpu().numpy(), rq)
+
+
+def test_objective_and_grad_parity(small):
+    say("objective/grad parity 64^3")
+    u, q, amp, amp_ref = PB.to_gpu(small)
+    plan = PB.gpu_plan(small)
+    F0, gu0, gq0 = PB.oracle_grad(small)
+    Fo = plan.holo_objective(u, q, amp, amp_ref).item()
+    F, gu, gq = plan.holo_grad(u, q, amp, amp_ref)
+    assert abs(Fo - F0) / F0 < TOL
+    assert abs(F.item() - F0) / F0 < TOL
+    assert rel(gu.cpu().numpy(), gu0) < TOL, rel(gu.cpu().numpy(), gu0)
+    assert rel(gq.cpu().numpy(), gq0) < TOL, rel(gq.cpu().numpy(), gq0)
+    # the object-only and probe-only entry points agree with the joint one
+    F1, gu1 = plan.holo_grad_object(u, q, amp, amp_ref)
+    F2, gq2 = plan.holo_grad_probe(u, q, amp, amp_ref)
+    assert F1.item() == F.item() and F2.item() == F.item()
+    assert rel(gu1.cpu().numpy(), gu.cpu().numpy()) < 1e-6
+    assert rel(gq2.cpu().numpy(), gq.cpu().numpy()) < 1e-6
+
+
+@pytest.mark.parametrize("H,W,n,chunk,shifts", [
+    (64, 64, 90, 0, False),        # the 64^3, 90-angle workload
+    (128, 256, 9, 4, True),        # rectangular, ragged last chunk
+    (192, 192, 7, 3, True),        # radix-3 FFT lengths
+    (64, 384, 5, 2, False),
+])
+def test_grad_parity_shapes(H, W, n, chunk, shifts):
+    say("grad parity", H, W, n, chunk, shifts)
+    p = PB.make_problem(H, W, n, config=0, chunk=chunk, shifts=shifts)
+    u, q, amp, amp_ref = PB.to_gpu(p)
+    plan = PB.gpu_plan(p)
+    F0, gu0, gq0 = PB.oracle_grad(p)
+    F, gu, gq = plan.holo_grad(u, q, amp, amp_ref)
+    assert abs(F.item() - F0) / F0 < TOL, (F.item(), F0)
+    assert rel(gu.cpu().numpy(), gu0) < TOL, rel(gu.cpu().numpy(), gu0)
+    assert rel(gq.cpu().numpy(), gq0) < TOL, rel(gq.cpu().numpy(), gq0)
+
+
+def test_repeat_calls_are_bitwise_identical(small):
+    say("determinism")
+    u, q, amp, amp_ref = PB.to_gpu(small)
+    plan = PB.gpu_plan(small)
+    a = plan.holo_grad(u, q, amp, amp_ref)
+    b = plan.holo_grad(u, q, amp, amp_ref)
+    assert a[0].item() == b[0].item()
+    assert bool((a[1] == b[1]).all()) and bool((a[2] == b[2]).all())
