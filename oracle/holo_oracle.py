@@ -192,15 +192,16 @@ def radon_T(p: np.ndarray, theta: float, W: int) -> np.ndarray:
             if not ok.any():
                 continue
             sel = idx[ok]
-            # Consecutive bins are >= 1 index apart along a step (the slope
-            # is 1/max(|cos|,|sin|) >= 1), so `sel` holds no repeated index
-            # and a plain fancy-index += is an exact scatter-add.
-            assert np.all(np.diff(sel) != 0)
             contrib = (wt[ok] * scale)[None, :] * p[:, ok]
-            if axis == 0:
-                g[:, step, sel] += contrib
+            where = (slice(None), step, sel) if axis == 0 else (slice(None), sel, step)
+            # Consecutive bins are >= 1 index apart along a step (the slope
+            # is 1/max(|cos|,|sin|) >= 1), so indices repeat only when
+            # rounding lands a crossing exactly on an integer; np.add.at keeps
+            # the scatter-add exact in that case too.
+            if np.all(np.diff(sel) != 0):
+                g[where] += contrib
             else:
-                g[:, sel, step] += contrib
+                np.add.at(g, where, contrib)
     return g
 
 

@@ -194,7 +194,7 @@ def test_radon_uniform_ball_chords():
             assert np.mean(err[inner] / chord[inner]) <= 0.02
 
 
-@pytest.mark.parametrize("theta", [0.1, math.pi / 4, 1.9, 3.0])
+@pytest.mark.parametrize("theta", [0.1, math.pi / 4, math.pi / 2, 1.9, 3.0])
 def test_radon_adjoint(theta):
     rng = np.random.default_rng(5)
     u = crandn(rng, 4, 20, 20)
