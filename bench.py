@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Throughput of one gradient evaluation of the joint holotomography objective.
+
+One step = holo_grad on the whole workload: ray sums and exp for every angle,
+the four-plane frame stages (forward propagation, residual, adjoint
+propagation, probe and object gradients), the transpose of the ray sums, the
+probe-gradient finish and the double-precision objective.  Inputs are
+synthetic, seeded and already resident in HBM when the timed region starts.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "gradient evals/s (fwd+adjoint, object+probe) at 1024², vs plain; HBM GB/s"
+PEAK_FP32_VALU_TFLOPS = 157.3   # MI355X published FP32 vector peak
+PEAK_HBM_GBS = 8000.0           # MI355X published HBM3E bandwidth
+FLOP_PER_LERP = 8               # 2 taps x (re, im) x fused multiply-add
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def frame_bytes_model(wl, steps):
+    """Pass-minimal HBM bytes of the frame stages per timed region: per angle
+    one read of psi and one write of h (8 + 8 B/px); per (angle, plane)
+    frame the amplitude read (4 B/px) and two row/column exchanges (write +
+    read, 16 B/px each)."""
+    P = wl.H * wl.W
+    per_eval = wl.n_angles * P * (16 + len(wl.mag_rel) * 36)
+    return per_eval * steps
+
+
+def cpu_baseline(wl, u_gpu, q, amp_gpu, amp_ref, slab):
+    """Time the FP64 oracle on a bounded sample of the same workload: one
+    angle with its ray sums and their transpose on a `slab`-slice slab of
+    the volume (scaled to all slices), plus that angle's full four-plane
+    frame stage; scaled to all angles."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import holo_oracle as O
+    k = wl.n_angles // 3
+    theta = float(wl.theta[k])
+    z0 = wl.H // 2 - slab // 2
+    u_slab = u_gpu[z0:z0 + slab].cpu().numpy()
+    amp_k = amp_gpu[k].cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(0)
+    psi = np.exp(1j * rng.uniform(0, 1, (wl.H, wl.W)))
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        p = O.radon(u_slab, theta)
+        t1 = time.perf_counter()
+        O.radon_T(p, theta, wl.W)
+        t2 = time.perf_counter()
+        O.holo2d_gradient(psi, q.astype(np.complex128), amp_k, amp_ref.astype(np.float64),
+                          wl.mag_rel, wl.m0, wl.fresnel0)
+        t3 = time.perf_counter()
+    t_angle = (t2 - t0) * (wl.H / slab) + (t3 - t2)
+    t_eval = t_angle * wl.n_angles
+    return {
+        "value": 1.0 / t_eval, "unit": "gradient evals/s", "cores": 1, "kind": "oracle",
+        "sample": ("angle %d of %d: ray sums + transpose on a %d-slice slab (x%d to %d slices, "
+                   "%.1f s measured) and the 4-plane frame stage at %dx%d (%.1f s); scaled x%d "
+                   "angles -> %.0f s per evaluation") %
+                  (k, wl.n_angles, slab, wl.H // slab, wl.H, t2 - t0, wl.H, wl.W, t3 - t2,
+                   wl.n_angles, t_eval),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="vol1024_a1800")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-slab", type=int, default=32)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one MI355X: the path runs on a single GPU "
+              "(multi-GPU sharding is a design note only); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2407_20304_amd import holo, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    holo.lib()  # fails loudly if the HIP library is missing
+    dev = torch.device("cuda:0")
+    wl = synth.WORKLOADS[args.workload]
+    H, W, N, nd = wl.H, wl.W, wl.n_angles, len(wl.mag_rel)
+    sd = lambda role: synth.seed_of(wl.config, role)
+
+    log("inputs: %s (volume %dx%dx%d, %d angles, %d planes, detector %dx%d)"
+        % (wl.name, H, W, W, N, nd, H, W))
+    u = synth.ellipsoid_volume(W, H, sd(4), device=dev)
+    q_np = synth.probe(H, W, sd(5))
+    q = torch.from_numpy(q_np).to(dev)
+    amp = synth.synthetic_amplitudes(N, nd, H, W, sd(9), device=dev)
+    amp_ref = synth.synthetic_amplitudes(1, 1, H, W, sd(9) + 500, device=dev)[0, 0].contiguous()
+    torch.cuda.synchronize()
+    log("inputs ready")
+
+    plan = holo.Plan.for_workload(wl)
+    ws = plan.workspace(dev)
+    F = torch.empty((1,), dtype=torch.float64, device=dev)
+    g_u = torch.empty_like(u)
+    g_q = torch.empty_like(q)
+    log("workspace %.1f GiB" % (plan.workspace_bytes / 2 ** 30))
+
+    for i in range(args.warmup):
+        plan.holo_grad(u, q, amp, amp_ref, F=F, g_u=g_u, g_q=g_q)
+        torch.cuda.synchronize()
+        log("warmup %d done" % i)
+
+    plan.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        plan.holo_grad(u, q, amp, amp_ref, F=F, g_u=g_u, g_q=g_q)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    plan.timing(False)
+    kt = plan.kernel_times()
+    log("timed %d steps: %.3f s" % (args.steps, elapsed))
+    Fv = F.item()
+    if not math.isfinite(Fv):
+        print("objective is not finite", file=sys.stderr)
+        sys.exit(1)
+
+    K = args.steps
+    lerps = float(N) * W * W * H * K
+    kernels = {}
+    for name, (ms, n) in kt.items():
+        if n == 0:
+            continue
+        ent = {"ms_per_step": ms / K, "launches_per_step": n / K, "avg_launch_ms": ms / n}
+        if name in ("radon_fwd", "radon_adj"):
+            tf = lerps * FLOP_PER_LERP / (ms * 1e-3) / 1e12
+            ent.update({"achieved": tf, "unit": "TFLOP/s", "frac": tf / PEAK_FP32_VALU_TFLOPS})
+        kernels[name] = ent
+    frame_ms = sum(kt[c][0] for c in ("pass_a", "pass_b", "pass_c", "pass_d"))
+    frame_gbs = frame_bytes_model(wl, K) / (frame_ms * 1e-3) / 1e9 if frame_ms > 0 else None
+    dom = max(("radon_fwd", "radon_adj"), key=lambda c: kt[c][0])
+    dms, dn = kt[dom]
+    per_launch_flop = lerps * FLOP_PER_LERP / dn
+    achieved = per_launch_flop / (dms / dn * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": "k_" + dom, "achieved": achieved,
+                "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": None,
+                "per_launch_flop": per_launch_flop, "avg_launch_ms": dms / dn}
+
+    result = {
+        "metric": METRIC,
+        "value": K / elapsed,
+        "unit": "gradient evals/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * elapsed / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "volume": [H, W, W], "n_angles": N, "chunk": wl.chunk,
+                   "n_dist": nd, "detector": [H, W], "parallelism": "single GPU"},
+        "objective": Fv,
+        "frame_stage_GBps": frame_gbs,
+        "frame_stage_hbm_frac": None if frame_gbs is None else frame_gbs / PEAK_HBM_GBS,
+        "kernels": kernels,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)")
+        result["cpu_baseline"] = cpu_baseline(wl, u, q_np, amp, amp_ref.cpu().numpy(),
+                                              args.cpu_slab)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -145,6 +145,30 @@ holo_status holo_grad_probe(holo_plan* plan, const holo_c64* u, const holo_c64* 
                             double* F_dev, holo_c64* g_q,
                             void* ws, size_t ws_bytes, void* stream);
 
+/* Kernel classes for the timing diagnostics below. */
+enum {
+  HOLO_K_RADON_FWD = 0,  /* ray sums + exp, one launch per angle chunk          */
+  HOLO_K_RADON_ADJ = 1,  /* transpose of the ray sums, one launch per call      */
+  HOLO_K_PASS_A = 2,     /* demagnify, probe product, row propagation           */
+  HOLO_K_PASS_B = 3,     /* column propagation, residual, adjoint columns       */
+  HOLO_K_PASS_C = 4,     /* adjoint rows, probe-gradient accumulation           */
+  HOLO_K_PASS_D = 5,     /* transpose of the demagnification, chain rule        */
+  HOLO_K_PROBE = 6,      /* probe-side propagations and the reference term      */
+  HOLO_K_OTHER = 7,      /* transposed volume copy, fills, sums, reductions     */
+  HOLO_K_COUNT = 8
+};
+
+/* Diagnostics.  holo_timing_enable(plan, 1) clears the counters and makes
+ * every later compute call of the plan record a HIP event pair around each
+ * kernel launch, on the call's stream; holo_timing_enable(plan, 0) stops
+ * recording.  holo_timing_read waits for the recorded events and returns,
+ * for one kernel class, the summed kernel time in milliseconds and the number
+ * of launches recorded since the counters were cleared.  Errors:
+ * INVALID_ARGUMENT (NULL plan or outputs, class out of range), HIP. */
+holo_status holo_timing_enable(holo_plan* plan, int32_t on);
+holo_status holo_timing_read(holo_plan* plan, int32_t kernel_class,
+                             double* total_ms, int64_t* launches);
+
 /* Message describing the last non-OK status returned on this thread. */
 const char* holo_last_error(void);
 

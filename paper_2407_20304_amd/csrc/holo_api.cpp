@@ -54,6 +54,12 @@ struct holo_plan {
   void* d_tables = nullptr;
   int device = -1;
   size_t off_twW = 0, off_twH = 0, off_chW = 0, off_chH = 0, off_ang = 0, off_shift = 0;
+  // timing diagnostics
+  bool timing = false;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  double t_ms[HOLO_K_COUNT] = {0};
+  int64_t t_n[HOLO_K_COUNT] = {0};
 };
 
 static void build_chirp(std::vector<float2>& out, int n, const std::vector<double>& rhos,
@@ -199,6 +205,12 @@ extern "C" holo_status holo_plan_create(const holo_geom* geom, holo_plan** out) 
 
 extern "C" holo_status holo_plan_destroy(holo_plan* P) {
   if (!P) return HOLO_OK;
+  for (auto& pe : P->ev_pending) {
+    (void)hipEventSynchronize(pe.second.second);
+    (void)hipEventDestroy(pe.second.first);
+    (void)hipEventDestroy(pe.second.second);
+  }
+  for (hipEvent_t e : P->ev_free) (void)hipEventDestroy(e);
   if (P->d_tables) {
     int cur = -1;
     (void)hipGetDevice(&cur);
@@ -229,6 +241,47 @@ holo_status hip_fail(hipError_t e, const char* where) {
     hipError_t e_ = (call);                             \
     if (e_ != hipSuccess) return hip_fail(e_, #call);   \
   } while (0)
+
+hipEvent_t take_event(holo_plan* P) {
+  if (!P->ev_free.empty()) {
+    hipEvent_t e = P->ev_free.back();
+    P->ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Run one launcher, bracketed by an event pair when timing is on.
+template <class F>
+hipError_t timed(holo_plan* P, int cls, hipStream_t st, F&& launch) {
+  if (!P->timing) return launch();
+  hipEvent_t a = take_event(P), b = take_event(P);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, st);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, st);
+  if (e != hipSuccess) return e;
+  P->ev_pending.push_back({cls, {a, b}});
+  return hipSuccess;
+}
+
+holo_status drain_events(holo_plan* P) {
+  for (auto& pe : P->ev_pending) {
+    HOLO_HIP(hipEventSynchronize(pe.second.second));
+    float ms = 0.f;
+    HOLO_HIP(hipEventElapsedTime(&ms, pe.second.first, pe.second.second));
+    P->t_ms[pe.first] += ms;
+    P->t_n[pe.first] += 1;
+    P->ev_free.push_back(pe.second.first);
+    P->ev_free.push_back(pe.second.second);
+  }
+  P->ev_pending.clear();
+  return HOLO_OK;
+}
 
 holo_status ensure_tables(holo_plan* P) {
   int dev = -1;
@@ -330,65 +383,83 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
       rj.job[rj.n++] = PropJob{q, Pref, nullptr, chirp_ref(nd), 0, 0};
       cj.job[cj.n++] = PropJob{Pref, Pref, amp_ref, chirp_ref(nd), 0, 0};
     }
-    HOLO_HIP(launch_rows_prop(g, rj, st));
-    HOLO_HIP(launch_cols_prop(g, cj, Fpart, st));
+    HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_rows_prop(g, rj, st); }));
+    HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_cols_prop(g, cj, Fpart, st); }));
     if (with_ref && want_gq) {
       PropJobs r2{}, c2{};
       r2.job[r2.n++] = PropJob{Pref, Pref, nullptr, chirp_ref(nd), 1, 0};
       c2.job[c2.n++] = PropJob{Pref, Pref, nullptr, chirp_ref(nd), 1, 0};
-      HOLO_HIP(launch_rows_prop(g, r2, st));
-      HOLO_HIP(launch_cols_prop(g, c2, Fpart, st));
+      HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_rows_prop(g, r2, st); }));
+      HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_cols_prop(g, c2, Fpart, st); }));
     }
   }
   bool xwalk = false;
   for (int k = k0; k < k1; ++k) xwalk |= P->ang[(size_t)k * kAngleStride + kBranch] != 0.0;
-  if (xwalk) HOLO_HIP(launch_transpose_xy(g, u, uT, st));
-  if (want_gq) HOLO_HIP(launch_fill_zero(Gacc, nd * HW, st));
+  if (xwalk) HOLO_HIP(timed(P, HOLO_K_OTHER, st, [&] { return launch_transpose_xy(g, u, uT, st); }));
+  if (want_gq) HOLO_HIP(timed(P, HOLO_K_OTHER, st, [&] { return launch_fill_zero(Gacc, nd * HW, st); }));
 
   const bool frames_back = want_gq || want_gu;
   for (int c0 = k0; c0 < k1; c0 += P->chunk) {
     const int Kc = std::min(P->chunk, k1 - c0);
-    HOLO_HIP(launch_radon_fwd(g, u, uT, psi, d_ang + (size_t)c0 * kAngleStride, Kc, st));
+    HOLO_HIP(timed(P, HOLO_K_RADON_FWD, st, [&] {
+      return launch_radon_fwd(g, u, uT, psi, d_ang + (size_t)c0 * kAngleStride, Kc, st);
+    }));
     double* Fc = Fpart + (size_t)tiles * (1 + (size_t)(c0 - k0) * nd);
     switch (mode) {
       case kFwd: {
         float2* v = v_out + (size_t)(c0 - k0) * nd * HW;
-        HOLO_HIP(launch_pass_a(g, psi, Q, v, c0, Kc, st));
-        HOLO_HIP(launch_pass_b(g, kColFwd, nullptr, v, nullptr, nullptr, Kc, st));
+        HOLO_HIP(timed(P, HOLO_K_PASS_A, st, [&] { return launch_pass_a(g, psi, Q, v, c0, Kc, st); }));
+        HOLO_HIP(timed(P, HOLO_K_PASS_B, st, [&] {
+          return launch_pass_b(g, kColFwd, nullptr, v, nullptr, nullptr, Kc, st);
+        }));
         break;
       }
       case kObj:
       case kGrad: {
-        HOLO_HIP(launch_pass_a(g, psi, Q, X, c0, Kc, st));
+        HOLO_HIP(timed(P, HOLO_K_PASS_A, st, [&] { return launch_pass_a(g, psi, Q, X, c0, Kc, st); }));
         const float* a = amp + (size_t)c0 * nd * HW;
-        HOLO_HIP(launch_pass_b(g, frames_back ? kColGrad : kColObj, nullptr, X, a, Fc, Kc, st));
+        HOLO_HIP(timed(P, HOLO_K_PASS_B, st, [&] {
+          return launch_pass_b(g, frames_back ? kColGrad : kColObj, nullptr, X, a, Fc, Kc, st);
+        }));
         break;
       }
       case kAdj: {
         const float2* w = w_in + (size_t)(c0 - k0) * nd * HW;
-        HOLO_HIP(launch_pass_b(g, kColAdj, w, X, nullptr, nullptr, Kc, st));
+        HOLO_HIP(timed(P, HOLO_K_PASS_B, st, [&] {
+          return launch_pass_b(g, kColAdj, w, X, nullptr, nullptr, Kc, st);
+        }));
         break;
       }
     }
     if ((mode == kGrad || mode == kAdj) && frames_back) {
-      HOLO_HIP(launch_pass_c(g, X, psi, Q, Gacc, want_gq ? 1 : 0, c0, Kc, st));
-      if (want_gu) HOLO_HIP(launch_pass_d(g, X, psi, S + (size_t)(c0 - k0) * HW, c0, Kc, st));
+      HOLO_HIP(timed(P, HOLO_K_PASS_C, st, [&] {
+        return launch_pass_c(g, X, psi, Q, Gacc, want_gq ? 1 : 0, c0, Kc, st);
+      }));
+      if (want_gu)
+        HOLO_HIP(timed(P, HOLO_K_PASS_D, st, [&] {
+          return launch_pass_d(g, X, psi, S + (size_t)(c0 - k0) * HW, c0, Kc, st);
+        }));
     }
   }
-  if (want_gu) HOLO_HIP(launch_radon_adj(g, S, gu, d_ang + (size_t)k0 * kAngleStride, k1 - k0, st));
+  if (want_gu)
+    HOLO_HIP(timed(P, HOLO_K_RADON_ADJ, st, [&] {
+      return launch_radon_adj(g, S, gu, d_ang + (size_t)k0 * kAngleStride, k1 - k0, st);
+    }));
   if (want_gq) {
     PropJobs rj{}, cj{};
     for (int j = 0; j < nd; ++j) {
       rj.job[rj.n++] = PropJob{Gacc + j * HW, Gacc + j * HW, nullptr, chirp_probe(nd, j), 1, 0};
       cj.job[cj.n++] = PropJob{Gacc + j * HW, Gacc + j * HW, nullptr, chirp_probe(nd, j), 1, 0};
     }
-    HOLO_HIP(launch_rows_prop(g, rj, st));
-    HOLO_HIP(launch_cols_prop(g, cj, Fpart, st));
-    HOLO_HIP(launch_sum_frames(Gacc, nd, with_ref ? Pref : nullptr, gq, HW, st));
+    HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_rows_prop(g, rj, st); }));
+    HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_cols_prop(g, cj, Fpart, st); }));
+    HOLO_HIP(timed(P, HOLO_K_OTHER, st, [&] {
+      return launch_sum_frames(Gacc, nd, with_ref ? Pref : nullptr, gq, HW, st);
+    }));
   }
   if (want_F) {
     const size_t n = (size_t)tiles * (1 + (size_t)(k1 - k0) * nd);
-    HOLO_HIP(launch_reduce_sum(Fpart, n, F, st));
+    HOLO_HIP(timed(P, HOLO_K_OTHER, st, [&] { return launch_reduce_sum(Fpart, n, F, st); }));
   }
   return HOLO_OK;
 }
@@ -457,4 +528,31 @@ extern "C" holo_status holo_grad_probe(holo_plan* P, const holo_c64* u, const ho
                                        holo_c64* g_q, void* ws, size_t ws_bytes, void* stream) {
   if (!g_q) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_grad_probe: g_q is NULL");
   return holo_grad(P, u, q, amp, amp_ref, F, nullptr, g_q, ws, ws_bytes, stream);
+}
+
+extern "C" holo_status holo_timing_enable(holo_plan* P, int32_t on) {
+  if (!P) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_timing_enable: plan is NULL");
+  if (on) {
+    holo_status s = drain_events(P);
+    if (s != HOLO_OK) return s;
+    for (int c = 0; c < HOLO_K_COUNT; ++c) {
+      P->t_ms[c] = 0.0;
+      P->t_n[c] = 0;
+    }
+  }
+  P->timing = on != 0;
+  return HOLO_OK;
+}
+
+extern "C" holo_status holo_timing_read(holo_plan* P, int32_t cls, double* total_ms,
+                                        int64_t* launches) {
+  if (!P || !total_ms || !launches)
+    return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_timing_read: NULL argument");
+  if (cls < 0 || cls >= HOLO_K_COUNT)
+    return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_timing_read: kernel class out of range");
+  holo_status s = drain_events(P);
+  if (s != HOLO_OK) return s;
+  *total_ms = P->t_ms[cls];
+  *launches = P->t_n[cls];
+  return HOLO_OK;
 }

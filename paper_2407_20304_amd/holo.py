@@ -22,8 +22,12 @@ LIB_PATH = os.path.join(_HERE, "libholo.so")
 EXPORTS = (
     "holo_plan_create", "holo_plan_destroy", "holo_workspace_bytes",
     "holo_fwd", "holo_adj", "holo_objective", "holo_grad",
-    "holo_grad_object", "holo_grad_probe", "holo_last_error",
+    "holo_grad_object", "holo_grad_probe", "holo_timing_enable", "holo_timing_read",
+    "holo_last_error",
 )
+
+KERNEL_CLASSES = ("radon_fwd", "radon_adj", "pass_a", "pass_b", "pass_c", "pass_d", "probe",
+                  "other")
 
 STATUS = {0: "HOLO_OK", 1: "HOLO_ERR_INVALID_ARGUMENT", 2: "HOLO_ERR_UNSUPPORTED_SIZE",
           3: "HOLO_ERR_WORKSPACE_TOO_SMALL", 4: "HOLO_ERR_HIP", 5: "HOLO_ERR_OUT_OF_HOST_MEMORY"}
@@ -66,6 +70,8 @@ def lib():
     L.holo_grad.argtypes = [P, P, P, P, P, P, P, P, P, c_size_t, P]
     L.holo_grad_object.argtypes = [P, P, P, P, P, P, P, P, c_size_t, P]
     L.holo_grad_probe.argtypes = [P, P, P, P, P, P, P, P, c_size_t, P]
+    L.holo_timing_enable.argtypes = [P, c_int32]
+    L.holo_timing_read.argtypes = [P, c_int32, POINTER(c_double), POINTER(ctypes.c_int64)]
     for name in EXPORTS[:-1]:
         getattr(L, name).restype = c_int32
     L.holo_last_error.restype = c_char_p
@@ -230,6 +236,19 @@ class Plan:
     def holo_grad_probe(self, u, q, amp, amp_ref, stream=None):
         F, _, g_q = self.holo_grad(u, q, amp, amp_ref, want_u=False, stream=stream)
         return F, g_q
+
+    def timing(self, on=True):
+        """Record HIP events around every kernel launch of later calls."""
+        _check(lib().holo_timing_enable(self._h, 1 if on else 0))
+
+    def kernel_times(self):
+        """{class: (total_ms, launches)} recorded since timing(True)."""
+        out = {}
+        for i, name in enumerate(KERNEL_CLASSES):
+            ms, n = c_double(), ctypes.c_int64()
+            _check(lib().holo_timing_read(self._h, i, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = (ms.value, int(n.value))
+        return out
 
     def _check_data(self, u, q, amp, amp_ref):
         import torch
