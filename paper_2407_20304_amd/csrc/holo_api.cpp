@@ -47,13 +47,18 @@ struct holo_plan {
   std::vector<double> ang;                  // [n_angles][kAngleStride]
   std::vector<float2> twW, twH, chirpW, chirpH;
   bool any_xwalk = false;
+  // forward ray-sum angle groups: consecutive angles of one walk direction
+  // whose staged row windows fit (first, count); group_of[k] = group index
+  std::vector<int2> groups;
+  std::vector<int> group_of;
   // workspace layout (byte offsets)
   size_t off_Q = 0, off_G = 0, off_P = 0, off_uT = 0, off_psi = 0, off_X = 0, off_S = 0,
          off_F = 0, ws_bytes = 0, n_fpart = 0;
   // device tables (lazily uploaded on the first compute call)
   void* d_tables = nullptr;
   int device = -1;
-  size_t off_twW = 0, off_twH = 0, off_chW = 0, off_chH = 0, off_ang = 0, off_shift = 0;
+  size_t off_twW = 0, off_twH = 0, off_chW = 0, off_chH = 0, off_ang = 0, off_shift = 0,
+         off_groups = 0;
   // timing diagnostics
   bool timing = false;
   std::vector<hipEvent_t> ev_free;
@@ -87,6 +92,30 @@ static void build_twiddles(std::vector<float2>& out, int n) {
 }
 
 static bool is_finite(double x) { return std::isfinite(x); }
+
+// Can angles [a, b) share the staged row windows of the forward ray sums?
+// The window of a (bin block, row) must span at most kFwdSeg - 6 columns
+// between the lowest and highest tap (margin for rounding).  Tap positions
+// are affine in bin and row, so the extremes sit at the block's end bins and
+// at the first and last row.
+static bool fwd_group_fits(const holo_plan* P, int a, int b) {
+  const int W = P->W;
+  for (int sb = 0; sb < W; sb += 64) {
+    for (int r : {0, W - 1}) {
+      double mn = 1e300, mx = -1e300;
+      for (int k = a; k < b; ++k) {
+        const double* g = &P->ang[(size_t)k * kAngleStride];
+        for (int bin : {sb, sb + 63}) {
+          const double f = g[kA] + (double)bin * g[kB] + (double)r * g[kD];
+          mn = std::fmin(mn, f);
+          mx = std::fmax(mx, f);
+        }
+      }
+      if (std::floor(mx) - std::floor(mn) > kFwdSeg - 6) return false;
+    }
+  }
+  return true;
+}
 
 extern "C" holo_status holo_plan_create(const holo_geom* geom, holo_plan** out) {
   if (!out) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_create: out is NULL");
@@ -159,6 +188,20 @@ extern "C" holo_status holo_plan_create(const holo_geom* geom, holo_plan** out) 
       }
     }
 
+    // Forward ray-sum groups (never larger than a chunk).
+    const int na_max = std::min(kFwdNA, P->chunk);
+    P->group_of.resize(P->n_angles);
+    for (int a = 0; a < P->n_angles;) {
+      int b = a + 1;
+      while (b < P->n_angles && b - a < na_max &&
+             P->ang[(size_t)b * kAngleStride + kBranch] == P->ang[(size_t)a * kAngleStride + kBranch] &&
+             fwd_group_fits(P, a, b + 1))
+        ++b;
+      for (int k = a; k < b; ++k) P->group_of[k] = (int)P->groups.size();
+      P->groups.push_back(make_int2(a, b - a));
+      a = b;
+    }
+
     // Transfer-function tables: detector steps, probe steps, reference.
     std::vector<double> rhos(chirp_rows(P->nd));
     for (int j = 0; j < P->nd; ++j) {
@@ -195,6 +238,7 @@ extern "C" holo_status holo_plan_create(const holo_geom* geom, holo_plan** out) 
     P->off_chH = t;   t = align_up(t + P->chirpH.size() * sizeof(float2));
     P->off_ang = t;   t = align_up(t + P->ang.size() * sizeof(double));
     P->off_shift = t; t = align_up(t + P->shift.size() * sizeof(float));
+    P->off_groups = t; t = align_up(t + P->groups.size() * sizeof(int2));
   } catch (const std::bad_alloc&) {
     delete P;
     return fail(HOLO_ERR_OUT_OF_HOST_MEMORY, "holo_plan_create: out of host memory");
@@ -292,7 +336,7 @@ holo_status ensure_tables(holo_plan* P) {
                                                  ", current device is " + std::to_string(dev));
     return HOLO_OK;
   }
-  const size_t bytes = P->off_shift + align_up(P->shift.size() * sizeof(float)) + 256;
+  const size_t bytes = P->off_groups + align_up(P->groups.size() * sizeof(int2)) + 256;
   void* d = nullptr;
   HOLO_HIP(hipMalloc(&d, bytes));
   char* b = (char*)d;
@@ -306,6 +350,7 @@ holo_status ensure_tables(holo_plan* P) {
   if (e == hipSuccess) e = put(P->off_chH, P->chirpH.data(), P->chirpH.size() * sizeof(float2));
   if (e == hipSuccess) e = put(P->off_ang, P->ang.data(), P->ang.size() * sizeof(double));
   if (e == hipSuccess) e = put(P->off_shift, P->shift.data(), P->shift.size() * sizeof(float));
+  if (e == hipSuccess) e = put(P->off_groups, P->groups.data(), P->groups.size() * sizeof(int2));
   if (e != hipSuccess) {
     (void)hipFree(d);
     return hip_fail(e, "uploading plan tables");
@@ -399,10 +444,23 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
   if (want_gq) HOLO_HIP(timed(P, HOLO_K_OTHER, st, [&] { return launch_fill_zero(Gacc, nd * HW, st); }));
 
   const bool frames_back = want_gq || want_gu;
-  for (int c0 = k0; c0 < k1; c0 += P->chunk) {
-    const int Kc = std::min(P->chunk, k1 - c0);
+  const int2* d_groups = (const int2*)((const char*)P->d_tables + P->off_groups);
+  for (int c0 = k0, c1 = k0; c0 < k1; c0 = c1) {
+    // Chunk [c0, c1): whole ray-sum groups (clipped to [k0, k1)), at most
+    // `chunk` angles.
+    c1 = c0;
+    while (c1 < k1) {
+      const int2 gr = P->groups[P->group_of[c1]];
+      const int end = std::min(gr.x + gr.y, k1);
+      if (end - c0 > P->chunk) break;
+      c1 = end;
+    }
+    if (c1 == c0) c1 = std::min(c0 + P->chunk, k1);
+    const int Kc = c1 - c0;
+    const int gfirst = P->group_of[c0], glast = P->group_of[c1 - 1];
     HOLO_HIP(timed(P, HOLO_K_RADON_FWD, st, [&] {
-      return launch_radon_fwd(g, u, uT, psi, d_ang + (size_t)c0 * kAngleStride, Kc, st);
+      return launch_radon_fwd(g, u, uT, psi, d_ang, d_groups, gfirst, glast - gfirst + 1, c0, c1,
+                              st);
     }));
     double* Fc = Fpart + (size_t)tiles * (1 + (size_t)(c0 - k0) * nd);
     switch (mode) {

@@ -63,7 +63,11 @@ enum ColMode { kColFwd = 0, kColObj = 1, kColGrad = 2, kColAdj = 3 };
 int rows_per_wg(int W);      // lines of W handled by one 256-thread workgroup
 int cols_per_wg(int H);      // columns of length H per workgroup
 bool fft_size_supported(int n);
-constexpr int kRadonZ = 16;  // slices per thread in the ray-sum kernels
+// Ray-sum tiling (see the kernels): forward angle-group size, slices per
+// thread, staged rows per block and staged columns per row; transpose
+// slices per thread, angles per staged group and bins per staged segment.
+constexpr int kFwdNA = 4, kFwdZT = 16, kFwdYB = 4, kFwdSeg = 112;
+constexpr int kAdjZT = 16, kAdjNA = 16, kAdjSeg = 28;
 
 // Launchers (all asynchronous on `st`; return hipSuccess or the launch error).
 hipError_t launch_rows_prop(const DevGeom& g, const PropJobs& jobs, hipStream_t st);
@@ -77,7 +81,8 @@ hipError_t launch_pass_c(const DevGeom& g, float2* X, const float2* psi, const f
 hipError_t launch_pass_d(const DevGeom& g, const float2* X, const float2* psi, float2* S,
                          int k_first, int Kc, hipStream_t st);
 hipError_t launch_radon_fwd(const DevGeom& g, const float2* u, const float2* uT, float2* psi,
-                            const double* ang, int Kc, hipStream_t st);
+                            const double* ang, const int2* groups, int g0, int ngroups, int c0,
+                            int c1, hipStream_t st);
 hipError_t launch_radon_adj(const DevGeom& g, const float2* S, float2* gu, const double* ang,
                             int K, hipStream_t st);
 hipError_t launch_transpose_xy(const DevGeom& g, const float2* u, float2* uT, hipStream_t st);

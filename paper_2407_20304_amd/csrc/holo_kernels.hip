@@ -7,11 +7,13 @@
 //   pass C  rows:    row FFT * conj(transfer) * IFFT -> w,
 //                    G_j += conj(phi) w (probe gradient), X := conj(Q_j) w
 //   pass D  pixels:  g_psi = sum_j B^T X_j (gather), h = -i kappa conj(psi) g_psi
-// Ray sums (VALU-bound):
-//   radon_fwd  Joseph ray sums over all slices at once (lanes = bins, each
-//              thread owns kRadonZ slices), fused exp(i kappa p) epilogue
+// Ray sums (bound by LDS operand delivery and VALU):
+//   radon_fwd  Joseph ray sums, angle groups sharing LDS-staged row windows
+//              (lanes = bins, each thread owns kFwdZT slices), fused
+//              exp(i kappa p) epilogue
 //   radon_adj  transpose as a triangle-footprint gather over all angles
-//              (lanes = a 16 x 16 voxel tile, each thread owns kRadonZ slices)
+//              (lanes = a 16 x 16 voxel tile, each thread owns kAdjZT
+//              slices), sinogram segments staged in LDS per angle group
 // Positions and interpolation weights are formed in double precision; field
 // arithmetic is single precision; costs and long ray/angle sums are carried
 // in double.
@@ -422,67 +424,97 @@ __global__ __launch_bounds__(kThreads) void k_pass_d(const float2* __restrict__ 
 // Joseph ray sums and their transpose
 // ---------------------------------------------------------------------------
 
-// Forward: lanes are 64 consecutive bins, each thread owns kRadonZ slices.
-// Taps (t0, t0 + 1) are adjacent along the tap axis, so one 16-byte load
-// fetches both; angles that walk along x read the x/y-transposed volume.
-__global__ __launch_bounds__(64) void k_radon_fwd(const float2* __restrict__ u,
-                                                  const float2* __restrict__ uT,
-                                                  float2* __restrict__ psi, DevGeom g,
-                                                  const double* __restrict__ ang) {
-  constexpr int ZL = kRadonZ;
+// Forward.  A workgroup owns up to kFwdNA consecutive angles of one walk
+// direction (one wave per angle), 64 consecutive bins (one per lane) and
+// kFwdZT slices (per thread).  It walks the rows of the volume in blocks of
+// kFwdYB, staging for each row the column window that all its rays cross
+// (shared by the angles of the group) into LDS, then every lane
+// interpolates its two taps for each of its slices from LDS.  Angles that
+// walk along x read the x/y-transposed volume, so both walk directions use
+// the same code.  The host groups angles so that every window fits.
+__global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restrict__ u,
+                                                         const float2* __restrict__ uT,
+                                                         float2* __restrict__ psi, DevGeom g,
+                                                         const double* __restrict__ ang,
+                                                         const int2* __restrict__ groups,
+                                                         int g0, int c0, int c1) {
+  constexpr int ZT = kFwdZT, YB = kFwdYB, SEG = kFwdSeg;
+  __shared__ float2 tile[YB][ZT][SEG];
+  __shared__ int s_xl[YB];
   const int W = g.W, H = g.H;
-  const int s = blockIdx.x * 64 + threadIdx.x;
-  const int z0 = blockIdx.y * ZL;
-  const int k = blockIdx.z;
-  const double* a = ang + (size_t)k * kAngleStride;
-  const double A = a[kA], B = a[kB], D = a[kD];
-  const float2* vol = (a[kBranch] != 0.0) ? uT : u;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sb = blockIdx.x * 64;
+  const int s = sb + lane;
+  const int z0 = blockIdx.y * ZT;
+  const int2 grp = groups[g0 + blockIdx.z];
+  const int gf = max(grp.x, c0), gl = min(grp.x + grp.y, c1);
+  const int na = gl - gf;
+  const bool active = wave < na;
+  const int k = active ? gf + wave : gf;
+  const double* aw = ang + (size_t)k * kAngleStride;
+  const float2* vol = (aw[kBranch] != 0.0) ? uT : u;
+  const double B = aw[kB], D = aw[kD];
+  const double fA = aw[kA] + (double)s * B;
   const size_t WW = (size_t)W * W;
-  const char* vbase = (const char*)(vol + (size_t)z0 * WW);
-  const double fA = A + (double)s * B;
 
-  float ax[ZL], ay[ZL];
-  double ox[ZL], oy[ZL];
+  float ax[ZT], ay[ZT];
+  double ox[ZT], oy[ZT];
 #pragma unroll
-  for (int i = 0; i < ZL; ++i) { ax[i] = ay[i] = 0.f; ox[i] = oy[i] = 0.0; }
+  for (int i = 0; i < ZT; ++i) { ax[i] = ay[i] = 0.f; ox[i] = oy[i] = 0.0; }
 
-  for (int step = 0; step < W; ++step) {
-    const double fpos = fA + (double)step * D;
-    const double fl = floor(fpos);
-    const int t0 = (int)fl;
-    const float w = (float)(fpos - fl);
-    float w0 = 1.0f - w, w1 = w;
-    int tc = t0;
-    if (t0 < 0) {            // only tap t0 + 1 = 0 may be inside
-      w0 = (t0 == -1) ? w : 0.0f;
-      w1 = 0.0f;
-      tc = 0;
-    } else if (t0 >= W - 1) {  // only tap t0 = W - 1 may be inside
-      w1 = (t0 == W - 1) ? 1.0f - w : 0.0f;
-      w0 = 0.0f;
-      tc = W - 2;
+  for (int y0 = 0; y0 < W; y0 += YB) {
+    if (threadIdx.x < YB) {
+      const int r = y0 + threadIdx.x;
+      double mn = 1e300;
+      for (int a = 0; a < na; ++a) {
+        const double* ap = ang + (size_t)(gf + a) * kAngleStride;
+        const double fr = ap[kA] + (double)r * ap[kD];
+        mn = fmin(mn, fmin(fr + (double)sb * ap[kB], fr + (double)(sb + 63) * ap[kB]));
+      }
+      s_xl[threadIdx.x] = (int)floor(mn) - 1;  // one column of margin for rounding
     }
-    const char* p = vbase + ((size_t)step * W + tc) * sizeof(float2);
-#pragma unroll
-    for (int i = 0; i < ZL; ++i) {
-      const f4a8 v = *(const f4a8*)(p + (size_t)i * WW * sizeof(float2));
-      ax[i] += w0 * v.x + w1 * v.z;
-      ay[i] += w0 * v.y + w1 * v.w;
+    __syncthreads();
+    for (int i = threadIdx.x; i < YB * ZT * SEG; i += kThreads) {
+      const int c = i % SEG, rz = i / SEG;
+      const int zz = rz % ZT, r = rz / ZT;
+      const int x = s_xl[r] + c;
+      float2 v = make_float2(0.f, 0.f);
+      if (x >= 0 && x < W) v = vol[(size_t)(z0 + zz) * WW + (size_t)(y0 + r) * W + x];
+      tile[r][zz][c] = v;
     }
-    if ((step & 31) == 31) {
+    __syncthreads();
+    if (active) {
 #pragma unroll
-      for (int i = 0; i < ZL; ++i) {
-        ox[i] += (double)ax[i];
-        oy[i] += (double)ay[i];
-        ax[i] = ay[i] = 0.f;
+      for (int r = 0; r < YB; ++r) {
+        const double f = fA + (double)(y0 + r) * D;
+        const double fl = floor(f);
+        const float w1 = (float)(f - fl), w0 = 1.0f - w1;
+        int col = (int)fl - s_xl[r];
+        col = min(max(col, 0), SEG - 2);
+#pragma unroll
+        for (int i = 0; i < ZT; ++i) {
+          const float2 v0 = tile[r][i][col], v1 = tile[r][i][col + 1];
+          ax[i] += w0 * v0.x + w1 * v1.x;
+          ay[i] += w0 * v0.y + w1 * v1.y;
+        }
+      }
+      if (((y0 / YB) & 7) == 7) {
+#pragma unroll
+        for (int i = 0; i < ZT; ++i) {
+          ox[i] += (double)ax[i];
+          oy[i] += (double)ay[i];
+          ax[i] = ay[i] = 0.f;
+        }
       }
     }
+    __syncthreads();
   }
-  const double scale = a[kScale];
+  if (!active) return;
+  const double scale = aw[kScale];
   const double kap = (double)g.kappa;
   const double twopi = 6.283185307179586476925;
 #pragma unroll
-  for (int i = 0; i < ZL; ++i) {
+  for (int i = 0; i < ZT; ++i) {
     const double px = (ox[i] + (double)ax[i]) * scale;
     const double py = (oy[i] + (double)ay[i]) * scale;
     double ph = kap * px;
@@ -490,71 +522,87 @@ __global__ __launch_bounds__(64) void k_radon_fwd(const float2* __restrict__ u,
     float sn, cs;
     sincosf((float)ph, &sn, &cs);
     const float mag = expf((float)(-kap * py));
-    psi[((size_t)k * H + z0 + i) * W + s] = make_float2(mag * cs, mag * sn);
+    psi[((size_t)(k - c0) * H + z0 + i) * W + s] = make_float2(mag * cs, mag * sn);
   }
 }
 
-// Transpose: lanes cover a 16 x 16 voxel tile, each thread owns kRadonZ
-// slices and loops over all angles.  A voxel projecting to fractional bin
-// q takes max(0, 1 - |i - q| / h) / h of bin i (h = max(|cos|, |sin|)),
-// which is exactly the weight Joseph's interpolation gave it.
-__global__ __launch_bounds__(kThreads) void k_radon_adj(const float2* __restrict__ S,
-                                                        float2* __restrict__ gu, DevGeom g,
-                                                        const double* __restrict__ ang,
-                                                        int K) {
-  constexpr int ZL = kRadonZ;
+// Transpose.  A workgroup owns a 16 x 16 voxel tile (one voxel per thread)
+// and kAdjZT slices (per thread) and loops over all angles in groups of
+// kAdjNA: it stages, for each angle of the group, the kAdjSeg bins that the
+// tile projects onto, then every thread gathers its two taps per slice from
+// LDS.  A voxel projecting to fractional bin q takes max(0, 1 - |i - q| / h)
+// / h of bin i (h = max(|cos|, |sin|)) -- exactly the weight Joseph's
+// interpolation gave it.  Bins outside the detector are staged as zeros.
+__global__ __launch_bounds__(kThreads, 2) void k_radon_adj(const float2* __restrict__ S,
+                                                         float2* __restrict__ gu, DevGeom g,
+                                                         const double* __restrict__ ang,
+                                                         int K) {
+  constexpr int ZT = kAdjZT, NA = kAdjNA, SEG = kAdjSeg;
+  __shared__ float2 tile[NA][ZT][SEG];
+  __shared__ int s_sl[NA];
   const int W = g.W, H = g.H;
-  const int x = blockIdx.x * 16 + (threadIdx.x & 15);
-  const int y = blockIdx.y * 16 + (threadIdx.x >> 4);
-  const int z0 = blockIdx.z * ZL;
+  const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 16;
+  const int x = x0 + (threadIdx.x & 15);
+  const int y = y0 + (threadIdx.x >> 4);
+  const int z0 = blockIdx.z * ZT;
   const double X = (double)x - g.cW, Y = (double)y - g.cW;
+  const double X0 = (double)x0 - g.cW, X1 = X0 + 15.0;
+  const double Y0 = (double)y0 - g.cW, Y1 = Y0 + 15.0;
   const size_t HW = (size_t)H * W;
 
-  float ax[ZL], ay[ZL];
-  double ox[ZL], oy[ZL];
+  float ax[ZT], ay[ZT];
+  double ox[ZT], oy[ZT];
 #pragma unroll
-  for (int i = 0; i < ZL; ++i) { ax[i] = ay[i] = 0.f; ox[i] = oy[i] = 0.0; }
+  for (int i = 0; i < ZT; ++i) { ax[i] = ay[i] = 0.f; ox[i] = oy[i] = 0.0; }
 
-  for (int k = 0; k < K; ++k) {
-    const double* a = ang + (size_t)k * kAngleStride;
-    const double invh = a[kInvH];
-    const double q = g.cW + X * a[kCos] + Y * a[kSin];
-    const double fl = floor(q);
-    const int s0 = (int)fl;
-    const double fr = q - fl;
-    float w0 = (float)(fmax(0.0, 1.0 - fr * invh) * invh);
-    float w1 = (float)(fmax(0.0, 1.0 - (1.0 - fr) * invh) * invh);
-    int sc = s0;
-    if (s0 < 0) {
-      w0 = (s0 == -1) ? w1 : 0.0f;
-      w1 = 0.0f;
-      sc = 0;
-    } else if (s0 >= W - 1) {
-      w1 = (s0 == W - 1) ? w0 : 0.0f;
-      w0 = 0.0f;
-      sc = W - 2;
+  for (int k0 = 0; k0 < K; k0 += NA) {
+    const int na = min(NA, K - k0);
+    if ((int)threadIdx.x < na) {
+      const double* a = ang + (size_t)(k0 + threadIdx.x) * kAngleStride;
+      const double C = a[kCos], Sn = a[kSin];
+      const double qmin = g.cW + fmin(X0 * C, X1 * C) + fmin(Y0 * Sn, Y1 * Sn);
+      s_sl[threadIdx.x] = (int)floor(qmin) - 2;  // two bins of margin for rounding
     }
-    const char* p = (const char*)(S + (size_t)k * HW + (size_t)z0 * W + sc);
-#pragma unroll
-    for (int i = 0; i < ZL; ++i) {
-      const f4a8 v = *(const f4a8*)(p + (size_t)i * W * sizeof(float2));
-      ax[i] += w0 * v.x + w1 * v.z;
-      ay[i] += w0 * v.y + w1 * v.w;
+    __syncthreads();
+    for (int i = threadIdx.x; i < na * ZT * SEG; i += kThreads) {
+      const int j = i % SEG, az = i / SEG;
+      const int zz = az % ZT, a = az / ZT;
+      const int bin = s_sl[a] + j;
+      float2 v = make_float2(0.f, 0.f);
+      if (bin >= 0 && bin < W) v = S[(size_t)(k0 + a) * HW + (size_t)(z0 + zz) * W + bin];
+      tile[a][zz][j] = v;
     }
-    if ((k & 31) == 31) {
+    __syncthreads();
+    for (int a = 0; a < na; ++a) {
+      const double* ap = ang + (size_t)(k0 + a) * kAngleStride;
+      const double invh = ap[kInvH];
+      const double q = g.cW + X * ap[kCos] + Y * ap[kSin];
+      const double fl = floor(q);
+      const double fr = q - fl;
+      const float w0 = (float)(fmax(0.0, 1.0 - fr * invh) * invh);
+      const float w1 = (float)(fmax(0.0, 1.0 - (1.0 - fr) * invh) * invh);
+      int j0 = (int)fl - s_sl[a];
+      j0 = min(max(j0, 0), SEG - 2);
 #pragma unroll
-      for (int i = 0; i < ZL; ++i) {
-        ox[i] += (double)ax[i];
-        oy[i] += (double)ay[i];
-        ax[i] = ay[i] = 0.f;
+      for (int i = 0; i < ZT; ++i) {
+        const float2 v0 = tile[a][i][j0], v1 = tile[a][i][j0 + 1];
+        ax[i] += w0 * v0.x + w1 * v1.x;
+        ay[i] += w0 * v0.y + w1 * v1.y;
       }
     }
+#pragma unroll
+    for (int i = 0; i < ZT; ++i) {
+      ox[i] += (double)ax[i];
+      oy[i] += (double)ay[i];
+      ax[i] = ay[i] = 0.f;
+    }
+    __syncthreads();
   }
   const size_t WW = (size_t)W * W;
 #pragma unroll
-  for (int i = 0; i < ZL; ++i) {
+  for (int i = 0; i < ZT; ++i) {
     gu[(size_t)(z0 + i) * WW + (size_t)y * W + x] =
-        make_float2((float)(ox[i] + (double)ax[i]), (float)(oy[i] + (double)ay[i]));
+        make_float2((float)ox[i], (float)oy[i]);
   }
 }
 
@@ -683,15 +731,16 @@ hipError_t launch_pass_d(const DevGeom& g, const float2* X, const float2* psi, f
 }
 
 hipError_t launch_radon_fwd(const DevGeom& g, const float2* u, const float2* uT, float2* psi,
-                            const double* ang, int Kc, hipStream_t st) {
-  const dim3 grid(g.W / 64, g.H / kRadonZ, Kc);
-  k_radon_fwd<<<grid, 64, 0, st>>>(u, uT, psi, g, ang);
+                            const double* ang, const int2* groups, int g0, int ngroups, int c0,
+                            int c1, hipStream_t st) {
+  const dim3 grid(g.W / 64, g.H / kFwdZT, ngroups);
+  k_radon_fwd<<<grid, kThreads, 0, st>>>(u, uT, psi, g, ang, groups, g0, c0, c1);
   return hipGetLastError();
 }
 
 hipError_t launch_radon_adj(const DevGeom& g, const float2* S, float2* gu, const double* ang,
                             int K, hipStream_t st) {
-  const dim3 grid(g.W / 16, g.W / 16, g.H / kRadonZ);
+  const dim3 grid(g.W / 16, g.W / 16, g.H / kAdjZT);
   k_radon_adj<<<grid, kThreads, 0, st>>>(S, gu, g, ang, K);
   return hipGetLastError();
 }

@@ -134,3 +134,19 @@ def test_repeat_calls_are_bitwise_identical(small):
     b = plan.holo_grad(u, q, amp, amp_ref)
     assert a[0].item() == b[0].item()
     assert bool((a[1] == b[1]).all()) and bool((a[2] == b[2]).all())
+
+
+def test_fwd_parity_fine_angles_across_walk_switch():
+    # 0.1-degree spacing (as in the 1800-angle workload) around the 45 and
+    # 90 degree switches of the walk direction, on a 512-wide detector: the
+    # forward ray sums stage shared row windows for such angle groups.
+    say("fwd parity 64x512x512, fine angles")
+    deg = np.array([0.0, 0.1, 0.2, 44.8, 44.9, 45.0, 45.1, 45.2, 89.9, 90.0, 90.1, 135.0,
+                    179.8, 179.9])
+    p = PB.make_problem(64, 512, len(deg), config=0, theta=np.deg2rad(deg), chunk=6)
+    u, q, _, _ = PB.to_gpu(p)
+    plan = PB.gpu_plan(p)
+    v = plan.holo_fwd(u, q).cpu().numpy()
+    ref = O.forward(PB.c128(p.u), PB.c128(p.q), p.geom)
+    for k in range(len(deg)):
+        assert rel(v[k], ref[k]) < TOL, (deg[k], rel(v[k], ref[k]))
