@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--workload", default="vol1024_a1800")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slab", type=int, default=32)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 1 GiB device-to-device copy before the timed region "
+                         "(a known-size reference for HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one MI355X: the path runs on a single GPU "
@@ -113,6 +116,14 @@ def main():
     amp_ref = synth.synthetic_amplitudes(1, 1, H, W, sd(9) + 500, device=dev)[0, 0].contiguous()
     torch.cuda.synchronize()
     log("inputs ready")
+
+    if args.calib_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("calibration copy: 1 GiB read + 1 GiB written")
 
     plan = holo.Plan.for_workload(wl)
     ws = plan.workspace(dev)

@@ -424,6 +424,15 @@ __global__ __launch_bounds__(kThreads) void k_pass_d(const float2* __restrict__ 
 // Joseph ray sums and their transpose
 // ---------------------------------------------------------------------------
 
+// The dispatcher hands workgroup h of a 1-D grid to XCD h mod 8.  Remap so
+// that each XCD walks a contiguous range of logical indices: neighbours in
+// logical order then share that XCD's L2.
+__device__ __forceinline__ int xcd_logical(int h, int n) {
+  const int q = n >> 3, r = n & 7;
+  const int x = h & 7, loc = h >> 3;
+  return x * q + min(x, r) + loc;
+}
+
 // Forward.  A workgroup owns up to kFwdNA consecutive angles of one walk
 // direction (one wave per angle), 64 consecutive bins (one per lane) and
 // kFwdZT slices (per thread).  It walks the rows of the volume in blocks of
@@ -437,16 +446,21 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
                                                          float2* __restrict__ psi, DevGeom g,
                                                          const double* __restrict__ ang,
                                                          const int2* __restrict__ groups,
-                                                         int g0, int c0, int c1) {
+                                                         int g0, int ngroups, int c0, int c1) {
   constexpr int ZT = kFwdZT, YB = kFwdYB, SEG = kFwdSeg;
   __shared__ float2 tile[YB][ZT][SEG];
   __shared__ int s_xl[YB];
   const int W = g.W, H = g.H;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int sb = blockIdx.x * 64;
+  // logical order: angle group fastest, then bin block, then slice block,
+  // so the groups reading the same windows run together on one XCD
+  const int L = xcd_logical(blockIdx.x, gridDim.x);
+  const int gi = L % ngroups, rest = L / ngroups;
+  const int nbb = W / 64;
+  const int sb = (rest % nbb) * 64;
   const int s = sb + lane;
-  const int z0 = blockIdx.y * ZT;
-  const int2 grp = groups[g0 + blockIdx.z];
+  const int z0 = (rest / nbb) * ZT;
+  const int2 grp = groups[g0 + gi];
   const int gf = max(grp.x, c0), gl = min(grp.x + grp.y, c1);
   const int na = gl - gf;
   const bool active = wave < na;
@@ -494,8 +508,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
 #pragma unroll
         for (int i = 0; i < ZT; ++i) {
           const float2 v0 = tile[r][i][col], v1 = tile[r][i][col + 1];
-          ax[i] += w0 * v0.x + w1 * v1.x;
-          ay[i] += w0 * v0.y + w1 * v1.y;
+          ax[i] = fmaf(w1, v1.x, fmaf(w0, v0.x, ax[i]));
+          ay[i] = fmaf(w1, v1.y, fmaf(w0, v0.y, ay[i]));
         }
       }
       if (((y0 / YB) & 7) == 7) {
@@ -541,10 +555,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_adj(const float2* __restr
   __shared__ float2 tile[NA][ZT][SEG];
   __shared__ int s_sl[NA];
   const int W = g.W, H = g.H;
-  const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 16;
+  // logical order: tile x fastest, then tile y, then slice block
+  const int L = xcd_logical(blockIdx.x, gridDim.x);
+  const int nt = W / 16;
+  const int x0 = (L % nt) * 16, y0 = ((L / nt) % nt) * 16;
   const int x = x0 + (threadIdx.x & 15);
   const int y = y0 + (threadIdx.x >> 4);
-  const int z0 = blockIdx.z * ZT;
+  const int z0 = (L / (nt * nt)) * ZT;
   const double X = (double)x - g.cW, Y = (double)y - g.cW;
   const double X0 = (double)x0 - g.cW, X1 = X0 + 15.0;
   const double Y0 = (double)y0 - g.cW, Y1 = Y0 + 15.0;
@@ -586,8 +603,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_adj(const float2* __restr
 #pragma unroll
       for (int i = 0; i < ZT; ++i) {
         const float2 v0 = tile[a][i][j0], v1 = tile[a][i][j0 + 1];
-        ax[i] += w0 * v0.x + w1 * v1.x;
-        ay[i] += w0 * v0.y + w1 * v1.y;
+        ax[i] = fmaf(w1, v1.x, fmaf(w0, v0.x, ax[i]));
+        ay[i] = fmaf(w1, v1.y, fmaf(w0, v0.y, ay[i]));
       }
     }
 #pragma unroll
@@ -733,15 +750,15 @@ hipError_t launch_pass_d(const DevGeom& g, const float2* X, const float2* psi, f
 hipError_t launch_radon_fwd(const DevGeom& g, const float2* u, const float2* uT, float2* psi,
                             const double* ang, const int2* groups, int g0, int ngroups, int c0,
                             int c1, hipStream_t st) {
-  const dim3 grid(g.W / 64, g.H / kFwdZT, ngroups);
-  k_radon_fwd<<<grid, kThreads, 0, st>>>(u, uT, psi, g, ang, groups, g0, c0, c1);
+  const unsigned n = (unsigned)(g.W / 64) * (unsigned)(g.H / kFwdZT) * (unsigned)ngroups;
+  k_radon_fwd<<<n, kThreads, 0, st>>>(u, uT, psi, g, ang, groups, g0, ngroups, c0, c1);
   return hipGetLastError();
 }
 
 hipError_t launch_radon_adj(const DevGeom& g, const float2* S, float2* gu, const double* ang,
                             int K, hipStream_t st) {
-  const dim3 grid(g.W / 16, g.W / 16, g.H / kAdjZT);
-  k_radon_adj<<<grid, kThreads, 0, st>>>(S, gu, g, ang, K);
+  const unsigned n = (unsigned)(g.W / 16) * (unsigned)(g.W / 16) * (unsigned)(g.H / kAdjZT);
+  k_radon_adj<<<n, kThreads, 0, st>>>(S, gu, g, ang, K);
   return hipGetLastError();
 }
 
