@@ -1,0 +1,85 @@
+"""The torch.autograd.Function around holo_grad, on the 256^3 / 360-angle
+workload: backward equals the library gradient, scales with the incoming
+gradient, and matches central finite differences of the objective along 20
+seeded directions (single-precision forward, so the gate is 1e-3
+relative)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2407_20304_amd import holo, synth
+    wl = synth.WORKLOADS["vol256_a360"]
+    dev = torch.device("cuda:0")
+    sd = lambda role: synth.seed_of(wl.config, role)
+    u = synth.ellipsoid_volume(wl.W, wl.H, sd(4), device=dev)
+    q = torch.from_numpy(synth.probe(wl.H, wl.W, sd(5))).to(dev)
+    amp = synth.synthetic_amplitudes(wl.n_angles, 4, wl.H, wl.W, sd(9), device=dev)
+    amp_ref = synth.synthetic_amplitudes(1, 1, wl.H, wl.W, sd(9) + 500, device=dev)[0, 0].contiguous()
+    plan = holo.Plan.for_workload(wl)
+    return holo, plan, u, q, amp, amp_ref
+
+
+def test_backward_is_the_library_gradient(setup):
+    import torch
+    holo, plan, u, q, amp, amp_ref = setup
+    say("autograd backward vs holo_grad, 256^3 / 360 angles")
+    ur = u.clone().requires_grad_(True)
+    qr = q.clone().requires_grad_(True)
+    F = holo.holo_loss(ur, qr, amp, amp_ref, plan)
+    (2.5 * F).backward()
+    F0, gu, gq = plan.holo_grad(u, q, amp, amp_ref)
+    assert F.item() == F0.item()
+    assert torch.allclose(ur.grad, 2.5 * gu, rtol=1e-6, atol=0)
+    assert torch.allclose(qr.grad, 2.5 * gq, rtol=1e-6, atol=0)
+    # only the requested gradient is computed
+    qr2 = q.clone().requires_grad_(True)
+    holo.holo_loss(u, qr2, amp, amp_ref, plan).backward()
+    assert torch.allclose(qr2.grad, gq, rtol=1e-6, atol=0)
+
+
+def test_finite_differences_20_directions(setup):
+    import torch
+    holo, plan, u, q, amp, amp_ref = setup
+    say("finite differences, 20 directions")
+    ur = u.clone().requires_grad_(True)
+    qr = q.clone().requires_grad_(True)
+    holo.holo_loss(ur, qr, amp, amp_ref, plan).backward()
+    gu, gq = ur.grad, qr.grad
+    gen = torch.Generator(device=u.device)
+    gen.manual_seed(1006)
+    worst = 0.0
+    for d in range(20):
+        hu = torch.randn(u.shape, dtype=torch.complex64, device=u.device, generator=gen)
+        hq = torch.randn(q.shape, dtype=torch.complex64, device=u.device, generator=gen)
+        # steps of 1e-3 of the variables' size
+        hu *= 1e-3 * (u.abs().pow(2).mean().sqrt() / hu.abs().pow(2).mean().sqrt())
+        hq *= 1e-3 * (q.abs().pow(2).mean().sqrt() / hq.abs().pow(2).mean().sqrt())
+        if d % 3 == 1:
+            hq.zero_()
+        elif d % 3 == 2:
+            hu.zero_()
+        Fp = plan.holo_objective(u + hu, q + hq, amp, amp_ref).item()
+        Fm = plan.holo_objective(u - hu, q - hq, amp, amp_ref).item()
+        fd = (Fp - Fm) / 2.0
+        an = (torch.vdot(gu.flatten(), hu.flatten()).real.double()
+              + torch.vdot(gq.flatten(), hq.flatten()).real.double()).item()
+        err = abs(an - fd) / max(abs(fd), 1e-30)
+        worst = max(worst, err)
+        say("  direction %d: analytic %.6e  fd %.6e  rel %.2e" % (d, an, fd, err))
+        assert err < 1e-3, (d, an, fd)
+    say("worst %.2e" % worst)
