@@ -145,6 +145,46 @@ holo_status holo_grad_probe(holo_plan* plan, const holo_c64* u, const holo_c64* 
                             double* F_dev, holo_c64* g_q,
                             void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched independent single-angle retrievals (Eq. 10 and Eq. 11 with one
+ * projection, psi the unknown, own probe and reference per instance).
+ *
+ * Instance i is an n_i x n_i problem (n_i one of 64, 128, 192, 256, 384, 512,
+ * 1024) with n_dist planes; all instances share the geometry (m~_j, m0, N_F0)
+ * and have no shifts.  Arrays are packed: with off_i from holo2d_offsets and
+ * T = sum_i n_i^2,
+ *   psi, q, g_psi, g_q   [T] complex; instance i at element off_i, row-major
+ *   amp, v               [n_dist * T]; instance i at n_dist * off_i, laid out
+ *                        [n_dist][n_i][n_i] (float for amp, complex for v)
+ *   amp_ref              [T] float
+ *   F                    [n_inst] double, one objective per instance
+ * Every pass is one launch over all instances.  Same ownership, validation
+ * and stream rules as above.
+ * ------------------------------------------------------------------------- */
+typedef struct holo2d_plan holo2d_plan;
+
+/* Errors: INVALID_ARGUMENT (NULL, n_inst < 1, n_dist outside 1..8, m0 <= 1,
+ * fresnel0 <= 0, mag_rel < 1), UNSUPPORTED_SIZE (an unsupported n_i). */
+holo_status holo2d_plan_create(int32_t n_inst, const int32_t* sizes, int32_t n_dist,
+                               const double* mag_rel, double m0, double fresnel0,
+                               holo2d_plan** out);
+holo_status holo2d_plan_destroy(holo2d_plan* plan);
+/* offsets[n_inst] (elements) and total T of the packed layout. */
+holo_status holo2d_offsets(const holo2d_plan* plan, int64_t* offsets, int64_t* total);
+holo_status holo2d_workspace_bytes(const holo2d_plan* plan, size_t* bytes);
+/* Detector fields v of every instance and plane (Eq. 8 with N_theta = 1). */
+holo_status holo2d_fwd(holo2d_plan* plan, const holo_c64* psi, const holo_c64* q, holo_c64* v,
+                       void* ws, size_t ws_bytes, void* stream);
+/* Objective of every instance (Eq. 10 with the reference term). */
+holo_status holo2d_objective(holo2d_plan* plan, const holo_c64* psi, const holo_c64* q,
+                             const float* amp, const float* amp_ref, double* F,
+                             void* ws, size_t ws_bytes, void* stream);
+/* Objectives and gradients; F, g_psi and g_q may each be NULL. */
+holo_status holo2d_grad(holo2d_plan* plan, const holo_c64* psi, const holo_c64* q,
+                        const float* amp, const float* amp_ref, double* F,
+                        holo_c64* g_psi, holo_c64* g_q, void* ws, size_t ws_bytes,
+                        void* stream);
+
 /* Kernel classes for the timing diagnostics below. */
 enum {
   HOLO_K_RADON_FWD = 0,  /* ray sums + exp, one launch per angle chunk          */

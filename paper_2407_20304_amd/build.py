@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libholo.so")
-SOURCES = ["holo_kernels.hip", "holo_api.cpp"]
+SOURCES = ["holo_kernels.hip", "holo_api.cpp", "holo2d.hip", "holo2d_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 (v_pk_*_f32) is disabled for every device pass.

@@ -1,0 +1,383 @@
+// Batched independent single-angle, multi-plane retrievals (psi is the
+// unknown; Eq. 10 and Eq. 11 with N_theta = 1, own probe and reference per
+// instance), for instances of uneven square sizes in one packed layout.
+//
+// Every pass is one launch over all instances and planes: a host-built table
+// lists one item per workgroup (instance, plane/job, first line), the kernel
+// switches on the instance's edge length to the FFT specialised for it.
+//   probe   rows+columns: Q_j = D_{rho_probe_j} q, P = D_1 q, reference cost
+//           and residual; rows+columns of D_{-1} on the residual
+//   A       rows: phi = 1 + B_j(psi - 1), x = Q_j phi, row propagation
+//   B       columns: propagation, residual, cost, adjoint propagation
+//   C       rows: adjoint propagation -> w, G_j = conj(phi) w, X = conj(Q_j) w
+//   Gq      rows+columns of D_{-rho_probe_j} on G_j
+//   gather  g_psi = sum_j B_j^T X_j and g_q = sum_j G_j + D_{-1} r_ref
+//   reduce  per-instance cost from double partials
+#include "holo2d_internal.hpp"
+#include "fft_lds.hpp"
+
+namespace holo {
+
+constexpr int kT2 = 256;
+
+__host__ __device__ constexpr int b_rows_tl(int n) { return fft_row_threads(n); }
+__host__ __device__ constexpr int b_rows_lpw(int n) { return kT2 / fft_row_threads(n); }
+__host__ __device__ constexpr int b_cols_tc(int n) { return n >= 1024 ? 8 : 16; }
+
+int b2_rows_per_wg(int n) { return b_rows_lpw(n); }
+int b2_cols_per_wg(int n) { return b_cols_tc(n); }
+bool b2_size_supported(int n) {
+  switch (n) {
+    case 64: case 128: case 192: case 256: case 384: case 512: case 1024: return true;
+    default: return false;
+  }
+}
+
+// LDS budget shared by every specialisation (twiddles + lines / columns).
+constexpr int kRowLds = 1024 + 3072;          // float2 elements
+constexpr int kColLds = 1024 + 8 * 1025;
+
+__device__ __forceinline__ double b_src_pos(double c, double m, int idx) {
+  return c + m * ((double)idx - c);
+}
+
+struct BTaps {
+  int i0, i1;
+  float w0, w1;
+};
+
+__device__ __forceinline__ BTaps b_fwd_taps(double c, double m, int idx, int n) {
+  const double sp = b_src_pos(c, m, idx);
+  const double fl = floor(sp);
+  const int i0 = (int)fl;
+  const float w = (float)(sp - fl);
+  BTaps t;
+  const bool v0 = i0 >= 0 && i0 < n, v1 = i0 + 1 >= 0 && i0 + 1 < n;
+  t.w0 = v0 ? 1.0f - w : 0.0f;
+  t.w1 = v1 ? w : 0.0f;
+  t.i0 = v0 ? i0 : 0;
+  t.i1 = v1 ? i0 + 1 : 0;
+  return t;
+}
+
+__device__ __forceinline__ float2 b_phi(const float2* __restrict__ psi, int n, const BTaps& ty,
+                                        const BTaps& tx) {
+  const float2 a = psi[(size_t)ty.i0 * n + tx.i0], b = psi[(size_t)ty.i0 * n + tx.i1];
+  const float2 c = psi[(size_t)ty.i1 * n + tx.i0], d = psi[(size_t)ty.i1 * n + tx.i1];
+  const float w00 = ty.w0 * tx.w0, w01 = ty.w0 * tx.w1, w10 = ty.w1 * tx.w0, w11 = ty.w1 * tx.w1;
+  return make_float2(1.0f + w00 * (a.x - 1.f) + w01 * (b.x - 1.f) + w10 * (c.x - 1.f) + w11 * (d.x - 1.f),
+                     w00 * a.y + w01 * b.y + w10 * c.y + w11 * d.y);
+}
+
+struct BAdj {
+  int d[3];
+  float w[3];
+};
+
+__device__ __forceinline__ BAdj b_adj_taps(double c, double m, int idx, int n) {
+  const double pre = ((double)idx - c) / m + c;
+  const int d0 = (int)floor(pre) - 1;
+  BAdj a;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int d = d0 + e;
+    const bool ok = d >= 0 && d < n;
+    const double sp = b_src_pos(c, m, d);
+    const double fl = floor(sp);
+    const int i0 = (int)fl;
+    const float w = (float)(sp - fl);
+    const float wt = (i0 == idx) ? 1.0f - w : ((i0 + 1 == idx) ? w : 0.0f);
+    a.d[e] = ok ? d : 0;
+    a.w[e] = ok ? wt : 0.0f;
+  }
+  return a;
+}
+
+// ---------------------------------------------------------------------------
+// Rows
+// ---------------------------------------------------------------------------
+
+template <int N>
+__device__ __forceinline__ void b_rows_body(const B2Args& A, const B2Item& it, float2* lds) {
+  constexpr int TL = b_rows_tl(N), LPW = b_rows_lpw(N), E = N / TL;
+  float2* s_tw = lds;
+  const int line = threadIdx.x / TL, lt = threadIdx.x % TL;
+  float2* L = lds + N + line * N;
+  const B2Inst in = A.inst[it.inst];
+  for (int i = threadIdx.x; i < N; i += kT2) s_tw[i] = in.tw[i];
+  const int z = it.line0 + line;
+  const size_t fr = (size_t)N * N;
+  const int j = it.job;
+  const int nd = A.nd;
+  const double c = N / 2.0;
+  const float2* src;
+  float2* dst;
+  int chirp;
+  bool conj;
+  switch (A.mode) {
+    case kB2RowsProbe:   // q -> Q_j (job < nd) or P (job == nd)
+      src = A.q + in.off;
+      dst = (j < nd) ? A.Q + in.off * nd + j * fr : A.P + in.off;
+      chirp = (j < nd) ? nd + j : 2 * nd;
+      conj = false;
+      break;
+    case kB2RowsRef:     // residual -> D_{-1}
+      src = A.P + in.off;
+      dst = A.P + in.off;
+      chirp = 2 * nd;
+      conj = true;
+      break;
+    case kB2RowsA:
+      src = nullptr;
+      dst = A.X + in.off * nd + j * fr;
+      chirp = j;
+      conj = false;
+      break;
+    case kB2RowsC:
+      src = A.X + in.off * nd + j * fr;
+      dst = A.X + in.off * nd + j * fr;
+      chirp = j;
+      conj = true;
+      break;
+    default:             // kB2RowsGq: G_j -> D_{-rho_probe_j}
+      src = A.G + in.off * nd + j * fr;
+      dst = A.G + in.off * nd + j * fr;
+      chirp = nd + j;
+      conj = true;
+      break;
+  }
+  if (A.mode == kB2RowsA) {
+    const double m = A.mag[j];
+    const BTaps ty = b_fwd_taps(c, m, z, N);
+    const float2* psi = A.psi + in.off;
+    const float2* Qr = A.Q + in.off * nd + j * fr + (size_t)z * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int s = lt + e * TL;
+      L[s] = cmul(Qr[s], b_phi(psi, N, ty, b_fwd_taps(c, m, s, N)));
+    }
+  } else {
+    const float2* r = src + (size_t)z * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) L[lt + e * TL] = r[lt + e * TL];
+  }
+  fft<N, TL, false>(L, s_tw, lt);
+  const float2* ch = in.chirp + (size_t)chirp * N;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int s = lt + e * TL;
+    L[s] = conj ? cmulc(L[s], ch[s]) : cmul(L[s], ch[s]);
+  }
+  fft<N, TL, true>(L, s_tw, lt);
+  float2* o = dst + (size_t)z * N;
+  if (A.mode == kB2RowsC) {
+    const double m = A.mag[j];
+    const BTaps ty = b_fwd_taps(c, m, z, N);
+    const float2* psi = A.psi + in.off;
+    const float2* Qr = A.Q + in.off * nd + j * fr + (size_t)z * N;
+    float2* Gr = A.G + in.off * nd + j * fr + (size_t)z * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int s = lt + e * TL;
+      const float2 w = L[s];
+      Gr[s] = cmulc(w, b_phi(psi, N, ty, b_fwd_taps(c, m, s, N)));
+      o[s] = cmulc(w, Qr[s]);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) o[lt + e * TL] = L[lt + e * TL];
+  }
+  (void)LPW;
+}
+
+__global__ __launch_bounds__(kT2) void k2_rows(B2Args A, const B2Item* __restrict__ items) {
+  __shared__ float2 lds[kRowLds];
+  const B2Item it = items[blockIdx.x];
+  switch (A.inst[it.inst].n) {
+#define CASE(N) case N: b_rows_body<N>(A, it, lds); break;
+    CASE(64) CASE(128) CASE(192) CASE(256) CASE(384) CASE(512) CASE(1024)
+#undef CASE
+    default: break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Columns
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double b_residual(float2& v, float a) {
+  const float av = sqrtf(v.x * v.x + v.y * v.y);
+  const double d = (double)av - (double)a;
+  const float sc = av > 0.0f ? 2.0f * (1.0f - a / av) : 2.0f;
+  v = make_float2(sc * v.x, sc * v.y);
+  return d * d;
+}
+
+__device__ __forceinline__ void b_block_sum(double v, double* out) {
+  __shared__ double red[kT2];
+  red[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int o = kT2 / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+template <int N>
+__device__ __forceinline__ void b_cols_body(const B2Args& A, const B2Item& it, float2* lds) {
+  constexpr int TC = b_cols_tc(N), TLc = kT2 / TC;
+  float2* s_tw = lds;
+  const int cidx = threadIdx.x / TLc, lt = threadIdx.x % TLc;
+  float2* col0 = lds + N;
+  float2* Lc = col0 + cidx * (N + 1);
+  const B2Inst in = A.inst[it.inst];
+  for (int i = threadIdx.x; i < N; i += kT2) s_tw[i] = in.tw[i];
+  const size_t fr = (size_t)N * N;
+  const int j = it.job, nd = A.nd;
+  const int s0 = it.line0;
+  float2* frame;
+  const float* amp = nullptr;
+  int chirp;
+  bool conj = false, adj_after = false;
+  switch (A.mode) {
+    case kB2ColsProbe:
+      frame = (j < nd) ? A.Q + in.off * nd + j * fr : A.P + in.off;
+      chirp = (j < nd) ? nd + j : 2 * nd;
+      if (j == nd) amp = A.amp_ref + in.off;
+      break;
+    case kB2ColsRef:
+      frame = A.P + in.off;
+      chirp = 2 * nd;
+      conj = true;
+      break;
+    case kB2ColsB:
+      frame = A.X + in.off * nd + j * fr;
+      chirp = j;
+      amp = A.amp ? A.amp + in.off * nd + j * fr : nullptr;
+      adj_after = A.amp != nullptr && A.want_grad;
+      break;
+    default:  // kB2ColsGq
+      frame = A.G + in.off * nd + j * fr;
+      chirp = nd + j;
+      conj = true;
+      break;
+  }
+  for (int i = threadIdx.x; i < N * TC; i += kT2) {
+    const int zz = i / TC, cc = i % TC;
+    col0[cc * (N + 1) + zz] = frame[(size_t)zz * N + s0 + cc];
+  }
+  const float2* ch = in.chirp + (size_t)chirp * N;
+  fft<N, TLc, false>(Lc, s_tw, lt);
+  for (int zz = lt; zz < N; zz += TLc) Lc[zz] = conj ? cmulc(Lc[zz], ch[zz]) : cmul(Lc[zz], ch[zz]);
+  fft<N, TLc, true>(Lc, s_tw, lt);
+  __syncthreads();
+  if (amp) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < N * TC; i += kT2) {
+      const int zz = i / TC, cc = i % TC;
+      float2 v = col0[cc * (N + 1) + zz];
+      acc += b_residual(v, amp[(size_t)zz * N + s0 + cc]);
+      col0[cc * (N + 1) + zz] = v;
+    }
+    b_block_sum(acc, A.Fpart + it.slot);
+    __syncthreads();
+  }
+  if (adj_after) {
+    fft<N, TLc, false>(Lc, s_tw, lt);
+    for (int zz = lt; zz < N; zz += TLc) Lc[zz] = cmulc(Lc[zz], ch[zz]);
+    fft<N, TLc, true>(Lc, s_tw, lt);
+    __syncthreads();
+  }
+  if (A.mode == kB2ColsB && A.amp && !A.want_grad) return;  // objective only
+  for (int i = threadIdx.x; i < N * TC; i += kT2) {
+    const int zz = i / TC, cc = i % TC;
+    frame[(size_t)zz * N + s0 + cc] = col0[cc * (N + 1) + zz];
+  }
+}
+
+__global__ __launch_bounds__(kT2) void k2_cols(B2Args A, const B2Item* __restrict__ items) {
+  __shared__ float2 lds[kColLds];
+  const B2Item it = items[blockIdx.x];
+  switch (A.inst[it.inst].n) {
+#define CASE(N) case N: b_cols_body<N>(A, it, lds); break;
+    CASE(64) CASE(128) CASE(192) CASE(256) CASE(384) CASE(512) CASE(1024)
+#undef CASE
+    default: break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gather (B^T over planes, probe-gradient sum) and per-instance reduction
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kT2) void k2_gather(B2Args A, const B2Item* __restrict__ items) {
+  const B2Item it = items[blockIdx.x];
+  const B2Inst in = A.inst[it.inst];
+  const int n = in.n;
+  const int p = it.line0 + threadIdx.x;
+  if (p >= n * n) return;
+  const int z = p / n, s = p % n;
+  const size_t fr = (size_t)n * n;
+  const double c = n / 2.0;
+  float ax = 0.f, ay = 0.f;
+  float2 gq = A.want_ref ? A.P[in.off + p] : make_float2(0.f, 0.f);
+  for (int j = 0; j < A.nd; ++j) {
+    const double m = A.mag[j];
+    const BAdj rz = b_adj_taps(c, m, z, n), rs = b_adj_taps(c, m, s, n);
+    const float2* Xj = A.X + in.off * A.nd + j * fr;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const float wt = rz.w[a] * rs.w[b];
+        if (wt != 0.0f) {
+          const float2 v = Xj[(size_t)rz.d[a] * n + rs.d[b]];
+          ax += wt * v.x;
+          ay += wt * v.y;
+        }
+      }
+    }
+    const float2 gj = A.G[in.off * A.nd + j * fr + p];
+    gq.x += gj.x;
+    gq.y += gj.y;
+  }
+  if (A.g_psi) A.g_psi[in.off + p] = make_float2(ax, ay);
+  if (A.g_q) A.g_q[in.off + p] = gq;
+}
+
+__global__ __launch_bounds__(kT2) void k2_reduce(const double* __restrict__ parts,
+                                                 const int2* __restrict__ ranges,
+                                                 double* __restrict__ F) {
+  const int2 r = ranges[blockIdx.x];
+  double acc = 0.0;
+  for (int i = r.x + threadIdx.x; i < r.y; i += kT2) acc += parts[i];
+  b_block_sum(acc, F + blockIdx.x);
+}
+
+hipError_t launch_b2_rows(const B2Args& A, const B2Item* items, int n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  k2_rows<<<n, kT2, 0, st>>>(A, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_b2_cols(const B2Args& A, const B2Item* items, int n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  k2_cols<<<n, kT2, 0, st>>>(A, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_b2_gather(const B2Args& A, const B2Item* items, int n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  k2_gather<<<n, kT2, 0, st>>>(A, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_b2_reduce(const double* parts, const int2* ranges, int n_inst, double* F,
+                            hipStream_t st) {
+  k2_reduce<<<n_inst, kT2, 0, st>>>(parts, ranges, F);
+  return hipGetLastError();
+}
+
+}  // namespace holo

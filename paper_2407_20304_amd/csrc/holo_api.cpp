@@ -39,6 +39,11 @@ enum Mode { kFwd, kAdj, kObj, kGrad };
 
 }  // namespace
 
+namespace holo {
+// Shared with the batched entry points (holo2d_api.cpp).
+holo_status set_last_error(holo_status st, const std::string& msg) { return fail(st, msg); }
+}  // namespace holo
+
 struct holo_plan {
   int H = 0, W = 0, n_angles = 0, nd = 0, chunk = 64;
   double m0 = 0, fresnel0 = 0, kappa = 0;

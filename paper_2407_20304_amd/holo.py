@@ -22,8 +22,10 @@ LIB_PATH = os.path.join(_HERE, "libholo.so")
 EXPORTS = (
     "holo_plan_create", "holo_plan_destroy", "holo_workspace_bytes",
     "holo_fwd", "holo_adj", "holo_objective", "holo_grad",
-    "holo_grad_object", "holo_grad_probe", "holo_timing_enable", "holo_timing_read",
-    "holo_last_error",
+    "holo_grad_object", "holo_grad_probe",
+    "holo2d_plan_create", "holo2d_plan_destroy", "holo2d_offsets", "holo2d_workspace_bytes",
+    "holo2d_fwd", "holo2d_objective", "holo2d_grad",
+    "holo_timing_enable", "holo_timing_read", "holo_last_error",
 )
 
 KERNEL_CLASSES = ("radon_fwd", "radon_adj", "pass_a", "pass_b", "pass_c", "pass_d", "probe",
@@ -70,6 +72,14 @@ def lib():
     L.holo_grad.argtypes = [P, P, P, P, P, P, P, P, P, c_size_t, P]
     L.holo_grad_object.argtypes = [P, P, P, P, P, P, P, P, c_size_t, P]
     L.holo_grad_probe.argtypes = [P, P, P, P, P, P, P, P, c_size_t, P]
+    L.holo2d_plan_create.argtypes = [c_int32, POINTER(c_int32), c_int32, POINTER(c_double),
+                                     c_double, c_double, POINTER(c_void_p)]
+    L.holo2d_plan_destroy.argtypes = [P]
+    L.holo2d_offsets.argtypes = [P, POINTER(ctypes.c_int64), POINTER(ctypes.c_int64)]
+    L.holo2d_workspace_bytes.argtypes = [P, POINTER(c_size_t)]
+    L.holo2d_fwd.argtypes = [P, P, P, P, P, c_size_t, P]
+    L.holo2d_objective.argtypes = [P, P, P, P, P, P, P, c_size_t, P]
+    L.holo2d_grad.argtypes = [P, P, P, P, P, P, P, P, P, c_size_t, P]
     L.holo_timing_enable.argtypes = [P, c_int32]
     L.holo_timing_read.argtypes = [P, c_int32, POINTER(c_double), POINTER(ctypes.c_int64)]
     for name in EXPORTS[:-1]:
@@ -255,6 +265,121 @@ class Plan:
         self._vol(u, "u"), self._frame(q, "q")
         self._frames(amp, self.n_angles, "amp", torch.float32)
         self._frame(amp_ref, "amp_ref", torch.float32)
+
+
+class Plan2D:
+    """A holo2d_plan: independent single-angle problems of uneven sizes in one
+    packed layout (see include/holo.h)."""
+
+    def __init__(self, sizes, mag_rel, m0, fresnel0):
+        self.sizes = [int(n) for n in sizes]
+        self.n_inst = len(self.sizes)
+        self._mag = np.ascontiguousarray(mag_rel, dtype=np.float64)
+        self.n_dist = len(self._mag)
+        sz = (c_int32 * self.n_inst)(*self.sizes)
+        h = c_void_p()
+        _check(lib().holo2d_plan_create(self.n_inst, sz, self.n_dist,
+                                        self._mag.ctypes.data_as(POINTER(c_double)),
+                                        float(m0), float(fresnel0), ctypes.byref(h)))
+        self._h = h
+        offs = (ctypes.c_int64 * self.n_inst)()
+        tot = ctypes.c_int64()
+        _check(lib().holo2d_offsets(h, offs, ctypes.byref(tot)))
+        self.offsets = [int(o) for o in offs]
+        self.total = int(tot.value)
+        n = c_size_t()
+        _check(lib().holo2d_workspace_bytes(h, ctypes.byref(n)))
+        self.workspace_bytes = int(n.value)
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().holo2d_plan_destroy(self._h)
+            self._h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, device):
+        import torch
+        if self._ws is None or self._ws.device != torch.device(device):
+            self._ws = torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=device)
+        return self._ws
+
+    # packing helpers (host-side list <-> packed tensor)
+    def pack(self, frames, planes=False, dtype=None, device=None):
+        import torch
+        parts = []
+        for f in frames:
+            t = torch.as_tensor(np.ascontiguousarray(f))
+            parts.append(t.reshape(-1))
+        out = torch.cat(parts)
+        if dtype is not None:
+            out = out.to(dtype)
+        return out.to(device) if device is not None else out
+
+    def unpack(self, packed, planes=False):
+        out = []
+        k = self.n_dist if planes else 1
+        for i, n in enumerate(self.sizes):
+            o = k * self.offsets[i]
+            blk = packed[o:o + k * n * n]
+            out.append(blk.reshape((k, n, n) if planes else (n, n)))
+        return out
+
+    def _chk(self, t, planes, name, dtype):
+        k = self.n_dist if planes else 1
+        if t.dtype != dtype or not t.is_cuda or not t.is_contiguous() or t.numel() != k * self.total:
+            raise ValueError("%s must be a contiguous packed %s GPU tensor of %d elements"
+                             % (name, dtype, k * self.total))
+
+    def holo2d_fwd(self, psi, q, v=None, stream=None):
+        import torch
+        self._chk(psi, False, "psi", torch.complex64)
+        self._chk(q, False, "q", torch.complex64)
+        if v is None:
+            v = torch.empty(self.n_dist * self.total, dtype=torch.complex64, device=psi.device)
+        self._chk(v, True, "v", torch.complex64)
+        ws = self.workspace(psi.device)
+        _check(lib().holo2d_fwd(self._h, _ptr(psi), _ptr(q), _ptr(v), _ptr(ws),
+                                c_size_t(ws.numel()), _stream(stream)))
+        return v
+
+    def holo2d_objective(self, psi, q, amp, amp_ref, F=None, stream=None):
+        import torch
+        self._chk_data(psi, q, amp, amp_ref)
+        if F is None:
+            F = torch.empty(self.n_inst, dtype=torch.float64, device=psi.device)
+        ws = self.workspace(psi.device)
+        _check(lib().holo2d_objective(self._h, _ptr(psi), _ptr(q), _ptr(amp), _ptr(amp_ref),
+                                      _ptr(F), _ptr(ws), c_size_t(ws.numel()), _stream(stream)))
+        return F
+
+    def holo2d_grad(self, psi, q, amp, amp_ref, F=None, g_psi=None, g_q=None, stream=None):
+        import torch
+        self._chk_data(psi, q, amp, amp_ref)
+        if F is None:
+            F = torch.empty(self.n_inst, dtype=torch.float64, device=psi.device)
+        if g_psi is None:
+            g_psi = torch.empty_like(psi)
+        if g_q is None:
+            g_q = torch.empty_like(q)
+        ws = self.workspace(psi.device)
+        _check(lib().holo2d_grad(self._h, _ptr(psi), _ptr(q), _ptr(amp), _ptr(amp_ref), _ptr(F),
+                                 _ptr(g_psi), _ptr(g_q), _ptr(ws), c_size_t(ws.numel()),
+                                 _stream(stream)))
+        return F, g_psi, g_q
+
+    def _chk_data(self, psi, q, amp, amp_ref):
+        import torch
+        self._chk(psi, False, "psi", torch.complex64)
+        self._chk(q, False, "q", torch.complex64)
+        self._chk(amp, True, "amp", torch.float32)
+        self._chk(amp_ref, False, "amp_ref", torch.float32)
 
 
 def _make_autograd():

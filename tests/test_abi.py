@@ -21,7 +21,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(holo.LIB_PATH),
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(holo_\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(holo(?:2d)?_\w+)\s*\(", text)))
 
 
 def test_header_and_binding_agree():
@@ -93,3 +93,26 @@ def test_null_arguments_return_invalid_argument():
     assert L.holo_grad(p._h, buf, buf, buf, buf, buf, buf, buf, buf, 16, None) == 3
     assert L.holo_plan_destroy(None) == 0
     p.close()
+
+
+def test_batch_plan_offsets_and_validation():
+    p = holo.Plan2D([128, 192, 512, 64], [1.0, 1.08, 1.25, 1.5], 300.0, 0.01)
+    assert p.offsets == [0, 128 ** 2, 128 ** 2 + 192 ** 2, 128 ** 2 + 192 ** 2 + 512 ** 2]
+    assert p.total == 128 ** 2 + 192 ** 2 + 512 ** 2 + 64 ** 2
+    fr = p.total * 8
+    assert p.workspace_bytes >= fr * (4 + 1 + 4 + 4)
+    p.close()
+    for sizes, status in (([100], 2), ([2048], 2), ([], 1)):
+        with pytest.raises(holo.HoloError) as e:
+            holo.Plan2D(sizes, [1.0, 1.1], 300.0, 0.01)
+        assert e.value.status == status
+    with pytest.raises(holo.HoloError) as e:
+        holo.Plan2D([128], [1.0, 0.5], 300.0, 0.01)
+    assert e.value.status == 1
+    L = holo.lib()
+    q = holo.Plan2D([128], [1.0], 300.0, 0.01)
+    buf = ctypes.c_void_p(1)
+    assert L.holo2d_grad(q._h, None, buf, buf, buf, buf, buf, buf, buf, 1 << 40, None) == 1
+    assert L.holo2d_grad(q._h, buf, buf, buf, buf, buf, buf, buf, buf, 8, None) == 3
+    assert L.holo2d_fwd(q._h, buf, buf, None, buf, 1 << 40, None) == 1
+    q.close()

@@ -1,0 +1,97 @@
+"""Batched independent single-angle retrievals (uneven sizes, one launch per
+pass for all instances) against the FP64 oracle, instance by instance."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import holo_oracle as O
+from paper_2407_20304_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def make_instances(sizes, config=2):
+    """Truth (roles 1/2), oracle-simulated Poisson data (role 3), evaluation
+    point (roles 4/5); instance i offsets every seed by 100 i."""
+    out = []
+    mag = synth.MAG_REL
+    for i, n in enumerate(sizes):
+        sd = lambda role: synth.seed_of(config, role) + 100 * i
+        psi_t = synth.phase_object_2d(n, sd(1)).astype(np.complex128)
+        q_t = synth.probe(n, n, sd(2)).astype(np.complex128)
+        v = O.holo2d_forward(psi_t, q_t, mag, synth.M0, synth.FRESNEL0)
+        amp = synth.poisson_amplitude(np.abs(v) ** 2, sd(3))
+        P = O.propagate(q_t, 1.0, synth.FRESNEL0)
+        amp_ref = synth.poisson_amplitude(np.abs(P) ** 2, sd(3) + 50)
+        out.append((synth.phase_object_2d(n, sd(4)), synth.probe(n, n, sd(5)), amp, amp_ref))
+    return out
+
+
+def run_batch(sizes, inst):
+    import torch
+    from paper_2407_20304_amd import holo
+    plan = holo.Plan2D(sizes, synth.MAG_REL, synth.M0, synth.FRESNEL0)
+    dev = torch.device("cuda:0")
+    psi = plan.pack([x[0] for x in inst], device=dev)
+    q = plan.pack([x[1] for x in inst], device=dev)
+    amp = plan.pack([x[2] for x in inst], device=dev)
+    amp_ref = plan.pack([x[3] for x in inst], device=dev)
+    F, gpsi, gq = plan.holo2d_grad(psi, q, amp, amp_ref)
+    Fo = plan.holo2d_objective(psi, q, amp, amp_ref)
+    v = plan.holo2d_fwd(psi, q)
+    return (plan, F.cpu().numpy(), Fo.cpu().numpy(), plan.unpack(gpsi.cpu()),
+            plan.unpack(gq.cpu()), plan.unpack(v.cpu(), planes=True))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def test_mixed_sizes_against_oracle():
+    sizes = [512, 384, 256, 192, 128, 64, 128, 192, 1024]
+    say("batch parity, sizes", sizes)
+    inst = make_instances(sizes)
+    plan, F, Fo, gpsi, gq, v = run_batch(sizes, inst)
+    for i, (ps, q, a, ar) in enumerate(inst):
+        F0, gp0, gq0 = O.holo2d_gradient(ps.astype(np.complex128), q.astype(np.complex128),
+                                         a.astype(np.float64), ar.astype(np.float64),
+                                         synth.MAG_REL, synth.M0, synth.FRESNEL0)
+        v0 = O.holo2d_forward(ps.astype(np.complex128), q.astype(np.complex128), synth.MAG_REL,
+                              synth.M0, synth.FRESNEL0)
+        eF, eo = abs(F[i] - F0) / F0, abs(Fo[i] - F0) / F0
+        ep, eq = O.rel_err(gpsi[i].numpy(), gp0), O.rel_err(gq[i].numpy(), gq0)
+        ev = O.rel_err(v[i].numpy(), v0)
+        say("  inst %d n=%d: F %.1e obj %.1e g_psi %.1e g_q %.1e v %.1e" % (i, sizes[i], eF, eo, ep, eq, ev))
+        assert max(eF, eo, ep, eq, ev) < TOL
+
+
+def test_96_instances_batch_equals_single_instances():
+    sizes = synth.batch_sizes()
+    assert len(sizes) == 96
+    say("96-instance batch: mix", {n: sizes.count(n) for n in sorted(set(sizes))})
+    inst = make_instances(sizes)
+    plan, F, Fo, gpsi, gq, v = run_batch(sizes, inst)
+    assert np.all(np.isfinite(F)) and np.array_equal(F, Fo)
+    for i in (0, 17, 95):
+        _, F1, _, gp1, gq1, _ = run_batch([sizes[i]], [inst[i]])
+        assert F1[0] == F[i]
+        assert bool((gp1[0] == gpsi[i]).all()) and bool((gq1[0] == gq[i]).all())
+    # every 8th instance against the oracle
+    for i in range(0, 96, 8):
+        ps, q, a, ar = inst[i]
+        F0, gp0, gq0 = O.holo2d_gradient(ps.astype(np.complex128), q.astype(np.complex128),
+                                         a.astype(np.float64), ar.astype(np.float64),
+                                         synth.MAG_REL, synth.M0, synth.FRESNEL0)
+        assert abs(F[i] - F0) / F0 < TOL
+        assert O.rel_err(gpsi[i].numpy(), gp0) < TOL and O.rel_err(gq[i].numpy(), gq0) < TOL
