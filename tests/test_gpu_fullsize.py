@@ -121,10 +121,14 @@ def test_full_workload_invariants(full):
     gen = torch.Generator(device=u.device)
     gen.manual_seed(3006)
     for d in range(2):
+        # random direction plus an equal-norm part along the gradient (see
+        # the autograd test), steps of 1e-3 of the variables' size
         hu = torch.randn(u.shape, dtype=torch.complex64, device=u.device, generator=gen)
+        hu = hu / hu.norm() + gu / gu.norm()
+        hu *= 1e-3 * u.norm() / hu.norm()
         hq = torch.randn(q.shape, dtype=torch.complex64, device=u.device, generator=gen)
-        hu *= 1e-3 * (u.abs().pow(2).mean().sqrt() / hu.abs().pow(2).mean().sqrt())
-        hq *= 1e-3 * (q.abs().pow(2).mean().sqrt() / hq.abs().pow(2).mean().sqrt())
+        hq = hq / hq.norm() + gq / gq.norm()
+        hq *= 1e-3 * q.norm() / hq.norm()
         up, um, qp, qm = u + hu, u - hu, q + hq, q - hq
         Fp = plan.holo_objective(up, qp, amp, amp_ref).item()
         Fm = plan.holo_objective(um, qm, amp, amp_ref).item()
