@@ -66,8 +66,10 @@ bool fft_size_supported(int n);
 // Ray-sum tiling (see the kernels): forward angle-group size, slices per
 // thread, staged rows per block and staged columns per row; transpose
 // slices per thread, angles per staged group and bins per staged segment.
-constexpr int kFwdNA = 4, kFwdZT = 16, kFwdYB = 4, kFwdSeg = 112;
-constexpr int kAdjZT = 16, kAdjNA = 16, kAdjSeg = 28;
+constexpr int kFwdNA = 4, kFwdZT = 16, kFwdYB = 2, kFwdSeg = 112;
+constexpr int kAdjZT = 16, kAdjNA = 8, kAdjSeg = 28;
+// Largest detector edge (the forward kernel keeps one window start per row).
+constexpr int kMaxW = 2048;
 
 // Launchers (all asynchronous on `st`; return hipSuccess or the launch error).
 hipError_t launch_rows_prop(const DevGeom& g, const PropJobs& jobs, hipStream_t st);

@@ -436,11 +436,13 @@ __device__ __forceinline__ int xcd_logical(int h, int n) {
 // Forward.  A workgroup owns up to kFwdNA consecutive angles of one walk
 // direction (one wave per angle), 64 consecutive bins (one per lane) and
 // kFwdZT slices (per thread).  It walks the rows of the volume in blocks of
-// kFwdYB, staging for each row the column window that all its rays cross
-// (shared by the angles of the group) into LDS, then every lane
-// interpolates its two taps for each of its slices from LDS.  Angles that
-// walk along x read the x/y-transposed volume, so both walk directions use
-// the same code.  The host groups angles so that every window fits.
+// kFwdYB: for each row it stages into LDS the column window that all its rays
+// cross (shared by the angles of the group), then every lane interpolates its
+// two taps for each of its slices from LDS.  The next block's window is
+// loaded into registers while the current one is consumed, so the global
+// load latency overlaps the interpolation.  Angles that walk along x read
+// the x/y-transposed volume, so both walk directions use the same code.  The
+// host groups angles so that every window fits.
 __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restrict__ u,
                                                          const float2* __restrict__ uT,
                                                          float2* __restrict__ psi, DevGeom g,
@@ -448,8 +450,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
                                                          const int2* __restrict__ groups,
                                                          int g0, int ngroups, int c0, int c1) {
   constexpr int ZT = kFwdZT, YB = kFwdYB, SEG = kFwdSeg;
+  constexpr int PER = (YB * ZT * SEG) / kThreads;   // staged elements per thread per block
+  static_assert((YB * ZT * SEG) % kThreads == 0, "block must split evenly");
   __shared__ float2 tile[YB][ZT][SEG];
-  __shared__ int s_xl[YB];
+  __shared__ int s_xl[kMaxW];
   const int W = g.W, H = g.H;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // logical order: angle group fastest, then bin block, then slice block,
@@ -471,39 +475,51 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
   const double fA = aw[kA] + (double)s * B;
   const size_t WW = (size_t)W * W;
 
+  // window start of every row: lowest tap over the group's angles and the
+  // block's end bins, minus one column of margin for rounding
+  for (int r = threadIdx.x; r < W; r += kThreads) {
+    double mn = 1e300;
+    for (int a = 0; a < na; ++a) {
+      const double* ap = ang + (size_t)(gf + a) * kAngleStride;
+      const double fr = ap[kA] + (double)r * ap[kD];
+      mn = fmin(mn, fmin(fr + (double)sb * ap[kB], fr + (double)(sb + 63) * ap[kB]));
+    }
+    s_xl[r] = (int)floor(mn) - 1;
+  }
+  __syncthreads();
+
+  float2 pre[PER];
+  auto fetch = [&](int y0) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int i = threadIdx.x + e * kThreads;
+      const int c = i % SEG, rz = i / SEG;
+      const int zz = rz % ZT, r = rz / ZT;
+      const int x = s_xl[y0 + r] + c;
+      pre[e] = (x >= 0 && x < W) ? vol[(size_t)(z0 + zz) * WW + (size_t)(y0 + r) * W + x]
+                                 : make_float2(0.f, 0.f);
+    }
+  };
+
   float ax[ZT], ay[ZT];
   double ox[ZT], oy[ZT];
 #pragma unroll
   for (int i = 0; i < ZT; ++i) { ax[i] = ay[i] = 0.f; ox[i] = oy[i] = 0.0; }
 
+  fetch(0);
   for (int y0 = 0; y0 < W; y0 += YB) {
-    if (threadIdx.x < YB) {
-      const int r = y0 + threadIdx.x;
-      double mn = 1e300;
-      for (int a = 0; a < na; ++a) {
-        const double* ap = ang + (size_t)(gf + a) * kAngleStride;
-        const double fr = ap[kA] + (double)r * ap[kD];
-        mn = fmin(mn, fmin(fr + (double)sb * ap[kB], fr + (double)(sb + 63) * ap[kB]));
-      }
-      s_xl[threadIdx.x] = (int)floor(mn) - 1;  // one column of margin for rounding
-    }
+    __syncthreads();  // every wave is done with the previous block
+#pragma unroll
+    for (int e = 0; e < PER; ++e) (&tile[0][0][0])[threadIdx.x + e * kThreads] = pre[e];
     __syncthreads();
-    for (int i = threadIdx.x; i < YB * ZT * SEG; i += kThreads) {
-      const int c = i % SEG, rz = i / SEG;
-      const int zz = rz % ZT, r = rz / ZT;
-      const int x = s_xl[r] + c;
-      float2 v = make_float2(0.f, 0.f);
-      if (x >= 0 && x < W) v = vol[(size_t)(z0 + zz) * WW + (size_t)(y0 + r) * W + x];
-      tile[r][zz][c] = v;
-    }
-    __syncthreads();
+    if (y0 + YB < W) fetch(y0 + YB);
     if (active) {
 #pragma unroll
       for (int r = 0; r < YB; ++r) {
         const double f = fA + (double)(y0 + r) * D;
         const double fl = floor(f);
         const float w1 = (float)(f - fl), w0 = 1.0f - w1;
-        int col = (int)fl - s_xl[r];
+        int col = (int)fl - s_xl[y0 + r];
         col = min(max(col, 0), SEG - 2);
 #pragma unroll
         for (int i = 0; i < ZT; ++i) {
@@ -512,7 +528,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
           ay[i] = fmaf(w1, v1.y, fmaf(w0, v0.y, ay[i]));
         }
       }
-      if (((y0 / YB) & 7) == 7) {
+      if (((y0 / YB) & 15) == 15) {
 #pragma unroll
         for (int i = 0; i < ZT; ++i) {
           ox[i] += (double)ax[i];
@@ -521,7 +537,6 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
         }
       }
     }
-    __syncthreads();
   }
   if (!active) return;
   const double scale = aw[kScale];
@@ -544,16 +559,20 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
 // and kAdjZT slices (per thread) and loops over all angles in groups of
 // kAdjNA: it stages, for each angle of the group, the kAdjSeg bins that the
 // tile projects onto, then every thread gathers its two taps per slice from
-// LDS.  A voxel projecting to fractional bin q takes max(0, 1 - |i - q| / h)
-// / h of bin i (h = max(|cos|, |sin|)) -- exactly the weight Joseph's
-// interpolation gave it.  Bins outside the detector are staged as zeros.
+// LDS.  The next group's segments are loaded into registers while the
+// current group is consumed.  A voxel projecting to fractional bin q takes
+// max(0, 1 - |i - q| / h) / h of bin i (h = max(|cos|, |sin|)) -- exactly
+// the weight Joseph's interpolation gave it.  Bins outside the detector are
+// staged as zeros.
 __global__ __launch_bounds__(kThreads, 2) void k_radon_adj(const float2* __restrict__ S,
                                                          float2* __restrict__ gu, DevGeom g,
                                                          const double* __restrict__ ang,
                                                          int K) {
   constexpr int ZT = kAdjZT, NA = kAdjNA, SEG = kAdjSeg;
+  constexpr int PER = (NA * ZT * SEG) / kThreads;
+  static_assert((NA * ZT * SEG) % kThreads == 0, "group must split evenly");
   __shared__ float2 tile[NA][ZT][SEG];
-  __shared__ int s_sl[NA];
+  __shared__ int s_sl[2][NA];   // first staged bin per angle, by group parity
   const int W = g.W, H = g.H;
   // logical order: tile x fastest, then tile y, then slice block
   const int L = xcd_logical(blockIdx.x, gridDim.x);
@@ -567,29 +586,48 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_adj(const float2* __restr
   const double Y0 = (double)y0 - g.cW, Y1 = Y0 + 15.0;
   const size_t HW = (size_t)H * W;
 
+  // first staged bin of angle kk: lowest projection of the tile's corners
+  // minus two bins of margin for rounding
+  auto first_bin = [&](int kk) {
+    const double* ap = ang + (size_t)kk * kAngleStride;
+    const double C = ap[kCos], Sn = ap[kSin];
+    return (int)floor(g.cW + fmin(X0 * C, X1 * C) + fmin(Y0 * Sn, Y1 * Sn)) - 2;
+  };
+  float2 pre[PER];
+  auto fetch = [&](int k0, const int* sl) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int i = threadIdx.x + e * kThreads;
+      const int j = i % SEG, az = i / SEG;
+      const int zz = az % ZT, a = az / ZT;
+      const int kk = k0 + a;
+      float2 v = make_float2(0.f, 0.f);
+      if (kk < K) {
+        const int bin = sl[a] + j;
+        if (bin >= 0 && bin < W) v = S[(size_t)kk * HW + (size_t)(z0 + zz) * W + bin];
+      }
+      pre[e] = v;
+    }
+  };
+
   float ax[ZT], ay[ZT];
   double ox[ZT], oy[ZT];
 #pragma unroll
   for (int i = 0; i < ZT; ++i) { ax[i] = ay[i] = 0.f; ox[i] = oy[i] = 0.0; }
 
-  for (int k0 = 0; k0 < K; k0 += NA) {
+  if ((int)threadIdx.x < NA && (int)threadIdx.x < K) s_sl[0][threadIdx.x] = first_bin(threadIdx.x);
+  __syncthreads();
+  fetch(0, s_sl[0]);
+  for (int k0 = 0, par = 0; k0 < K; k0 += NA, par ^= 1) {
     const int na = min(NA, K - k0);
-    if ((int)threadIdx.x < na) {
-      const double* a = ang + (size_t)(k0 + threadIdx.x) * kAngleStride;
-      const double C = a[kCos], Sn = a[kSin];
-      const double qmin = g.cW + fmin(X0 * C, X1 * C) + fmin(Y0 * Sn, Y1 * Sn);
-      s_sl[threadIdx.x] = (int)floor(qmin) - 2;  // two bins of margin for rounding
-    }
+    __syncthreads();  // every wave is done with the previous group
+#pragma unroll
+    for (int e = 0; e < PER; ++e) (&tile[0][0][0])[threadIdx.x + e * kThreads] = pre[e];
+    if ((int)threadIdx.x < NA && k0 + NA + (int)threadIdx.x < K)
+      s_sl[par ^ 1][threadIdx.x] = first_bin(k0 + NA + threadIdx.x);
     __syncthreads();
-    for (int i = threadIdx.x; i < na * ZT * SEG; i += kThreads) {
-      const int j = i % SEG, az = i / SEG;
-      const int zz = az % ZT, a = az / ZT;
-      const int bin = s_sl[a] + j;
-      float2 v = make_float2(0.f, 0.f);
-      if (bin >= 0 && bin < W) v = S[(size_t)(k0 + a) * HW + (size_t)(z0 + zz) * W + bin];
-      tile[a][zz][j] = v;
-    }
-    __syncthreads();
+    if (k0 + NA < K) fetch(k0 + NA, s_sl[par ^ 1]);
+    const int* sl = s_sl[par];
     for (int a = 0; a < na; ++a) {
       const double* ap = ang + (size_t)(k0 + a) * kAngleStride;
       const double invh = ap[kInvH];
@@ -598,7 +636,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_adj(const float2* __restr
       const double fr = q - fl;
       const float w0 = (float)(fmax(0.0, 1.0 - fr * invh) * invh);
       const float w1 = (float)(fmax(0.0, 1.0 - (1.0 - fr) * invh) * invh);
-      int j0 = (int)fl - s_sl[a];
+      int j0 = (int)fl - sl[a];
       j0 = min(max(j0, 0), SEG - 2);
 #pragma unroll
       for (int i = 0; i < ZT; ++i) {
@@ -613,13 +651,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_adj(const float2* __restr
       oy[i] += (double)ay[i];
       ax[i] = ay[i] = 0.f;
     }
-    __syncthreads();
   }
   const size_t WW = (size_t)W * W;
 #pragma unroll
   for (int i = 0; i < ZT; ++i) {
-    gu[(size_t)(z0 + i) * WW + (size_t)y * W + x] =
-        make_float2((float)ox[i], (float)oy[i]);
+    gu[(size_t)(z0 + i) * WW + (size_t)y * W + x] = make_float2((float)ox[i], (float)oy[i]);
   }
 }
 
