@@ -57,7 +57,7 @@ struct holo_plan {
   std::vector<int2> groups;
   std::vector<int> group_of;
   // workspace layout (byte offsets)
-  size_t off_Q = 0, off_G = 0, off_P = 0, off_uT = 0, off_psi = 0, off_X = 0, off_S = 0,
+  size_t off_Q = 0, off_G = 0, off_P = 0, off_ub = 0, off_uTb = 0, off_psi = 0, off_X = 0, off_S = 0,
          off_F = 0, ws_bytes = 0, n_fpart = 0;
   // device tables (lazily uploaded on the first compute call)
   void* d_tables = nullptr;
@@ -226,7 +226,9 @@ extern "C" holo_status holo_plan_create(const holo_geom* geom, holo_plan** out) 
     P->off_Q = o;   o = align_up(o + fr * P->nd);
     P->off_G = o;   o = align_up(o + fr * P->nd);
     P->off_P = o;   o = align_up(o + fr);
-    P->off_uT = o;  o = align_up(o + (P->any_xwalk ? fr * P->W : 0));
+    // z-blocked copies of the volume read by the ray sums (one per walk direction)
+    P->off_ub = o;  o = align_up(o + fr * P->W);
+    P->off_uTb = o; o = align_up(o + (P->any_xwalk ? fr * P->W : 0));
     P->off_psi = o; o = align_up(o + fr * P->chunk);
     P->off_X = o;   o = align_up(o + fr * P->chunk * P->nd);
     P->off_S = o;   o = align_up(o + fr * P->n_angles);
@@ -409,7 +411,8 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
   float2* Q = (float2*)(wsb + P->off_Q);
   float2* Gacc = (float2*)(wsb + P->off_G);
   float2* Pref = (float2*)(wsb + P->off_P);
-  float2* uT = (float2*)(wsb + P->off_uT);
+  float2* ub = (float2*)(wsb + P->off_ub);
+  float2* uTb = (float2*)(wsb + P->off_uTb);
   float2* psi = (float2*)(wsb + P->off_psi);
   float2* X = (float2*)(wsb + P->off_X);
   float2* S = (float2*)(wsb + P->off_S);
@@ -445,7 +448,9 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
   }
   bool xwalk = false;
   for (int k = k0; k < k1; ++k) xwalk |= P->ang[(size_t)k * kAngleStride + kBranch] != 0.0;
-  if (xwalk) HOLO_HIP(timed(P, HOLO_K_OTHER, st, [&] { return launch_transpose_xy(g, u, uT, st); }));
+  HOLO_HIP(timed(P, HOLO_K_OTHER, st, [&] {
+    return launch_block_volume(g, u, ub, xwalk ? uTb : nullptr, st);
+  }));
   if (want_gq) HOLO_HIP(timed(P, HOLO_K_OTHER, st, [&] { return launch_fill_zero(Gacc, nd * HW, st); }));
 
   const bool frames_back = want_gq || want_gu;
@@ -464,7 +469,7 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
     const int Kc = c1 - c0;
     const int gfirst = P->group_of[c0], glast = P->group_of[c1 - 1];
     HOLO_HIP(timed(P, HOLO_K_RADON_FWD, st, [&] {
-      return launch_radon_fwd(g, u, uT, psi, d_ang, d_groups, gfirst, glast - gfirst + 1, c0, c1,
+      return launch_radon_fwd(g, ub, uTb, psi, d_ang, d_groups, gfirst, glast - gfirst + 1, c0, c1,
                               st);
     }));
     double* Fc = Fpart + (size_t)tiles * (1 + (size_t)(c0 - k0) * nd);

@@ -82,12 +82,13 @@ hipError_t launch_pass_c(const DevGeom& g, float2* X, const float2* psi, const f
                          float2* G, int accumulate, int k_first, int Kc, hipStream_t st);
 hipError_t launch_pass_d(const DevGeom& g, const float2* X, const float2* psi, float2* S,
                          int k_first, int Kc, hipStream_t st);
-hipError_t launch_radon_fwd(const DevGeom& g, const float2* u, const float2* uT, float2* psi,
+hipError_t launch_radon_fwd(const DevGeom& g, const float2* ub, const float2* uTb, float2* psi,
                             const double* ang, const int2* groups, int g0, int ngroups, int c0,
                             int c1, hipStream_t st);
 hipError_t launch_radon_adj(const DevGeom& g, const float2* S, float2* gu, const double* ang,
                             int K, hipStream_t st);
-hipError_t launch_transpose_xy(const DevGeom& g, const float2* u, float2* uT, hipStream_t st);
+hipError_t launch_block_volume(const DevGeom& g, const float2* u, float2* ub, float2* uTb,
+                               hipStream_t st);
 hipError_t launch_fill_zero(float2* p, size_t n, hipStream_t st);
 hipError_t launch_sum_frames(const float2* G, int nd, const float2* extra, float2* out,
                              size_t n, hipStream_t st);

@@ -386,10 +386,15 @@ __global__ __launch_bounds__(kThreads) void k_pass_d(const float2* __restrict__ 
                                                      const float2* __restrict__ psi,
                                                      float2* __restrict__ S, DevGeom g,
                                                      int k_first) {
+  // a workgroup covers kAdjZT rows x (256 / kAdjZT) columns; consecutive
+  // threads take consecutive rows so that the z-blocked output
+  // S[k][z / kAdjZT][s][z % kAdjZT] is written in contiguous runs
+  constexpr int ZT = kAdjZT, SC = kThreads / ZT;
   const int H = g.H, W = g.W;
-  const int p = blockIdx.x * kThreads + threadIdx.x;
-  if (p >= H * W) return;
-  const int z = p / W, s = p % W;
+  const int zz = threadIdx.x % ZT;
+  const int nsb = W / SC;
+  const int z0 = (blockIdx.x / nsb) * ZT;
+  const int z = z0 + zz, s = (blockIdx.x % nsb) * SC + threadIdx.x / ZT;
   const int k = blockIdx.y;
   float ax = 0.f, ay = 0.f;
   for (int j = 0; j < g.nd; ++j) {
@@ -417,7 +422,37 @@ __global__ __launch_bounds__(kThreads) void k_pass_d(const float2* __restrict__ 
   const float cx = ps.x * ax + ps.y * ay;
   const float cy = ps.x * ay - ps.y * ax;
   // -i kappa (cx + i cy) = kappa cy - i kappa cx
-  S[((size_t)k * H + z) * W + s] = make_float2(g.kappa * cy, -g.kappa * cx);
+  S[(size_t)k * H * W + (size_t)z0 * W + (size_t)s * ZT + zz] =
+      make_float2(g.kappa * cy, -g.kappa * cx);
+}
+
+// Z-blocked copies of the volume for the ray sums: ub[z / ZT][y][x][z % ZT]
+// (walks along y) and uTb[z / ZT][x][y][z % ZT] (walks along x, i.e. the
+// x/y-transposed volume).  A workgroup moves a 16 x 16 x ZT brick.
+__global__ __launch_bounds__(kThreads) void k_block_volume(const float2* __restrict__ u,
+                                                           float2* __restrict__ ub,
+                                                           float2* __restrict__ uTb, int W) {
+  constexpr int ZT = kFwdZT;
+  __shared__ float2 brick[ZT][16][17];
+  const int nt = W / 16;
+  const int x0 = (blockIdx.x % nt) * 16, y0 = (blockIdx.x / nt) * 16;
+  const int zb = blockIdx.y;
+  const size_t WW = (size_t)W * W;
+  // read along x (contiguous)
+  for (int i = threadIdx.x; i < ZT * 256; i += kThreads) {
+    const int xx = i & 15, yy = (i >> 4) & 15, zz = i >> 8;
+    brick[zz][yy][xx] = u[(size_t)(zb * ZT + zz) * WW + (size_t)(y0 + yy) * W + x0 + xx];
+  }
+  __syncthreads();
+  float2* bb = ub + (size_t)zb * WW * ZT;
+  float2* tb = uTb ? uTb + (size_t)zb * WW * ZT : nullptr;
+  // write with z fastest (contiguous 128-byte runs)
+  for (int i = threadIdx.x; i < ZT * 256; i += kThreads) {
+    const int zz = i % ZT, p = i / ZT;
+    const int a = p & 15, b = p >> 4;
+    bb[((size_t)(y0 + b) * W + x0 + a) * ZT + zz] = brick[zz][b][a];
+    if (tb) tb[((size_t)(x0 + b) * W + y0 + a) * ZT + zz] = brick[zz][a][b];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -444,7 +479,7 @@ __device__ __forceinline__ int xcd_logical(int h, int n) {
 // the x/y-transposed volume, so both walk directions use the same code.  The
 // host groups angles so that every window fits.
 __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restrict__ u,
-                                                         const float2* __restrict__ uT,
+                                                         const float2* __restrict__ uT,  // z-blocked
                                                          float2* __restrict__ psi, DevGeom g,
                                                          const double* __restrict__ ang,
                                                          const int2* __restrict__ groups,
@@ -452,7 +487,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
   constexpr int ZT = kFwdZT, YB = kFwdYB, SEG = kFwdSeg;
   constexpr int PER = (YB * ZT * SEG) / kThreads;   // staged elements per thread per block
   static_assert((YB * ZT * SEG) % kThreads == 0, "block must split evenly");
-  __shared__ float2 tile[YB][ZT][SEG];
+  __shared__ float2 tile[YB][ZT][SEG + 1];           // +1: spreads the staging writes over banks
   __shared__ int s_xl[kMaxW];
   const int W = g.W, H = g.H;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -488,15 +523,19 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
   }
   __syncthreads();
 
+  // The volume copy is z-blocked, vol[z / ZT][row][col][z % ZT]: the ZT
+  // slices of one voxel column are one contiguous 128-byte run, so a staged
+  // window row is a single contiguous stretch of memory.
+  const float2* vb = vol + (size_t)(z0 / ZT) * WW * ZT;
   float2 pre[PER];
   auto fetch = [&](int y0) {
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int i = threadIdx.x + e * kThreads;
-      const int c = i % SEG, rz = i / SEG;
-      const int zz = rz % ZT, r = rz / ZT;
+      const int zz = i % ZT, cr = i / ZT;
+      const int c = cr % SEG, r = cr / SEG;
       const int x = s_xl[y0 + r] + c;
-      pre[e] = (x >= 0 && x < W) ? vol[(size_t)(z0 + zz) * WW + (size_t)(y0 + r) * W + x]
+      pre[e] = (x >= 0 && x < W) ? vb[((size_t)(y0 + r) * W + x) * ZT + zz]
                                  : make_float2(0.f, 0.f);
     }
   };
@@ -510,7 +549,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
   for (int y0 = 0; y0 < W; y0 += YB) {
     __syncthreads();  // every wave is done with the previous block
 #pragma unroll
-    for (int e = 0; e < PER; ++e) (&tile[0][0][0])[threadIdx.x + e * kThreads] = pre[e];
+    for (int e = 0; e < PER; ++e) {
+      const int i = threadIdx.x + e * kThreads;
+      const int zz = i % ZT, cr = i / ZT;
+      tile[cr / SEG][zz][cr % SEG] = pre[e];
+    }
     __syncthreads();
     if (y0 + YB < W) fetch(y0 + YB);
     if (active) {
@@ -571,7 +614,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_adj(const float2* __restr
   constexpr int ZT = kAdjZT, NA = kAdjNA, SEG = kAdjSeg;
   constexpr int PER = (NA * ZT * SEG) / kThreads;
   static_assert((NA * ZT * SEG) % kThreads == 0, "group must split evenly");
-  __shared__ float2 tile[NA][ZT][SEG];
+  __shared__ float2 tile[NA][ZT][SEG + 1];           // +1: spreads the staging writes over banks
   __shared__ int s_sl[2][NA];   // first staged bin per angle, by group parity
   const int W = g.W, H = g.H;
   // logical order: tile x fastest, then tile y, then slice block
@@ -593,18 +636,20 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_adj(const float2* __restr
     const double C = ap[kCos], Sn = ap[kSin];
     return (int)floor(g.cW + fmin(X0 * C, X1 * C) + fmin(Y0 * Sn, Y1 * Sn)) - 2;
   };
+  // The sinogram is z-blocked, S[k][z / ZT][bin][z % ZT]: the ZT slices of
+  // one bin are one contiguous 128-byte run.
   float2 pre[PER];
   auto fetch = [&](int k0, const int* sl) {
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int i = threadIdx.x + e * kThreads;
-      const int j = i % SEG, az = i / SEG;
-      const int zz = az % ZT, a = az / ZT;
+      const int zz = i % ZT, ja = i / ZT;
+      const int j = ja % SEG, a = ja / SEG;
       const int kk = k0 + a;
       float2 v = make_float2(0.f, 0.f);
       if (kk < K) {
         const int bin = sl[a] + j;
-        if (bin >= 0 && bin < W) v = S[(size_t)kk * HW + (size_t)(z0 + zz) * W + bin];
+        if (bin >= 0 && bin < W) v = S[(size_t)kk * HW + ((size_t)z0 * W) + (size_t)bin * ZT + zz];
       }
       pre[e] = v;
     }
@@ -622,7 +667,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_adj(const float2* __restr
     const int na = min(NA, K - k0);
     __syncthreads();  // every wave is done with the previous group
 #pragma unroll
-    for (int e = 0; e < PER; ++e) (&tile[0][0][0])[threadIdx.x + e * kThreads] = pre[e];
+    for (int e = 0; e < PER; ++e) {
+      const int i = threadIdx.x + e * kThreads;
+      const int zz = i % ZT, ja = i / ZT;
+      tile[ja / SEG][zz][ja % SEG] = pre[e];
+    }
     if ((int)threadIdx.x < NA && k0 + NA + (int)threadIdx.x < K)
       s_sl[par ^ 1][threadIdx.x] = first_bin(k0 + NA + threadIdx.x);
     __syncthreads();
@@ -657,18 +706,6 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_adj(const float2* __restr
   for (int i = 0; i < ZT; ++i) {
     gu[(size_t)(z0 + i) * WW + (size_t)y * W + x] = make_float2((float)ox[i], (float)oy[i]);
   }
-}
-
-// uT[z][x][y] = u[z][y][x]
-__global__ __launch_bounds__(kThreads) void k_transpose_xy(const float2* __restrict__ u,
-                                                           float2* __restrict__ uT, int W) {
-  __shared__ float2 tile[32][33];
-  const size_t zoff = (size_t)blockIdx.z * W * W;
-  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  for (int r = ty; r < 32; r += 8) tile[r][tx] = u[zoff + (size_t)(by + r) * W + bx + tx];
-  __syncthreads();
-  for (int r = ty; r < 32; r += 8) uT[zoff + (size_t)(bx + r) * W + by + tx] = tile[tx][r];
 }
 
 __global__ void k_fill_zero(float2* __restrict__ p, size_t n) {
@@ -778,16 +815,16 @@ hipError_t launch_pass_c(const DevGeom& g, float2* X, const float2* psi, const f
 
 hipError_t launch_pass_d(const DevGeom& g, const float2* X, const float2* psi, float2* S,
                          int k_first, int Kc, hipStream_t st) {
-  const dim3 grid((g.H * g.W + kThreads - 1) / kThreads, Kc);
+  const dim3 grid((g.H / kAdjZT) * (g.W / (kThreads / kAdjZT)), Kc);
   k_pass_d<<<grid, kThreads, 0, st>>>(X, psi, S, g, k_first);
   return hipGetLastError();
 }
 
-hipError_t launch_radon_fwd(const DevGeom& g, const float2* u, const float2* uT, float2* psi,
+hipError_t launch_radon_fwd(const DevGeom& g, const float2* ub, const float2* uTb, float2* psi,
                             const double* ang, const int2* groups, int g0, int ngroups, int c0,
                             int c1, hipStream_t st) {
   const unsigned n = (unsigned)(g.W / 64) * (unsigned)(g.H / kFwdZT) * (unsigned)ngroups;
-  k_radon_fwd<<<n, kThreads, 0, st>>>(u, uT, psi, g, ang, groups, g0, ngroups, c0, c1);
+  k_radon_fwd<<<n, kThreads, 0, st>>>(ub, uTb, psi, g, ang, groups, g0, ngroups, c0, c1);
   return hipGetLastError();
 }
 
@@ -798,9 +835,10 @@ hipError_t launch_radon_adj(const DevGeom& g, const float2* S, float2* gu, const
   return hipGetLastError();
 }
 
-hipError_t launch_transpose_xy(const DevGeom& g, const float2* u, float2* uT, hipStream_t st) {
-  const dim3 grid(g.W / 32, g.W / 32, g.H);
-  k_transpose_xy<<<grid, kThreads, 0, st>>>(u, uT, g.W);
+hipError_t launch_block_volume(const DevGeom& g, const float2* u, float2* ub, float2* uTb,
+                               hipStream_t st) {
+  const dim3 grid((g.W / 16) * (g.W / 16), g.H / kFwdZT);
+  k_block_volume<<<grid, kThreads, 0, st>>>(u, ub, uTb, g.W);
   return hipGetLastError();
 }
 
