@@ -262,12 +262,13 @@ __global__ __launch_bounds__(kThreads) void k_rows_prop(PropJobs jobs, DevGeom g
 // Column kernels (lines of length H along the detector rows)
 // ---------------------------------------------------------------------------
 
+template <int NT>
 __device__ __forceinline__ void block_sum_store(double v, double* out) {
-  __shared__ double red[kThreads];
+  __shared__ double red[NT];
   red[threadIdx.x] = v;
   __syncthreads();
 #pragma unroll
-  for (int o = kThreads / 2; o > 0; o >>= 1) {
+  for (int o = NT / 2; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
@@ -283,53 +284,71 @@ __device__ __forceinline__ double residual(float2& v, float a) {
   return d * d;
 }
 
+// Column workgroups are 512 threads (8 waves) so that two of them per CU
+// keep 16 waves in flight with the column tile in LDS.  The tile order is
+// remapped per XCD: neighbouring column tiles (the two halves of a cache
+// line) are read and written through the same L2.
+constexpr int kColThreads = 512;
+
+// The dispatcher hands workgroup h of a 1-D grid to XCD h mod 8.  Remap so
+// that each XCD walks a contiguous range of logical indices: neighbours in
+// logical order then share that XCD's L2.
+__device__ __forceinline__ int xcd_logical(int h, int n) {
+  const int q = n >> 3, r = n & 7;
+  const int x = h & 7, loc = h >> 3;
+  return x * q + min(x, r) + loc;
+}
+
 template <int H, int MODE>
-__global__ __launch_bounds__(kThreads) void k_pass_b(const float2* __restrict__ src,
-                                                     float2* __restrict__ X,
-                                                     const float* __restrict__ amp,
-                                                     double* __restrict__ Fpart, DevGeom g) {
-  constexpr int TC = cols_tc(H), TLc = kThreads / TC;
+__global__ __launch_bounds__(kColThreads) void k_pass_b(const float2* __restrict__ src,
+                                                        float2* __restrict__ X,
+                                                        const float* __restrict__ amp,
+                                                        double* __restrict__ Fpart, DevGeom g,
+                                                        int ntiles) {
+  constexpr int TC = cols_tc(H), TLc = kColThreads / TC;
   __shared__ float2 s_tw[H];
   __shared__ float2 s_col[TC][H + 1];
   const int c = threadIdx.x / TLc, lt = threadIdx.x % TLc;
   const int W = g.W;
-  const int s0 = blockIdx.x * TC;
-  const int f = blockIdx.y;
+  const int L = xcd_logical(blockIdx.x, gridDim.x);
+  const int tile = L % ntiles;
+  const int s0 = tile * TC;
+  const int f = L / ntiles;
   const int j = f % g.nd;
-  for (int i = threadIdx.x; i < H; i += kThreads) s_tw[i] = g.twH[i];
+  for (int i = threadIdx.x; i < H; i += kColThreads) s_tw[i] = g.twH[i];
   const float2* in = (MODE == kColAdj ? src : X) + (size_t)f * H * W + s0;
-  for (int i = threadIdx.x; i < H * TC; i += kThreads) {
+  for (int i = threadIdx.x; i < H * TC; i += kColThreads) {
     const int zz = i / TC, cc = i % TC;
     s_col[cc][zz] = in[(size_t)zz * W + cc];
   }
-  float2* L = s_col[c];
+  float2* Lc = s_col[c];
   const float2* ch = g.chirpH + (size_t)chirp_det(j) * H;
   if (MODE != kColAdj) {
-    fft<H, TLc, false>(L, s_tw, lt);
-    for (int zz = lt; zz < H; zz += TLc) L[zz] = cmul(L[zz], ch[zz]);
-    fft<H, TLc, true>(L, s_tw, lt);
+    fft<H, TLc, false>(Lc, s_tw, lt);
+    for (int zz = lt; zz < H; zz += TLc) Lc[zz] = cmul(Lc[zz], ch[zz]);
+    fft<H, TLc, true>(Lc, s_tw, lt);
     __syncthreads();
   }
   if (MODE == kColObj || MODE == kColGrad) {
     double acc = 0.0;
     const float* a = amp + (size_t)f * H * W + s0;
-    for (int i = threadIdx.x; i < H * TC; i += kThreads) {
+    for (int i = threadIdx.x; i < H * TC; i += kColThreads) {
       const int zz = i / TC, cc = i % TC;
       float2 v = s_col[cc][zz];
       acc += residual(v, a[(size_t)zz * W + cc]);
       s_col[cc][zz] = v;
     }
-    block_sum_store(acc, Fpart + (size_t)f * gridDim.x + blockIdx.x);
+    block_sum_store<kColThreads>(acc, Fpart + (size_t)f * ntiles + tile);
   }
   if (MODE == kColGrad || MODE == kColAdj) {
-    fft<H, TLc, false>(L, s_tw, lt);
-    for (int zz = lt; zz < H; zz += TLc) L[zz] = cmulc(L[zz], ch[zz]);
-    fft<H, TLc, true>(L, s_tw, lt);
+    fft<H, TLc, false>(Lc, s_tw, lt);
+    for (int zz = lt; zz < H; zz += TLc) Lc[zz] = cmulc(Lc[zz], ch[zz]);
+    fft<H, TLc, true>(Lc, s_tw, lt);
     __syncthreads();
   }
   if (MODE != kColObj) {
     float2* out = X + (size_t)f * H * W + s0;
-    for (int i = threadIdx.x; i < H * TC; i += kThreads) {
+    for (int i = threadIdx.x; i < H * TC; i += kColThreads) {
       const int zz = i / TC, cc = i % TC;
       out[(size_t)zz * W + cc] = s_col[cc][zz];
     }
@@ -337,18 +356,18 @@ __global__ __launch_bounds__(kThreads) void k_pass_b(const float2* __restrict__ 
 }
 
 template <int H>
-__global__ __launch_bounds__(kThreads) void k_cols_prop(PropJobs jobs, double* __restrict__ Fpart,
-                                                        DevGeom g) {
-  constexpr int TC = cols_tc(H), TLc = kThreads / TC;
+__global__ __launch_bounds__(kColThreads) void k_cols_prop(PropJobs jobs, double* __restrict__ Fpart,
+                                                           DevGeom g) {
+  constexpr int TC = cols_tc(H), TLc = kColThreads / TC;
   __shared__ float2 s_tw[H];
   __shared__ float2 s_col[TC][H + 1];
   const int c = threadIdx.x / TLc, lt = threadIdx.x % TLc;
   const int W = g.W;
   const int s0 = blockIdx.x * TC;
   const PropJob& jb = jobs.job[blockIdx.y];
-  for (int i = threadIdx.x; i < H; i += kThreads) s_tw[i] = g.twH[i];
+  for (int i = threadIdx.x; i < H; i += kColThreads) s_tw[i] = g.twH[i];
   const float2* in = jb.src + s0;
-  for (int i = threadIdx.x; i < H * TC; i += kThreads) {
+  for (int i = threadIdx.x; i < H * TC; i += kColThreads) {
     const int zz = i / TC, cc = i % TC;
     s_col[cc][zz] = in[(size_t)zz * W + cc];
   }
@@ -361,17 +380,17 @@ __global__ __launch_bounds__(kThreads) void k_cols_prop(PropJobs jobs, double* _
   if (jb.amp) {
     double acc = 0.0;
     const float* a = jb.amp + s0;
-    for (int i = threadIdx.x; i < H * TC; i += kThreads) {
+    for (int i = threadIdx.x; i < H * TC; i += kColThreads) {
       const int zz = i / TC, cc = i % TC;
       float2 v = s_col[cc][zz];
       acc += residual(v, a[(size_t)zz * W + cc]);
       s_col[cc][zz] = v;
     }
-    block_sum_store(acc, Fpart + (size_t)jb.fslot * gridDim.x + blockIdx.x);
+    block_sum_store<kColThreads>(acc, Fpart + (size_t)jb.fslot * gridDim.x + blockIdx.x);
     __syncthreads();
   }
   float2* out = jb.dst + s0;
-  for (int i = threadIdx.x; i < H * TC; i += kThreads) {
+  for (int i = threadIdx.x; i < H * TC; i += kColThreads) {
     const int zz = i / TC, cc = i % TC;
     out[(size_t)zz * W + cc] = s_col[cc][zz];
   }
@@ -458,15 +477,6 @@ __global__ __launch_bounds__(kThreads) void k_block_volume(const float2* __restr
 // ---------------------------------------------------------------------------
 // Joseph ray sums and their transpose
 // ---------------------------------------------------------------------------
-
-// The dispatcher hands workgroup h of a 1-D grid to XCD h mod 8.  Remap so
-// that each XCD walks a contiguous range of logical indices: neighbours in
-// logical order then share that XCD's L2.
-__device__ __forceinline__ int xcd_logical(int h, int n) {
-  const int q = n >> 3, r = n & 7;
-  const int x = h & 7, loc = h >> 3;
-  return x * q + min(x, r) + loc;
-}
 
 // Forward.  A workgroup owns up to kFwdNA consecutive angles of one walk
 // direction (one wave per angle), 64 consecutive bins (one per lane) and
@@ -734,7 +744,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce_sum(const double* __restric
                                                          double* __restrict__ out) {
   double acc = 0.0;
   for (size_t i = threadIdx.x; i < n; i += kThreads) acc += parts[i];
-  block_sum_store(acc, out);
+  block_sum_store<kThreads>(acc, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -759,7 +769,7 @@ hipError_t launch_cols_prop(const DevGeom& g, const PropJobs& jobs, double* Fpar
   if (jobs.n == 0) return hipSuccess;
   const dim3 grid(g.W / cols_per_wg(g.H), jobs.n);
   switch (g.H) {
-#define CASE(N) case N: k_cols_prop<N><<<grid, kThreads, 0, st>>>(jobs, Fpart, g); break;
+#define CASE(N) case N: k_cols_prop<N><<<grid, kColThreads, 0, st>>>(jobs, Fpart, g); break;
     HOLO_FOR_SIZES(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -781,17 +791,26 @@ hipError_t launch_pass_a(const DevGeom& g, const float2* psi, const float2* Q, f
 
 hipError_t launch_pass_b(const DevGeom& g, int mode, const float2* src, float2* X,
                          const float* amp, double* Fpart, int Kc, hipStream_t st) {
-  const dim3 grid(g.W / cols_per_wg(g.H), Kc * g.nd);
+  const int ntiles = g.W / cols_per_wg(g.H);
+  const unsigned grid = (unsigned)ntiles * (unsigned)(Kc * g.nd);
   switch (g.H) {
-#define CASE(N)                                                                               \
-  case N:                                                                                     \
-    switch (mode) {                                                                           \
-      case kColFwd: k_pass_b<N, kColFwd><<<grid, kThreads, 0, st>>>(src, X, amp, Fpart, g); break; \
-      case kColObj: k_pass_b<N, kColObj><<<grid, kThreads, 0, st>>>(src, X, amp, Fpart, g); break; \
-      case kColGrad: k_pass_b<N, kColGrad><<<grid, kThreads, 0, st>>>(src, X, amp, Fpart, g); break; \
-      case kColAdj: k_pass_b<N, kColAdj><<<grid, kThreads, 0, st>>>(src, X, amp, Fpart, g); break; \
-      default: return hipErrorInvalidValue;                                                   \
-    }                                                                                         \
+#define CASE(N)                                                                                 \
+  case N:                                                                                       \
+    switch (mode) {                                                                             \
+      case kColFwd:                                                                             \
+        k_pass_b<N, kColFwd><<<grid, kColThreads, 0, st>>>(src, X, amp, Fpart, g, ntiles);      \
+        break;                                                                                  \
+      case kColObj:                                                                             \
+        k_pass_b<N, kColObj><<<grid, kColThreads, 0, st>>>(src, X, amp, Fpart, g, ntiles);      \
+        break;                                                                                  \
+      case kColGrad:                                                                            \
+        k_pass_b<N, kColGrad><<<grid, kColThreads, 0, st>>>(src, X, amp, Fpart, g, ntiles);     \
+        break;                                                                                  \
+      case kColAdj:                                                                             \
+        k_pass_b<N, kColAdj><<<grid, kColThreads, 0, st>>>(src, X, amp, Fpart, g, ntiles);      \
+        break;                                                                                  \
+      default: return hipErrorInvalidValue;                                                     \
+    }                                                                                           \
     break;
     HOLO_FOR_SIZES(CASE)
 #undef CASE

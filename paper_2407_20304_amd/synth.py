@@ -217,12 +217,17 @@ def synthetic_amplitudes(n_angles: int, n_dist: int, H: int, W: int, seed: int,
     x = torch.arange(W, dtype=torch.float32, device=device)[None, :]
     env = torch.exp(-((x - W / 2) ** 2) / (2 * (0.375 * W) ** 2)
                     - ((y - H / 2) ** 2) / (2 * (0.375 * H) ** 2))
-    for k in range(n_angles):
-        for j in range(n_dist):
-            arg = 2 * math.pi * (float(fy[k, j]) * y / H + float(fx[k, j]) * x / W) + float(ph[k, j])
-            inten = env * (1.0 + 0.2 * torch.sin(arg))
-            counts = torch.poisson(photons * inten, generator=gen)
-            out[k, j] = torch.sqrt(counts / photons)
+    # blocks of frames at a time (a few hundred MB of temporaries)
+    per = max(1, (1 << 26) // (n_dist * H * W))
+    for k0 in range(0, n_angles, per):
+        k1 = min(n_angles, k0 + per)
+        cy = torch.tensor(fy[k0:k1], dtype=torch.float32, device=device)[:, :, None, None]
+        cx = torch.tensor(fx[k0:k1], dtype=torch.float32, device=device)[:, :, None, None]
+        cp = torch.tensor(ph[k0:k1], dtype=torch.float32, device=device)[:, :, None, None]
+        arg = 2 * math.pi * (cy * (y / H) + cx * (x / W)) + cp
+        inten = env * (1.0 + 0.2 * torch.sin(arg))
+        counts = torch.poisson(photons * inten, generator=gen)
+        out[k0:k1] = torch.sqrt(counts / photons)
     return out
 
 
