@@ -67,7 +67,7 @@ bool fft_size_supported(int n);
 // thread, staged rows per block and staged columns per row; transpose
 // slices per thread, angles per staged group and bins per staged segment.
 constexpr int kFwdNA = 4, kFwdZT = 16, kFwdYB = 2, kFwdSeg = 112;
-constexpr int kAdjZT = 16, kAdjNA = 8, kAdjSeg = 28;
+constexpr int kAdjZT = 16, kAdjNA = 8, kAdjSeg = 32;
 // Largest detector edge (the forward kernel keeps one window start per row).
 constexpr int kMaxW = 2048;
 

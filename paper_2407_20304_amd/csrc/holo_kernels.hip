@@ -613,55 +613,79 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
 // kAdjNA: it stages, for each angle of the group, the kAdjSeg bins that the
 // tile projects onto, then every thread gathers its two taps per slice from
 // LDS.  The next group's segments are loaded into registers while the
-// current group is consumed.  A voxel projecting to fractional bin q takes
+// current group is consumed; the loads are unconditional (addresses clamped
+// into the sinogram, out-of-range bins zeroed when staged) so that they all
+// stay in flight together.  A voxel projecting to fractional bin q takes
 // max(0, 1 - |i - q| / h) / h of bin i (h = max(|cos|, |sin|)) -- exactly
-// the weight Joseph's interpolation gave it.  Bins outside the detector are
-// staged as zeros.
+// the weight Joseph's interpolation gave it.
 __global__ __launch_bounds__(kThreads, 2) void k_radon_adj(const float2* __restrict__ S,
                                                          float2* __restrict__ gu, DevGeom g,
                                                          const double* __restrict__ ang,
                                                          int K) {
-  constexpr int ZT = kAdjZT, NA = kAdjNA, SEG = kAdjSeg;
-  constexpr int PER = (NA * ZT * SEG) / kThreads;
-  static_assert((NA * ZT * SEG) % kThreads == 0, "group must split evenly");
+  constexpr int ZT = kAdjZT, NA = kAdjNA, SEG = kAdjSeg, TW = kThreads;
+  constexpr int TPB = kThreads / ZT;                // bins one pass of the workgroup covers
+  constexpr int PER = NA * SEG / TPB;               // staged elements per thread per group
+  static_assert(SEG % TPB == 0 && TW % NA == 0 && PER <= 32, "staging layout");
   __shared__ float2 tile[NA][ZT][SEG + 1];           // +1: spreads the staging writes over banks
-  __shared__ int s_sl[2][NA];   // first staged bin per angle, by group parity
+  // Per-angle set-up for a window of TW angles, double-buffered by window
+  // parity: first staged bin, fractional bin of the tile corner relative to
+  // it, cos, sin and 1/h.
+  __shared__ int s_sl[2][TW];
+  __shared__ float s_f0[2][TW], s_c[2][TW], s_s[2][TW], s_ih[2][TW];
   const int W = g.W, H = g.H;
   // logical order: tile x fastest, then tile y, then slice block
   const int L = xcd_logical(blockIdx.x, gridDim.x);
   const int nt = W / 16;
   const int x0 = (L % nt) * 16, y0 = ((L / nt) % nt) * 16;
-  const int x = x0 + (threadIdx.x & 15);
-  const int y = y0 + (threadIdx.x >> 4);
+  const int dx = threadIdx.x & 15, dy = threadIdx.x >> 4;
+  const int x = x0 + dx, y = y0 + dy;
   const int z0 = (L / (nt * nt)) * ZT;
-  const double X = (double)x - g.cW, Y = (double)y - g.cW;
   const double X0 = (double)x0 - g.cW, X1 = X0 + 15.0;
   const double Y0 = (double)y0 - g.cW, Y1 = Y0 + 15.0;
   const size_t HW = (size_t)H * W;
 
-  // first staged bin of angle kk: lowest projection of the tile's corners
-  // minus two bins of margin for rounding
-  auto first_bin = [&](int kk) {
-    const double* ap = ang + (size_t)kk * kAngleStride;
-    const double C = ap[kCos], Sn = ap[kSin];
-    return (int)floor(g.cW + fmin(X0 * C, X1 * C) + fmin(Y0 * Sn, Y1 * Sn)) - 2;
+  // Set-up of angle w * TW + threadIdx.x, in double precision: the first
+  // staged bin is the lowest projection of the tile's corners minus two bins
+  // of margin; a voxel's fractional bin relative to it is
+  // f0 + dx cos + dy sin, a small number that single precision holds to
+  // ~1e-6 of a bin.  Angles past the end get a segment wholly off the
+  // detector.
+  auto setup_window = [&](int w) {
+    const int slot = w & 1, t = threadIdx.x, kk = w * TW + t;
+    if (kk < K) {
+      const double* ap = ang + (size_t)kk * kAngleStride;
+      const double C = ap[kCos], Sn = ap[kSin];
+      const double q0 = g.cW + X0 * C + Y0 * Sn;
+      const int sl = (int)floor(g.cW + fmin(X0 * C, X1 * C) + fmin(Y0 * Sn, Y1 * Sn)) - 2;
+      s_sl[slot][t] = sl;
+      s_f0[slot][t] = (float)(q0 - (double)sl);
+      s_c[slot][t] = (float)C;
+      s_s[slot][t] = (float)Sn;
+      s_ih[slot][t] = (float)ap[kInvH];
+    } else {
+      s_sl[slot][t] = -2 * SEG;
+      s_f0[slot][t] = s_c[slot][t] = s_s[slot][t] = s_ih[slot][t] = 0.f;
+    }
   };
   // The sinogram is z-blocked, S[k][z / ZT][bin][z % ZT]: the ZT slices of
-  // one bin are one contiguous 128-byte run.
+  // one bin are one contiguous 128-byte run.  Element e of a thread is bin
+  // (TPB e) % SEG + threadIdx.x / ZT of angle (TPB e) / SEG of the group.
+  const int zz = threadIdx.x % ZT, tb = threadIdx.x / ZT;
+  const float2* Sz = S + (size_t)z0 * W + zz;
   float2 pre[PER];
-  auto fetch = [&](int k0, const int* sl) {
+  unsigned valid = 0u;
+  auto fetch = [&](int k0) {
+    const int slot = (k0 / TW) & 1, base = k0 % TW;
+    valid = 0u;
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
-      const int i = threadIdx.x + e * kThreads;
-      const int zz = i % ZT, ja = i / ZT;
-      const int j = ja % SEG, a = ja / SEG;
+      const int a = (TPB * e) / SEG, j = (TPB * e) % SEG + tb;
       const int kk = k0 + a;
-      float2 v = make_float2(0.f, 0.f);
-      if (kk < K) {
-        const int bin = sl[a] + j;
-        if (bin >= 0 && bin < W) v = S[(size_t)kk * HW + ((size_t)z0 * W) + (size_t)bin * ZT + zz];
-      }
-      pre[e] = v;
+      const int bin = s_sl[slot][base + a] + j;
+      const bool ok = kk < K && bin >= 0 && bin < W;
+      const int kc = min(kk, K - 1), bc = min(max(bin, 0), W - 1);
+      pre[e] = Sz[(size_t)kc * HW + (size_t)bc * ZT];
+      valid |= ok ? (1u << e) : 0u;
     }
   };
 
@@ -670,32 +694,33 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_adj(const float2* __restr
 #pragma unroll
   for (int i = 0; i < ZT; ++i) { ax[i] = ay[i] = 0.f; ox[i] = oy[i] = 0.0; }
 
-  if ((int)threadIdx.x < NA && (int)threadIdx.x < K) s_sl[0][threadIdx.x] = first_bin(threadIdx.x);
+  setup_window(0);
   __syncthreads();
-  fetch(0, s_sl[0]);
-  for (int k0 = 0, par = 0; k0 < K; k0 += NA, par ^= 1) {
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += NA) {
     const int na = min(NA, K - k0);
     __syncthreads();  // every wave is done with the previous group
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
-      const int i = threadIdx.x + e * kThreads;
-      const int zz = i % ZT, ja = i / ZT;
-      tile[ja / SEG][zz][ja % SEG] = pre[e];
+      const int a = (TPB * e) / SEG, j = (TPB * e) % SEG + tb;
+      tile[a][zz][j] = ((valid >> e) & 1u) ? pre[e] : make_float2(0.f, 0.f);
     }
-    if ((int)threadIdx.x < NA && k0 + NA + (int)threadIdx.x < K)
-      s_sl[par ^ 1][threadIdx.x] = first_bin(k0 + NA + threadIdx.x);
+    const int kn = k0 + NA;
+    // the window of the next group's angles, into the slot of the window
+    // before the current one (no longer read)
+    if (kn < K && kn % TW == 0) setup_window(kn / TW);
     __syncthreads();
-    if (k0 + NA < K) fetch(k0 + NA, s_sl[par ^ 1]);
-    const int* sl = s_sl[par];
+    if (kn < K) fetch(kn);
+    const int slot = (k0 / TW) & 1, base = k0 % TW;
     for (int a = 0; a < na; ++a) {
-      const double* ap = ang + (size_t)(k0 + a) * kAngleStride;
-      const double invh = ap[kInvH];
-      const double q = g.cW + X * ap[kCos] + Y * ap[kSin];
-      const double fl = floor(q);
-      const double fr = q - fl;
-      const float w0 = (float)(fmax(0.0, 1.0 - fr * invh) * invh);
-      const float w1 = (float)(fmax(0.0, 1.0 - (1.0 - fr) * invh) * invh);
-      int j0 = (int)fl - sl[a];
+      const float invh = s_ih[slot][base + a];
+      const float qr = fmaf((float)dy, s_s[slot][base + a],
+                            fmaf((float)dx, s_c[slot][base + a], s_f0[slot][base + a]));
+      const float fl = floorf(qr);
+      const float fr = qr - fl;
+      const float w0 = fmaxf(0.0f, fmaf(-fr, invh, 1.0f)) * invh;
+      const float w1 = fmaxf(0.0f, fmaf(fr - 1.0f, invh, 1.0f)) * invh;
+      int j0 = (int)fl;
       j0 = min(max(j0, 0), SEG - 2);
 #pragma unroll
       for (int i = 0; i < ZT; ++i) {
@@ -704,11 +729,14 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_adj(const float2* __restr
         ay[i] = fmaf(w1, v1.y, fmaf(w0, v0.y, ay[i]));
       }
     }
+    // single-precision partial sums of up to 2 NA angles, flushed to double
+    if (((k0 / NA) & 1) == 1 || kn >= K) {
 #pragma unroll
-    for (int i = 0; i < ZT; ++i) {
-      ox[i] += (double)ax[i];
-      oy[i] += (double)ay[i];
-      ax[i] = ay[i] = 0.f;
+      for (int i = 0; i < ZT; ++i) {
+        ox[i] += (double)ax[i];
+        oy[i] += (double)ay[i];
+        ax[i] = ay[i] = 0.f;
+      }
     }
   }
   const size_t WW = (size_t)W * W;
