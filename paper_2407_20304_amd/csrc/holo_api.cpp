@@ -231,7 +231,8 @@ extern "C" holo_status holo_plan_create(const holo_geom* geom, holo_plan** out) 
     P->off_uTb = o; o = align_up(o + (P->any_xwalk ? fr * P->W : 0));
     P->off_psi = o; o = align_up(o + fr * P->chunk);
     P->off_X = o;   o = align_up(o + fr * P->chunk * P->nd);
-    P->off_S = o;   o = align_up(o + fr * P->n_angles);
+    // sinogram rows carry kAdjPad zero bins on each side
+    P->off_S = o;   o = align_up(o + (size_t)P->H * sino_row(P->W) * sizeof(float2) * P->n_angles);
     const size_t tiles = (size_t)P->W / cols_per_wg(P->H);
     P->n_fpart = tiles * (1 + (size_t)P->n_angles * P->nd);
     P->off_F = o;   o = align_up(o + P->n_fpart * sizeof(double));
@@ -505,7 +506,7 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
       }));
       if (want_gu)
         HOLO_HIP(timed(P, HOLO_K_PASS_D, st, [&] {
-          return launch_pass_d(g, X, psi, S + (size_t)(c0 - k0) * HW, c0, Kc, st);
+          return launch_pass_d(g, X, psi, S + (size_t)(c0 - k0) * H * sino_row(W), c0, Kc, st);
         }));
     }
   }

@@ -68,6 +68,11 @@ bool fft_size_supported(int n);
 // slices per thread, angles per staged group and bins per staged segment.
 constexpr int kFwdNA = 4, kFwdZT = 16, kFwdYB = 2, kFwdSeg = 112;
 constexpr int kAdjZT = 16, kAdjNA = 8, kAdjSeg = 32;
+// Zero bins on each side of every sinogram row read by the transpose: a
+// staged segment is then always valid memory (segments wholly off the
+// detector are moved into the padding, which reads as zeros).
+constexpr int kAdjPad = kAdjSeg;
+inline __host__ __device__ int sino_row(int W) { return W + 2 * kAdjPad; }
 // Largest detector edge (the forward kernel keeps one window start per row).
 constexpr int kMaxW = 2048;
 

@@ -405,16 +405,23 @@ __global__ __launch_bounds__(kThreads) void k_pass_d(const float2* __restrict__ 
                                                      const float2* __restrict__ psi,
                                                      float2* __restrict__ S, DevGeom g,
                                                      int k_first) {
-  // a workgroup covers kAdjZT rows x (256 / kAdjZT) columns; consecutive
+  // A workgroup covers kAdjZT rows x (256 / kAdjZT) padded bins; consecutive
   // threads take consecutive rows so that the z-blocked output
-  // S[k][z / kAdjZT][s][z % kAdjZT] is written in contiguous runs
+  // S[k][z / kAdjZT][kAdjPad + s][z % kAdjZT] is written in contiguous runs.
+  // Workgroups over the padding write its zeros.
   constexpr int ZT = kAdjZT, SC = kThreads / ZT;
-  const int H = g.H, W = g.W;
+  const int H = g.H, W = g.W, Wp = sino_row(W);
   const int zz = threadIdx.x % ZT;
-  const int nsb = W / SC;
+  const int nsb = Wp / SC;
   const int z0 = (blockIdx.x / nsb) * ZT;
-  const int z = z0 + zz, s = (blockIdx.x % nsb) * SC + threadIdx.x / ZT;
+  const int z = z0 + zz, sp = (blockIdx.x % nsb) * SC + threadIdx.x / ZT;
+  const int s = sp - kAdjPad;
   const int k = blockIdx.y;
+  float2* out = S + (size_t)k * H * Wp + (size_t)z0 * Wp + (size_t)sp * ZT + zz;
+  if (s < 0 || s >= W) {
+    *out = make_float2(0.f, 0.f);
+    return;
+  }
   float ax = 0.f, ay = 0.f;
   for (int j = 0; j < g.nd; ++j) {
     double ty, tx;
@@ -441,8 +448,7 @@ __global__ __launch_bounds__(kThreads) void k_pass_d(const float2* __restrict__ 
   const float cx = ps.x * ax + ps.y * ay;
   const float cy = ps.x * ay - ps.y * ax;
   // -i kappa (cx + i cy) = kappa cy - i kappa cx
-  S[(size_t)k * H * W + (size_t)z0 * W + (size_t)s * ZT + zz] =
-      make_float2(g.kappa * cy, -g.kappa * cx);
+  *out = make_float2(g.kappa * cy, -g.kappa * cx);
 }
 
 // Z-blocked copies of the volume for the ray sums: ub[z / ZT][y][x][z % ZT]
@@ -613,26 +619,28 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
 // kAdjNA: it stages, for each angle of the group, the kAdjSeg bins that the
 // tile projects onto, then every thread gathers its two taps per slice from
 // LDS.  The next group's segments are loaded into registers while the
-// current group is consumed; the loads are unconditional (addresses clamped
-// into the sinogram, out-of-range bins zeroed when staged) so that they all
-// stay in flight together.  A voxel projecting to fractional bin q takes
-// max(0, 1 - |i - q| / h) / h of bin i (h = max(|cos|, |sin|)) -- exactly
-// the weight Joseph's interpolation gave it.
+// current group is consumed.  Sinogram rows are zero-padded by kAdjPad bins,
+// so a segment is read without bounds checks from a wave-uniform base.  A
+// voxel projecting to fractional bin q takes max(0, 1 - |i - q| / h) / h of
+// bin i (h = max(|cos|, |sin|)) -- exactly the weight Joseph's interpolation
+// gave it.
 __global__ __launch_bounds__(kThreads, 2) void k_radon_adj(const float2* __restrict__ S,
                                                          float2* __restrict__ gu, DevGeom g,
                                                          const double* __restrict__ ang,
                                                          int K) {
-  constexpr int ZT = kAdjZT, NA = kAdjNA, SEG = kAdjSeg, TW = kThreads;
+  constexpr int ZT = kAdjZT, NA = kAdjNA, SEG = kAdjSeg, TW = kThreads, BP = ZT + 1;
   constexpr int TPB = kThreads / ZT;                // bins one pass of the workgroup covers
   constexpr int PER = NA * SEG / TPB;               // staged elements per thread per group
-  static_assert(SEG % TPB == 0 && TW % NA == 0 && PER <= 32, "staging layout");
-  __shared__ float2 tile[NA][ZT][SEG + 1];           // +1: spreads the staging writes over banks
+  static_assert(SEG % TPB == 0 && TW % NA == 0 && kAdjPad >= SEG, "staging layout");
+  // tile[a][bin][slice], slices fastest; the odd pitch (ZT + 1) puts the
+  // different bins that the lanes of a wave read on different banks
+  __shared__ float2 tile[NA * SEG * BP];
   // Per-angle set-up for a window of TW angles, double-buffered by window
   // parity: first staged bin, fractional bin of the tile corner relative to
-  // it, cos, sin and 1/h.
+  // it, cos, sin, 1/h and 1/h^2.
   __shared__ int s_sl[2][TW];
-  __shared__ float s_f0[2][TW], s_c[2][TW], s_s[2][TW], s_ih[2][TW];
-  const int W = g.W, H = g.H;
+  __shared__ float s_f0[2][TW], s_c[2][TW], s_s[2][TW], s_ih[2][TW], s_ih2[2][TW];
+  const int W = g.W, H = g.H, Wp = sino_row(W);
   // logical order: tile x fastest, then tile y, then slice block
   const int L = xcd_logical(blockIdx.x, gridDim.x);
   const int nt = W / 16;
@@ -642,51 +650,47 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_adj(const float2* __restr
   const int z0 = (L / (nt * nt)) * ZT;
   const double X0 = (double)x0 - g.cW, X1 = X0 + 15.0;
   const double Y0 = (double)y0 - g.cW, Y1 = Y0 + 15.0;
-  const size_t HW = (size_t)H * W;
 
   // Set-up of angle w * TW + threadIdx.x, in double precision: the first
   // staged bin is the lowest projection of the tile's corners minus two bins
-  // of margin; a voxel's fractional bin relative to it is
+  // of margin, moved into [-kAdjPad, W + kAdjPad - SEG] (a segment outside
+  // that range lies wholly off the detector, and the padding it is moved to
+  // holds zeros); a voxel's fractional bin relative to it is
   // f0 + dx cos + dy sin, a small number that single precision holds to
-  // ~1e-6 of a bin.  Angles past the end get a segment wholly off the
-  // detector.
+  // ~1e-6 of a bin.
   auto setup_window = [&](int w) {
-    const int slot = w & 1, t = threadIdx.x, kk = w * TW + t;
-    if (kk < K) {
-      const double* ap = ang + (size_t)kk * kAngleStride;
-      const double C = ap[kCos], Sn = ap[kSin];
-      const double q0 = g.cW + X0 * C + Y0 * Sn;
-      const int sl = (int)floor(g.cW + fmin(X0 * C, X1 * C) + fmin(Y0 * Sn, Y1 * Sn)) - 2;
-      s_sl[slot][t] = sl;
-      s_f0[slot][t] = (float)(q0 - (double)sl);
-      s_c[slot][t] = (float)C;
-      s_s[slot][t] = (float)Sn;
-      s_ih[slot][t] = (float)ap[kInvH];
-    } else {
-      s_sl[slot][t] = -2 * SEG;
-      s_f0[slot][t] = s_c[slot][t] = s_s[slot][t] = s_ih[slot][t] = 0.f;
-    }
+    const int slot = w & 1, t = threadIdx.x, kk = min(w * TW + t, K - 1);
+    const double* ap = ang + (size_t)kk * kAngleStride;
+    const double C = ap[kCos], Sn = ap[kSin], ih = ap[kInvH];
+    const double q0 = g.cW + X0 * C + Y0 * Sn;
+    int sl = (int)floor(g.cW + fmin(X0 * C, X1 * C) + fmin(Y0 * Sn, Y1 * Sn)) - 2;
+    sl = min(max(sl, -kAdjPad), W + kAdjPad - SEG);
+    s_sl[slot][t] = sl;
+    s_f0[slot][t] = (float)(q0 - (double)sl);
+    s_c[slot][t] = (float)C;
+    s_s[slot][t] = (float)Sn;
+    s_ih[slot][t] = (float)ih;
+    s_ih2[slot][t] = (float)(ih * ih);
   };
-  // The sinogram is z-blocked, S[k][z / ZT][bin][z % ZT]: the ZT slices of
-  // one bin are one contiguous 128-byte run.  Element e of a thread is bin
-  // (TPB e) % SEG + threadIdx.x / ZT of angle (TPB e) / SEG of the group.
-  const int zz = threadIdx.x % ZT, tb = threadIdx.x / ZT;
-  const float2* Sz = S + (size_t)z0 * W + zz;
+  // The sinogram is z-blocked and padded, S[k][z / ZT][kAdjPad + bin][z % ZT]:
+  // the ZT slices of one bin are one contiguous 128-byte run.  Element e of
+  // a thread is bin (TPB e) % SEG + threadIdx.x / ZT of angle (TPB e) / SEG
+  // of the group, i.e. float2 number threadIdx.x + ZT ((TPB e) % SEG) past
+  // the segment start of that angle.
+  const size_t HWp = (size_t)H * Wp;
+  const float2* Sz = S + (size_t)z0 * Wp + kAdjPad * ZT + threadIdx.x;
   float2 pre[PER];
-  unsigned valid = 0u;
   auto fetch = [&](int k0) {
     const int slot = (k0 / TW) & 1, base = k0 % TW;
-    valid = 0u;
+    const float2* seg[NA];
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int a = (TPB * e) / SEG, j = (TPB * e) % SEG + tb;
-      const int kk = k0 + a;
-      const int bin = s_sl[slot][base + a] + j;
-      const bool ok = kk < K && bin >= 0 && bin < W;
-      const int kc = min(kk, K - 1), bc = min(max(bin, 0), W - 1);
-      pre[e] = Sz[(size_t)kc * HW + (size_t)bc * ZT];
-      valid |= ok ? (1u << e) : 0u;
+    for (int a = 0; a < NA; ++a) {
+      const int kk = min(k0 + a, K - 1);                // past the end: never read back
+      const int sl = __builtin_amdgcn_readfirstlane(s_sl[slot][base + a]);
+      seg[a] = Sz + (size_t)kk * HWp + (ptrdiff_t)sl * ZT;
     }
+#pragma unroll
+    for (int e = 0; e < PER; ++e) pre[e] = seg[(TPB * e) / SEG][ZT * ((TPB * e) % SEG)];
   };
 
   float ax[ZT], ay[ZT];
@@ -694,6 +698,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_adj(const float2* __restr
 #pragma unroll
   for (int i = 0; i < ZT; ++i) { ax[i] = ay[i] = 0.f; ox[i] = oy[i] = 0.0; }
 
+  const int zz = threadIdx.x % ZT, tb = threadIdx.x / ZT;
+  float2* st = tile + tb * BP + zz;
   setup_window(0);
   __syncthreads();
   fetch(0);
@@ -702,8 +708,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_adj(const float2* __restr
     __syncthreads();  // every wave is done with the previous group
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
-      const int a = (TPB * e) / SEG, j = (TPB * e) % SEG + tb;
-      tile[a][zz][j] = ((valid >> e) & 1u) ? pre[e] : make_float2(0.f, 0.f);
+      const int a = (TPB * e) / SEG, j = (TPB * e) % SEG;
+      st[(a * SEG + j) * BP] = pre[e];
     }
     const int kn = k0 + NA;
     // the window of the next group's angles, into the slot of the window
@@ -713,24 +719,24 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_adj(const float2* __restr
     if (kn < K) fetch(kn);
     const int slot = (k0 / TW) & 1, base = k0 % TW;
     for (int a = 0; a < na; ++a) {
-      const float invh = s_ih[slot][base + a];
+      const float ih = s_ih[slot][base + a], ih2 = s_ih2[slot][base + a];
       const float qr = fmaf((float)dy, s_s[slot][base + a],
                             fmaf((float)dx, s_c[slot][base + a], s_f0[slot][base + a]));
       const float fl = floorf(qr);
       const float fr = qr - fl;
-      const float w0 = fmaxf(0.0f, fmaf(-fr, invh, 1.0f)) * invh;
-      const float w1 = fmaxf(0.0f, fmaf(fr - 1.0f, invh, 1.0f)) * invh;
-      int j0 = (int)fl;
-      j0 = min(max(j0, 0), SEG - 2);
+      const float w0 = fmaxf(0.0f, fmaf(-fr, ih2, ih));
+      const float w1 = fmaxf(0.0f, fmaf(fr - 1.0f, ih2, ih));
+      const int j0 = min(max((int)fl, 0), SEG - 2);
+      const float2* tp = tile + (a * SEG + j0) * BP;
 #pragma unroll
       for (int i = 0; i < ZT; ++i) {
-        const float2 v0 = tile[a][i][j0], v1 = tile[a][i][j0 + 1];
+        const float2 v0 = tp[i], v1 = tp[BP + i];
         ax[i] = fmaf(w1, v1.x, fmaf(w0, v0.x, ax[i]));
         ay[i] = fmaf(w1, v1.y, fmaf(w0, v0.y, ay[i]));
       }
     }
-    // single-precision partial sums of up to 2 NA angles, flushed to double
-    if (((k0 / NA) & 1) == 1 || kn >= K) {
+    // single-precision partial sums of up to 4 NA angles, flushed to double
+    if (((k0 / NA) & 3) == 3 || kn >= K) {
 #pragma unroll
       for (int i = 0; i < ZT; ++i) {
         ox[i] += (double)ax[i];
@@ -862,7 +868,7 @@ hipError_t launch_pass_c(const DevGeom& g, float2* X, const float2* psi, const f
 
 hipError_t launch_pass_d(const DevGeom& g, const float2* X, const float2* psi, float2* S,
                          int k_first, int Kc, hipStream_t st) {
-  const dim3 grid((g.H / kAdjZT) * (g.W / (kThreads / kAdjZT)), Kc);
+  const dim3 grid((g.H / kAdjZT) * (sino_row(g.W) / (kThreads / kAdjZT)), Kc);
   k_pass_d<<<grid, kThreads, 0, st>>>(X, psi, S, g, k_first);
   return hipGetLastError();
 }
