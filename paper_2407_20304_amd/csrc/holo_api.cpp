@@ -226,9 +226,11 @@ extern "C" holo_status holo_plan_create(const holo_geom* geom, holo_plan** out) 
     P->off_Q = o;   o = align_up(o + fr * P->nd);
     P->off_G = o;   o = align_up(o + fr * P->nd);
     P->off_P = o;   o = align_up(o + fr);
-    // z-blocked copies of the volume read by the ray sums (one per walk direction)
-    P->off_ub = o;  o = align_up(o + fr * P->W);
-    P->off_uTb = o; o = align_up(o + (P->any_xwalk ? fr * P->W : 0));
+    // z-blocked copies of the volume read by the ray sums (one per walk
+    // direction), rows padded by kFwdPad zero columns on each side
+    const size_t vb = (size_t)P->H * P->W * vol_row(P->W) * sizeof(float2);
+    P->off_ub = o;  o = align_up(o + vb);
+    P->off_uTb = o; o = align_up(o + (P->any_xwalk ? vb : 0));
     P->off_psi = o; o = align_up(o + fr * P->chunk);
     P->off_X = o;   o = align_up(o + fr * P->chunk * P->nd);
     // sinogram rows carry kAdjPad zero bins on each side

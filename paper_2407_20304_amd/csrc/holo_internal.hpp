@@ -73,6 +73,11 @@ constexpr int kAdjZT = 16, kAdjNA = 8, kAdjSeg = 32;
 // detector are moved into the padding, which reads as zeros).
 constexpr int kAdjPad = kAdjSeg;
 inline __host__ __device__ int sino_row(int W) { return W + 2 * kAdjPad; }
+// Zero columns on each side of every row of the forward's volume copies: a
+// staged row window is then always valid memory (windows wholly outside the
+// volume are moved into the padding, which reads as zeros).
+constexpr int kFwdPad = kFwdSeg;
+inline __host__ __device__ int vol_row(int W) { return W + 2 * kFwdPad; }
 // Largest detector edge (the forward kernel keeps one window start per row).
 constexpr int kMaxW = 2048;
 

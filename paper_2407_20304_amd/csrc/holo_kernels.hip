@@ -451,32 +451,53 @@ __global__ __launch_bounds__(kThreads) void k_pass_d(const float2* __restrict__ 
   *out = make_float2(g.kappa * cy, -g.kappa * cx);
 }
 
-// Z-blocked copies of the volume for the ray sums: ub[z / ZT][y][x][z % ZT]
-// (walks along y) and uTb[z / ZT][x][y][z % ZT] (walks along x, i.e. the
-// x/y-transposed volume).  A workgroup moves a 16 x 16 x ZT brick.
+// Z-blocked copies of the volume for the ray sums: ub[z / ZT][y][P + x][z % ZT]
+// (walks along y) and uTb[z / ZT][x][P + y][z % ZT] (walks along x, i.e. the
+// x/y-transposed volume), rows padded by P = kFwdPad zero columns on each
+// side.  A workgroup moves a 16 x 16 x ZT brick; the workgroups at the
+// first and last brick column also clear the padding of their 16 rows.
 __global__ __launch_bounds__(kThreads) void k_block_volume(const float2* __restrict__ u,
                                                            float2* __restrict__ ub,
                                                            float2* __restrict__ uTb, int W) {
-  constexpr int ZT = kFwdZT;
+  constexpr int ZT = kFwdZT, P = kFwdPad;
   __shared__ float2 brick[ZT][16][17];
-  const int nt = W / 16;
+  const int nt = W / 16, Wf = vol_row(W);
   const int x0 = (blockIdx.x % nt) * 16, y0 = (blockIdx.x / nt) * 16;
   const int zb = blockIdx.y;
-  const size_t WW = (size_t)W * W;
+  const size_t WW = (size_t)W * W, WWf = (size_t)W * Wf;
   // read along x (contiguous)
   for (int i = threadIdx.x; i < ZT * 256; i += kThreads) {
     const int xx = i & 15, yy = (i >> 4) & 15, zz = i >> 8;
     brick[zz][yy][xx] = u[(size_t)(zb * ZT + zz) * WW + (size_t)(y0 + yy) * W + x0 + xx];
   }
   __syncthreads();
-  float2* bb = ub + (size_t)zb * WW * ZT;
-  float2* tb = uTb ? uTb + (size_t)zb * WW * ZT : nullptr;
+  float2* bb = ub + (size_t)zb * WWf * ZT;
+  float2* tb = uTb ? uTb + (size_t)zb * WWf * ZT : nullptr;
   // write with z fastest (contiguous 128-byte runs)
   for (int i = threadIdx.x; i < ZT * 256; i += kThreads) {
     const int zz = i % ZT, p = i / ZT;
     const int a = p & 15, b = p >> 4;
-    bb[((size_t)(y0 + b) * W + x0 + a) * ZT + zz] = brick[zz][b][a];
-    if (tb) tb[((size_t)(x0 + b) * W + y0 + a) * ZT + zz] = brick[zz][a][b];
+    bb[((size_t)(y0 + b) * Wf + P + x0 + a) * ZT + zz] = brick[zz][b][a];
+    if (tb) tb[((size_t)(x0 + b) * Wf + P + y0 + a) * ZT + zz] = brick[zz][a][b];
+  }
+  // padding: rows y0..y0+15 of ub (brick column 0 / last) and rows
+  // x0..x0+15 of uTb (brick row 0 / last)
+  const float2 zero = make_float2(0.f, 0.f);
+  const bool lo = x0 == 0, hi = x0 == W - 16;
+  if (lo || hi) {
+    for (int i = threadIdx.x; i < 16 * P * ZT; i += kThreads) {
+      const int zz = i % ZT, c = (i / ZT) % P, r = i / (ZT * P);
+      const int col = lo ? c : P + W + c;
+      bb[((size_t)(y0 + r) * Wf + col) * ZT + zz] = zero;
+    }
+  }
+  const bool tlo = y0 == 0, thi = y0 == W - 16;
+  if (tb && (tlo || thi)) {
+    for (int i = threadIdx.x; i < 16 * P * ZT; i += kThreads) {
+      const int zz = i % ZT, c = (i / ZT) % P, r = i / (ZT * P);
+      const int col = tlo ? c : P + W + c;
+      tb[((size_t)(x0 + r) * Wf + col) * ZT + zz] = zero;
+    }
   }
 }
 
@@ -535,26 +556,33 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
       const double fr = ap[kA] + (double)r * ap[kD];
       mn = fmin(mn, fmin(fr + (double)sb * ap[kB], fr + (double)(sb + 63) * ap[kB]));
     }
-    s_xl[r] = (int)floor(mn) - 1;
+    // a window wholly outside the volume is moved into the zero padding
+    s_xl[r] = min(max((int)floor(mn) - 1, -kFwdPad), W + kFwdPad - SEG);
   }
   __syncthreads();
 
-  // The volume copy is z-blocked, vol[z / ZT][row][col][z % ZT]: the ZT
-  // slices of one voxel column are one contiguous 128-byte run, so a staged
-  // window row is a single contiguous stretch of memory.
-  const float2* vb = vol + (size_t)(z0 / ZT) * WW * ZT;
+  // The volume copy is z-blocked and padded, vol[z / ZT][row][P + col][z % ZT]:
+  // the ZT slices of one voxel column are one contiguous 128-byte run, so a
+  // staged window row is a single contiguous stretch of memory, read from a
+  // wave-uniform base.  Element e of a thread is staged row e / EPR and
+  // float2 number threadIdx.x + kThreads (e % EPR) of that row's window.
+  static_assert(SEG % (kThreads / ZT) == 0, "a window row splits into whole passes");
+  constexpr int EPR = SEG / (kThreads / ZT);       // elements per staged row
+  const int Wf = vol_row(W);
+  const float2* vb = vol + (size_t)(z0 / ZT) * W * Wf * ZT + (size_t)kFwdPad * ZT + threadIdx.x;
   float2 pre[PER];
   auto fetch = [&](int y0) {
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int i = threadIdx.x + e * kThreads;
-      const int zz = i % ZT, cr = i / ZT;
-      const int c = cr % SEG, r = cr / SEG;
-      const int x = s_xl[y0 + r] + c;
-      pre[e] = (x >= 0 && x < W) ? vb[((size_t)(y0 + r) * W + x) * ZT + zz]
-                                 : make_float2(0.f, 0.f);
+    for (int r = 0; r < YB; ++r) {
+      const int xl = __builtin_amdgcn_readfirstlane(s_xl[y0 + r]);
+      const float2* row = vb + ((size_t)(y0 + r) * Wf + xl) * ZT;
+#pragma unroll
+      for (int e = 0; e < EPR; ++e) pre[r * EPR + e] = row[e * kThreads];
     }
   };
+  // staging position of element e: tile[e / EPR][threadIdx.x % ZT][c], with
+  // c = (kThreads / ZT) (e % EPR) + threadIdx.x / ZT
+  float2* stg = &tile[0][threadIdx.x % ZT][threadIdx.x / ZT];
 
   float ax[ZT], ay[ZT];
   double ox[ZT], oy[ZT];
@@ -565,11 +593,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
   for (int y0 = 0; y0 < W; y0 += YB) {
     __syncthreads();  // every wave is done with the previous block
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int i = threadIdx.x + e * kThreads;
-      const int zz = i % ZT, cr = i / ZT;
-      tile[cr / SEG][zz][cr % SEG] = pre[e];
-    }
+    for (int e = 0; e < PER; ++e)
+      stg[(e / EPR) * ZT * (SEG + 1) + (kThreads / ZT) * (e % EPR)] = pre[e];
     __syncthreads();
     if (y0 + YB < W) fetch(y0 + YB);
     if (active) {

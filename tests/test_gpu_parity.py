@@ -150,3 +150,31 @@ def test_fwd_parity_fine_angles_across_walk_switch():
     ref = O.forward(PB.c128(p.u), PB.c128(p.q), p.geom)
     for k in range(len(deg)):
         assert rel(v[k], ref[k]) < TOL, (deg[k], rel(v[k], ref[k]))
+
+
+def test_dense_volume_with_poisoned_workspace():
+    # A volume that is non-zero out to the corners, so the ray sums' staged
+    # row windows and sinogram segments at and beyond the volume's edges
+    # carry data, and a workspace filled with NaN bytes beforehand: the
+    # zero padding the ray sums read outside the volume and the detector
+    # must be written by the call itself.
+    import torch
+    say("dense volume, poisoned workspace, 64x128x128, 24 angles")
+    deg = np.concatenate([np.arange(0.0, 180.0, 9.0), [44.9, 45.0, 45.1, 134.9]])
+    p = PB.make_problem(64, 128, len(deg), config=0, theta=np.deg2rad(deg), chunk=7)
+    rng = np.random.default_rng(11)
+    u_np = (1e-5 * (rng.random((64, 128, 128)) + 0.1j * rng.random((64, 128, 128)))).astype(np.complex64)
+    u = torch.from_numpy(u_np).cuda()
+    q = torch.from_numpy(np.ascontiguousarray(p.q)).cuda()
+    plan = PB.gpu_plan(p)
+    plan.workspace(u.device).fill_(255)
+    v = plan.holo_fwd(u, q).cpu().numpy()
+    ref = O.forward(PB.c128(u_np), PB.c128(p.q), p.geom)
+    for k in range(len(deg)):
+        assert rel(v[k], ref[k]) < TOL, (deg[k], rel(v[k], ref[k]))
+    w = (rng.standard_normal(v.shape) + 1j * rng.standard_normal(v.shape)).astype(np.complex64)
+    plan.workspace(u.device).fill_(255)
+    gu, gq = plan.holo_adj(u, q, torch.from_numpy(w).cuda())
+    ru, rq = O.adjoint(PB.c128(u_np), PB.c128(p.q), PB.c128(w), p.geom)
+    assert rel(gu.cpu().numpy(), ru) < TOL, rel(gu.cpu().numpy(), ru)
+    assert rel(gq.cpu().numpy(), rq) < TOL, rel(gq.cpu().numpy(), rq)
