@@ -99,24 +99,25 @@ static void build_twiddles(std::vector<float2>& out, int n) {
 static bool is_finite(double x) { return std::isfinite(x); }
 
 // Can angles [a, b) share the staged row windows of the forward ray sums?
-// The window of a (bin block, row) must span at most kFwdSeg - 6 columns
-// between the lowest and highest tap (margin for rounding).  Tap positions
-// are affine in bin and row, so the extremes sit at the block's end bins and
-// at the first and last row.
+// The window of a (bin block, row) must span at most kFwdSeg - 4 columns
+// between the lowest and highest tap (the kernel adds one column of margin
+// below and reads one tap to the right; the rest covers rounding).  Tap
+// positions are affine in bin and row, so the extremes sit at the block's
+// end bins and at the first and last row.
 static bool fwd_group_fits(const holo_plan* P, int a, int b) {
   const int W = P->W;
-  for (int sb = 0; sb < W; sb += 64) {
+  for (int sb = 0; sb < W; sb += kFwdNB) {
     for (int r : {0, W - 1}) {
       double mn = 1e300, mx = -1e300;
       for (int k = a; k < b; ++k) {
         const double* g = &P->ang[(size_t)k * kAngleStride];
-        for (int bin : {sb, sb + 63}) {
+        for (int bin : {sb, sb + kFwdNB - 1}) {
           const double f = g[kA] + (double)bin * g[kB] + (double)r * g[kD];
           mn = std::fmin(mn, f);
           mx = std::fmax(mx, f);
         }
       }
-      if (std::floor(mx) - std::floor(mn) > kFwdSeg - 6) return false;
+      if (std::floor(mx) - std::floor(mn) > kFwdSeg - 4) return false;
     }
   }
   return true;

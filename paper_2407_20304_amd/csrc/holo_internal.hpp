@@ -63,11 +63,13 @@ enum ColMode { kColFwd = 0, kColObj = 1, kColGrad = 2, kColAdj = 3 };
 int rows_per_wg(int W);      // lines of W handled by one 256-thread workgroup
 int cols_per_wg(int H);      // columns of length H per workgroup
 bool fft_size_supported(int n);
-// Ray-sum tiling (see the kernels): forward angle-group size, slices per
-// thread, staged rows per block and staged columns per row; transpose
-// slices per thread, angles per staged group and bins per staged segment.
-constexpr int kFwdNA = 4, kFwdZT = 16, kFwdYB = 2, kFwdSeg = 112;
+// Ray-sum tiling (see the kernels): forward angle-group size, slices and
+// bins per workgroup, staged rows per block and staged columns per row;
+// transpose slices per thread, angles per staged group and bins per staged
+// segment; slice blocking of the forward's volume copies.
+constexpr int kFwdNA = 4, kFwdZT = 64, kFwdNB = 16, kFwdYB = 2, kFwdSeg = 32;
 constexpr int kAdjZT = 16, kAdjNA = 8, kAdjSeg = 32;
+constexpr int kVolZB = 16;
 // Zero bins on each side of every sinogram row read by the transpose: a
 // staged segment is then always valid memory (segments wholly off the
 // detector are moved into the padding, which reads as zeros).

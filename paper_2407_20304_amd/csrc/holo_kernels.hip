@@ -459,7 +459,7 @@ __global__ __launch_bounds__(kThreads) void k_pass_d(const float2* __restrict__ 
 __global__ __launch_bounds__(kThreads) void k_block_volume(const float2* __restrict__ u,
                                                            float2* __restrict__ ub,
                                                            float2* __restrict__ uTb, int W) {
-  constexpr int ZT = kFwdZT, P = kFwdPad;
+  constexpr int ZT = kVolZB, P = kFwdPad;
   __shared__ float2 brick[ZT][16][17];
   const int nt = W / 16, Wf = vol_row(W);
   const int x0 = (blockIdx.x % nt) * 16, y0 = (blockIdx.x / nt) * 16;
@@ -506,35 +506,40 @@ __global__ __launch_bounds__(kThreads) void k_block_volume(const float2* __restr
 // ---------------------------------------------------------------------------
 
 // Forward.  A workgroup owns up to kFwdNA consecutive angles of one walk
-// direction (one wave per angle), 64 consecutive bins (one per lane) and
-// kFwdZT slices (per thread).  It walks the rows of the volume in blocks of
-// kFwdYB: for each row it stages into LDS the column window that all its rays
-// cross (shared by the angles of the group), then every lane interpolates its
-// two taps for each of its slices from LDS.  The next block's window is
-// loaded into registers while the current one is consumed, so the global
-// load latency overlaps the interpolation.  Angles that walk along x read
-// the x/y-transposed volume, so both walk directions use the same code.  The
-// host groups angles so that every window fits.
+// direction (one wave per angle), kFwdNB consecutive bins and kFwdZT slices.
+// Within a wave, 32 consecutive lanes are 32 consecutive slices of one bin
+// and a thread takes 2 slices (32 apart) of 8 consecutive bins.  The
+// workgroup walks the rows of the volume in blocks of kFwdYB: for each row
+// it stages into LDS the column window that all its rays cross (shared by
+// the angles of the group), stored [row][column][slice]; a lane then reads
+// its two taps per slice, and the 32 lanes of one LDS pass read 256
+// contiguous bytes, free of bank conflicts.  The next block's window is
+// loaded into registers while the current one is consumed.  Angles that
+// walk along x read the x/y-transposed volume, so both walk directions use
+// the same code.  The host groups angles so that every window fits.
 __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restrict__ u,
                                                          const float2* __restrict__ uT,  // z-blocked
                                                          float2* __restrict__ psi, DevGeom g,
                                                          const double* __restrict__ ang,
                                                          const int2* __restrict__ groups,
                                                          int g0, int ngroups, int c0, int c1) {
-  constexpr int ZT = kFwdZT, YB = kFwdYB, SEG = kFwdSeg;
-  constexpr int PER = (YB * ZT * SEG) / kThreads;   // staged elements per thread per block
-  static_assert((YB * ZT * SEG) % kThreads == 0, "block must split evenly");
-  __shared__ float2 tile[YB][ZT][SEG + 1];           // +1: spreads the staging writes over banks
+  constexpr int ZT = kFwdZT, NB = kFwdNB, YB = kFwdYB, SEG = kFwdSeg, ZB = kVolZB;
+  constexpr int BPT = NB / 2;                       // bins per thread
+  constexpr int PER = (YB * SEG * ZT) / kThreads;   // staged elements per thread per block
+  constexpr int CPP = kThreads / ZT;                // columns per staging pass
+  static_assert(ZT == 64 && NB % 2 == 0 && SEG % CPP == 0 && PER % YB == 0, "tiling");
+  __shared__ float2 tile[YB * SEG * ZT];
   __shared__ int s_xl[kMaxW];
   const int W = g.W, H = g.H;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int zl = lane & 31, bg = lane >> 5;
   // logical order: angle group fastest, then bin block, then slice block,
   // so the groups reading the same windows run together on one XCD
   const int L = xcd_logical(blockIdx.x, gridDim.x);
   const int gi = L % ngroups, rest = L / ngroups;
-  const int nbb = W / 64;
-  const int sb = (rest % nbb) * 64;
-  const int s = sb + lane;
+  const int nbb = W / NB;
+  const int sb = (rest % nbb) * NB;
+  const int s0 = sb + bg * BPT;                     // first bin of this thread
   const int z0 = (rest / nbb) * ZT;
   const int2 grp = groups[g0 + gi];
   const int gf = max(grp.x, c0), gl = min(grp.x + grp.y, c1);
@@ -544,8 +549,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
   const double* aw = ang + (size_t)k * kAngleStride;
   const float2* vol = (aw[kBranch] != 0.0) ? uT : u;
   const double B = aw[kB], D = aw[kD];
-  const double fA = aw[kA] + (double)s * B;
-  const size_t WW = (size_t)W * W;
+  const double fA = aw[kA] + (double)s0 * B;
+  const float Bf = (float)B;
 
   // window start of every row: lowest tap over the group's angles and the
   // block's end bins, minus one column of margin for rounding
@@ -554,71 +559,77 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
     for (int a = 0; a < na; ++a) {
       const double* ap = ang + (size_t)(gf + a) * kAngleStride;
       const double fr = ap[kA] + (double)r * ap[kD];
-      mn = fmin(mn, fmin(fr + (double)sb * ap[kB], fr + (double)(sb + 63) * ap[kB]));
+      mn = fmin(mn, fmin(fr + (double)sb * ap[kB], fr + (double)(sb + NB - 1) * ap[kB]));
     }
     // a window wholly outside the volume is moved into the zero padding
     s_xl[r] = min(max((int)floor(mn) - 1, -kFwdPad), W + kFwdPad - SEG);
   }
   __syncthreads();
 
-  // The volume copy is z-blocked and padded, vol[z / ZT][row][P + col][z % ZT]:
-  // the ZT slices of one voxel column are one contiguous 128-byte run, so a
-  // staged window row is a single contiguous stretch of memory, read from a
-  // wave-uniform base.  Element e of a thread is staged row e / EPR and
-  // float2 number threadIdx.x + kThreads (e % EPR) of that row's window.
-  static_assert(SEG % (kThreads / ZT) == 0, "a window row splits into whole passes");
-  constexpr int EPR = SEG / (kThreads / ZT);       // elements per staged row
+  // The volume copies are slice-blocked and padded, vol[z / ZB][row][P + col][z % ZB].
+  // Element e of a thread is slice threadIdx.x % ZT, column
+  // threadIdx.x / ZT + CPP (e % (PER / YB)) of staged row e / (PER / YB):
+  // a wave-uniform base per row plus a fixed per-lane offset.
   const int Wf = vol_row(W);
-  const float2* vb = vol + (size_t)(z0 / ZT) * W * Wf * ZT + (size_t)kFwdPad * ZT + threadIdx.x;
+  const size_t plane = (size_t)W * Wf * ZB;
+  const int ts = threadIdx.x % ZT, tc = threadIdx.x / ZT;
+  const float2* vb = vol + (size_t)((z0 + ts) / ZB) * plane + (size_t)(kFwdPad + tc) * ZB + ts % ZB;
   float2 pre[PER];
   auto fetch = [&](int y0) {
 #pragma unroll
     for (int r = 0; r < YB; ++r) {
       const int xl = __builtin_amdgcn_readfirstlane(s_xl[y0 + r]);
-      const float2* row = vb + ((size_t)(y0 + r) * Wf + xl) * ZT;
+      const float2* row = vb + ((size_t)(y0 + r) * Wf + xl) * ZB;
 #pragma unroll
-      for (int e = 0; e < EPR; ++e) pre[r * EPR + e] = row[e * kThreads];
+      for (int e = 0; e < PER / YB; ++e) pre[r * (PER / YB) + e] = row[e * CPP * ZB];
     }
   };
-  // staging position of element e: tile[e / EPR][threadIdx.x % ZT][c], with
-  // c = (kThreads / ZT) (e % EPR) + threadIdx.x / ZT
-  float2* stg = &tile[0][threadIdx.x % ZT][threadIdx.x / ZT];
 
-  float ax[ZT], ay[ZT];
-  double ox[ZT], oy[ZT];
+  float ax[BPT][2], ay[BPT][2];
+  double ox[BPT][2], oy[BPT][2];
 #pragma unroll
-  for (int i = 0; i < ZT; ++i) { ax[i] = ay[i] = 0.f; ox[i] = oy[i] = 0.0; }
+  for (int b = 0; b < BPT; ++b)
+#pragma unroll
+    for (int m = 0; m < 2; ++m) { ax[b][m] = ay[b][m] = 0.f; ox[b][m] = oy[b][m] = 0.0; }
 
   fetch(0);
   for (int y0 = 0; y0 < W; y0 += YB) {
     __syncthreads();  // every wave is done with the previous block
 #pragma unroll
-    for (int e = 0; e < PER; ++e)
-      stg[(e / EPR) * ZT * (SEG + 1) + (kThreads / ZT) * (e % EPR)] = pre[e];
+    for (int e = 0; e < PER; ++e) tile[threadIdx.x + e * kThreads] = pre[e];
     __syncthreads();
     if (y0 + YB < W) fetch(y0 + YB);
     if (active) {
 #pragma unroll
       for (int r = 0; r < YB; ++r) {
-        const double f = fA + (double)(y0 + r) * D;
-        const double fl = floor(f);
-        const float w1 = (float)(f - fl), w0 = 1.0f - w1;
-        int col = (int)fl - s_xl[y0 + r];
-        col = min(max(col, 0), SEG - 2);
+        // tap position of the thread's first bin relative to the window, in
+        // double precision; the other bins add b B (< NB / 2 * sqrt(2))
+        const float rel = (float)(fA + (double)(y0 + r) * D - (double)s_xl[y0 + r]);
+        const float2* tr = tile + r * SEG * ZT + zl;
 #pragma unroll
-        for (int i = 0; i < ZT; ++i) {
-          const float2 v0 = tile[r][i][col], v1 = tile[r][i][col + 1];
-          ax[i] = fmaf(w1, v1.x, fmaf(w0, v0.x, ax[i]));
-          ay[i] = fmaf(w1, v1.y, fmaf(w0, v0.y, ay[i]));
+        for (int b = 0; b < BPT; ++b) {
+          const float q = fmaf((float)b, Bf, rel);
+          const float fl = floorf(q);
+          const float w1 = q - fl, w0 = 1.0f - w1;
+          const int col = min(max((int)fl, 0), SEG - 2);
+          const float2* tp = tr + col * ZT;
+#pragma unroll
+          for (int m = 0; m < 2; ++m) {
+            const float2 v0 = tp[32 * m], v1 = tp[ZT + 32 * m];
+            ax[b][m] = fmaf(w1, v1.x, fmaf(w0, v0.x, ax[b][m]));
+            ay[b][m] = fmaf(w1, v1.y, fmaf(w0, v0.y, ay[b][m]));
+          }
         }
       }
       if (((y0 / YB) & 15) == 15) {
 #pragma unroll
-        for (int i = 0; i < ZT; ++i) {
-          ox[i] += (double)ax[i];
-          oy[i] += (double)ay[i];
-          ax[i] = ay[i] = 0.f;
-        }
+        for (int b = 0; b < BPT; ++b)
+#pragma unroll
+          for (int m = 0; m < 2; ++m) {
+            ox[b][m] += (double)ax[b][m];
+            oy[b][m] += (double)ay[b][m];
+            ax[b][m] = ay[b][m] = 0.f;
+          }
       }
     }
   }
@@ -627,16 +638,18 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
   const double kap = (double)g.kappa;
   const double twopi = 6.283185307179586476925;
 #pragma unroll
-  for (int i = 0; i < ZT; ++i) {
-    const double px = (ox[i] + (double)ax[i]) * scale;
-    const double py = (oy[i] + (double)ay[i]) * scale;
-    double ph = kap * px;
-    ph -= twopi * rint(ph / twopi);
-    float sn, cs;
-    sincosf((float)ph, &sn, &cs);
-    const float mag = expf((float)(-kap * py));
-    psi[((size_t)(k - c0) * H + z0 + i) * W + s] = make_float2(mag * cs, mag * sn);
-  }
+  for (int b = 0; b < BPT; ++b)
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const double px = (ox[b][m] + (double)ax[b][m]) * scale;
+      const double py = (oy[b][m] + (double)ay[b][m]) * scale;
+      double ph = kap * px;
+      ph -= twopi * rint(ph / twopi);
+      float sn, cs;
+      sincosf((float)ph, &sn, &cs);
+      const float mag = expf((float)(-kap * py));
+      psi[((size_t)(k - c0) * H + z0 + zl + 32 * m) * W + s0 + b] = make_float2(mag * cs, mag * sn);
+    }
 }
 
 // Transpose.  A workgroup owns a 16 x 16 voxel tile (one voxel per thread)
@@ -901,7 +914,7 @@ hipError_t launch_pass_d(const DevGeom& g, const float2* X, const float2* psi, f
 hipError_t launch_radon_fwd(const DevGeom& g, const float2* ub, const float2* uTb, float2* psi,
                             const double* ang, const int2* groups, int g0, int ngroups, int c0,
                             int c1, hipStream_t st) {
-  const unsigned n = (unsigned)(g.W / 64) * (unsigned)(g.H / kFwdZT) * (unsigned)ngroups;
+  const unsigned n = (unsigned)(g.W / kFwdNB) * (unsigned)(g.H / kFwdZT) * (unsigned)ngroups;
   k_radon_fwd<<<n, kThreads, 0, st>>>(ub, uTb, psi, g, ang, groups, g0, ngroups, c0, c1);
   return hipGetLastError();
 }
@@ -915,7 +928,7 @@ hipError_t launch_radon_adj(const DevGeom& g, const float2* S, float2* gu, const
 
 hipError_t launch_block_volume(const DevGeom& g, const float2* u, float2* ub, float2* uTb,
                                hipStream_t st) {
-  const dim3 grid((g.W / 16) * (g.W / 16), g.H / kFwdZT);
+  const dim3 grid((g.W / 16) * (g.W / 16), g.H / kVolZB);
   k_block_volume<<<grid, kThreads, 0, st>>>(u, ub, uTb, g.W);
   return hipGetLastError();
 }
