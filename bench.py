@@ -26,9 +26,39 @@ PEAK_FP32_VALU_TFLOPS = 157.3   # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0           # MI355X published HBM3E bandwidth
 FLOP_PER_LERP = 8               # 2 taps x (re, im) x fused multiply-add
 
+# HBM traffic per launch of the dominant kernel, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean over the launches of
+# one gradient evaluation), each scaled by what the same counter reads for a
+# 1 GiB device-to-device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  The
+# figures hold for the library sources they were taken on (SHA-256 over the
+# csrc files); after any change to those sources the field reports null.
+TRAFFIC = {
+    "k_radon_fwd": {"fetch_kib": 14346698.68, "write_kib": 891614.79,
+                    "fetch_scale": 2.0, "write_scale": 1.0,
+                    "sources_sha256": "34edcaa8ddc42c254c1d4eb803459b4697eb1cb2d0de7f9a976271e77a2742a5"},
+}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def csrc_sha256():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2407_20304_amd", "csrc", "*"))):
+        if p.endswith((".hip", ".hpp", ".cpp", ".h")):
+            with open(p, "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_bytes(kernel):
+    t = TRAFFIC.get(kernel)
+    if t is None or t["sources_sha256"] != csrc_sha256():
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
 
 def frame_bytes_model(wl, steps):
@@ -171,7 +201,7 @@ def main():
     achieved = per_launch_flop / (dms / dn * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": "k_" + dom, "achieved": achieved,
                 "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": None,
+                "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": traffic_bytes("k_" + dom),
                 "per_launch_flop": per_launch_flop, "avg_launch_ms": dms / dn}
 
     result = {
