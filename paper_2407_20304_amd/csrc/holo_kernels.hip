@@ -551,6 +551,12 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
   const double B = aw[kB], D = aw[kD];
   const double fA = aw[kA] + (double)s0 * B;
   const float Bf = (float)B;
+  // Range of the per-row base that keeps every tap of the thread's bins
+  // inside the staged window.  Inside the volume the host's grouping already
+  // guarantees it (so the clamp changes nothing there); a window moved into
+  // the zero padding reads zeros wherever the taps land.
+  const float span = (float)(BPT - 1) * Bf;
+  const float rel_lo = fmaxf(0.0f, -span), rel_hi = (float)(SEG - 2) - fmaxf(0.0f, span) - 0.01f;
 
   // window start of every row: lowest tap over the group's angles and the
   // block's end bins, minus one column of margin for rounding
@@ -604,14 +610,14 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
       for (int r = 0; r < YB; ++r) {
         // tap position of the thread's first bin relative to the window, in
         // double precision; the other bins add b B (< NB / 2 * sqrt(2))
-        const float rel = (float)(fA + (double)(y0 + r) * D - (double)s_xl[y0 + r]);
+        float rel = (float)(fA + (double)(y0 + r) * D - (double)s_xl[y0 + r]);
+        rel = fminf(fmaxf(rel, rel_lo), rel_hi);
         const float2* tr = tile + r * SEG * ZT + zl;
 #pragma unroll
         for (int b = 0; b < BPT; ++b) {
-          const float q = fmaf((float)b, Bf, rel);
-          const float fl = floorf(q);
-          const float w1 = q - fl, w0 = 1.0f - w1;
-          const int col = min(max((int)fl, 0), SEG - 2);
+          const float q = fmaf((float)b, Bf, rel);        // >= 0, < SEG - 2
+          const float w1 = __builtin_amdgcn_fractf(q), w0 = 1.0f - w1;
+          const int col = (int)q;                          // truncation = floor here
           const float2* tp = tr + col * ZT;
 #pragma unroll
           for (int m = 0; m < 2; ++m) {
