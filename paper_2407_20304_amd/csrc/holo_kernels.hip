@@ -509,27 +509,30 @@ __global__ __launch_bounds__(kThreads) void k_block_volume(const float2* __restr
 // direction (one wave per angle), kFwdNB consecutive bins and kFwdZT slices.
 // Within a wave, 32 consecutive lanes are 32 consecutive slices of one bin
 // and a thread takes 2 slices (32 apart) of 8 consecutive bins.  The
-// workgroup walks the rows of the volume in blocks of kFwdYB: for each row
-// it stages into LDS the column window that all its rays cross (shared by
-// the angles of the group), stored [row][column][slice]; a lane then reads
-// its two taps per slice, and the 32 lanes of one LDS pass read 256
-// contiguous bytes, free of bank conflicts.  The next block's window is
-// loaded into registers while the current one is consumed.  Angles that
-// walk along x read the x/y-transposed volume, so both walk directions use
-// the same code.  The host groups angles so that every window fits.
+// workgroup walks the rows of the volume one at a time: each row's column
+// window that all its rays cross (shared by the angles of the group) is
+// copied straight from memory into LDS, [column][slice], by LDS-direct
+// loads two rows ahead of use (three row buffers), so staging costs no
+// registers and no LDS writes by the waves.  A lane then reads its two taps
+// per slice; the 32 lanes of one LDS pass read 256 contiguous bytes, free
+// of bank conflicts.  Angles that walk along x read the x/y-transposed
+// volume, so both walk directions use the same code.  The host groups
+// angles so that every window fits.
 __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restrict__ u,
                                                          const float2* __restrict__ uT,  // z-blocked
                                                          float2* __restrict__ psi, DevGeom g,
                                                          const double* __restrict__ ang,
                                                          const int2* __restrict__ groups,
                                                          int g0, int ngroups, int c0, int c1) {
-  constexpr int ZT = kFwdZT, NB = kFwdNB, YB = kFwdYB, SEG = kFwdSeg, ZB = kVolZB;
+  constexpr int ZT = kFwdZT, NB = kFwdNB, SEG = kFwdSeg, ZB = kVolZB;
   constexpr int BPT = NB / 2;                       // bins per thread
-  constexpr int PER = (YB * SEG * ZT) / kThreads;   // staged elements per thread per block
-  constexpr int CPP = kThreads / ZT;                // columns per staging pass
-  static_assert(ZT == 64 && NB % 2 == 0 && SEG % CPP == 0 && PER % YB == 0, "tiling");
-  __shared__ float2 tile[YB * SEG * ZT];
-  __shared__ int s_xl[kMaxW];
+  constexpr int NBUF = 3;                           // row buffers (loads run 2 rows ahead)
+  constexpr int ROWF2 = SEG * ZT;                   // float2 per staged row
+  constexpr int LPW = ROWF2 / (4 * 128);            // LDS-direct loads (16 B per lane) per wave per row
+  static_assert(ZT == 64 && NB % 2 == 0 && LPW == 4 && kThreads == 256, "tiling");
+  __shared__ float4 tile4[NBUF * ROWF2 / 2];
+  __shared__ short s_xl[kMaxW];
+  float2* tile = reinterpret_cast<float2*>(tile4);
   const int W = g.W, H = g.H;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int zl = lane & 31, bg = lane >> 5;
@@ -568,27 +571,38 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
       mn = fmin(mn, fmin(fr + (double)sb * ap[kB], fr + (double)(sb + NB - 1) * ap[kB]));
     }
     // a window wholly outside the volume is moved into the zero padding
-    s_xl[r] = min(max((int)floor(mn) - 1, -kFwdPad), W + kFwdPad - SEG);
+    s_xl[r] = (short)min(max((int)floor(mn) - 1, -kFwdPad), W + kFwdPad - SEG);
   }
   __syncthreads();
 
   // The volume copies are slice-blocked and padded, vol[z / ZB][row][P + col][z % ZB].
-  // Element e of a thread is slice threadIdx.x % ZT, column
-  // threadIdx.x / ZT + CPP (e % (PER / YB)) of staged row e / (PER / YB):
-  // a wave-uniform base per row plus a fixed per-lane offset.
+  // Load i of wave w moves 1 KB: lane l brings slices 2 (l % 8) and
+  // 2 (l % 8) + 1 of slice block (l / 8) % 4 of column 8 w + 2 i + l / 32,
+  // which is where the [column][slice] row layout wants them (lane l lands
+  // at byte 16 l of the load's 1 KB).
   const int Wf = vol_row(W);
   const size_t plane = (size_t)W * Wf * ZB;
-  const int ts = threadIdx.x % ZT, tc = threadIdx.x / ZT;
-  const float2* vb = vol + (size_t)((z0 + ts) / ZB) * plane + (size_t)(kFwdPad + tc) * ZB + ts % ZB;
-  float2 pre[PER];
-  auto fetch = [&](int y0) {
+  const float2* vl = vol + (size_t)(z0 / ZB + ((lane >> 3) & 3)) * plane +
+                     (size_t)(kFwdPad + 8 * wave + (lane >> 5)) * ZB + 2 * (lane & 7);
+  // The loads are issued as inline assembly: the compiler does not track
+  // them, so it adds no waits of its own; the loop below waits for them
+  // explicitly (vector-memory counter) before the barrier that publishes a
+  // row.  M0 holds the wave's LDS destination of each load.
+  const unsigned lds0 = (unsigned)(uintptr_t)(__attribute__((address_space(3))) float4*)tile4;
+  auto issue = [&](int y) {
+    const int xl = __builtin_amdgcn_readfirstlane((int)s_xl[y]);
+    const float2* row = vl + ((size_t)y * Wf + xl) * ZB;
+    const unsigned dst = __builtin_amdgcn_readfirstlane(
+        lds0 + (unsigned)(((y % NBUF) * (ROWF2 / 2) + wave * (LPW * 64)) * 16));
 #pragma unroll
-    for (int r = 0; r < YB; ++r) {
-      const int xl = __builtin_amdgcn_readfirstlane(s_xl[y0 + r]);
-      const float2* row = vb + ((size_t)(y0 + r) * Wf + xl) * ZB;
-#pragma unroll
-      for (int e = 0; e < PER / YB; ++e) pre[r * (PER / YB) + e] = row[e * CPP * ZB];
-    }
+    for (int i = 0; i < LPW; ++i)
+      asm volatile(
+          "s_mov_b32 m0, %0\n\t"
+          "s_nop 0\n\t"
+          "global_load_lds_dwordx4 %1, off"
+          :
+          : "s"(dst + 1024u * i), "v"(row + 2 * i * ZB)
+          : "memory", "m0");
   };
 
   float ax[BPT][2], ay[BPT][2];
@@ -598,36 +612,38 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
 #pragma unroll
     for (int m = 0; m < 2; ++m) { ax[b][m] = ay[b][m] = 0.f; ox[b][m] = oy[b][m] = 0.0; }
 
-  fetch(0);
-  for (int y0 = 0; y0 < W; y0 += YB) {
-    __syncthreads();  // every wave is done with the previous block
-#pragma unroll
-    for (int e = 0; e < PER; ++e) tile[threadIdx.x + e * kThreads] = pre[e];
-    __syncthreads();
-    if (y0 + YB < W) fetch(y0 + YB);
+  issue(0);
+  if (W > 1) issue(1);
+  for (int y = 0; y < W; ++y) {
+    // this wave's loads of row y are complete (those of row y + 1 may be in
+    // flight) and its LDS reads of row y - 1 have returned; the barrier then
+    // publishes row y of every wave and retires row y - 1, whose buffer the
+    // loads of row y + 2 reuse
+    if (y + 1 < W) asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)" ::"n"(LPW) : "memory");
+    else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (y + 2 < W) issue(y + 2);
     if (active) {
+      // tap position of the thread's first bin relative to the window, in
+      // double precision; the other bins add b B (< NB / 2 * sqrt(2))
+      float rel = (float)(fA + (double)y * D - (double)s_xl[y]);
+      rel = fminf(fmaxf(rel, rel_lo), rel_hi);
+      const float2* tr = tile + (y % NBUF) * ROWF2 + zl;
 #pragma unroll
-      for (int r = 0; r < YB; ++r) {
-        // tap position of the thread's first bin relative to the window, in
-        // double precision; the other bins add b B (< NB / 2 * sqrt(2))
-        float rel = (float)(fA + (double)(y0 + r) * D - (double)s_xl[y0 + r]);
-        rel = fminf(fmaxf(rel, rel_lo), rel_hi);
-        const float2* tr = tile + r * SEG * ZT + zl;
+      for (int b = 0; b < BPT; ++b) {
+        const float q = fmaf((float)b, Bf, rel);          // >= 0, < SEG - 2
+        const float w1 = __builtin_amdgcn_fractf(q), w0 = 1.0f - w1;
+        const int col = (int)q;                            // truncation = floor here
+        const float2* tp = tr + col * ZT;
 #pragma unroll
-        for (int b = 0; b < BPT; ++b) {
-          const float q = fmaf((float)b, Bf, rel);        // >= 0, < SEG - 2
-          const float w1 = __builtin_amdgcn_fractf(q), w0 = 1.0f - w1;
-          const int col = (int)q;                          // truncation = floor here
-          const float2* tp = tr + col * ZT;
-#pragma unroll
-          for (int m = 0; m < 2; ++m) {
-            const float2 v0 = tp[32 * m], v1 = tp[ZT + 32 * m];
-            ax[b][m] = fmaf(w1, v1.x, fmaf(w0, v0.x, ax[b][m]));
-            ay[b][m] = fmaf(w1, v1.y, fmaf(w0, v0.y, ay[b][m]));
-          }
+        for (int m = 0; m < 2; ++m) {
+          const float2 v0 = tp[32 * m], v1 = tp[ZT + 32 * m];
+          ax[b][m] = fmaf(w1, v1.x, fmaf(w0, v0.x, ax[b][m]));
+          ay[b][m] = fmaf(w1, v1.y, fmaf(w0, v0.y, ay[b][m]));
         }
       }
-      if (((y0 / YB) & 15) == 15) {
+      if ((y & 31) == 31) {
 #pragma unroll
         for (int b = 0; b < BPT; ++b)
 #pragma unroll
