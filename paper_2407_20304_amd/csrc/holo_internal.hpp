@@ -68,11 +68,13 @@ bool fft_size_supported(int n);
 // transpose slices per thread, angles per staged group and bins per staged
 // segment; slice blocking of the forward's volume copies.
 constexpr int kFwdNA = 4, kFwdZT = 64, kFwdNB = 16, kFwdYB = 2, kFwdSeg = 32;
-constexpr int kAdjZT = 16, kAdjNA = 8, kAdjSeg = 32;
+constexpr int kAdjZT = 16, kAdjNA = 4, kAdjSeg = 32;
+constexpr int kAdjWin = 64;   // angles per transpose set-up window
 constexpr int kVolZB = 16;
-// Zero bins on each side of every sinogram row read by the transpose: a
-// staged segment is then always valid memory (segments wholly off the
-// detector are moved into the padding, which reads as zeros).
+// Zero bins on each side of every row of the sinogram read by the transpose,
+// stored S[k][z][kAdjPad + bin]: a staged segment is then always valid
+// memory (segments wholly off the detector are moved into the padding,
+// which reads as zeros).
 constexpr int kAdjPad = kAdjSeg;
 inline __host__ __device__ int sino_row(int W) { return W + 2 * kAdjPad; }
 // Zero columns on each side of every row of the forward's volume copies: a

@@ -405,19 +405,17 @@ __global__ __launch_bounds__(kThreads) void k_pass_d(const float2* __restrict__ 
                                                      const float2* __restrict__ psi,
                                                      float2* __restrict__ S, DevGeom g,
                                                      int k_first) {
-  // A workgroup covers kAdjZT rows x (256 / kAdjZT) padded bins; consecutive
-  // threads take consecutive rows so that the z-blocked output
-  // S[k][z / kAdjZT][kAdjPad + s][z % kAdjZT] is written in contiguous runs.
-  // Workgroups over the padding write its zeros.
-  constexpr int ZT = kAdjZT, SC = kThreads / ZT;
+  // A workgroup covers 16 rows x 16 padded bins, bins fastest, of the
+  // sinogram S[k][z][kAdjPad + s] (rows padded by kAdjPad zero bins on each
+  // side).  Workgroups over the padding write its zeros.
+  constexpr int SC = 16, ZR = kThreads / SC;
   const int H = g.H, W = g.W, Wp = sino_row(W);
-  const int zz = threadIdx.x % ZT;
   const int nsb = Wp / SC;
-  const int z0 = (blockIdx.x / nsb) * ZT;
-  const int z = z0 + zz, sp = (blockIdx.x % nsb) * SC + threadIdx.x / ZT;
+  const int z = (blockIdx.x / nsb) * ZR + threadIdx.x / SC;
+  const int sp = (blockIdx.x % nsb) * SC + threadIdx.x % SC;
   const int s = sp - kAdjPad;
   const int k = blockIdx.y;
-  float2* out = S + (size_t)k * H * Wp + (size_t)z0 * Wp + (size_t)sp * ZT + zz;
+  float2* out = S + ((size_t)k * H + z) * Wp + sp;
   if (s < 0 || s >= W) {
     *out = make_float2(0.f, 0.f);
     return;
@@ -676,31 +674,34 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
 
 // Transpose.  A workgroup owns a 16 x 16 voxel tile (one voxel per thread)
 // and kAdjZT slices (per thread) and loops over all angles in groups of
-// kAdjNA: it stages, for each angle of the group, the kAdjSeg bins that the
-// tile projects onto, then every thread gathers its two taps per slice from
-// LDS.  The next group's segments are loaded into registers while the
-// current group is consumed.  Sinogram rows are zero-padded by kAdjPad bins,
-// so a segment is read without bounds checks from a wave-uniform base.  A
-// voxel projecting to fractional bin q takes max(0, 1 - |i - q| / h) / h of
-// bin i (h = max(|cos|, |sin|)) -- exactly the weight Joseph's interpolation
-// gave it.
-__global__ __launch_bounds__(kThreads, 2) void k_radon_adj(const float2* __restrict__ S,
+// kAdjNA (one wave loads each angle of a group): the kAdjSeg bins of each
+// slice that the tile projects onto are copied straight from the sinogram
+// into LDS, [angle][slice][bin], by LDS-direct loads two groups ahead of use
+// (three group buffers), then every thread gathers its two taps per slice.
+// The lanes of a wave read different bins of one 256-byte bin row: no bank
+// conflicts.  Sinogram rows are zero-padded by kAdjPad bins, so a segment
+// is read without bounds checks.  A voxel projecting to fractional bin q
+// takes max(0, 1 - |i - q| / h) / h of bin i (h = max(|cos|, |sin|)) --
+// exactly the weight Joseph's interpolation gave it.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_radon_adj(const float2* __restrict__ S,
                                                          float2* __restrict__ gu, DevGeom g,
                                                          const double* __restrict__ ang,
                                                          int K) {
-  constexpr int ZT = kAdjZT, NA = kAdjNA, SEG = kAdjSeg, TW = kThreads, BP = ZT + 1;
-  constexpr int TPB = kThreads / ZT;                // bins one pass of the workgroup covers
-  constexpr int PER = NA * SEG / TPB;               // staged elements per thread per group
-  static_assert(SEG % TPB == 0 && TW % NA == 0 && kAdjPad >= SEG, "staging layout");
-  // tile[a][bin][slice], slices fastest; the odd pitch (ZT + 1) puts the
-  // different bins that the lanes of a wave read on different banks
-  __shared__ float2 tile[NA * SEG * BP];
+  constexpr int ZT = kAdjZT, NA = kAdjNA, SEG = kAdjSeg, TW = kAdjWin;
+  constexpr int NBUF = 3;                           // group buffers (loads run 2 groups ahead)
+  constexpr int GF2 = NA * ZT * SEG;                // float2 per staged group
+  constexpr int LPW = ZT * SEG / 128;               // LDS-direct loads (1 KB) per wave per group
+  static_assert(NA == kThreads / 64 && SEG == 32 && LPW == 4 && TW % NA == 0 && kAdjPad >= SEG,
+                "staging layout");
+  __shared__ float4 tile4[NBUF * GF2 / 2];
   // Per-angle set-up for a window of TW angles, double-buffered by window
   // parity: first staged bin, fractional bin of the tile corner relative to
   // it, cos, sin, 1/h and 1/h^2.
   __shared__ int s_sl[2][TW];
   __shared__ float s_f0[2][TW], s_c[2][TW], s_s[2][TW], s_ih[2][TW], s_ih2[2][TW];
+  const float2* tile = reinterpret_cast<const float2*>(tile4);
   const int W = g.W, H = g.H, Wp = sino_row(W);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // logical order: tile x fastest, then tile y, then slice block
   const int L = xcd_logical(blockIdx.x, gridDim.x);
   const int nt = W / 16;
@@ -711,46 +712,58 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_adj(const float2* __restr
   const double X0 = (double)x0 - g.cW, X1 = X0 + 15.0;
   const double Y0 = (double)y0 - g.cW, Y1 = Y0 + 15.0;
 
-  // Set-up of angle w * TW + threadIdx.x, in double precision: the first
-  // staged bin is the lowest projection of the tile's corners minus two bins
-  // of margin, moved into [-kAdjPad, W + kAdjPad - SEG] (a segment outside
-  // that range lies wholly off the detector, and the padding it is moved to
-  // holds zeros); a voxel's fractional bin relative to it is
+  // Set-up of angle w * TW + t for threads t < TW, in double precision: the
+  // first staged bin is the lowest projection of the tile's corners minus two
+  // or three bins of margin (even, so each lane's bin pair is 16-byte
+  // aligned), moved into [-kAdjPad, W + kAdjPad - SEG] (a segment
+  // outside that range lies wholly off the detector, and the padding it is
+  // moved to holds zeros); a voxel's fractional bin relative to it is
   // f0 + dx cos + dy sin, a small number that single precision holds to
   // ~1e-6 of a bin.
   auto setup_window = [&](int w) {
-    const int slot = w & 1, t = threadIdx.x, kk = min(w * TW + t, K - 1);
-    const double* ap = ang + (size_t)kk * kAngleStride;
-    const double C = ap[kCos], Sn = ap[kSin], ih = ap[kInvH];
-    const double q0 = g.cW + X0 * C + Y0 * Sn;
-    int sl = (int)floor(g.cW + fmin(X0 * C, X1 * C) + fmin(Y0 * Sn, Y1 * Sn)) - 2;
-    sl = min(max(sl, -kAdjPad), W + kAdjPad - SEG);
-    s_sl[slot][t] = sl;
-    s_f0[slot][t] = (float)(q0 - (double)sl);
-    s_c[slot][t] = (float)C;
-    s_s[slot][t] = (float)Sn;
-    s_ih[slot][t] = (float)ih;
-    s_ih2[slot][t] = (float)(ih * ih);
-  };
-  // The sinogram is z-blocked and padded, S[k][z / ZT][kAdjPad + bin][z % ZT]:
-  // the ZT slices of one bin are one contiguous 128-byte run.  Element e of
-  // a thread is bin (TPB e) % SEG + threadIdx.x / ZT of angle (TPB e) / SEG
-  // of the group, i.e. float2 number threadIdx.x + ZT ((TPB e) % SEG) past
-  // the segment start of that angle.
-  const size_t HWp = (size_t)H * Wp;
-  const float2* Sz = S + (size_t)z0 * Wp + kAdjPad * ZT + threadIdx.x;
-  float2 pre[PER];
-  auto fetch = [&](int k0) {
-    const int slot = (k0 / TW) & 1, base = k0 % TW;
-    const float2* seg[NA];
-#pragma unroll
-    for (int a = 0; a < NA; ++a) {
-      const int kk = min(k0 + a, K - 1);                // past the end: never read back
-      const int sl = __builtin_amdgcn_readfirstlane(s_sl[slot][base + a]);
-      seg[a] = Sz + (size_t)kk * HWp + (ptrdiff_t)sl * ZT;
+    const int slot = w & 1, t = threadIdx.x;
+    if (t < TW) {
+      const int kk = min(w * TW + t, K - 1);
+      const double* ap = ang + (size_t)kk * kAngleStride;
+      const double C = ap[kCos], Sn = ap[kSin], ih = ap[kInvH];
+      const double q0 = g.cW + X0 * C + Y0 * Sn;
+      int sl = (int)floor(g.cW + fmin(X0 * C, X1 * C) + fmin(Y0 * Sn, Y1 * Sn)) - 2;
+      sl -= sl & 1;                                     // even: 16-byte aligned bin pairs
+      sl = min(max(sl, -kAdjPad), W + kAdjPad - SEG);
+      s_sl[slot][t] = sl;
+      s_f0[slot][t] = (float)(q0 - (double)sl);
+      s_c[slot][t] = (float)C;
+      s_s[slot][t] = (float)Sn;
+      s_ih[slot][t] = (float)ih;
+      s_ih2[slot][t] = (float)(ih * ih);
     }
+  };
+
+  // The sinogram is S[k][z][kAdjPad + bin].  Load i of wave a (angle a of the
+  // group) moves 1 KB: lane l brings bins 2 (l % 16) and 2 (l % 16) + 1 of
+  // the segment of slice 4 i + l / 16, which lands at byte 16 l of the
+  // load's 1 KB -- the [slice][bin] layout of that angle.  Issued as inline
+  // assembly (M0 = LDS destination) so the compiler adds no waits of its
+  // own; the loop waits for them explicitly.
+  const size_t HWp = (size_t)H * Wp;
+  const float2* Sl = S + (size_t)(z0 + (lane >> 4)) * Wp + kAdjPad + 2 * (lane & 15);
+  const unsigned lds0 = (unsigned)(uintptr_t)(__attribute__((address_space(3))) float4*)tile4;
+  auto issue = [&](int gidx) {
+    const int k0 = gidx * NA;
+    const int kk = min(k0 + wave, K - 1);                // past the end: never read back
+    const int sl = __builtin_amdgcn_readfirstlane(s_sl[(k0 / TW) & 1][k0 % TW + wave]);
+    const float2* src = Sl + (size_t)kk * HWp + sl;
+    const unsigned dst = __builtin_amdgcn_readfirstlane(
+        lds0 + (unsigned)((((gidx % NBUF) * GF2) + wave * ZT * SEG) * 8));
 #pragma unroll
-    for (int e = 0; e < PER; ++e) pre[e] = seg[(TPB * e) / SEG][ZT * ((TPB * e) % SEG)];
+    for (int i = 0; i < LPW; ++i)
+      asm volatile(
+          "s_mov_b32 m0, %0\n\t"
+          "s_nop 0\n\t"
+          "global_load_lds_dwordx4 %1, off"
+          :
+          : "s"(dst + 1024u * i), "v"(src + (size_t)4 * i * Wp)
+          : "memory", "m0");
   };
 
   float ax[ZT], ay[ZT];
@@ -758,26 +771,29 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_adj(const float2* __restr
 #pragma unroll
   for (int i = 0; i < ZT; ++i) { ax[i] = ay[i] = 0.f; ox[i] = oy[i] = 0.0; }
 
-  const int zz = threadIdx.x % ZT, tb = threadIdx.x / ZT;
-  float2* st = tile + tb * BP + zz;
+  const int ng = (K + NA - 1) / NA;
+  constexpr int GPW = TW / NA;                      // groups per set-up window
   setup_window(0);
   __syncthreads();
-  fetch(0);
-  for (int k0 = 0; k0 < K; k0 += NA) {
+  issue(0);
+  if (ng > 1) issue(1);
+  for (int gi = 0; gi < ng; ++gi) {
+    const int k0 = gi * NA;
     const int na = min(NA, K - k0);
-    __syncthreads();  // every wave is done with the previous group
-#pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int a = (TPB * e) / SEG, j = (TPB * e) % SEG;
-      st[(a * SEG + j) * BP] = pre[e];
-    }
-    const int kn = k0 + NA;
-    // the window of the next group's angles, into the slot of the window
-    // before the current one (no longer read)
-    if (kn < K && kn % TW == 0) setup_window(kn / TW);
-    __syncthreads();
-    if (kn < K) fetch(kn);
+    // this wave's loads of group gi are complete (those of gi + 1 may be in
+    // flight) and its LDS reads of group gi - 1 have returned; the barrier
+    // publishes group gi of every wave, retires group gi - 1 (whose buffer
+    // the loads of gi + 2 reuse) and the set-up window written below
+    if (gi + 1 < ng) asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)" ::"n"(LPW) : "memory");
+    else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (gi + 2 < ng) issue(gi + 2);
+    // the next window's set-up, written three groups before its first group
+    // is issued, into the slot of the window before the current one
+    if ((gi + 3) % GPW == 0 && (gi + 3) * NA < K) setup_window((gi + 3) / GPW);
     const int slot = (k0 / TW) & 1, base = k0 % TW;
+    const float2* gb = tile + (gi % NBUF) * GF2;
     for (int a = 0; a < na; ++a) {
       const float ih = s_ih[slot][base + a], ih2 = s_ih2[slot][base + a];
       const float qr = fmaf((float)dy, s_s[slot][base + a],
@@ -787,16 +803,28 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_adj(const float2* __restr
       const float w0 = fmaxf(0.0f, fmaf(-fr, ih2, ih));
       const float w1 = fmaxf(0.0f, fmaf(fr - 1.0f, ih2, ih));
       const int j0 = min(max((int)fl, 0), SEG - 2);
-      const float2* tp = tile + (a * SEG + j0) * BP;
+      const float2* tp = gb + a * ZT * SEG + j0;
+      // software pipeline: the taps of slice i + LA are requested before
+      // slice i is accumulated, so LA + 1 LDS reads are in flight
+      constexpr int LA = 3;
+      float4 v[ZT];
+#pragma unroll
+      for (int i = 0; i < LA; ++i) {
+        const float2 v0 = tp[i * SEG], v1 = tp[i * SEG + 1];
+        v[i] = make_float4(v0.x, v0.y, v1.x, v1.y);
+      }
 #pragma unroll
       for (int i = 0; i < ZT; ++i) {
-        const float2 v0 = tp[i], v1 = tp[BP + i];
-        ax[i] = fmaf(w1, v1.x, fmaf(w0, v0.x, ax[i]));
-        ay[i] = fmaf(w1, v1.y, fmaf(w0, v0.y, ay[i]));
+        if (i + LA < ZT) {
+          const float2 v0 = tp[(i + LA) * SEG], v1 = tp[(i + LA) * SEG + 1];
+          v[i + LA] = make_float4(v0.x, v0.y, v1.x, v1.y);
+        }
+        ax[i] = fmaf(w1, v[i].z, fmaf(w0, v[i].x, ax[i]));
+        ay[i] = fmaf(w1, v[i].w, fmaf(w0, v[i].y, ay[i]));
       }
     }
-    // single-precision partial sums of up to 4 NA angles, flushed to double
-    if (((k0 / NA) & 3) == 3 || kn >= K) {
+    // single-precision partial sums of up to 8 NA angles, flushed to double
+    if ((gi & 7) == 7 || gi + 1 >= ng) {
 #pragma unroll
       for (int i = 0; i < ZT; ++i) {
         ox[i] += (double)ax[i];
@@ -928,7 +956,7 @@ hipError_t launch_pass_c(const DevGeom& g, float2* X, const float2* psi, const f
 
 hipError_t launch_pass_d(const DevGeom& g, const float2* X, const float2* psi, float2* S,
                          int k_first, int Kc, hipStream_t st) {
-  const dim3 grid((g.H / kAdjZT) * (sino_row(g.W) / (kThreads / kAdjZT)), Kc);
+  const dim3 grid((g.H / 16) * (sino_row(g.W) / 16), Kc);
   k_pass_d<<<grid, kThreads, 0, st>>>(X, psi, S, g, k_first);
   return hipGetLastError();
 }
