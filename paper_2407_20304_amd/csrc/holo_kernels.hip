@@ -628,17 +628,29 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
       float rel = (float)(fA + (double)y * D - (double)s_xl[y]);
       rel = fminf(fmaxf(rel, rel_lo), rel_hi);
       const float2* tr = tile + (y % NBUF) * ROWF2 + zl;
-#pragma unroll
-      for (int b = 0; b < BPT; ++b) {
+      // software pipeline: the taps of bin b + LA are requested before bin b
+      // is accumulated, so the reads of LA + 1 bins are in flight
+      constexpr int LA = 2;
+      float4 v[BPT][2];
+      auto fetch_bin = [&](int b) {
         const float q = fmaf((float)b, Bf, rel);          // >= 0, < SEG - 2
-        const float w1 = __builtin_amdgcn_fractf(q), w0 = 1.0f - w1;
-        const int col = (int)q;                            // truncation = floor here
-        const float2* tp = tr + col * ZT;
+        const float2* tp = tr + (int)q * ZT;             // truncation = floor here
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
           const float2 v0 = tp[32 * m], v1 = tp[ZT + 32 * m];
-          ax[b][m] = fmaf(w1, v1.x, fmaf(w0, v0.x, ax[b][m]));
-          ay[b][m] = fmaf(w1, v1.y, fmaf(w0, v0.y, ay[b][m]));
+          v[b][m] = make_float4(v0.x, v0.y, v1.x, v1.y);
+        }
+      };
+#pragma unroll
+      for (int b = 0; b < LA; ++b) fetch_bin(b);
+#pragma unroll
+      for (int b = 0; b < BPT; ++b) {
+        if (b + LA < BPT) fetch_bin(b + LA);
+        const float w1 = __builtin_amdgcn_fractf(fmaf((float)b, Bf, rel)), w0 = 1.0f - w1;
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          ax[b][m] = fmaf(w1, v[b][m].z, fmaf(w0, v[b][m].x, ax[b][m]));
+          ay[b][m] = fmaf(w1, v[b][m].w, fmaf(w0, v[b][m].y, ay[b][m]));
         }
       }
       if ((y & 31) == 31) {
