@@ -29,6 +29,10 @@ constexpr int kThreads = 256;
 __host__ __device__ constexpr int rows_tl(int W) { return fft_row_threads(W); }
 __host__ __device__ constexpr int rows_lpw(int W) { return kThreads / fft_row_threads(W); }
 __host__ __device__ constexpr int cols_tc(int H) { return H >= 2048 ? 4 : (H >= 1024 ? 8 : 16); }
+// Pitch of one column line in the column kernels' LDS tile: the padded line
+// plus 4, so that the tile loads (8 columns x 4 rows per LDS pass) hit
+// distinct banks.
+__host__ __device__ constexpr int col_pitch(int H) { return fft_line_len(H) + 4; }
 
 int rows_per_wg(int W) { return rows_lpw(W); }
 int cols_per_wg(int H) { return cols_tc(H); }
@@ -135,8 +139,12 @@ __global__ __launch_bounds__(kThreads) void k_pass_a(const float2* __restrict__ 
                                                      int k_first) {
   constexpr int TL = rows_tl(W), LPW = rows_lpw(W), E = W / TL;
   __shared__ float2 s_tw[W];
-  __shared__ float2 s_line[LPW][W];
+  __shared__ float2 s_line[LPW][fft_line_len(W)];
   const int line = threadIdx.x / TL, lt = threadIdx.x % TL;
+  // padded position of element lt + e TL of the line (TL is a multiple of 8)
+  static_assert(TL % 8 == 0, "padded row addressing");
+  constexpr int TLP = TL + TL / 8;
+  const int lp = fpi(lt);
   const int z = blockIdx.x * LPW + line;
   const int f = blockIdx.y;
   const int k = f / g.nd, j = f % g.nd;
@@ -153,21 +161,21 @@ __global__ __launch_bounds__(kThreads) void k_pass_a(const float2* __restrict__ 
   for (int e = 0; e < E; ++e) {
     const int s = lt + e * TL;
     const AxisTaps txt = fwd_taps(g.cW, m, tx, s, W);
-    L[s] = cmul(Qrow[s], sample_phi(psik, W, tyt, txt));
+    L[lp + e * TLP] = cmul(Qrow[s], sample_phi(psik, W, tyt, txt));
   }
-  fft<W, TL, false>(L, s_tw, lt);
+  fft<W, TL, false, true>(L, s_tw, lt);
   const float2* ch = g.chirpW + (size_t)chirp_det(j) * W;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int s = lt + e * TL;
-    L[s] = cmul(L[s], ch[s]);
+    L[lp + e * TLP] = cmul(L[lp + e * TLP], ch[s]);
   }
-  fft<W, TL, true>(L, s_tw, lt);
+  fft<W, TL, true, true>(L, s_tw, lt);
   float2* out = X + ((size_t)f * g.H + z) * W;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int s = lt + e * TL;
-    out[s] = L[s];
+    out[s] = L[lp + e * TLP];
   }
 }
 
@@ -179,8 +187,12 @@ __global__ __launch_bounds__(kThreads) void k_pass_c(float2* __restrict__ X,
                                                      int accumulate, int k_first, int Kc) {
   constexpr int TL = rows_tl(W), LPW = rows_lpw(W), E = W / TL;
   __shared__ float2 s_tw[W];
-  __shared__ float2 s_line[LPW][W];
+  __shared__ float2 s_line[LPW][fft_line_len(W)];
   const int line = threadIdx.x / TL, lt = threadIdx.x % TL;
+  // padded position of element lt + e TL of the line (TL is a multiple of 8)
+  static_assert(TL % 8 == 0, "padded row addressing");
+  constexpr int TLP = TL + TL / 8;
+  const int lp = fpi(lt);
   const int z = blockIdx.x * LPW + line;
   const int j = blockIdx.y;
   for (int i = threadIdx.x; i < W; i += kThreads) s_tw[i] = g.twW[i];
@@ -195,14 +207,14 @@ __global__ __launch_bounds__(kThreads) void k_pass_c(float2* __restrict__ X,
   for (int k = 0; k < Kc; ++k) {
     float2* row = X + (((size_t)k * g.nd + j) * g.H + z) * W;
 #pragma unroll
-    for (int e = 0; e < E; ++e) L[lt + e * TL] = row[lt + e * TL];
-    fft<W, TL, false>(L, s_tw, lt);
+    for (int e = 0; e < E; ++e) L[lp + e * TLP] = row[lt + e * TL];
+    fft<W, TL, false, true>(L, s_tw, lt);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int s = lt + e * TL;
-      L[s] = cmulc(L[s], ch[s]);
+      L[lp + e * TLP] = cmulc(L[lp + e * TLP], ch[s]);
     }
-    fft<W, TL, true>(L, s_tw, lt);
+    fft<W, TL, true, true>(L, s_tw, lt);
     double ty, tx;
     shift_of(g, k_first + k, j, ty, tx);
     const AxisTaps tyt = fwd_taps(g.cH, m, ty, z, g.H);
@@ -210,7 +222,7 @@ __global__ __launch_bounds__(kThreads) void k_pass_c(float2* __restrict__ X,
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int s = lt + e * TL;
-      const float2 w = L[s];
+      const float2 w = L[lp + e * TLP];
       if (accumulate) {
         const AxisTaps txt = fwd_taps(g.cW, m, tx, s, W);
         const float2 phi = sample_phi(psik, W, tyt, txt);
@@ -236,26 +248,30 @@ template <int W>
 __global__ __launch_bounds__(kThreads) void k_rows_prop(PropJobs jobs, DevGeom g) {
   constexpr int TL = rows_tl(W), LPW = rows_lpw(W), E = W / TL;
   __shared__ float2 s_tw[W];
-  __shared__ float2 s_line[LPW][W];
+  __shared__ float2 s_line[LPW][fft_line_len(W)];
   const int line = threadIdx.x / TL, lt = threadIdx.x % TL;
+  // padded position of element lt + e TL of the line (TL is a multiple of 8)
+  static_assert(TL % 8 == 0, "padded row addressing");
+  constexpr int TLP = TL + TL / 8;
+  const int lp = fpi(lt);
   const int z = blockIdx.x * LPW + line;
   const PropJob& jb = jobs.job[blockIdx.y];
   for (int i = threadIdx.x; i < W; i += kThreads) s_tw[i] = g.twW[i];
   const float2* in = jb.src + (size_t)z * W;
   float2* L = s_line[line];
 #pragma unroll
-  for (int e = 0; e < E; ++e) L[lt + e * TL] = in[lt + e * TL];
-  fft<W, TL, false>(L, s_tw, lt);
+  for (int e = 0; e < E; ++e) L[lp + e * TLP] = in[lt + e * TL];
+  fft<W, TL, false, true>(L, s_tw, lt);
   const float2* ch = g.chirpW + (size_t)jb.chirp * W;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int s = lt + e * TL;
-    L[s] = jb.conj ? cmulc(L[s], ch[s]) : cmul(L[s], ch[s]);
+    L[lp + e * TLP] = jb.conj ? cmulc(L[lp + e * TLP], ch[s]) : cmul(L[lp + e * TLP], ch[s]);
   }
-  fft<W, TL, true>(L, s_tw, lt);
+  fft<W, TL, true, true>(L, s_tw, lt);
   float2* out = jb.dst + (size_t)z * W;
 #pragma unroll
-  for (int e = 0; e < E; ++e) out[lt + e * TL] = L[lt + e * TL];
+  for (int e = 0; e < E; ++e) out[lt + e * TL] = L[lp + e * TLP];
 }
 
 // ---------------------------------------------------------------------------
@@ -264,15 +280,19 @@ __global__ __launch_bounds__(kThreads) void k_rows_prop(PropJobs jobs, DevGeom g
 
 template <int NT>
 __device__ __forceinline__ void block_sum_store(double v, double* out) {
-  __shared__ double red[NT];
-  red[threadIdx.x] = v;
-  __syncthreads();
+  // butterfly sum within each wave, then the wave sums in order: a fixed
+  // summation order, so the result is reproducible bit for bit
+  __shared__ double red[NT / 64];
 #pragma unroll
-  for (int o = NT / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) t += red[w];
+    *out = t;
   }
-  if (threadIdx.x == 0) *out = red[0];
 }
 
 // r = 2 (v - a v/|v|) in place (v/|v| := 0 at |v| = 0); returns (|v| - a)^2.
@@ -306,8 +326,8 @@ __global__ __launch_bounds__(kColThreads) void k_pass_b(const float2* __restrict
                                                         double* __restrict__ Fpart, DevGeom g,
                                                         int ntiles) {
   constexpr int TC = cols_tc(H), TLc = kColThreads / TC;
-  __shared__ float2 s_tw[H];
-  __shared__ float2 s_col[TC][H + 1];
+  __shared__ float2 s_tw[H / 2];
+  __shared__ float2 s_col[TC][col_pitch(H)];
   const int c = threadIdx.x / TLc, lt = threadIdx.x % TLc;
   const int W = g.W;
   const int L = xcd_logical(blockIdx.x, gridDim.x);
@@ -315,18 +335,18 @@ __global__ __launch_bounds__(kColThreads) void k_pass_b(const float2* __restrict
   const int s0 = tile * TC;
   const int f = L / ntiles;
   const int j = f % g.nd;
-  for (int i = threadIdx.x; i < H; i += kColThreads) s_tw[i] = g.twH[i];
+  for (int i = threadIdx.x; i < H / 2; i += kColThreads) s_tw[i] = g.twH[i];
   const float2* in = (MODE == kColAdj ? src : X) + (size_t)f * H * W + s0;
   for (int i = threadIdx.x; i < H * TC; i += kColThreads) {
     const int zz = i / TC, cc = i % TC;
-    s_col[cc][zz] = in[(size_t)zz * W + cc];
+    s_col[cc][fpi(zz)] = in[(size_t)zz * W + cc];
   }
   float2* Lc = s_col[c];
   const float2* ch = g.chirpH + (size_t)chirp_det(j) * H;
   if (MODE != kColAdj) {
-    fft<H, TLc, false>(Lc, s_tw, lt);
-    for (int zz = lt; zz < H; zz += TLc) Lc[zz] = cmul(Lc[zz], ch[zz]);
-    fft<H, TLc, true>(Lc, s_tw, lt);
+    fft<H, TLc, false, true, true>(Lc, s_tw, lt);
+    for (int zz = lt; zz < H; zz += TLc) Lc[fpi(zz)] = cmul(Lc[fpi(zz)], ch[zz]);
+    fft<H, TLc, true, true, true>(Lc, s_tw, lt);
     __syncthreads();
   }
   if (MODE == kColObj || MODE == kColGrad) {
@@ -334,23 +354,23 @@ __global__ __launch_bounds__(kColThreads) void k_pass_b(const float2* __restrict
     const float* a = amp + (size_t)f * H * W + s0;
     for (int i = threadIdx.x; i < H * TC; i += kColThreads) {
       const int zz = i / TC, cc = i % TC;
-      float2 v = s_col[cc][zz];
+      float2 v = s_col[cc][fpi(zz)];
       acc += residual(v, a[(size_t)zz * W + cc]);
-      s_col[cc][zz] = v;
+      s_col[cc][fpi(zz)] = v;
     }
     block_sum_store<kColThreads>(acc, Fpart + (size_t)f * ntiles + tile);
   }
   if (MODE == kColGrad || MODE == kColAdj) {
-    fft<H, TLc, false>(Lc, s_tw, lt);
-    for (int zz = lt; zz < H; zz += TLc) Lc[zz] = cmulc(Lc[zz], ch[zz]);
-    fft<H, TLc, true>(Lc, s_tw, lt);
+    fft<H, TLc, false, true, true>(Lc, s_tw, lt);
+    for (int zz = lt; zz < H; zz += TLc) Lc[fpi(zz)] = cmulc(Lc[fpi(zz)], ch[zz]);
+    fft<H, TLc, true, true, true>(Lc, s_tw, lt);
     __syncthreads();
   }
   if (MODE != kColObj) {
     float2* out = X + (size_t)f * H * W + s0;
     for (int i = threadIdx.x; i < H * TC; i += kColThreads) {
       const int zz = i / TC, cc = i % TC;
-      out[(size_t)zz * W + cc] = s_col[cc][zz];
+      out[(size_t)zz * W + cc] = s_col[cc][fpi(zz)];
     }
   }
 }
@@ -359,32 +379,32 @@ template <int H>
 __global__ __launch_bounds__(kColThreads) void k_cols_prop(PropJobs jobs, double* __restrict__ Fpart,
                                                            DevGeom g) {
   constexpr int TC = cols_tc(H), TLc = kColThreads / TC;
-  __shared__ float2 s_tw[H];
-  __shared__ float2 s_col[TC][H + 1];
+  __shared__ float2 s_tw[H / 2];
+  __shared__ float2 s_col[TC][col_pitch(H)];
   const int c = threadIdx.x / TLc, lt = threadIdx.x % TLc;
   const int W = g.W;
   const int s0 = blockIdx.x * TC;
   const PropJob& jb = jobs.job[blockIdx.y];
-  for (int i = threadIdx.x; i < H; i += kColThreads) s_tw[i] = g.twH[i];
+  for (int i = threadIdx.x; i < H / 2; i += kColThreads) s_tw[i] = g.twH[i];
   const float2* in = jb.src + s0;
   for (int i = threadIdx.x; i < H * TC; i += kColThreads) {
     const int zz = i / TC, cc = i % TC;
-    s_col[cc][zz] = in[(size_t)zz * W + cc];
+    s_col[cc][fpi(zz)] = in[(size_t)zz * W + cc];
   }
   float2* L = s_col[c];
   const float2* ch = g.chirpH + (size_t)jb.chirp * H;
-  fft<H, TLc, false>(L, s_tw, lt);
-  for (int zz = lt; zz < H; zz += TLc) L[zz] = jb.conj ? cmulc(L[zz], ch[zz]) : cmul(L[zz], ch[zz]);
-  fft<H, TLc, true>(L, s_tw, lt);
+  fft<H, TLc, false, true, true>(L, s_tw, lt);
+  for (int zz = lt; zz < H; zz += TLc) L[fpi(zz)] = jb.conj ? cmulc(L[fpi(zz)], ch[zz]) : cmul(L[fpi(zz)], ch[zz]);
+  fft<H, TLc, true, true, true>(L, s_tw, lt);
   __syncthreads();
   if (jb.amp) {
     double acc = 0.0;
     const float* a = jb.amp + s0;
     for (int i = threadIdx.x; i < H * TC; i += kColThreads) {
       const int zz = i / TC, cc = i % TC;
-      float2 v = s_col[cc][zz];
+      float2 v = s_col[cc][fpi(zz)];
       acc += residual(v, a[(size_t)zz * W + cc]);
-      s_col[cc][zz] = v;
+      s_col[cc][fpi(zz)] = v;
     }
     block_sum_store<kColThreads>(acc, Fpart + (size_t)jb.fslot * gridDim.x + blockIdx.x);
     __syncthreads();
@@ -392,7 +412,7 @@ __global__ __launch_bounds__(kColThreads) void k_cols_prop(PropJobs jobs, double
   float2* out = jb.dst + s0;
   for (int i = threadIdx.x; i < H * TC; i += kColThreads) {
     const int zz = i / TC, cc = i % TC;
-    out[(size_t)zz * W + cc] = s_col[cc][zz];
+    out[(size_t)zz * W + cc] = s_col[cc][fpi(zz)];
   }
 }
 
