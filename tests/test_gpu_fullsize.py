@@ -1,6 +1,8 @@
-"""Parity at the full 1024^3 / 1800-angle size, in the launch configuration
-the benchmark times (chunks of 64 angles), on outputs the oracle can compute
-one angle at a time, plus properties that hold at any size.
+"""Parity at the full sizes -- the 1024^3 / 1800-angle volume in the launch
+configuration the benchmark times (chunks of 64 angles), and the
+2048^2 x 512-slice slab with 900 angles (chunks of 32) -- on outputs the
+oracle can compute one angle at a time, plus properties that hold at any
+size.
 
 The oracle's ray sums are slice-local, so it runs slab by slab (printing
 progress) on the same complex64 volume the GPU sees."""
@@ -28,11 +30,17 @@ def full():
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+    yield workload_inputs("vol1024_a1800")
+    torch.cuda.empty_cache()
+
+
+def workload_inputs(name):
+    import torch
     from paper_2407_20304_amd import holo, synth
-    wl = synth.WORKLOADS["vol1024_a1800"]
+    wl = synth.WORKLOADS[name]
     dev = torch.device("cuda:0")
     sd = lambda role: synth.seed_of(wl.config, role)
-    say("full-size inputs")
+    say("full-size inputs", name)
     u = synth.ellipsoid_volume(wl.W, wl.H, sd(4), device=dev)
     q_np = synth.probe(wl.H, wl.W, sd(5))
     q = torch.from_numpy(q_np).to(dev)
@@ -61,15 +69,13 @@ def oracle_radon_T(h, theta, W, slab=128):
     return np.concatenate(out, axis=0)
 
 
-def test_one_angle_forward_and_gradient_at_full_size(full):
+def one_angle_parity(inputs, k, slab):
     import torch
-    holo, synth, wl, u, q, q_np, amp, amp_ref = full
-    k = K_SAMPLE
+    holo, synth, wl, u, q, q_np, amp, amp_ref = inputs
     theta = float(wl.theta[k])
-    geom1 = O.Geometry(H=wl.H, W=wl.W, theta=[theta], mag_rel=wl.mag_rel, m0=wl.m0,
-                       fresnel0=wl.fresnel0, kappa=wl.kappa)
-    # GPU: the benchmark's plan (1800 angles, chunks of 64) for the forward
-    # field of angle k, and a one-angle plan for the full gradient.
+    # GPU: the benchmark-style plan (all angles, the workload's chunks) for
+    # the forward field of angle k, and a one-angle plan for the full
+    # gradient.
     plan = holo.Plan.for_workload(wl)
     v_gpu = plan.holo_fwd(u, q, k, k + 1).cpu().numpy()[0]
     plan.close()
@@ -79,11 +85,11 @@ def test_one_angle_forward_and_gradient_at_full_size(full):
     gq_gpu = gq_gpu.cpu().numpy()
     u_np = u.cpu().numpy()
     gu_gpu = gu_gpu.cpu().numpy()
-    del plan1
+    plan1.close()
     torch.cuda.empty_cache()
 
-    say("oracle, angle %d at 1024^3" % k)
-    p = oracle_radon(u_np, theta)
+    say("oracle, angle %d of %s" % (k, wl.name))
+    p = oracle_radon(u_np, theta, slab)
     psi = np.exp(1j * wl.kappa * p)
     del p
     qc = q_np.astype(np.complex128)
@@ -96,12 +102,17 @@ def test_one_angle_forward_and_gradient_at_full_size(full):
         assert e < TOL
     F_ref, g_psi, gq_ref = O.holo2d_gradient(psi, qc, a_k, a_ref, wl.mag_rel, wl.m0, wl.fresnel0)
     h = -1j * wl.kappa * np.conj(psi) * g_psi
-    gu_ref = oracle_radon_T(h, theta, wl.W)
+    del u_np
+    gu_ref = oracle_radon_T(h, theta, wl.W, slab)
     eF = abs(F_gpu - F_ref) / F_ref
     eq = O.rel_err(gq_gpu, gq_ref)
     eu = O.rel_err(gu_gpu, gu_ref)
     say("  F %.2e  g_q %.2e  g_u %.2e" % (eF, eq, eu))
     assert eF < TOL and eq < TOL and eu < TOL
+
+
+def test_one_angle_forward_and_gradient_at_full_size(full):
+    one_angle_parity(full, K_SAMPLE, 128)
 
 
 def test_full_workload_invariants(full):
@@ -144,3 +155,18 @@ def test_full_workload_invariants(full):
         del up, um
         say("  direction %d: analytic %.6e fd %.6e" % (d, an, fd))
         assert abs(an - fd) / abs(fd) < 1e-3
+
+
+@pytest.fixture(scope="module")
+def slab():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    yield workload_inputs("slab2048x512_a900")
+    torch.cuda.empty_cache()
+
+
+def test_one_angle_forward_and_gradient_on_the_2048_slab(slab):
+    # 42.4 degrees: a walk along y whose 2048-wide row windows split the
+    # angle groups; 2048-point row transforms, 512-point column transforms
+    one_angle_parity(slab, 212, 32)
