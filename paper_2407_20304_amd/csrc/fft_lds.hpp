@@ -51,23 +51,17 @@ __host__ __device__ constexpr int fft_pstride(int N, int s) {
 __host__ __device__ constexpr int fft_row_threads(int N) { return pow2_floor(N / 8); }
 
 // Padded line layout (PADDED transforms): element n of a line is stored at
-// n + n / 8.  The first radix-8 stages write with strides of 8 and 64
-// elements, which in a plain layout put 8 resp. 4 lanes of an LDS pass on
-// one bank; the padding spreads them over all banks.  HALFTW transforms
-// take a half-length twiddle table, w[m + N/2] = -w[m] (for callers short of
-// LDS; it costs a few VALU operations per twiddle).
-__host__ __device__ constexpr int fft_line_len(int N) { return N + N / 8; }
-__device__ __forceinline__ int fpi(int n) { return (int)((unsigned)n + ((unsigned)n >> 3)); }
+// n + n / 32, one spare slot per 32 elements (one bank cycle of 8-byte
+// elements).  Contiguous accesses stay conflict-free, and the first radix-8
+// stage, which writes with a stride of 8 elements (8 lanes of an LDS pass on
+// one bank in a plain layout), becomes conflict-free too.
+__host__ __device__ constexpr int fft_line_len(int N) { return N + N / 32; }
+__device__ __forceinline__ int fpi(int n) { return (int)((unsigned)n + ((unsigned)n >> 5)); }
 template <bool PADDED>
 __device__ __forceinline__ int fidx(int n) { return PADDED ? fpi(n) : n; }
-
-template <int N, bool HALFTW>
-__device__ __forceinline__ float2 twiddle(const float2* tw, int m) {
-  if (!HALFTW) return tw[m];
-  const bool hi = m >= N / 2;
-  float2 w = tw[hi ? m - N / 2 : m];
-  return hi ? make_float2(-w.x, -w.y) : w;
-}
+// padded length of a compile-time step
+template <bool PADDED>
+__host__ __device__ constexpr int pstep(int d) { return PADDED ? d + d / 32 : d; }
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -145,25 +139,33 @@ template <bool INV> struct Dft<8, INV> {
 };
 
 // One Stockham stage on `line` (LDS), executed by TL threads (thread lt).
-template <int N, int TL, int R, int P, bool INV, bool PADDED, bool HALFTW>
+template <int N, int TL, int R, int P, bool INV, bool PADDED>
 __device__ __forceinline__ void fft_stage(float2* line, const float2* tw, int lt) {
   constexpr int NB = N / R;
   constexpr int IT = (NB + TL - 1) / TL;
-  static_assert(!PADDED || NB % 8 == 0, "padded reads need strides that are multiples of 8");
-  // Padded addresses as a per-butterfly base plus compile-time steps: the
-  // read stride NB and, where the output positions of a butterfly stay in
-  // one group of 8 (or step by multiples of 8), the write stride P.
-  constexpr int RS = PADDED ? NB + NB / 8 : NB;
-  constexpr bool WLIN = !PADDED || P % 8 == 0 || (P == 1 && 8 % R == 0);
-  constexpr int WS = !PADDED ? P : (P % 8 == 0 ? P + P / 8 : 1);
+  // Padded addresses as a per-butterfly base plus compile-time steps:
+  // fpi(b + j d) = fpi(b) + j d + (j d) / 32 whenever the base's offset
+  // within its group of 32 never changes which group step j d lands in.
+  // Reads (b = i < NB, d = NB): NB a multiple of 32 or a divisor of 32.
+  // Writes (b = (i - k) R + k, d = P): P a multiple of 32, or P dividing 32
+  // with P R a divisor or a multiple of 32.  Other strides (around a radix-3
+  // stage) map each address on its own.
+  constexpr bool RLIN = !PADDED || NB % 32 == 0 || 32 % NB == 0;
+  constexpr bool WLIN = !PADDED || P % 32 == 0 ||
+                        (32 % P == 0 && (32 % (P * R) == 0 || (P * R) % 32 == 0));
   float2 v[IT][R];
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int i = lt + it * TL;
     if (NB % TL == 0 || i < NB) {
-      const int rb = fidx<PADDED>(i);
+      if constexpr (RLIN) {
+        const int rb = fidx<PADDED>(i);
 #pragma unroll
-      for (int j = 0; j < R; ++j) v[it][j] = line[rb + j * RS];
+        for (int j = 0; j < R; ++j) v[it][j] = line[rb + pstep<PADDED>(j * NB)];
+      } else {
+#pragma unroll
+        for (int j = 0; j < R; ++j) v[it][j] = line[fidx<PADDED>(i + j * NB)];
+      }
     }
   }
   __syncthreads();
@@ -175,7 +177,7 @@ __device__ __forceinline__ void fft_stage(float2* line, const float2* tw, int lt
       if (P > 1) {
 #pragma unroll
         for (int j = 1; j < R; ++j) {
-          float2 w = twiddle<N, HALFTW>(tw, j * k * (N / (P * R)));
+          float2 w = tw[j * k * (N / (P * R))];
           if (INV) w.y = -w.y;
           v[it][j] = cmul(v[it][j], w);
         }
@@ -185,7 +187,7 @@ __device__ __forceinline__ void fft_stage(float2* line, const float2* tw, int lt
       if constexpr (WLIN) {
         const int wb = fidx<PADDED>(base);
 #pragma unroll
-        for (int j = 0; j < R; ++j) line[wb + j * WS] = v[it][j];
+        for (int j = 0; j < R; ++j) line[wb + pstep<PADDED>(j * P)] = v[it][j];
       } else {
 #pragma unroll
         for (int j = 0; j < R; ++j) line[fidx<PADDED>(base + j * P)] = v[it][j];
@@ -195,23 +197,23 @@ __device__ __forceinline__ void fft_stage(float2* line, const float2* tw, int lt
   __syncthreads();
 }
 
-template <int N, int TL, bool INV, bool PADDED, bool HALFTW, int S>
+template <int N, int TL, bool INV, bool PADDED, int S>
 __device__ __forceinline__ void fft_stages(float2* line, const float2* tw, int lt) {
   if constexpr (S < fft_nstages(N)) {
-    fft_stage<N, TL, fft_radix(N, S), fft_pstride(N, S), INV, PADDED, HALFTW>(line, tw, lt);
-    fft_stages<N, TL, INV, PADDED, HALFTW, S + 1>(line, tw, lt);
+    fft_stage<N, TL, fft_radix(N, S), fft_pstride(N, S), INV, PADDED>(line, tw, lt);
+    fft_stages<N, TL, INV, PADDED, S + 1>(line, tw, lt);
   }
 }
 
 // Unnormalised DFT of `line` (forward: exp(-2 pi i jk/N); INV: exp(+...)).
 // All threads of the workgroup must call it (it synchronises); the line must
 // be fully written before the call.  PADDED: the line is stored padded
-// (element n at fpi(n), fft_line_len(N) elements), otherwise plain.
-// HALFTW: `tw` holds the first N/2 twiddles, otherwise all N.
-template <int N, int TL, bool INV, bool PADDED = false, bool HALFTW = false>
+// (element n at fpi(n), fft_line_len(N) elements), otherwise plain.  `tw`
+// holds the N twiddles.
+template <int N, int TL, bool INV, bool PADDED = false>
 __device__ __forceinline__ void fft(float2* line, const float2* tw, int lt) {
   __syncthreads();
-  fft_stages<N, TL, INV, PADDED, HALFTW, 0>(line, tw, lt);
+  fft_stages<N, TL, INV, PADDED, 0>(line, tw, lt);
 }
 
 }  // namespace holo

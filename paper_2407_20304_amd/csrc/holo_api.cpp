@@ -238,7 +238,8 @@ extern "C" holo_status holo_plan_create(const holo_geom* geom, holo_plan** out) 
     P->off_S = o;   o = align_up(o + (size_t)P->H * sino_row(P->W) * sizeof(float2) * P->n_angles);
     const size_t tiles = (size_t)P->W / cols_per_wg(P->H);
     P->n_fpart = tiles * (1 + (size_t)P->n_angles * P->nd);
-    P->off_F = o;   o = align_up(o + P->n_fpart * sizeof(double));
+    // cost partials, then the reduction's stage-one sums
+    P->off_F = o;   o = align_up(o + (P->n_fpart + kReduceParts) * sizeof(double));
     P->ws_bytes = o;
 
     // Device table layout.
@@ -531,7 +532,9 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
   }
   if (want_F) {
     const size_t n = (size_t)tiles * (1 + (size_t)(k1 - k0) * nd);
-    HOLO_HIP(timed(P, HOLO_K_OTHER, st, [&] { return launch_reduce_sum(Fpart, n, F, st); }));
+    HOLO_HIP(timed(P, HOLO_K_OTHER, st, [&] {
+      return launch_reduce_sum(Fpart, n, Fpart + P->n_fpart, F, st);
+    }));
   }
   return HOLO_OK;
 }

@@ -106,6 +106,9 @@ hipError_t launch_block_volume(const DevGeom& g, const float2* u, float2* ub, fl
 hipError_t launch_fill_zero(float2* p, size_t n, hipStream_t st);
 hipError_t launch_sum_frames(const float2* G, int nd, const float2* extra, float2* out,
                              size_t n, hipStream_t st);
-hipError_t launch_reduce_sum(const double* parts, size_t n, double* out, hipStream_t st);
+// Deterministic two-stage sum of n doubles; `scratch` holds kReduceParts.
+constexpr int kReduceParts = 256;
+hipError_t launch_reduce_sum(const double* parts, size_t n, double* scratch, double* out,
+                             hipStream_t st);
 
 }  // namespace holo

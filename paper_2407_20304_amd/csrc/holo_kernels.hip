@@ -17,6 +17,8 @@
 // Positions and interpolation weights are formed in double precision; field
 // arithmetic is single precision; costs and long ray/angle sums are carried
 // in double.
+#include <algorithm>
+
 #include "holo_internal.hpp"
 #include "fft_lds.hpp"
 
@@ -32,6 +34,11 @@ __host__ __device__ constexpr int cols_tc(int H) { return H >= 2048 ? 4 : (H >= 
 // Pitch of one column line in the column kernels' LDS tile: the padded line
 // plus 4, so that the tile loads (8 columns x 4 rows per LDS pass) hit
 // distinct banks.
+// Padded LDS position of element lt + e TL of a row line (see fpi).
+template <int TL>
+__device__ __forceinline__ int rowpos(int lp, int lt, int e) {
+  return TL % 32 == 0 ? lp + e * (TL + TL / 32) : fpi(lt + e * TL);
+}
 __host__ __device__ constexpr int col_pitch(int H) { return fft_line_len(H) + 4; }
 
 int rows_per_wg(int W) { return rows_lpw(W); }
@@ -141,10 +148,7 @@ __global__ __launch_bounds__(kThreads) void k_pass_a(const float2* __restrict__ 
   __shared__ float2 s_tw[W];
   __shared__ float2 s_line[LPW][fft_line_len(W)];
   const int line = threadIdx.x / TL, lt = threadIdx.x % TL;
-  // padded position of element lt + e TL of the line (TL is a multiple of 8)
-  static_assert(TL % 8 == 0, "padded row addressing");
-  constexpr int TLP = TL + TL / 8;
-  const int lp = fpi(lt);
+  const int lp = fpi(lt);   // padded position of the thread's first element
   const int z = blockIdx.x * LPW + line;
   const int f = blockIdx.y;
   const int k = f / g.nd, j = f % g.nd;
@@ -161,21 +165,21 @@ __global__ __launch_bounds__(kThreads) void k_pass_a(const float2* __restrict__ 
   for (int e = 0; e < E; ++e) {
     const int s = lt + e * TL;
     const AxisTaps txt = fwd_taps(g.cW, m, tx, s, W);
-    L[lp + e * TLP] = cmul(Qrow[s], sample_phi(psik, W, tyt, txt));
+    L[rowpos<TL>(lp, lt, e)] = cmul(Qrow[s], sample_phi(psik, W, tyt, txt));
   }
   fft<W, TL, false, true>(L, s_tw, lt);
   const float2* ch = g.chirpW + (size_t)chirp_det(j) * W;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int s = lt + e * TL;
-    L[lp + e * TLP] = cmul(L[lp + e * TLP], ch[s]);
+    L[rowpos<TL>(lp, lt, e)] = cmul(L[rowpos<TL>(lp, lt, e)], ch[s]);
   }
   fft<W, TL, true, true>(L, s_tw, lt);
   float2* out = X + ((size_t)f * g.H + z) * W;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int s = lt + e * TL;
-    out[s] = L[lp + e * TLP];
+    out[s] = L[rowpos<TL>(lp, lt, e)];
   }
 }
 
@@ -189,10 +193,7 @@ __global__ __launch_bounds__(kThreads) void k_pass_c(float2* __restrict__ X,
   __shared__ float2 s_tw[W];
   __shared__ float2 s_line[LPW][fft_line_len(W)];
   const int line = threadIdx.x / TL, lt = threadIdx.x % TL;
-  // padded position of element lt + e TL of the line (TL is a multiple of 8)
-  static_assert(TL % 8 == 0, "padded row addressing");
-  constexpr int TLP = TL + TL / 8;
-  const int lp = fpi(lt);
+  const int lp = fpi(lt);   // padded position of the thread's first element
   const int z = blockIdx.x * LPW + line;
   const int j = blockIdx.y;
   for (int i = threadIdx.x; i < W; i += kThreads) s_tw[i] = g.twW[i];
@@ -207,12 +208,12 @@ __global__ __launch_bounds__(kThreads) void k_pass_c(float2* __restrict__ X,
   for (int k = 0; k < Kc; ++k) {
     float2* row = X + (((size_t)k * g.nd + j) * g.H + z) * W;
 #pragma unroll
-    for (int e = 0; e < E; ++e) L[lp + e * TLP] = row[lt + e * TL];
+    for (int e = 0; e < E; ++e) L[rowpos<TL>(lp, lt, e)] = row[lt + e * TL];
     fft<W, TL, false, true>(L, s_tw, lt);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int s = lt + e * TL;
-      L[lp + e * TLP] = cmulc(L[lp + e * TLP], ch[s]);
+      L[rowpos<TL>(lp, lt, e)] = cmulc(L[rowpos<TL>(lp, lt, e)], ch[s]);
     }
     fft<W, TL, true, true>(L, s_tw, lt);
     double ty, tx;
@@ -222,7 +223,7 @@ __global__ __launch_bounds__(kThreads) void k_pass_c(float2* __restrict__ X,
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int s = lt + e * TL;
-      const float2 w = L[lp + e * TLP];
+      const float2 w = L[rowpos<TL>(lp, lt, e)];
       if (accumulate) {
         const AxisTaps txt = fwd_taps(g.cW, m, tx, s, W);
         const float2 phi = sample_phi(psik, W, tyt, txt);
@@ -250,28 +251,25 @@ __global__ __launch_bounds__(kThreads) void k_rows_prop(PropJobs jobs, DevGeom g
   __shared__ float2 s_tw[W];
   __shared__ float2 s_line[LPW][fft_line_len(W)];
   const int line = threadIdx.x / TL, lt = threadIdx.x % TL;
-  // padded position of element lt + e TL of the line (TL is a multiple of 8)
-  static_assert(TL % 8 == 0, "padded row addressing");
-  constexpr int TLP = TL + TL / 8;
-  const int lp = fpi(lt);
+  const int lp = fpi(lt);   // padded position of the thread's first element
   const int z = blockIdx.x * LPW + line;
   const PropJob& jb = jobs.job[blockIdx.y];
   for (int i = threadIdx.x; i < W; i += kThreads) s_tw[i] = g.twW[i];
   const float2* in = jb.src + (size_t)z * W;
   float2* L = s_line[line];
 #pragma unroll
-  for (int e = 0; e < E; ++e) L[lp + e * TLP] = in[lt + e * TL];
+  for (int e = 0; e < E; ++e) L[rowpos<TL>(lp, lt, e)] = in[lt + e * TL];
   fft<W, TL, false, true>(L, s_tw, lt);
   const float2* ch = g.chirpW + (size_t)jb.chirp * W;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int s = lt + e * TL;
-    L[lp + e * TLP] = jb.conj ? cmulc(L[lp + e * TLP], ch[s]) : cmul(L[lp + e * TLP], ch[s]);
+    L[rowpos<TL>(lp, lt, e)] = jb.conj ? cmulc(L[rowpos<TL>(lp, lt, e)], ch[s]) : cmul(L[rowpos<TL>(lp, lt, e)], ch[s]);
   }
   fft<W, TL, true, true>(L, s_tw, lt);
   float2* out = jb.dst + (size_t)z * W;
 #pragma unroll
-  for (int e = 0; e < E; ++e) out[lt + e * TL] = L[lp + e * TLP];
+  for (int e = 0; e < E; ++e) out[lt + e * TL] = L[rowpos<TL>(lp, lt, e)];
 }
 
 // ---------------------------------------------------------------------------
@@ -326,7 +324,7 @@ __global__ __launch_bounds__(kColThreads) void k_pass_b(const float2* __restrict
                                                         double* __restrict__ Fpart, DevGeom g,
                                                         int ntiles) {
   constexpr int TC = cols_tc(H), TLc = kColThreads / TC;
-  __shared__ float2 s_tw[H / 2];
+  __shared__ float2 s_tw[H];
   __shared__ float2 s_col[TC][col_pitch(H)];
   const int c = threadIdx.x / TLc, lt = threadIdx.x % TLc;
   const int W = g.W;
@@ -335,7 +333,7 @@ __global__ __launch_bounds__(kColThreads) void k_pass_b(const float2* __restrict
   const int s0 = tile * TC;
   const int f = L / ntiles;
   const int j = f % g.nd;
-  for (int i = threadIdx.x; i < H / 2; i += kColThreads) s_tw[i] = g.twH[i];
+  for (int i = threadIdx.x; i < H; i += kColThreads) s_tw[i] = g.twH[i];
   const float2* in = (MODE == kColAdj ? src : X) + (size_t)f * H * W + s0;
   for (int i = threadIdx.x; i < H * TC; i += kColThreads) {
     const int zz = i / TC, cc = i % TC;
@@ -344,9 +342,9 @@ __global__ __launch_bounds__(kColThreads) void k_pass_b(const float2* __restrict
   float2* Lc = s_col[c];
   const float2* ch = g.chirpH + (size_t)chirp_det(j) * H;
   if (MODE != kColAdj) {
-    fft<H, TLc, false, true, true>(Lc, s_tw, lt);
+    fft<H, TLc, false, true>(Lc, s_tw, lt);
     for (int zz = lt; zz < H; zz += TLc) Lc[fpi(zz)] = cmul(Lc[fpi(zz)], ch[zz]);
-    fft<H, TLc, true, true, true>(Lc, s_tw, lt);
+    fft<H, TLc, true, true>(Lc, s_tw, lt);
     __syncthreads();
   }
   if (MODE == kColObj || MODE == kColGrad) {
@@ -361,9 +359,9 @@ __global__ __launch_bounds__(kColThreads) void k_pass_b(const float2* __restrict
     block_sum_store<kColThreads>(acc, Fpart + (size_t)f * ntiles + tile);
   }
   if (MODE == kColGrad || MODE == kColAdj) {
-    fft<H, TLc, false, true, true>(Lc, s_tw, lt);
+    fft<H, TLc, false, true>(Lc, s_tw, lt);
     for (int zz = lt; zz < H; zz += TLc) Lc[fpi(zz)] = cmulc(Lc[fpi(zz)], ch[zz]);
-    fft<H, TLc, true, true, true>(Lc, s_tw, lt);
+    fft<H, TLc, true, true>(Lc, s_tw, lt);
     __syncthreads();
   }
   if (MODE != kColObj) {
@@ -379,13 +377,13 @@ template <int H>
 __global__ __launch_bounds__(kColThreads) void k_cols_prop(PropJobs jobs, double* __restrict__ Fpart,
                                                            DevGeom g) {
   constexpr int TC = cols_tc(H), TLc = kColThreads / TC;
-  __shared__ float2 s_tw[H / 2];
+  __shared__ float2 s_tw[H];
   __shared__ float2 s_col[TC][col_pitch(H)];
   const int c = threadIdx.x / TLc, lt = threadIdx.x % TLc;
   const int W = g.W;
   const int s0 = blockIdx.x * TC;
   const PropJob& jb = jobs.job[blockIdx.y];
-  for (int i = threadIdx.x; i < H / 2; i += kColThreads) s_tw[i] = g.twH[i];
+  for (int i = threadIdx.x; i < H; i += kColThreads) s_tw[i] = g.twH[i];
   const float2* in = jb.src + s0;
   for (int i = threadIdx.x; i < H * TC; i += kColThreads) {
     const int zz = i / TC, cc = i % TC;
@@ -393,9 +391,9 @@ __global__ __launch_bounds__(kColThreads) void k_cols_prop(PropJobs jobs, double
   }
   float2* L = s_col[c];
   const float2* ch = g.chirpH + (size_t)jb.chirp * H;
-  fft<H, TLc, false, true, true>(L, s_tw, lt);
+  fft<H, TLc, false, true>(L, s_tw, lt);
   for (int zz = lt; zz < H; zz += TLc) L[fpi(zz)] = jb.conj ? cmulc(L[fpi(zz)], ch[zz]) : cmul(L[fpi(zz)], ch[zz]);
-  fft<H, TLc, true, true, true>(L, s_tw, lt);
+  fft<H, TLc, true, true>(L, s_tw, lt);
   __syncthreads();
   if (jb.amp) {
     double acc = 0.0;
@@ -894,11 +892,14 @@ __global__ void k_sum_frames(const float2* __restrict__ G, int nd, const float2*
 }
 
 // Deterministic single-workgroup sum of double partials.
+// Workgroup b sums parts[b per, min(n, (b + 1) per)) into out[b]; a fixed
+// partition and order, so the total is reproducible bit for bit.
 __global__ __launch_bounds__(kThreads) void k_reduce_sum(const double* __restrict__ parts, size_t n,
-                                                         double* __restrict__ out) {
+                                                         size_t per, double* __restrict__ out) {
+  const size_t lo = (size_t)blockIdx.x * per, hi = min(n, lo + per);
   double acc = 0.0;
-  for (size_t i = threadIdx.x; i < n; i += kThreads) acc += parts[i];
-  block_sum_store<kThreads>(acc, out);
+  for (size_t i = lo + threadIdx.x; i < hi; i += kThreads) acc += parts[i];
+  block_sum_store<kThreads>(acc, out + blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1034,8 +1035,15 @@ hipError_t launch_sum_frames(const float2* G, int nd, const float2* extra, float
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_sum(const double* parts, size_t n, double* out, hipStream_t st) {
-  k_reduce_sum<<<1, kThreads, 0, st>>>(parts, n, out);
+hipError_t launch_reduce_sum(const double* parts, size_t n, double* scratch, double* out,
+                             hipStream_t st) {
+  // two stages: up to kReduceParts workgroups of consecutive partials, then one
+  const size_t g = std::max<size_t>(1, std::min<size_t>(kReduceParts, (n + 8191) / 8192));
+  const size_t per = (n + g - 1) / g;
+  k_reduce_sum<<<(unsigned)g, kThreads, 0, st>>>(parts, n, per, scratch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_reduce_sum<<<1, kThreads, 0, st>>>(scratch, g, g, out);
   return hipGetLastError();
 }
 
