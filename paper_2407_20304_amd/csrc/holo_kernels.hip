@@ -7,13 +7,15 @@
 //   pass C  rows:    row FFT * conj(transfer) * IFFT -> w,
 //                    G_j += conj(phi) w (probe gradient), X := conj(Q_j) w
 //   pass D  pixels:  g_psi = sum_j B^T X_j (gather), h = -i kappa conj(psi) g_psi
-// Ray sums (bound by LDS operand delivery and VALU):
-//   radon_fwd  Joseph ray sums, angle groups sharing LDS-staged row windows
-//              (lanes = bins, each thread owns kFwdZT slices), fused
+// Ray sums (bound by VALU and LDS operand delivery):
+//   radon_fwd  Joseph ray sums, angle groups sharing row windows staged in
+//              LDS by LDS-direct loads (lanes = consecutive slices of one
+//              bin, each thread owns 2 slices x 8 bins), fused
 //              exp(i kappa p) epilogue
 //   radon_adj  transpose as a triangle-footprint gather over all angles
 //              (lanes = a 16 x 16 voxel tile, each thread owns kAdjZT
 //              slices), sinogram segments staged in LDS per angle group
+//              by LDS-direct loads
 // Positions and interpolation weights are formed in double precision; field
 // arithmetic is single precision; costs and long ray/angle sums are carried
 // in double.
