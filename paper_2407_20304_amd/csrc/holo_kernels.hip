@@ -16,9 +16,10 @@
 //              (lanes = a 16 x 16 voxel tile, each thread owns kAdjZT
 //              slices), sinogram segments staged in LDS per angle group
 //              by LDS-direct loads
-// Positions and interpolation weights are formed in double precision; field
-// arithmetic is single precision; costs and long ray/angle sums are carried
-// in double.
+// Positions and interpolation weights are formed in double precision (or as
+// single-precision offsets of a few bins from double-precision bases); field
+// arithmetic is single precision; costs and long ray sums are carried in
+// double, the transpose's sums over angles in two levels of single precision.
 #include <algorithm>
 
 #include "holo_internal.hpp"
@@ -715,12 +716,12 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
 // is read without bounds checks.  A voxel projecting to fractional bin q
 // takes max(0, 1 - |i - q| / h) / h of bin i (h = max(|cos|, |sin|)) --
 // exactly the weight Joseph's interpolation gave it.
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_radon_adj(const float2* __restrict__ S,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_radon_adj(const float2* __restrict__ S,
                                                          float2* __restrict__ gu, DevGeom g,
                                                          const double* __restrict__ ang,
                                                          int K) {
   constexpr int ZT = kAdjZT, NA = kAdjNA, SEG = kAdjSeg, TW = kAdjWin;
-  constexpr int NBUF = 3;                           // group buffers (loads run 2 groups ahead)
+  constexpr int NBUF = 2;                           // group buffers (loads run 1 group ahead)
   constexpr int GF2 = NA * ZT * SEG;                // float2 per staged group
   constexpr int LPW = ZT * SEG / 128;               // LDS-direct loads (1 KB) per wave per group
   static_assert(NA == kThreads / 64 && SEG == 32 && LPW == 4 && TW % NA == 0 && kAdjPad >= SEG,
@@ -799,31 +800,29 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 3))
   };
 
   float ax[ZT], ay[ZT];
-  double ox[ZT], oy[ZT];
+  float ox[ZT], oy[ZT];
 #pragma unroll
-  for (int i = 0; i < ZT; ++i) { ax[i] = ay[i] = 0.f; ox[i] = oy[i] = 0.0; }
+  for (int i = 0; i < ZT; ++i) { ax[i] = ay[i] = 0.f; ox[i] = oy[i] = 0.f; }
 
   const int ng = (K + NA - 1) / NA;
   constexpr int GPW = TW / NA;                      // groups per set-up window
   setup_window(0);
   __syncthreads();
   issue(0);
-  if (ng > 1) issue(1);
   for (int gi = 0; gi < ng; ++gi) {
     const int k0 = gi * NA;
     const int na = min(NA, K - k0);
-    // this wave's loads of group gi are complete (those of gi + 1 may be in
-    // flight) and its LDS reads of group gi - 1 have returned; the barrier
-    // publishes group gi of every wave, retires group gi - 1 (whose buffer
-    // the loads of gi + 2 reuse) and the set-up window written below
-    if (gi + 1 < ng) asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)" ::"n"(LPW) : "memory");
-    else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+    // this wave's loads of group gi are complete and its LDS reads of group
+    // gi - 1 have returned; the barrier publishes group gi of every wave,
+    // retires group gi - 1 (whose buffer the loads of gi + 1 reuse) and the
+    // set-up window written below
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
-    if (gi + 2 < ng) issue(gi + 2);
-    // the next window's set-up, written three groups before its first group
+    if (gi + 1 < ng) issue(gi + 1);
+    // the next window's set-up, written two groups before its first group
     // is issued, into the slot of the window before the current one
-    if ((gi + 3) % GPW == 0 && (gi + 3) * NA < K) setup_window((gi + 3) / GPW);
+    if ((gi + 2) % GPW == 0 && (gi + 2) * NA < K) setup_window((gi + 2) / GPW);
     const int slot = (k0 / TW) & 1, base = k0 % TW;
     const float2* gb = tile + (gi % NBUF) * GF2;
     for (int a = 0; a < na; ++a) {
@@ -855,12 +854,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 3))
         ay[i] = fmaf(w1, v[i].w, fmaf(w0, v[i].y, ay[i]));
       }
     }
-    // single-precision partial sums of up to 8 NA angles, flushed to double
+    // two-level single-precision sums: partials of up to 8 NA angles are
+    // added into the outer sums
     if ((gi & 7) == 7 || gi + 1 >= ng) {
 #pragma unroll
       for (int i = 0; i < ZT; ++i) {
-        ox[i] += (double)ax[i];
-        oy[i] += (double)ay[i];
+        ox[i] += ax[i];
+        oy[i] += ay[i];
         ax[i] = ay[i] = 0.f;
       }
     }
@@ -868,7 +868,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 3))
   const size_t WW = (size_t)W * W;
 #pragma unroll
   for (int i = 0; i < ZT; ++i) {
-    gu[(size_t)(z0 + i) * WW + (size_t)y * W + x] = make_float2((float)ox[i], (float)oy[i]);
+    gu[(size_t)(z0 + i) * WW + (size_t)y * W + x] = make_float2(ox[i], oy[i]);
   }
 }
 
