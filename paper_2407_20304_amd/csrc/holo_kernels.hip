@@ -834,22 +834,27 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
       const float w0 = fmaxf(0.0f, fmaf(-fr, ih2, ih));
       const float w1 = fmaxf(0.0f, fmaf(fr - 1.0f, ih2, ih));
       const int j0 = min(max((int)fl, 0), SEG - 2);
-      const float2* tp = gb + a * ZT * SEG + j0;
+      // two bases, 8 slices apart: each slice's tap pair is then one read
+      // at an immediate offset (the offset field spans 8 slice rows)
+      int hi_idx = a * ZT * SEG + j0 + 8 * SEG;
+      asm volatile("" : "+v"(hi_idx));                 // keep it a base of its own
+      const float2* tpl = gb + a * ZT * SEG + j0;
+      const float2* tph = gb + hi_idx;
+      auto tap = [&](int i) {
+        const float2* t = (i < 8 ? tpl : tph) + (i & 7) * SEG;
+        const float2 v0 = t[0], v1 = t[1];
+        return make_float4(v0.x, v0.y, v1.x, v1.y);
+      };
       // software pipeline: the taps of slice i + LA are requested before
       // slice i is accumulated, so LA + 1 LDS reads are in flight
       constexpr int LA = 3;
+      static_assert(ZT == 16, "two bases of 8 slices");
       float4 v[ZT];
 #pragma unroll
-      for (int i = 0; i < LA; ++i) {
-        const float2 v0 = tp[i * SEG], v1 = tp[i * SEG + 1];
-        v[i] = make_float4(v0.x, v0.y, v1.x, v1.y);
-      }
+      for (int i = 0; i < LA; ++i) v[i] = tap(i);
 #pragma unroll
       for (int i = 0; i < ZT; ++i) {
-        if (i + LA < ZT) {
-          const float2 v0 = tp[(i + LA) * SEG], v1 = tp[(i + LA) * SEG + 1];
-          v[i + LA] = make_float4(v0.x, v0.y, v1.x, v1.y);
-        }
+        if (i + LA < ZT) v[i + LA] = tap(i + LA);
         ax[i] = fmaf(w1, v[i].z, fmaf(w0, v[i].x, ax[i]));
         ay[i] = fmaf(w1, v[i].w, fmaf(w0, v[i].y, ay[i]));
       }
