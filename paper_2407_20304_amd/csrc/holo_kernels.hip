@@ -648,7 +648,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
       // double precision; the other bins add b B (< NB / 2 * sqrt(2))
       float rel = (float)(fA + (double)y * D - (double)s_xl[y]);
       rel = fminf(fmaxf(rel, rel_lo), rel_hi);
-      const float2* tr = tile + (y % NBUF) * ROWF2 + zl;
+      int tb = (y % NBUF) * ROWF2 + zl;
+      asm volatile("" : "+v"(tb));                     // one base register per row
+      const float2* tr = tile + tb;
       // software pipeline: the taps of bin b + LA are requested before bin b
       // is accumulated, so the reads of LA + 1 bins are in flight
       constexpr int LA = 2;
