@@ -428,14 +428,44 @@ __global__ __launch_bounds__(kThreads) void k_pass_d(const float2* __restrict__ 
                                                      int k_first) {
   // A workgroup covers 16 rows x 16 padded bins, bins fastest, of the
   // sinogram S[k][z][kAdjPad + s] (rows padded by kAdjPad zero bins on each
-  // side).  Workgroups over the padding write its zeros.
+  // side).  Workgroups over the padding write its zeros.  The transposed
+  // resampling is separable, so its taps are formed once per workgroup: per
+  // plane, the three row taps of each of the 16 rows and the three column
+  // taps of each of the 16 bins.
   constexpr int SC = 16, ZR = kThreads / SC;
+  static_assert(kMaxDist * 2 * SC <= kThreads, "one tap set per thread");
+  __shared__ int s_d[kMaxDist][2 * SC][3];
+  __shared__ float s_w[kMaxDist][2 * SC][3];
   const int H = g.H, W = g.W, Wp = sino_row(W);
   const int nsb = Wp / SC;
-  const int z = (blockIdx.x / nsb) * ZR + threadIdx.x / SC;
-  const int sp = (blockIdx.x % nsb) * SC + threadIdx.x % SC;
+  const int z0 = (blockIdx.x / nsb) * ZR, sp0 = (blockIdx.x % nsb) * SC;
+  const int r = threadIdx.x / SC, c = threadIdx.x % SC;
+  const int z = z0 + r, sp = sp0 + c;
   const int s = sp - kAdjPad;
   const int k = blockIdx.y;
+  if ((int)threadIdx.x < g.nd * 2 * SC) {
+    // thread (j, e): plane j; e < 16 the taps of row z0 + e, else those of
+    // bin sp0 + e - 16 (none for bins in the padding)
+    const int j = threadIdx.x / (2 * SC), e = threadIdx.x % (2 * SC);
+    double ty, tx;
+    shift_of(g, k_first + k, j, ty, tx);
+    const double m = g.mag[j];
+    AdjTaps t;
+    if (e < SC) {
+      t = adj_taps(g.cH, m, ty, z0 + e, H);
+    } else {
+      const int sb = sp0 + e - SC - kAdjPad;
+      if (sb >= 0 && sb < W) {
+        t = adj_taps(g.cW, m, tx, sb, W);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) { t.d[q] = 0; t.w[q] = 0.f; }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) { s_d[j][e][q] = t.d[q]; s_w[j][e][q] = t.w[q]; }
+  }
+  __syncthreads();
   float2* out = S + ((size_t)k * H + z) * Wp + sp;
   if (s < 0 || s >= W) {
     *out = make_float2(0.f, 0.f);
@@ -443,19 +473,16 @@ __global__ __launch_bounds__(kThreads) void k_pass_d(const float2* __restrict__ 
   }
   float ax = 0.f, ay = 0.f;
   for (int j = 0; j < g.nd; ++j) {
-    double ty, tx;
-    shift_of(g, k_first + k, j, ty, tx);
-    const double m = g.mag[j];
-    const AdjTaps rz = adj_taps(g.cH, m, ty, z, H);
-    const AdjTaps rs = adj_taps(g.cW, m, tx, s, W);
     const float2* Xj = X + ((size_t)k * g.nd + j) * H * W;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
+      const float wz = s_w[j][r][a];
+      const float2* Xr = Xj + (size_t)s_d[j][r][a] * W;
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
-        const float wt = rz.w[a] * rs.w[b];
+        const float wt = wz * s_w[j][SC + c][b];
         if (wt != 0.0f) {
-          const float2 v = Xj[(size_t)rz.d[a] * W + rs.d[b]];
+          const float2 v = Xr[s_d[j][SC + c][b]];
           ax += wt * v.x;
           ay += wt * v.y;
         }
