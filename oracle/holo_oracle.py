@@ -44,6 +44,21 @@ in the design notes of the repository):
   R6 Data are given directly as amplitudes a = sqrt(d~) on the computational
      grid (the m0^2 M_{1/m0} rescaling is the identity there).
 
+The solver around the gradient (Sec. 2, the CG iteration with the
+Dai-Yuan formula, Eq. (12)-(13), and the initial probe):
+  C1 The unknown is the joint vector x = (u, q) with the real inner product
+     <a, b> = Re sum conj(a) b over both parts (the one in which -g is the
+     steepest-descent direction, R5); one Dai-Yuan beta and one step length
+     per iteration for the whole vector.
+  C2 The line search is only required to keep F from increasing.  Here:
+     halve a trial step until F(x + gamma eta) <= F(x); the first trial of
+     the first iteration is given, later ones start at twice the previous
+     accepted step; after 30 halvings the step is 0.
+  C3 If the Dai-Yuan denominator <g_new - g_old, eta> is not positive, the
+     direction restarts from -g (beta = 0).
+  C4 The initial probe is the reference amplitude, with zero phase,
+     propagated back to sample plane 0: q0 = D_{-1}(sqrt(d~r)).
+
 Array layouts (the same ones the C ABI uses):
   u, g_u      (H, W, W) complex  -- u[z, y, x], z = detector row = slice
   q, g_q      (H, W) complex
@@ -380,6 +395,88 @@ def holo2d_gradient(psi, q, amp, amp_ref, mag_rel, m0, fresnel0):
         g_q += propagate(np.conj(phi) * w, -rho_p[j], fresnel0)
     Fr, gr = reference_term(q, amp_ref, fresnel0)
     return F + Fr, g_psi, g_q + gr
+
+
+# ---------------------------------------------------------------------------
+# The solver: conjugate gradients with the Dai-Yuan formula (Sec. 2)
+# ---------------------------------------------------------------------------
+
+def inner(a, b) -> float:
+    """<a, b> = Re sum conj(a) b over all parts of two tuples of arrays (C1)."""
+    return float(sum(np.real(np.vdot(x, y)) for x, y in zip(a, b)))
+
+
+def backtracking(f, x, eta, F, gamma_try, max_halvings=30):
+    """Monotone line search (C2): halve gamma from gamma_try until
+    f(x + gamma eta) <= F.  Returns (gamma, f at the new point, new point,
+    number of halvings); gamma = 0 if no trial is accepted."""
+    gamma = gamma_try
+    for h in range(max_halvings + 1):
+        xt = tuple(xi + gamma * ei for xi, ei in zip(x, eta))
+        Ft = f(xt)
+        if Ft <= F:
+            return gamma, Ft, xt, h
+        gamma *= 0.5
+    return 0.0, F, x, max_halvings + 1
+
+
+def dai_yuan_direction(g_new, g_old, eta):
+    """The next search direction of Eq. (13): -g_new + beta eta with
+    beta = ||g_new||^2 / <g_new - g_old, eta> (restart with beta = 0 when the
+    denominator is not positive, C3).  Returns (direction, beta)."""
+    den = inner(g_new, eta) - inner(g_old, eta)
+    beta = inner(g_new, g_new) / den if den > 0.0 else 0.0
+    return tuple(-gn + beta * ei for gn, ei in zip(g_new, eta)), beta
+
+
+def cg_dai_yuan(f, grad, x0, iters, step0, line_search=None):
+    """Conjugate gradients with the Dai-Yuan formula (Eq. 12-13):
+    x_{m+1} = x_m + gamma_m eta_m, eta_0 = -g_0,
+    eta_{m+1} = -g_{m+1} + ||g_{m+1}||^2 / <g_{m+1} - g_m, eta_m> eta_m.
+
+    `f` and `grad` act on tuples of arrays; `grad` returns (F, g).  The line
+    search (default: `backtracking`, C2) is called as
+    line_search(f, x, eta, F, gamma_try) and returns
+    (gamma, F_new, x_new, halvings).  Returns the final x, the objective
+    after every iteration (F_0 first), the accepted steps and the halvings."""
+    search = line_search or backtracking
+    x = tuple(np.asarray(xi) for xi in x0)
+    F, g = grad(x)
+    eta = tuple(-gi for gi in g)
+    hist, steps, halv = [F], [], []
+    gamma_try = step0
+    for _ in range(iters):
+        gamma, F_new, x_new, h = search(f, x, eta, F, gamma_try)
+        steps.append(gamma)
+        halv.append(h)
+        if gamma == 0.0:
+            hist.append(F)
+            continue
+        x = x_new
+        F, g_new = grad(x)
+        eta, _ = dai_yuan_direction(g_new, g, eta)
+        g = g_new
+        hist.append(F)
+        gamma_try = 2.0 * gamma
+    return x, hist, steps, halv
+
+
+def probe_init(amp_ref, fresnel0) -> np.ndarray:
+    """Initial probe (C4): q0 = D_{-1}(sqrt(d~r)), the reference amplitude
+    with zero phase propagated back to sample plane 0."""
+    return propagate(np.asarray(amp_ref, dtype=np.complex128), -1.0, fresnel0)
+
+
+def holo_cg(u0, q0, amp, amp_ref, geom: Geometry, iters, step0):
+    """`iters` Dai-Yuan CG iterations on the joint objective F(u, q)."""
+    f = lambda x: objective(x[0], x[1], amp, amp_ref, geom)
+
+    def grad(x):
+        F, gu, gq = gradient(x[0], x[1], amp, amp_ref, geom)
+        return F, (gu, gq)
+
+    (u, q), hist, steps, halv = cg_dai_yuan(f, grad, (u0, q0), iters, step0)
+    return u, q, hist, steps, halv
 
 
 # ---------------------------------------------------------------------------

@@ -370,3 +370,121 @@ def test_residual_at_zero_field():
     F, r = O._residual(np.array([0j, 1 + 0j]), np.array([0.5, 1.0]))
     assert F == pytest.approx(0.25)
     np.testing.assert_allclose(r, [0, 0], atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# The solver: Dai-Yuan conjugate gradients (Sec. 2) and the initial probe
+# ---------------------------------------------------------------------------
+
+def exact_search(A_apply, grad_of):
+    """Exact line search for a quadratic with Hessian A (in the real inner
+    product): gamma = -<g, eta> / <eta, A eta>."""
+    def search(f, x, eta, F, gamma_try):
+        g = grad_of(x)
+        Ae = A_apply(eta)
+        gamma = -O.inner(g, eta) / O.inner(eta, Ae)
+        xn = tuple(xi + gamma * ei for xi, ei in zip(x, eta))
+        return gamma, f(xn), xn, 0
+    return search
+
+
+def test_dai_yuan_cg_terminates_on_a_quadratic():
+    # With an exact line search on a strictly convex quadratic, Dai-Yuan CG is
+    # the linear conjugate-gradient method: its iterates are those of the
+    # textbook recursion (r = b - A x, p = r + (|r_new|^2/|r|^2) p), and it
+    # reaches the minimiser A^{-1} b in n steps (finite termination)
+    rng = np.random.default_rng(31)
+    n = 12
+    Qm, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = Qm @ np.diag(np.linspace(1.0, 20.0, n)) @ Qm.T
+    b = rng.standard_normal(n)
+    f = lambda x: 0.5 * x[0] @ A @ x[0] - b @ x[0]
+    grad_of = lambda x: (A @ x[0] - b,)
+    grad = lambda x: (f(x), grad_of(x))
+    search = exact_search(lambda e: (A @ e[0],), grad_of)
+    xt, r = np.zeros(n), b.copy()
+    p = r.copy()
+    for it in range(1, n + 1):
+        Ap = A @ p
+        alpha = (r @ r) / (p @ Ap)
+        xt = xt + alpha * p
+        rn = r - alpha * Ap
+        p = rn + (rn @ rn) / (r @ r) * p
+        r = rn
+        x, hist, _, _ = O.cg_dai_yuan(f, grad, (np.zeros(n),), it, 1.0, line_search=search)
+        np.testing.assert_allclose(x[0], xt, rtol=0, atol=1e-10)
+        assert all(h1 <= h0 + 1e-12 for h0, h1 in zip(hist, hist[1:]))
+        if it == n - 3:
+            assert np.linalg.norm(x[0] - np.linalg.solve(A, b)) > 1e-6
+    np.testing.assert_allclose(x[0], np.linalg.solve(A, b), rtol=0, atol=1e-10)
+
+
+def test_dai_yuan_cg_on_complex_least_squares_in_two_parts():
+    # F(z) = ||M z - y||^2 over z = (z1, z2) complex, with the gradient
+    # convention g = dF/dRe + i dF/dIm = 2 M^H (M z - y).  In the real inner
+    # product Re <a, b> this is a strictly convex quadratic on R^(2n); CG with
+    # an exact line search finds the least-squares solution in <= 2n steps.
+    rng = np.random.default_rng(32)
+    m, n1, n2 = 14, 3, 4
+    M = crandn(rng, m, n1 + n2)
+    y = crandn(rng, m)
+    split = lambda z: (z[:n1], z[n1:])
+    join = lambda x: np.concatenate(x)
+    f = lambda x: float(np.linalg.norm(M @ join(x) - y) ** 2)
+    grad_of = lambda x: split(2.0 * M.conj().T @ (M @ join(x) - y))
+    grad = lambda x: (f(x), grad_of(x))
+    A_apply = lambda e: split(2.0 * M.conj().T @ (M @ join(e)))
+    x, hist, _, _ = O.cg_dai_yuan(f, grad, split(np.zeros(n1 + n2, complex)), 2 * (n1 + n2), 1.0,
+                                  line_search=exact_search(A_apply, grad_of))
+    ref = np.linalg.lstsq(M, y, rcond=None)[0]
+    np.testing.assert_allclose(join(x), ref, rtol=0, atol=1e-9)
+
+
+def test_cg_on_the_joint_objective_is_monotone_and_decreases():
+    geom, u, q, amp, amp_ref = tiny_problem(seed=33)
+    _, gu, gq = O.gradient(u, q, amp, amp_ref, geom)
+    step0 = 0.05 * math.sqrt(np.vdot(u, u).real + np.vdot(q, q).real) / \
+        math.sqrt(np.vdot(gu, gu).real + np.vdot(gq, gq).real)
+    u2, q2, hist, steps, halv = O.holo_cg(u, q, amp, amp_ref, geom, 4, step0)
+    assert all(h1 <= h0 for h0, h1 in zip(hist, hist[1:]))
+    assert hist[-1] < 0.9 * hist[0]
+    assert all(s > 0 for s in steps)
+    assert O.objective(u2, q2, amp, amp_ref, geom) == pytest.approx(hist[-1], rel=1e-12)
+
+
+def test_initial_probe_reproduces_the_reference_amplitude():
+    # q0 = D_{-1}(a_ref): D_1 q0 = a_ref exactly (D_a D_b = D_{a+b}), so the
+    # reference term of the objective and its probe gradient vanish at q0
+    rng = np.random.default_rng(34)
+    a_ref = np.abs(crandn(rng, 24, 32)) + 0.5
+    q0 = O.probe_init(a_ref, 0.01)
+    np.testing.assert_allclose(O.propagate(q0, 1.0, 0.01), a_ref, atol=1e-12)
+    Fr, gr = O.reference_term(q0, a_ref, 0.01)
+    assert Fr < 1e-24 and np.max(np.abs(gr)) < 1e-12
+
+
+def test_dai_yuan_direction_identity():
+    # The Dai-Yuan choice of beta is the one for which the new direction's
+    # slope relates to the old one by <g_new, eta_new> = beta <g_old, eta_old>
+    # (whatever the step that led from g_old to g_new); the Fletcher-Reeves
+    # or Polak-Ribiere choices do not satisfy it.  Checked on random complex
+    # two-part vectors, beta read back from eta_new = -g_new + beta eta_old.
+    rng = np.random.default_rng(35)
+    for _ in range(5):
+        g0 = (crandn(rng, 5, 4), crandn(rng, 3))
+        eta = tuple(-x + 0.3 * crandn(rng, *x.shape) for x in g0)
+        g1 = tuple(x + 0.8 * crandn(rng, *x.shape) for x in g0)
+        if O.inner(g1, eta) - O.inner(g0, eta) <= 0:
+            continue
+        eta1, beta = O.dai_yuan_direction(g1, g0, eta)
+        beta_back = O.inner(tuple(e + g for e, g in zip(eta1, g1)), eta) / O.inner(eta, eta)
+        assert beta_back == pytest.approx(beta, rel=1e-12)
+        assert O.inner(g1, eta1) == pytest.approx(beta * O.inner(g0, eta), rel=1e-10)
+        # and the Fletcher-Reeves choice would not satisfy it
+        bfr = O.inner(g1, g1) / O.inner(g0, g0)
+        eta_fr = tuple(-g + bfr * e for g, e in zip(g1, eta))
+        assert abs(O.inner(g1, eta_fr) - bfr * O.inner(g0, eta)) > 1e-6 * abs(bfr * O.inner(g0, eta))
+    # a non-positive denominator restarts along -g_new (C3)
+    g0 = (np.ones(3, complex),)
+    eta, beta = O.dai_yuan_direction(g0, g0, (np.ones(3, complex),))
+    assert beta == 0.0 and np.allclose(eta[0], -1.0)
