@@ -146,6 +146,45 @@ holo_status holo_grad_probe(holo_plan* plan, const holo_c64* u, const holo_c64* 
                             void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * The solver around the gradient (Sec. 2: conjugate gradients with the
+ * Dai-Yuan formula, Eq. 12-13, and the initial probe).
+ * ------------------------------------------------------------------------- */
+
+/* Initial probe q_out = D_{-1}(amp_ref): the reference amplitude with zero
+ * phase propagated back to sample plane 0 (Sec. 2, initial guess).  amp_ref
+ * [H][W] float and q_out [H][W] complex are device pointers; q_out may not
+ * alias amp_ref.  Asynchronous on `stream`; needs no workspace. */
+holo_status holo_probe_init(holo_plan* plan, const float* amp_ref, holo_c64* q_out,
+                            void* stream);
+
+/* Workspace of holo_cg: holo_workspace_bytes plus three vectors the size of
+ * (u, q) (gradient, search direction, trial point) and a few kB of partials. */
+holo_status holo_cg_workspace_bytes(const holo_plan* plan, size_t* bytes);
+
+/* `iters` iterations of conjugate gradients with the Dai-Yuan formula on the
+ * joint objective F(u, q) of Eq. (10) with Eq. (17):
+ *   x = (u, q), <a, b> = Re sum conj(a) b over both parts,
+ *   eta_0 = -g_0,  x_{m+1} = x_m + gamma_m eta_m,
+ *   eta_{m+1} = -g_{m+1} + ||g_{m+1}||^2 / <g_{m+1} - g_m, eta_m> eta_m
+ *   (restart eta = -g when that denominator is not positive).
+ * gamma_m: halving from a trial step until F does not increase; the first
+ * trial of the first iteration is step0 > 0, later ones start at twice the
+ * previous accepted step; after 30 halvings the step is 0 and x stays.
+ * u [H][W][W] and q [H][W] (device) are read as the starting point and
+ * overwritten with the final iterate.  Host outputs: F_hist[iters + 1] (F
+ * before the first and after every iteration), and optionally
+ * steps[iters] (accepted gamma, 0 if none) and halvings[iters] (halvings of
+ * the accepted trial; 31 if none was accepted).  Inner products and F are
+ * formed in double on the device.  The line search decides on the host, so
+ * the call returns only when the iterations are done (it synchronises
+ * `stream`).  Argument errors are returned before any device work. */
+holo_status holo_cg(holo_plan* plan, holo_c64* u, holo_c64* q,
+                    const float* amp, const float* amp_ref,
+                    int32_t iters, double step0,
+                    double* F_hist, double* steps, int32_t* halvings,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Batched independent single-angle retrievals (Eq. 10 and Eq. 11 with one
  * projection, psi the unknown, own probe and reference per instance).
  *

@@ -605,6 +605,168 @@ extern "C" holo_status holo_grad_probe(holo_plan* P, const holo_c64* u, const ho
   return holo_grad(P, u, q, amp, amp_ref, F, nullptr, g_q, ws, ws_bytes, stream);
 }
 
+// ---------------------------------------------------------------------------
+// Solver: Dai-Yuan conjugate gradients and the initial probe
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct CgLayout {
+  size_t nu, nq;                       // complex elements of u and q
+  size_t off_gu, off_gq, off_eu, off_eq, off_xu, off_xq, off_d, bytes;
+};
+
+CgLayout cg_layout(const holo_plan* P) {
+  CgLayout L{};
+  L.nu = (size_t)P->H * P->W * P->W;
+  L.nq = (size_t)P->H * P->W;
+  size_t o = P->ws_bytes;
+  L.off_gu = o; o = align_up(o + L.nu * sizeof(float2));
+  L.off_gq = o; o = align_up(o + L.nq * sizeof(float2));
+  L.off_eu = o; o = align_up(o + L.nu * sizeof(float2));
+  L.off_eq = o; o = align_up(o + L.nq * sizeof(float2));
+  L.off_xu = o; o = align_up(o + L.nu * sizeof(float2));
+  L.off_xq = o; o = align_up(o + L.nq * sizeof(float2));
+  // doubles: F, three inner products, dot partials, reduction scratch
+  L.off_d = o;  o = align_up(o + (4 + kDotParts + kReduceParts) * sizeof(double));
+  L.bytes = o;
+  return L;
+}
+
+}  // namespace
+
+extern "C" holo_status holo_probe_init(holo_plan* P, const float* amp_ref, holo_c64* q_out,
+                                       void* stream) {
+  if (!P) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_probe_init: plan is NULL");
+  if (!amp_ref || !q_out)
+    return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_probe_init: amp_ref or q_out is NULL");
+  if ((const void*)amp_ref == (const void*)q_out)
+    return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_probe_init: q_out aliases amp_ref");
+  holo_status ts = ensure_tables(P);
+  if (ts != HOLO_OK) return ts;
+  hipStream_t st = (hipStream_t)stream;
+  const DevGeom g = make_geom(P);
+  float2* q = (float2*)q_out;
+  HOLO_HIP(launch_real_to_c64(amp_ref, q, (size_t)P->H * P->W, st));
+  // D_{-1}: the reference step with the conjugate transfer, rows then columns
+  PropJobs rj{}, cj{};
+  rj.job[rj.n++] = PropJob{q, q, nullptr, chirp_ref(P->nd), 1, 0};
+  cj.job[cj.n++] = PropJob{q, q, nullptr, chirp_ref(P->nd), 1, 0};
+  HOLO_HIP(launch_rows_prop(g, rj, st));
+  HOLO_HIP(launch_cols_prop(g, cj, nullptr, st));
+  return HOLO_OK;
+}
+
+extern "C" holo_status holo_cg_workspace_bytes(const holo_plan* P, size_t* bytes) {
+  if (!P || !bytes) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_cg_workspace_bytes: NULL argument");
+  *bytes = cg_layout(P).bytes;
+  return HOLO_OK;
+}
+
+extern "C" holo_status holo_cg(holo_plan* P, holo_c64* u_, holo_c64* q_, const float* amp,
+                               const float* amp_ref, int32_t iters, double step0, double* F_hist,
+                               double* steps, int32_t* halvings, void* ws, size_t ws_bytes,
+                               void* stream) {
+  holo_status s = check_common(P, u_, q_, "holo_cg");
+  if (s != HOLO_OK) return s;
+  if (!amp || !amp_ref) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_cg: amp or amp_ref is NULL");
+  if (!F_hist) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_cg: F_hist is NULL");
+  if (iters < 0) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_cg: iters must be >= 0");
+  if (!(step0 > 0.0) || !std::isfinite(step0))
+    return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_cg: step0 must be positive and finite");
+  if (!ws) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_cg: workspace is NULL");
+  const CgLayout L = cg_layout(P);
+  if (ws_bytes < L.bytes)
+    return fail(HOLO_ERR_WORKSPACE_TOO_SMALL, "holo_cg: workspace needs " +
+                                                  std::to_string(L.bytes) + " bytes, got " +
+                                                  std::to_string(ws_bytes));
+  constexpr int kMaxHalvings = 30;
+  hipStream_t st = (hipStream_t)stream;
+  char* wsb = (char*)ws;
+  float2* u = (float2*)u_;
+  float2* q = (float2*)q_;
+  float2* gu = (float2*)(wsb + L.off_gu);
+  float2* gq = (float2*)(wsb + L.off_gq);
+  float2* eu = (float2*)(wsb + L.off_eu);
+  float2* eq = (float2*)(wsb + L.off_eq);
+  float2* xu = (float2*)(wsb + L.off_xu);
+  float2* xq = (float2*)(wsb + L.off_xq);
+  double* dF = (double*)(wsb + L.off_d);
+  double* ddot = dF + 1;
+  double* dparts = dF + 4;
+  double* dscratch = dparts + kDotParts;
+  auto c64 = [](float2* p) { return (holo_c64*)p; };
+  auto fetch = [&](const double* dev, double* host) -> holo_status {
+    HOLO_HIP(hipMemcpyAsync(host, dev, sizeof(double), hipMemcpyDeviceToHost, st));
+    HOLO_HIP(hipStreamSynchronize(st));
+    return HOLO_OK;
+  };
+  auto dot = [&](const float2* a1, const float2* b1, const float2* a2, const float2* b2,
+                 double* host) -> holo_status {
+    HOLO_HIP(launch_dot_re(a1, b1, L.nu, a2, b2, L.nq, dparts, dscratch, ddot, st));
+    return fetch(ddot, host);
+  };
+#define HOLO_TRY(call)                      \
+  do {                                      \
+    holo_status s_ = (call);                \
+    if (s_ != HOLO_OK) return s_;           \
+  } while (0)
+
+  double F = 0.0;
+  HOLO_TRY(run(P, kGrad, c64(u), c64(q), 0, P->n_angles, nullptr, nullptr, amp, amp_ref, dF,
+               c64(gu), c64(gq), ws, P->ws_bytes, stream));
+  HOLO_TRY(fetch(dF, &F));
+  F_hist[0] = F;
+  HOLO_HIP(launch_cg_dir(gu, eu, 0.f, 1, L.nu, st));
+  HOLO_HIP(launch_cg_dir(gq, eq, 0.f, 1, L.nq, st));
+  double gamma_try = step0;
+  for (int m = 0; m < iters; ++m) {
+    double d_old = 0.0;   // <g_m, eta_m>, for the Dai-Yuan denominator
+    HOLO_TRY(dot(gu, eu, gq, eq, &d_old));
+    double t = gamma_try;
+    int h = 0;
+    bool accepted = false;
+    for (; h <= kMaxHalvings; ++h, t *= 0.5) {
+      HOLO_HIP(launch_axpy(u, eu, (float)t, xu, L.nu, st));
+      HOLO_HIP(launch_axpy(q, eq, (float)t, xq, L.nq, st));
+      double Ft = 0.0;
+      HOLO_TRY(run(P, kObj, c64(xu), c64(xq), 0, P->n_angles, nullptr, nullptr, amp, amp_ref, dF,
+                   nullptr, nullptr, ws, P->ws_bytes, stream));
+      HOLO_TRY(fetch(dF, &Ft));
+      if (Ft <= F) {
+        accepted = true;
+        break;
+      }
+    }
+    if (!accepted) {   // x stays; the next iteration repeats the same search
+      F_hist[m + 1] = F;
+      if (steps) steps[m] = 0.0;
+      if (halvings) halvings[m] = kMaxHalvings + 1;
+      continue;
+    }
+    HOLO_HIP(hipMemcpyAsync(u, xu, L.nu * sizeof(float2), hipMemcpyDeviceToDevice, st));
+    HOLO_HIP(hipMemcpyAsync(q, xq, L.nq * sizeof(float2), hipMemcpyDeviceToDevice, st));
+    HOLO_TRY(run(P, kGrad, c64(u), c64(q), 0, P->n_angles, nullptr, nullptr, amp, amp_ref, dF,
+                 c64(gu), c64(gq), ws, P->ws_bytes, stream));
+    HOLO_TRY(fetch(dF, &F));
+    double gg = 0.0, g_eta = 0.0;
+    HOLO_TRY(dot(gu, gu, gq, gq, &gg));
+    HOLO_TRY(dot(gu, eu, gq, eq, &g_eta));
+    const double den = g_eta - d_old;
+    const bool restart = !(den > 0.0);
+    const double beta = restart ? 0.0 : gg / den;
+    HOLO_HIP(launch_cg_dir(gu, eu, (float)beta, restart ? 1 : 0, L.nu, st));
+    HOLO_HIP(launch_cg_dir(gq, eq, (float)beta, restart ? 1 : 0, L.nq, st));
+    F_hist[m + 1] = F;
+    if (steps) steps[m] = t;
+    if (halvings) halvings[m] = h;
+    gamma_try = 2.0 * t;
+  }
+#undef HOLO_TRY
+  HOLO_HIP(hipStreamSynchronize(st));
+  return HOLO_OK;
+}
+
 extern "C" holo_status holo_timing_enable(holo_plan* P, int32_t on) {
   if (!P) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_timing_enable: plan is NULL");
   if (on) {

@@ -110,5 +110,16 @@ hipError_t launch_sum_frames(const float2* G, int nd, const float2* extra, float
 constexpr int kReduceParts = 256;
 hipError_t launch_reduce_sum(const double* parts, size_t n, double* scratch, double* out,
                              hipStream_t st);
+// Solver vector operations.  launch_dot_re: *out = Re <a1, b1> + Re <a2, b2>
+// in double, deterministic; `parts` holds kDotParts, `scratch` kReduceParts.
+constexpr int kDotParts = 1024;
+hipError_t launch_dot_re(const float2* a1, const float2* b1, size_t n1, const float2* a2,
+                         const float2* b2, size_t n2, double* parts, double* scratch, double* out,
+                         hipStream_t st);
+hipError_t launch_axpy(const float2* x, const float2* e, float t, float2* out, size_t n,
+                       hipStream_t st);
+hipError_t launch_cg_dir(const float2* g, float2* eta, float beta, int restart, size_t n,
+                         hipStream_t st);
+hipError_t launch_real_to_c64(const float* a, float2* out, size_t n, hipStream_t st);
 
 }  // namespace holo

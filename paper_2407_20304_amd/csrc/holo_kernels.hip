@@ -939,6 +939,56 @@ __global__ __launch_bounds__(kThreads) void k_reduce_sum(const double* __restric
 }
 
 // ---------------------------------------------------------------------------
+// Solver vector operations (complex64 vectors, double-precision products)
+// ---------------------------------------------------------------------------
+
+// Workgroup b sums Re(conj(a) b) over [b per, min(n, (b + 1) per)).
+__global__ __launch_bounds__(kThreads) void k_dot_re(const float2* __restrict__ a,
+                                                     const float2* __restrict__ b, size_t n,
+                                                     size_t per, double* __restrict__ parts) {
+  const size_t lo = (size_t)blockIdx.x * per, hi = min(n, lo + per);
+  double acc = 0.0;
+  for (size_t i = lo + threadIdx.x; i < hi; i += kThreads) {
+    const float2 x = a[i], y = b[i];
+    acc += (double)x.x * (double)y.x + (double)x.y * (double)y.y;
+  }
+  block_sum_store<kThreads>(acc, parts + blockIdx.x);
+}
+
+// out = x + t e
+__global__ void k_axpy(const float2* __restrict__ x, const float2* __restrict__ e, float t,
+                       float2* __restrict__ out, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) {
+    const float2 a = x[i], d = e[i];
+    out[i] = make_float2(fmaf(t, d.x, a.x), fmaf(t, d.y, a.y));
+  }
+}
+
+// eta = -g + beta eta, or eta = -g when `restart` (eta is then not read)
+__global__ void k_cg_dir(const float2* __restrict__ g, float2* __restrict__ eta, float beta,
+                         int restart, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) {
+    const float2 gv = g[i];
+    if (restart) {
+      eta[i] = make_float2(-gv.x, -gv.y);
+    } else {
+      const float2 e = eta[i];
+      eta[i] = make_float2(fmaf(beta, e.x, -gv.x), fmaf(beta, e.y, -gv.y));
+    }
+  }
+}
+
+__global__ void k_real_to_c64(const float* __restrict__ a, float2* __restrict__ out, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) out[i] = make_float2(a[i], 0.f);
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 
@@ -1068,6 +1118,40 @@ hipError_t launch_fill_zero(float2* p, size_t n, hipStream_t st) {
 hipError_t launch_sum_frames(const float2* G, int nd, const float2* extra, float2* out, size_t n,
                              hipStream_t st) {
   k_sum_frames<<<grid_for(n), kThreads, 0, st>>>(G, nd, extra, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot_re(const float2* a1, const float2* b1, size_t n1, const float2* a2,
+                         const float2* b2, size_t n2, double* parts, double* scratch, double* out,
+                         hipStream_t st) {
+  // fixed partitions of both parts, then the two-stage sum of the partials
+  auto groups = [](size_t n) {
+    return std::max<size_t>(1, std::min<size_t>(kDotParts / 2, (n + 65535) / 65536));
+  };
+  const size_t g1 = groups(n1), g2 = groups(n2);
+  k_dot_re<<<(unsigned)g1, kThreads, 0, st>>>(a1, b1, n1, (n1 + g1 - 1) / g1, parts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_dot_re<<<(unsigned)g2, kThreads, 0, st>>>(a2, b2, n2, (n2 + g2 - 1) / g2, parts + g1);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_reduce_sum(parts, g1 + g2, scratch, out, st);
+}
+
+hipError_t launch_axpy(const float2* x, const float2* e, float t, float2* out, size_t n,
+                       hipStream_t st) {
+  k_axpy<<<grid_for(n), kThreads, 0, st>>>(x, e, t, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_dir(const float2* g, float2* eta, float beta, int restart, size_t n,
+                         hipStream_t st) {
+  k_cg_dir<<<grid_for(n), kThreads, 0, st>>>(g, eta, beta, restart, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_real_to_c64(const float* a, float2* out, size_t n, hipStream_t st) {
+  k_real_to_c64<<<grid_for(n), kThreads, 0, st>>>(a, out, n);
   return hipGetLastError();
 }
 

@@ -23,6 +23,7 @@ EXPORTS = (
     "holo_plan_create", "holo_plan_destroy", "holo_workspace_bytes",
     "holo_fwd", "holo_adj", "holo_objective", "holo_grad",
     "holo_grad_object", "holo_grad_probe",
+    "holo_probe_init", "holo_cg_workspace_bytes", "holo_cg",
     "holo2d_plan_create", "holo2d_plan_destroy", "holo2d_offsets", "holo2d_workspace_bytes",
     "holo2d_fwd", "holo2d_objective", "holo2d_grad",
     "holo_timing_enable", "holo_timing_read", "holo_last_error",
@@ -72,6 +73,9 @@ def lib():
     L.holo_grad.argtypes = [P, P, P, P, P, P, P, P, P, c_size_t, P]
     L.holo_grad_object.argtypes = [P, P, P, P, P, P, P, P, c_size_t, P]
     L.holo_grad_probe.argtypes = [P, P, P, P, P, P, P, P, c_size_t, P]
+    L.holo_probe_init.argtypes = [P, P, P, P]
+    L.holo_cg_workspace_bytes.argtypes = [P, POINTER(c_size_t)]
+    L.holo_cg.argtypes = [P, P, P, P, P, c_int32, c_double, P, P, P, P, c_size_t, P]
     L.holo2d_plan_create.argtypes = [c_int32, POINTER(c_int32), c_int32, POINTER(c_double),
                                      c_double, c_double, POINTER(c_void_p)]
     L.holo2d_plan_destroy.argtypes = [P]
@@ -246,6 +250,42 @@ class Plan:
     def holo_grad_probe(self, u, q, amp, amp_ref, stream=None):
         F, _, g_q = self.holo_grad(u, q, amp, amp_ref, want_u=False, stream=stream)
         return F, g_q
+
+    def holo_probe_init(self, amp_ref, q=None, stream=None):
+        """Initial probe: the reference amplitude propagated back to sample
+        plane 0 (complex64 (H, W) on amp_ref's device)."""
+        import torch
+        self._frame(amp_ref, "amp_ref", torch.float32)
+        if q is None:
+            q = torch.empty(amp_ref.shape, dtype=torch.complex64, device=amp_ref.device)
+        self._frame(q, "q")
+        _check(lib().holo_probe_init(self._h, _ptr(amp_ref), _ptr(q), _stream(stream)))
+        return q
+
+    def cg_workspace_bytes(self):
+        n = c_size_t()
+        _check(lib().holo_cg_workspace_bytes(self._h, ctypes.byref(n)))
+        return int(n.value)
+
+    def holo_cg(self, u, q, amp, amp_ref, iters, step0, in_place=False, stream=None):
+        """`iters` Dai-Yuan conjugate-gradient iterations on (u, q).  Returns
+        (u, q, F_hist[iters + 1], steps[iters], halvings[iters]); u and q are
+        overwritten when in_place, else copies are iterated."""
+        import torch
+        self._check_data(u, q, amp, amp_ref)
+        if not in_place:
+            u, q = u.clone(), q.clone()
+        iters = int(iters)
+        F_hist = np.zeros(max(iters + 1, 1), dtype=np.float64)
+        steps = np.zeros(max(iters, 1), dtype=np.float64)
+        halv = np.zeros(max(iters, 1), dtype=np.int32)
+        ws = torch.empty(self.cg_workspace_bytes(), dtype=torch.uint8, device=u.device)
+        _check(lib().holo_cg(self._h, _ptr(u), _ptr(q), _ptr(amp), _ptr(amp_ref),
+                             c_int32(iters), c_double(step0),
+                             F_hist.ctypes.data_as(c_void_p), steps.ctypes.data_as(c_void_p),
+                             halv.ctypes.data_as(c_void_p), _ptr(ws), c_size_t(ws.numel()),
+                             _stream(stream)))
+        return u, q, F_hist[:iters + 1], steps[:iters], halv[:iters]
 
     def timing(self, on=True):
         """Record HIP events around every kernel launch of later calls."""

@@ -95,6 +95,36 @@ def test_null_arguments_return_invalid_argument():
     p.close()
 
 
+def test_solver_entry_points_validate_on_the_host():
+    L = holo.lib()
+    p = make_plan()
+    buf = ctypes.c_void_p(1)
+    F = (ctypes.c_double * 4)()
+    n = ctypes.c_size_t()
+    assert L.holo_cg_workspace_bytes(None, ctypes.byref(n)) == 1
+    assert L.holo_cg_workspace_bytes(p._h, ctypes.byref(n)) == 0
+    # three (u, q)-sized vectors beyond the gradient's own workspace
+    assert n.value >= p.workspace_bytes + 3 * 8 * (64 ** 3 + 64 ** 2)
+    big = n.value
+    assert L.holo_cg(None, buf, buf, buf, buf, 2, 1e-3, F, None, None, buf, big, None) == 1
+    assert L.holo_cg(p._h, None, buf, buf, buf, 2, 1e-3, F, None, None, buf, big, None) == 1
+    assert L.holo_cg(p._h, buf, buf, None, buf, 2, 1e-3, F, None, None, buf, big, None) == 1
+    assert L.holo_cg(p._h, buf, buf, buf, buf, 2, 1e-3, None, None, None, buf, big, None) == 1
+    assert L.holo_cg(p._h, buf, buf, buf, buf, -1, 1e-3, F, None, None, buf, big, None) == 1
+    for step0 in (0.0, -1.0, float("nan"), float("inf")):
+        assert L.holo_cg(p._h, buf, buf, buf, buf, 2, step0, F, None, None, buf, big, None) == 1
+    assert L.holo_cg(p._h, buf, buf, buf, buf, 2, 1e-3, F, None, None, None, big, None) == 1
+    assert L.holo_cg(p._h, buf, buf, buf, buf, 2, 1e-3, F, None, None, buf, big - 1, None) == 3
+    # the gradient's workspace alone is not enough
+    assert L.holo_cg(p._h, buf, buf, buf, buf, 2, 1e-3, F, None, None, buf,
+                     p.workspace_bytes, None) == 3
+    assert L.holo_probe_init(None, buf, buf, None) == 1
+    assert L.holo_probe_init(p._h, None, buf, None) == 1
+    assert L.holo_probe_init(p._h, buf, None, None) == 1
+    assert L.holo_probe_init(p._h, buf, buf, None) == 1
+    p.close()
+
+
 def test_batch_plan_offsets_and_validation():
     p = holo.Plan2D([128, 192, 512, 64], [1.0, 1.08, 1.25, 1.5], 300.0, 0.01)
     assert p.offsets == [0, 128 ** 2, 128 ** 2 + 192 ** 2, 128 ** 2 + 192 ** 2 + 512 ** 2]
