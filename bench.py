@@ -33,9 +33,9 @@ FLOP_PER_LERP = 8               # 2 taps x (re, im) x fused multiply-add
 # figures hold for the library sources they were taken on (SHA-256 over the
 # csrc files); after any change to those sources the field reports null.
 TRAFFIC = {
-    "k_radon_fwd": {"fetch_kib": 16641694.73, "write_kib": 1233500.06,
+    "k_radon_fwd": {"fetch_kib": 16718983.70, "write_kib": 1248190.17,
                     "fetch_scale": 2.0, "write_scale": 1.0,
-                    "sources_sha256": "ed1b8d6bea0ced39a4ba9642e5c27702dd8093d0be099d72a8aa4a842a701518"},
+                    "sources_sha256": "52d2c4eaeb3409612ea783ef4b983c6c769a4c2d2ece71f30baceccfd26ab153"},
 }
 
 
@@ -114,6 +114,56 @@ def cpu_baseline(wl, u_gpu, q, amp_gpu, amp_ref, slab):
     }
 
 
+def solver_bench(args, wl, plan, u, amp, amp_ref):
+    """Dai-Yuan conjugate gradients at the full workload: iterations per
+    second, objective and gradient evaluations per iteration, and the HBM
+    rate of the solver's own vector kernels (inner products, x + t eta,
+    -g + beta eta, copies) against a pass-minimal byte count."""
+    import torch
+    q0 = plan.holo_probe_init(amp_ref)
+    F, g_u, g_q = plan.holo_grad(u, q0, amp, amp_ref)
+    gg = float(torch.linalg.vector_norm(g_u).double() ** 2 + torch.linalg.vector_norm(g_q).double() ** 2)
+    step0 = F.item() / gg          # the step that zeroes the linear model of F along -g
+    torch.cuda.synchronize()
+    log("solver: F0 %.6e, ||g||^2 %.3e, first trial step %.3e" % (F.item(), gg, step0))
+    plan.timing(True)
+    t0 = time.perf_counter()
+    _, _, F_hist, steps, halv = plan.holo_cg(u, q0, amp, amp_ref, args.solver, step0,
+                                             in_place=True)
+    elapsed = time.perf_counter() - t0
+    plan.timing(False)
+    kt = plan.kernel_times()
+    log("solver: %d iterations in %.3f s, F %s, halvings %s"
+        % (args.solver, elapsed, [float(f) for f in F_hist], [int(h) for h in halv]))
+    n = u.numel() + q0.numel()
+    accepted = [bool(h <= 30) for h in halv]
+    trials = sum(min(int(h), 30) + 1 for h in halv)
+    # bytes per element (complex64): first direction 16; per iteration the
+    # slope dot 16 and 24 per trial point; per accepted step the copies 16,
+    # ||g||^2 8, <g, eta> 16 and the new direction 24
+    solver_bytes = n * 8 * (2 + sum(2 + 3 * (min(int(h), 30) + 1) + (8 if a else 0)
+                                    for h, a in zip(halv, accepted)))
+    sms, sn = kt["solver"]
+    ev_grad = 1 + int(sum(accepted))
+    result = {
+        "metric": "CG iterations/s (Dai-Yuan, joint u and q)",
+        "value": args.solver / elapsed, "unit": "iterations/s", "n_gpus": 1,
+        "iterations": args.solver, "seconds": elapsed, "higher_is_better": True,
+        "dtype": "c64", "data": "synthetic",
+        "config": {"workload": wl.name, "volume": [wl.H, wl.W, wl.W], "n_angles": wl.n_angles,
+                   "chunk": wl.chunk, "n_dist": len(wl.mag_rel)},
+        "F_hist": [float(f) for f in F_hist], "steps": [float(t) for t in steps],
+        "halvings": [int(h) for h in halv],
+        "gradient_evals": ev_grad, "objective_evals": trials,
+        "solver_kernels": {"ms": sms, "launches": sn, "bytes": solver_bytes,
+                           "GBps": solver_bytes / (sms * 1e-3) / 1e9 if sms > 0 else None,
+                           "hbm_frac": (solver_bytes / (sms * 1e-3) / 1e9 / PEAK_HBM_GBS)
+                           if sms > 0 else None},
+        "kernel_ms": {k: v[0] for k, v in kt.items() if v[1] > 0},
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +175,10 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy before the timed region "
                          "(a known-size reference for HBM traffic counters)")
+    ap.add_argument("--solver", type=int, default=0, metavar="ITERS",
+                    help="instead of the gradient step, time ITERS conjugate-gradient "
+                         "iterations (holo_cg) from u and the back-propagated reference probe "
+                         "and print their own JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one MI355X: the path runs on a single GPU "
@@ -163,6 +217,9 @@ def main():
         log("calibration copy: 1 GiB read + 1 GiB written")
 
     plan = holo.Plan.for_workload(wl)
+    if args.solver > 0:
+        solver_bench(args, wl, plan, u, amp, amp_ref)
+        return
     ws = plan.workspace(dev)
     F = torch.empty((1,), dtype=torch.float64, device=dev)
     g_u = torch.empty_like(u)

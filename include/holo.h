@@ -234,7 +234,8 @@ enum {
   HOLO_K_PASS_D = 5,     /* transpose of the demagnification, chain rule        */
   HOLO_K_PROBE = 6,      /* probe-side propagations and the reference term      */
   HOLO_K_OTHER = 7,      /* transposed volume copy, fills, sums, reductions     */
-  HOLO_K_COUNT = 8
+  HOLO_K_SOLVER = 8,     /* holo_cg's inner products, updates and copies        */
+  HOLO_K_COUNT = 9
 };
 
 /* Diagnostics.  holo_timing_enable(plan, 1) clears the counters and makes

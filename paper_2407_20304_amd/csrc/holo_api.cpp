@@ -647,13 +647,14 @@ extern "C" holo_status holo_probe_init(holo_plan* P, const float* amp_ref, holo_
   hipStream_t st = (hipStream_t)stream;
   const DevGeom g = make_geom(P);
   float2* q = (float2*)q_out;
-  HOLO_HIP(launch_real_to_c64(amp_ref, q, (size_t)P->H * P->W, st));
+  HOLO_HIP(timed(P, HOLO_K_PROBE, st,
+                 [&] { return launch_real_to_c64(amp_ref, q, (size_t)P->H * P->W, st); }));
   // D_{-1}: the reference step with the conjugate transfer, rows then columns
   PropJobs rj{}, cj{};
   rj.job[rj.n++] = PropJob{q, q, nullptr, chirp_ref(P->nd), 1, 0};
   cj.job[cj.n++] = PropJob{q, q, nullptr, chirp_ref(P->nd), 1, 0};
-  HOLO_HIP(launch_rows_prop(g, rj, st));
-  HOLO_HIP(launch_cols_prop(g, cj, nullptr, st));
+  HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_rows_prop(g, rj, st); }));
+  HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_cols_prop(g, cj, nullptr, st); }));
   return HOLO_OK;
 }
 
@@ -703,7 +704,9 @@ extern "C" holo_status holo_cg(holo_plan* P, holo_c64* u_, holo_c64* q_, const f
   };
   auto dot = [&](const float2* a1, const float2* b1, const float2* a2, const float2* b2,
                  double* host) -> holo_status {
-    HOLO_HIP(launch_dot_re(a1, b1, L.nu, a2, b2, L.nq, dparts, dscratch, ddot, st));
+    HOLO_HIP(timed(P, HOLO_K_SOLVER, st, [&] {
+      return launch_dot_re(a1, b1, L.nu, a2, b2, L.nq, dparts, dscratch, ddot, st);
+    }));
     return fetch(ddot, host);
   };
 #define HOLO_TRY(call)                      \
@@ -717,8 +720,12 @@ extern "C" holo_status holo_cg(holo_plan* P, holo_c64* u_, holo_c64* q_, const f
                c64(gu), c64(gq), ws, P->ws_bytes, stream));
   HOLO_TRY(fetch(dF, &F));
   F_hist[0] = F;
-  HOLO_HIP(launch_cg_dir(gu, eu, 0.f, 1, L.nu, st));
-  HOLO_HIP(launch_cg_dir(gq, eq, 0.f, 1, L.nq, st));
+  auto direction = [&](float beta, int restart) -> holo_status {
+    HOLO_HIP(timed(P, HOLO_K_SOLVER, st, [&] { return launch_cg_dir(gu, eu, beta, restart, L.nu, st); }));
+    HOLO_HIP(timed(P, HOLO_K_SOLVER, st, [&] { return launch_cg_dir(gq, eq, beta, restart, L.nq, st); }));
+    return HOLO_OK;
+  };
+  HOLO_TRY(direction(0.f, 1));
   double gamma_try = step0;
   for (int m = 0; m < iters; ++m) {
     double d_old = 0.0;   // <g_m, eta_m>, for the Dai-Yuan denominator
@@ -727,8 +734,9 @@ extern "C" holo_status holo_cg(holo_plan* P, holo_c64* u_, holo_c64* q_, const f
     int h = 0;
     bool accepted = false;
     for (; h <= kMaxHalvings; ++h, t *= 0.5) {
-      HOLO_HIP(launch_axpy(u, eu, (float)t, xu, L.nu, st));
-      HOLO_HIP(launch_axpy(q, eq, (float)t, xq, L.nq, st));
+      const float tf = (float)t;
+      HOLO_HIP(timed(P, HOLO_K_SOLVER, st, [&] { return launch_axpy(u, eu, tf, xu, L.nu, st); }));
+      HOLO_HIP(timed(P, HOLO_K_SOLVER, st, [&] { return launch_axpy(q, eq, tf, xq, L.nq, st); }));
       double Ft = 0.0;
       HOLO_TRY(run(P, kObj, c64(xu), c64(xq), 0, P->n_angles, nullptr, nullptr, amp, amp_ref, dF,
                    nullptr, nullptr, ws, P->ws_bytes, stream));
@@ -744,8 +752,12 @@ extern "C" holo_status holo_cg(holo_plan* P, holo_c64* u_, holo_c64* q_, const f
       if (halvings) halvings[m] = kMaxHalvings + 1;
       continue;
     }
-    HOLO_HIP(hipMemcpyAsync(u, xu, L.nu * sizeof(float2), hipMemcpyDeviceToDevice, st));
-    HOLO_HIP(hipMemcpyAsync(q, xq, L.nq * sizeof(float2), hipMemcpyDeviceToDevice, st));
+    HOLO_HIP(timed(P, HOLO_K_SOLVER, st, [&] {
+      return hipMemcpyAsync(u, xu, L.nu * sizeof(float2), hipMemcpyDeviceToDevice, st);
+    }));
+    HOLO_HIP(timed(P, HOLO_K_SOLVER, st, [&] {
+      return hipMemcpyAsync(q, xq, L.nq * sizeof(float2), hipMemcpyDeviceToDevice, st);
+    }));
     HOLO_TRY(run(P, kGrad, c64(u), c64(q), 0, P->n_angles, nullptr, nullptr, amp, amp_ref, dF,
                  c64(gu), c64(gq), ws, P->ws_bytes, stream));
     HOLO_TRY(fetch(dF, &F));
@@ -755,8 +767,7 @@ extern "C" holo_status holo_cg(holo_plan* P, holo_c64* u_, holo_c64* q_, const f
     const double den = g_eta - d_old;
     const bool restart = !(den > 0.0);
     const double beta = restart ? 0.0 : gg / den;
-    HOLO_HIP(launch_cg_dir(gu, eu, (float)beta, restart ? 1 : 0, L.nu, st));
-    HOLO_HIP(launch_cg_dir(gq, eq, (float)beta, restart ? 1 : 0, L.nq, st));
+    HOLO_TRY(direction((float)beta, restart ? 1 : 0));
     F_hist[m + 1] = F;
     if (steps) steps[m] = t;
     if (halvings) halvings[m] = h;

@@ -30,7 +30,7 @@ EXPORTS = (
 )
 
 KERNEL_CLASSES = ("radon_fwd", "radon_adj", "pass_a", "pass_b", "pass_c", "pass_d", "probe",
-                  "other")
+                  "other", "solver")
 
 STATUS = {0: "HOLO_OK", 1: "HOLO_ERR_INVALID_ARGUMENT", 2: "HOLO_ERR_UNSUPPORTED_SIZE",
           3: "HOLO_ERR_WORKSPACE_TOO_SMALL", 4: "HOLO_ERR_HIP", 5: "HOLO_ERR_OUT_OF_HOST_MEMORY"}
