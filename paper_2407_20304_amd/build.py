@@ -1,4 +1,5 @@
-"""Build libholo.so (HIP kernels + host runtime) for gfx950, in-tree."""
+"""Build libholo.so (HIP kernels + host runtime) and libholo_plain.so (the
+plain per-angle ray sums of the comparison baseline) for gfx950, in-tree."""
 import os
 import subprocess
 import sys
@@ -10,6 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libholo.so")
 SOURCES = ["holo_kernels.hip", "holo_api.cpp", "holo2d.hip", "holo2d_api.cpp"]
+PLAIN_LIB = os.path.join(HERE, "libholo_plain.so")
+PLAIN_SOURCES = [os.path.join("plain", "plain_radon.hip")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 (v_pk_*_f32) is disabled for every device pass.
@@ -18,7 +21,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include")]
 
 
 def _compile(src):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    obj = os.path.join(BUILD, os.path.splitext(src)[0].replace(os.sep, "_") + ".o")
     cmd = [HIPCC] + DEVICE_FLAGS + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
@@ -28,18 +31,24 @@ def _compile(src):
     return obj
 
 
-def build(verbose=True):
-    os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+def _link(objs, lib):
+    tmp = lib + ".tmp"
     cmd = [HIPCC] + DEVICE_FLAGS + ["-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s%s" % (" ".join(cmd), r.stdout, r.stderr))
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose=True):
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = SOURCES + PLAIN_SOURCES
+    with ThreadPoolExecutor(max_workers=len(srcs)) as ex:
+        objs = list(ex.map(_compile, srcs))
+    _link(objs[:len(SOURCES)], LIB)
+    _link(objs[len(SOURCES):], PLAIN_LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", PLAIN_LIB)
     return LIB
 
 

@@ -125,6 +125,22 @@ def test_solver_entry_points_validate_on_the_host():
     p.close()
 
 
+def test_plain_library_exports_and_validates():
+    from paper_2407_20304_amd import plain
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "holo_plain.h")).read(),
+                  flags=re.S)
+    names = sorted(set(re.findall(r"\b(holo_plain_\w+)\s*\(", text)))
+    assert names == ["holo_plain_radon", "holo_plain_radon_adj"]
+    L = plain.lib()
+    buf = ctypes.c_void_p(1)
+    for fn in (L.holo_plain_radon, L.holo_plain_radon_adj):
+        assert fn(None, 8, 64, 0.5, buf, None) == 1
+        assert fn(buf, 8, 64, 0.5, None, None) == 1
+        assert fn(buf, 0, 64, 0.5, buf, None) == 1
+        assert fn(buf, 8, 1, 0.5, buf, None) == 1
+        assert fn(buf, 8, 64, float("nan"), buf, None) == 1
+
+
 def test_batch_plan_offsets_and_validation():
     p = holo.Plan2D([128, 192, 512, 64], [1.0, 1.08, 1.25, 1.5], 300.0, 0.01)
     assert p.offsets == [0, 128 ** 2, 128 ** 2 + 192 ** 2, 128 ** 2 + 192 ** 2 + 512 ** 2]
