@@ -327,6 +327,10 @@ __global__ __launch_bounds__(kColThreads) void k_pass_b(const float2* __restrict
                                                         double* __restrict__ Fpart, DevGeom g,
                                                         int ntiles) {
   constexpr int TC = cols_tc(H), TLc = kColThreads / TC;
+  constexpr int NPT = H * TC / kColThreads;       // tile elements per thread
+  constexpr int RS = kColThreads / TC;            // tile rows between a thread's elements
+  static_assert(H * TC % kColThreads == 0 && RS % 32 == 0, "column tile");
+  constexpr bool kResidual = MODE == kColObj || MODE == kColGrad;
   __shared__ float2 s_tw[H];
   __shared__ float2 s_col[TC][col_pitch(H)];
   const int c = threadIdx.x / TLc, lt = threadIdx.x % TLc;
@@ -336,12 +340,29 @@ __global__ __launch_bounds__(kColThreads) void k_pass_b(const float2* __restrict
   const int s0 = tile * TC;
   const int f = L / ntiles;
   const int j = f % g.nd;
-  for (int i = threadIdx.x; i < H; i += kColThreads) s_tw[i] = g.twH[i];
+  // Element r of this thread is tile row z0 + r RS, column cc: global
+  // offset g0 + r RS W, LDS position l0 + r (RS + RS / 32) of column cc
+  // (RS is a multiple of 32, so the padding adds RS / 32 per step).  Every
+  // global load of the tile and of the twiddles (and below, of the
+  // amplitudes) is issued before the first is used, so their latencies
+  // overlap.  The bases are re-made opaque before each phase so that the
+  // per-element addresses are not kept live across the transforms.
+  const int z0 = threadIdx.x / TC, cc = threadIdx.x % TC;
+  const unsigned gstep = (unsigned)(RS * W);
+  unsigned g0 = (unsigned)(z0 * W + cc);
+  float2* l0 = &s_col[cc][fpi(z0)];
+  constexpr int LSTEP = RS + RS / 32;
   const float2* in = (MODE == kColAdj ? src : X) + (size_t)f * H * W + s0;
-  for (int i = threadIdx.x; i < H * TC; i += kColThreads) {
-    const int zz = i / TC, cc = i % TC;
-    s_col[cc][fpi(zz)] = in[(size_t)zz * W + cc];
+  float2 t[NPT];
+#pragma unroll
+  for (int r = 0; r < NPT; ++r) t[r] = in[g0 + r * gstep];
+#pragma unroll
+  for (int r = 0; r < (H + kColThreads - 1) / kColThreads; ++r) {
+    const int i = threadIdx.x + r * kColThreads;
+    if (i < H) s_tw[i] = g.twH[i];
   }
+#pragma unroll
+  for (int r = 0; r < NPT; ++r) l0[r * LSTEP] = t[r];
   float2* Lc = s_col[c];
   const float2* ch = g.chirpH + (size_t)chirp_det(j) * H;
   if (MODE != kColAdj) {
@@ -350,14 +371,18 @@ __global__ __launch_bounds__(kColThreads) void k_pass_b(const float2* __restrict
     fft<H, TLc, true, true>(Lc, s_tw, lt);
     __syncthreads();
   }
-  if (MODE == kColObj || MODE == kColGrad) {
-    double acc = 0.0;
+  if (kResidual) {
+    asm volatile("" : "+v"(g0), "+v"(l0));
     const float* a = amp + (size_t)f * H * W + s0;
-    for (int i = threadIdx.x; i < H * TC; i += kColThreads) {
-      const int zz = i / TC, cc = i % TC;
-      float2 v = s_col[cc][fpi(zz)];
-      acc += residual(v, a[(size_t)zz * W + cc]);
-      s_col[cc][fpi(zz)] = v;
+    float ar[NPT];
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) ar[r] = a[g0 + r * gstep];
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+      float2 v = l0[r * LSTEP];
+      acc += residual(v, ar[r]);
+      l0[r * LSTEP] = v;
     }
     block_sum_store<kColThreads>(acc, Fpart + (size_t)f * ntiles + tile);
   }
@@ -368,11 +393,10 @@ __global__ __launch_bounds__(kColThreads) void k_pass_b(const float2* __restrict
     __syncthreads();
   }
   if (MODE != kColObj) {
+    asm volatile("" : "+v"(g0), "+v"(l0));
     float2* out = X + (size_t)f * H * W + s0;
-    for (int i = threadIdx.x; i < H * TC; i += kColThreads) {
-      const int zz = i / TC, cc = i % TC;
-      out[(size_t)zz * W + cc] = s_col[cc][fpi(zz)];
-    }
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) out[g0 + r * gstep] = l0[r * LSTEP];
   }
 }
 
