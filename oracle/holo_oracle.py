@@ -277,6 +277,16 @@ def _residual(v: np.ndarray, a: np.ndarray):
     return float(np.sum((av - a) ** 2)), 2.0 * (v - a * unit)
 
 
+def _residual_intensity(v: np.ndarray, d: np.ndarray):
+    """Intensity functional F1 (Eq. 9): (|v|^2 - d)^2 summed, and its
+    gradient in v, r = dF/dRe v + i dF/dIm v = 4 (|v|^2 - d) v."""
+    e = np.abs(v) ** 2 - d
+    return float(np.sum(e ** 2)), 4.0 * e * v
+
+
+RESIDUALS = {"amplitude": _residual, "intensity": _residual_intensity}
+
+
 def forward(u: np.ndarray, q: np.ndarray, geom: Geometry, ks=None) -> np.ndarray:
     """Detector fields v_kj of Eq. (17) for the angles `ks` (default: all)."""
     ks = range(geom.n_angles) if ks is None else ks
@@ -291,22 +301,30 @@ def forward(u: np.ndarray, q: np.ndarray, geom: Geometry, ks=None) -> np.ndarray
     return out
 
 
-def reference_term(q: np.ndarray, amp_ref: np.ndarray, fresnel0: float):
-    """|| |D_1 q| - sqrt(d~r) ||^2 and its probe gradient D_{-1}(r_ref)."""
+def reference_term(q: np.ndarray, amp_ref: np.ndarray, fresnel0: float,
+                   functional: str = "amplitude"):
+    """|| |D_1 q| - sqrt(d~r) ||^2 (or, for the intensity functional,
+    || |D_1 q|^2 - d~r ||^2 with amp_ref holding d~r) and its probe gradient
+    D_{-1}(r_ref)."""
     P = propagate(q, 1.0, fresnel0)
-    F, r = _residual(P, amp_ref)
+    F, r = RESIDUALS[functional](P, amp_ref)
     return F, propagate(r, -1.0, fresnel0)
 
 
-def objective(u, q, amp, amp_ref, geom: Geometry) -> float:
-    """F(u, q) = F2(psi_k = exp(i kappa R_k u), q), Eq. (10) with Eq. (17)."""
+def objective(u, q, amp, amp_ref, geom: Geometry, functional: str = "amplitude") -> float:
+    """F(u, q) = F2(psi_k = exp(i kappa R_k u), q), Eq. (10) with Eq. (17);
+    with functional="intensity" the F1 of Eq. (9) instead (amp and amp_ref
+    then hold the intensities d~ and d~r)."""
     v = forward(u, q, geom)
-    F = float(np.sum((np.abs(v) - amp) ** 2))
-    return F + reference_term(q, amp_ref, geom.fresnel0)[0]
+    F = sum(RESIDUALS[functional](v[k, j], amp[k, j])[0]
+            for k in range(v.shape[0]) for j in range(v.shape[1]))
+    return F + reference_term(q, amp_ref, geom.fresnel0, functional)[0]
 
 
-def gradient(u, q, amp, amp_ref, geom: Geometry, with_reference=True):
-    """F, g_u, g_q of the joint objective.
+def gradient(u, q, amp, amp_ref, geom: Geometry, with_reference=True,
+             functional: str = "amplitude"):
+    """F, g_u, g_q of the joint objective (F2, or F1 with
+    functional="intensity").
 
     Per angle: forward to v_kj, residual r_kj (Eq. 11), w_kj = D_{-rho}(r_kj)
     (D* = D_{-z}), probe part conj(phi_kj) w_kj (display after Eq. 11),
@@ -325,7 +343,7 @@ def gradient(u, q, amp, amp_ref, geom: Geometry, with_reference=True):
             ty, tx = geom.t(k, j)
             phi = transmit(psi, geom.mag_rel[j], ty, tx)
             v = propagate(Q[j] * phi, rho_d[j], geom.fresnel0)
-            Fk, r = _residual(v, amp[k, j])
+            Fk, r = RESIDUALS[functional](v, amp[k, j])
             F += Fk
             w = propagate(r, -rho_d[j], geom.fresnel0)
             G[j] += np.conj(phi) * w
@@ -334,7 +352,7 @@ def gradient(u, q, amp, amp_ref, geom: Geometry, with_reference=True):
         g_u += radon_T(h, geom.theta[k], geom.W)
     g_q = sum(propagate(G[j], -rho_p[j], geom.fresnel0) for j in range(geom.n_dist))
     if with_reference:
-        Fr, gr = reference_term(q, amp_ref, geom.fresnel0)
+        Fr, gr = reference_term(q, amp_ref, geom.fresnel0, functional)
         F += Fr
         g_q = g_q + gr
     return F, g_u, g_q

@@ -280,6 +280,53 @@ def test_gradient_central_differences():
             assert an == pytest.approx(fd, rel=1e-6, abs=1e-9 * abs(F))
 
 
+def test_intensity_functional_central_differences():
+    # F1 of Eq. (9): the same chain with the residual 4 (|v|^2 - d) v
+    geom, u, q, amp, amp_ref = tiny_problem(seed=21)
+    d, d_ref = amp ** 2, amp_ref ** 2
+    F, gu, gq = O.gradient(u, q, d, d_ref, geom, functional="intensity")
+    assert F == pytest.approx(O.objective(u, q, d, d_ref, geom, functional="intensity"), rel=1e-12)
+    rng = np.random.default_rng(22)
+    for trial in range(3):
+        du = 1e-4 * crandn(rng, *u.shape)
+        dq = 1e-2 * crandn(rng, *q.shape)
+        for (a, b) in ((du, 0 * dq), (0 * du, dq), (du, dq)):
+            eps = 1e-3
+            Fp = O.objective(u + eps * a, q + eps * b, d, d_ref, geom, functional="intensity")
+            Fm = O.objective(u - eps * a, q - eps * b, d, d_ref, geom, functional="intensity")
+            fd = (Fp - Fm) / (2 * eps)
+            an = np.real(np.vdot(gu, a)) + np.real(np.vdot(gq, b))
+            assert an == pytest.approx(fd, rel=1e-6, abs=1e-9 * abs(F))
+
+
+def test_intensity_functional_is_quartic_in_the_probe():
+    # v is linear in q, so F1(u, q + t h) is a polynomial of degree 4 in t:
+    # the five-point derivative stencil is then exact, which pins the probe
+    # gradient to rounding (no truncation error), and a sixth point lies on
+    # the quartic through the first five.
+    geom, u, q, amp, amp_ref = tiny_problem(seed=23)
+    d, d_ref = amp ** 2, amp_ref ** 2
+    _, _, gq = O.gradient(u, q, d, d_ref, geom, functional="intensity")
+    h = crandn(np.random.default_rng(24), *q.shape)
+    f = lambda t: O.objective(u, q + t * h, d, d_ref, geom, functional="intensity")
+    dt = 0.05
+    ts = np.array([-2, -1, 0, 1, 2]) * dt
+    vals = np.array([f(t) for t in ts])
+    deriv = (vals[0] - 8 * vals[1] + 8 * vals[3] - vals[4]) / (12 * dt)
+    assert deriv == pytest.approx(np.real(np.vdot(gq, h)), rel=1e-9)
+    coef = np.polyfit(ts, vals, 4)
+    assert f(3.3 * dt) == pytest.approx(np.polyval(coef, 3.3 * dt), rel=1e-9)
+
+
+def test_intensity_functional_vanishes_at_the_truth():
+    geom, u, q, _, _ = tiny_problem(seed=25)
+    d = np.abs(O.forward(u, q, geom)) ** 2
+    d_ref = np.abs(O.propagate(q, 1.0, geom.fresnel0)) ** 2
+    F, gu, gq = O.gradient(u, q, d, d_ref, geom, functional="intensity")
+    assert F < 1e-24
+    assert np.max(np.abs(gu)) < 1e-9 and np.max(np.abs(gq)) < 1e-9
+
+
 def test_probe_phase_invariance():
     geom, u, q, amp, amp_ref = tiny_problem(seed=12)
     F0 = O.objective(u, q, amp, amp_ref, geom)
