@@ -107,6 +107,22 @@ holo_status holo_plan_destroy(holo_plan* plan);
 /* Bytes of device workspace every compute call of this plan needs. */
 holo_status holo_workspace_bytes(const holo_plan* plan, size_t* bytes);
 
+/* The least-squares functional that holo_objective, holo_grad*, holo_cg
+ * (and the residual they form) evaluate on this plan.
+ *   AMPLITUDE (default): F2 of Eq. (10),
+ *     sum || |v_kj| - a_kj ||^2 + || |D_1 q| - a_ref ||^2,
+ *     amp and amp_ref hold the amplitudes a = sqrt(d~).
+ *   INTENSITY: F1 of Eq. (9),
+ *     sum || |v_kj|^2 - d~_kj ||^2 + || |D_1 q|^2 - d~r ||^2,
+ *     amp and amp_ref then hold the intensities d~ themselves; the residual
+ *     is 4 (|v|^2 - d~) v.
+ * Errors: INVALID_ARGUMENT (NULL plan, unknown value).  Host-only. */
+typedef enum {
+  HOLO_FUNCTIONAL_AMPLITUDE = 0,
+  HOLO_FUNCTIONAL_INTENSITY = 1
+} holo_functional;
+holo_status holo_plan_set_functional(holo_plan* plan, int32_t functional);
+
 /* Forward model: v_kj for the angles k0 <= k < k1 (Eq. 8 with Eq. 17). */
 holo_status holo_fwd(holo_plan* plan, const holo_c64* u, const holo_c64* q,
                      int32_t k0, int32_t k1, holo_c64* v,

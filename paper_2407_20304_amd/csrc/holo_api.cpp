@@ -46,6 +46,7 @@ holo_status set_last_error(holo_status st, const std::string& msg) { return fail
 
 struct holo_plan {
   int H = 0, W = 0, n_angles = 0, nd = 0, chunk = 64;
+  int functional = HOLO_FUNCTIONAL_AMPLITUDE;
   double m0 = 0, fresnel0 = 0, kappa = 0;
   std::vector<double> theta, mag;
   std::vector<float> shift;                 // empty = no shifts
@@ -388,6 +389,7 @@ DevGeom make_geom(const holo_plan* P) {
   g.chirpW = (const float2*)(b + P->off_chW);
   g.chirpH = (const float2*)(b + P->off_chH);
   g.shift = P->shift.empty() ? nullptr : (const float*)(b + P->off_shift);
+  g.functional = P->functional;
   return g;
 }
 
@@ -775,6 +777,14 @@ extern "C" holo_status holo_cg(holo_plan* P, holo_c64* u_, holo_c64* q_, const f
   }
 #undef HOLO_TRY
   HOLO_HIP(hipStreamSynchronize(st));
+  return HOLO_OK;
+}
+
+extern "C" holo_status holo_plan_set_functional(holo_plan* P, int32_t functional) {
+  if (!P) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_set_functional: plan is NULL");
+  if (functional != HOLO_FUNCTIONAL_AMPLITUDE && functional != HOLO_FUNCTIONAL_INTENSITY)
+    return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_set_functional: unknown functional");
+  P->functional = functional;
   return HOLO_OK;
 }
 

@@ -33,6 +33,7 @@ struct DevGeom {
   const float2* chirpW;      // [3 nd + 1][W] transfer factors, times 1/W
   const float2* chirpH;      // [3 nd + 1][H] transfer factors, times 1/H
   const float* shift;        // [n_angles][nd][2] (t_y, t_x) or nullptr
+  int functional;            // 0: amplitude residual (F2), 1: intensity (F1)
 };
 
 // Transfer-function table rows: detector step of plane j, probe step of

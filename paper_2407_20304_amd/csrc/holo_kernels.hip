@@ -296,8 +296,16 @@ __device__ __forceinline__ void block_sum_store(double v, double* out) {
   }
 }
 
-// r = 2 (v - a v/|v|) in place (v/|v| := 0 at |v| = 0); returns (|v| - a)^2.
-__device__ __forceinline__ double residual(float2& v, float a) {
+// Amplitude functional (F2): r = 2 (v - a v/|v|) in place (v/|v| := 0 at
+// |v| = 0), returns (|v| - a)^2.  Intensity functional (F1, `a` is then the
+// intensity d): r = 4 (|v|^2 - d) v, returns (|v|^2 - d)^2.
+__device__ __forceinline__ double residual(float2& v, float a, int functional) {
+  if (functional) {
+    const double e = (double)fmaf(v.x, v.x, v.y * v.y) - (double)a;
+    const float sc = 4.0f * (float)e;
+    v = make_float2(sc * v.x, sc * v.y);
+    return e * e;
+  }
   const float av = sqrtf(v.x * v.x + v.y * v.y);
   const double d = (double)av - (double)a;
   const float sc = av > 0.0f ? 2.0f * (1.0f - a / av) : 2.0f;
@@ -381,7 +389,7 @@ __global__ __launch_bounds__(kColThreads) void k_pass_b(const float2* __restrict
 #pragma unroll
     for (int r = 0; r < NPT; ++r) {
       float2 v = l0[r * LSTEP];
-      acc += residual(v, ar[r]);
+      acc += residual(v, ar[r], g.functional);
       l0[r * LSTEP] = v;
     }
     block_sum_store<kColThreads>(acc, Fpart + (size_t)f * ntiles + tile);
@@ -428,7 +436,7 @@ __global__ __launch_bounds__(kColThreads) void k_cols_prop(PropJobs jobs, double
     for (int i = threadIdx.x; i < H * TC; i += kColThreads) {
       const int zz = i / TC, cc = i % TC;
       float2 v = s_col[cc][fpi(zz)];
-      acc += residual(v, a[(size_t)zz * W + cc]);
+      acc += residual(v, a[(size_t)zz * W + cc], g.functional);
       s_col[cc][fpi(zz)] = v;
     }
     block_sum_store<kColThreads>(acc, Fpart + (size_t)jb.fslot * gridDim.x + blockIdx.x);

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libholo.so")
 
 # Every symbol declared in include/holo.h.
 EXPORTS = (
-    "holo_plan_create", "holo_plan_destroy", "holo_workspace_bytes",
+    "holo_plan_create", "holo_plan_destroy", "holo_workspace_bytes", "holo_plan_set_functional",
     "holo_fwd", "holo_adj", "holo_objective", "holo_grad",
     "holo_grad_object", "holo_grad_probe",
     "holo_probe_init", "holo_cg_workspace_bytes", "holo_cg",
@@ -67,6 +67,7 @@ def lib():
     L.holo_plan_create.argtypes = [POINTER(holo_geom), POINTER(c_void_p)]
     L.holo_plan_destroy.argtypes = [P]
     L.holo_workspace_bytes.argtypes = [P, POINTER(c_size_t)]
+    L.holo_plan_set_functional.argtypes = [P, c_int32]
     L.holo_fwd.argtypes = [P, P, P, c_int32, c_int32, P, P, c_size_t, P]
     L.holo_adj.argtypes = [P, P, P, c_int32, c_int32, P, P, P, P, c_size_t, P]
     L.holo_objective.argtypes = [P, P, P, P, P, P, P, c_size_t, P]
@@ -161,6 +162,14 @@ class Plan:
         if self._ws is None or self._ws.device != torch.device(device):
             self._ws = torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=device)
         return self._ws
+
+    FUNCTIONALS = {"amplitude": 0, "intensity": 1}
+
+    def set_functional(self, name):
+        """"amplitude" (F2, default; amp = sqrt(d)) or "intensity" (F1; amp
+        and amp_ref then hold the intensities d)."""
+        _check(lib().holo_plan_set_functional(self._h, c_int32(self.FUNCTIONALS[name])))
+        self.functional = name
 
     # -- argument checks (shapes, dtypes, devices) -------------------------
     def _vol(self, t, name):

@@ -95,6 +95,19 @@ def test_null_arguments_return_invalid_argument():
     p.close()
 
 
+def test_functional_switch_validates_on_the_host():
+    L = holo.lib()
+    p = make_plan()
+    assert L.holo_plan_set_functional(None, 0) == 1
+    assert L.holo_plan_set_functional(p._h, 2) == 1
+    assert L.holo_plan_set_functional(p._h, -1) == 1
+    assert L.holo_plan_set_functional(p._h, 1) == 0
+    assert L.holo_plan_set_functional(p._h, 0) == 0
+    p.set_functional("intensity")
+    assert p.functional == "intensity"
+    p.close()
+
+
 def test_solver_entry_points_validate_on_the_host():
     L = holo.lib()
     p = make_plan()

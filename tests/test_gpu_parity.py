@@ -126,6 +126,32 @@ def test_grad_parity_shapes(H, W, n, chunk, shifts):
     assert rel(gq.cpu().numpy(), gq0) < TOL, rel(gq.cpu().numpy(), gq0)
 
 
+def test_intensity_functional_parity(small):
+    """F1 of Eq. (9): the plan switched to the intensity residual, data given
+    as intensities (the squared amplitudes)."""
+    import torch
+    say("intensity functional 64^3, 12 angles, shifts, chunk 5")
+    u, q, amp, amp_ref = PB.to_gpu(small)
+    plan = PB.gpu_plan(small)
+    plan.set_functional("intensity")
+    d, d_ref = (amp * amp).contiguous(), (amp_ref * amp_ref).contiguous()
+    F, g_u, g_q = plan.holo_grad(u, q, d, d_ref)
+    Fo = plan.holo_objective(u, q, d, d_ref)
+    # the same float32 intensities on both sides
+    d64 = (small.amp * small.amp).astype(np.float64)
+    dr64 = (small.amp_ref * small.amp_ref).astype(np.float64)
+    Fr, gur, gqr = O.gradient(PB.c128(small.u), PB.c128(small.q), d64, dr64, small.geom,
+                              functional="intensity")
+    assert abs(F.item() - Fr) / Fr < TOL and abs(Fo.item() - Fr) / Fr < TOL
+    assert rel(g_u.cpu().numpy(), gur) < TOL, rel(g_u.cpu().numpy(), gur)
+    assert rel(g_q.cpu().numpy(), gqr) < TOL, rel(g_q.cpu().numpy(), gqr)
+    # and back to the amplitude functional on the same plan
+    plan.set_functional("amplitude")
+    F2, _, _ = plan.holo_grad(u, q, amp, amp_ref)
+    Fo2, _, _ = PB.oracle_grad(small)
+    assert abs(F2.item() - Fo2) / Fo2 < TOL
+
+
 def test_repeat_calls_are_bitwise_identical(small):
     say("determinism")
     u, q, amp, amp_ref = PB.to_gpu(small)
