@@ -107,6 +107,28 @@ holo_status holo_plan_destroy(holo_plan* plan);
 /* Bytes of device workspace every compute call of this plan needs. */
 holo_status holo_workspace_bytes(const holo_plan* plan, size_t* bytes);
 
+/* Angles per chunk (the frames of one chunk are formed, back-propagated and
+ * dropped before the next; the workspace grows with it).  set_chunk changes
+ * the plan's workspace size (query holo_workspace_bytes again); chunks below
+ * the plan's largest forward angle group (at most 4 angles) are rejected
+ * with INVALID_ARGUMENT; values above n_angles are clamped.  Host-only. */
+holo_status holo_plan_set_chunk(holo_plan* plan, int32_t chunk);
+holo_status holo_plan_get_chunk(const holo_plan* plan, int32_t* chunk);
+
+/* Autotuner of the chunk size: one untimed gradient, then one gradient per
+ * candidate timed with HIP events on `stream` (times_ms[n_cand], may be
+ * NULL); the fastest candidate becomes the plan's chunk and is returned in
+ * *best_chunk.  The inputs and outputs are those of holo_grad (all
+ * required); `ws` must hold the workspace of the largest candidate
+ * (WORKSPACE_TOO_SMALL otherwise, before any device work).  Synchronises
+ * `stream`.  The chunk is a launch-shape choice: results agree with any
+ * other chunk to rounding. */
+holo_status holo_plan_autotune(holo_plan* plan, const holo_c64* u, const holo_c64* q,
+                               const float* amp, const float* amp_ref, double* F,
+                               holo_c64* g_u, holo_c64* g_q, const int32_t* candidates,
+                               int32_t n_cand, void* ws, size_t ws_bytes,
+                               int32_t* best_chunk, float* times_ms, void* stream);
+
 /* The least-squares functional that holo_objective, holo_grad*, holo_cg
  * (and the residual they form) evaluate on this plan.
  *   AMPLITUDE (default): F2 of Eq. (10),

@@ -47,6 +47,7 @@ holo_status set_last_error(holo_status st, const std::string& msg) { return fail
 struct holo_plan {
   int H = 0, W = 0, n_angles = 0, nd = 0, chunk = 64;
   int functional = HOLO_FUNCTIONAL_AMPLITUDE;
+  int max_group = 1;                        // largest forward angle group
   double m0 = 0, fresnel0 = 0, kappa = 0;
   std::vector<double> theta, mag;
   std::vector<float> shift;                 // empty = no shifts
@@ -122,6 +123,29 @@ static bool fwd_group_fits(const holo_plan* P, int a, int b) {
     }
   }
   return true;
+}
+
+// Workspace layout of a plan (depends on its chunk).
+static void layout_workspace(holo_plan* P) {
+  const size_t fr = (size_t)P->H * P->W * sizeof(float2);
+  size_t o = 0;
+  P->off_Q = o;   o = align_up(o + fr * P->nd);
+  P->off_G = o;   o = align_up(o + fr * P->nd);
+  P->off_P = o;   o = align_up(o + fr);
+  // z-blocked copies of the volume read by the ray sums (one per walk
+  // direction), rows padded by kFwdPad zero columns on each side
+  const size_t vb = (size_t)P->H * P->W * vol_row(P->W) * sizeof(float2);
+  P->off_ub = o;  o = align_up(o + vb);
+  P->off_uTb = o; o = align_up(o + (P->any_xwalk ? vb : 0));
+  P->off_psi = o; o = align_up(o + fr * P->chunk);
+  P->off_X = o;   o = align_up(o + fr * P->chunk * P->nd);
+  // sinogram rows carry kAdjPad zero bins on each side
+  P->off_S = o;   o = align_up(o + (size_t)P->H * sino_row(P->W) * sizeof(float2) * P->n_angles);
+  const size_t tiles = (size_t)P->W / cols_per_wg(P->H);
+  P->n_fpart = tiles * (1 + (size_t)P->n_angles * P->nd);
+  // cost partials, then the reduction's stage-one sums
+  P->off_F = o;   o = align_up(o + (P->n_fpart + kReduceParts) * sizeof(double));
+  P->ws_bytes = o;
 }
 
 extern "C" holo_status holo_plan_create(const holo_geom* geom, holo_plan** out) {
@@ -206,6 +230,7 @@ extern "C" holo_status holo_plan_create(const holo_geom* geom, holo_plan** out) 
         ++b;
       for (int k = a; k < b; ++k) P->group_of[k] = (int)P->groups.size();
       P->groups.push_back(make_int2(a, b - a));
+      P->max_group = std::max(P->max_group, b - a);
       a = b;
     }
 
@@ -222,26 +247,7 @@ extern "C" holo_status holo_plan_create(const holo_geom* geom, holo_plan** out) 
     build_twiddles(P->twW, P->W);
     build_twiddles(P->twH, P->H);
 
-    // Workspace layout.
-    const size_t fr = (size_t)P->H * P->W * sizeof(float2);
-    size_t o = 0;
-    P->off_Q = o;   o = align_up(o + fr * P->nd);
-    P->off_G = o;   o = align_up(o + fr * P->nd);
-    P->off_P = o;   o = align_up(o + fr);
-    // z-blocked copies of the volume read by the ray sums (one per walk
-    // direction), rows padded by kFwdPad zero columns on each side
-    const size_t vb = (size_t)P->H * P->W * vol_row(P->W) * sizeof(float2);
-    P->off_ub = o;  o = align_up(o + vb);
-    P->off_uTb = o; o = align_up(o + (P->any_xwalk ? vb : 0));
-    P->off_psi = o; o = align_up(o + fr * P->chunk);
-    P->off_X = o;   o = align_up(o + fr * P->chunk * P->nd);
-    // sinogram rows carry kAdjPad zero bins on each side
-    P->off_S = o;   o = align_up(o + (size_t)P->H * sino_row(P->W) * sizeof(float2) * P->n_angles);
-    const size_t tiles = (size_t)P->W / cols_per_wg(P->H);
-    P->n_fpart = tiles * (1 + (size_t)P->n_angles * P->nd);
-    // cost partials, then the reduction's stage-one sums
-    P->off_F = o;   o = align_up(o + (P->n_fpart + kReduceParts) * sizeof(double));
-    P->ws_bytes = o;
+    layout_workspace(P);
 
     // Device table layout.
     size_t t = 0;
@@ -778,6 +784,95 @@ extern "C" holo_status holo_cg(holo_plan* P, holo_c64* u_, holo_c64* q_, const f
 #undef HOLO_TRY
   HOLO_HIP(hipStreamSynchronize(st));
   return HOLO_OK;
+}
+
+extern "C" holo_status holo_plan_set_chunk(holo_plan* P, int32_t chunk) {
+  if (!P) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_set_chunk: plan is NULL");
+  if (chunk < P->max_group)
+    return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_set_chunk: chunk must be >= " +
+                                               std::to_string(P->max_group) +
+                                               " (the largest forward angle group)");
+  P->chunk = std::min<int>(chunk, P->n_angles);
+  layout_workspace(P);
+  return HOLO_OK;
+}
+
+extern "C" holo_status holo_plan_get_chunk(const holo_plan* P, int32_t* chunk) {
+  if (!P || !chunk) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_get_chunk: NULL argument");
+  *chunk = P->chunk;
+  return HOLO_OK;
+}
+
+extern "C" holo_status holo_plan_autotune(holo_plan* P, const holo_c64* u, const holo_c64* q,
+                                          const float* amp, const float* amp_ref, double* F,
+                                          holo_c64* g_u, holo_c64* g_q, const int32_t* candidates,
+                                          int32_t n_cand, void* ws, size_t ws_bytes,
+                                          int32_t* best_chunk, float* times_ms, void* stream) {
+  holo_status s = check_common(P, u, q, "holo_plan_autotune");
+  if (s != HOLO_OK) return s;
+  if (!amp || !amp_ref || !F || !g_u || !g_q || !candidates || !best_chunk || !ws)
+    return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_autotune: NULL argument");
+  if (n_cand < 1) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_autotune: no candidates");
+  const int chunk0 = P->chunk;
+  size_t need = 0;
+  for (int i = 0; i < n_cand; ++i) {
+    if (candidates[i] < P->max_group) {
+      P->chunk = chunk0;
+      layout_workspace(P);
+      return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_autotune: candidate " +
+                                                 std::to_string(candidates[i]) + " is below " +
+                                                 std::to_string(P->max_group));
+    }
+    P->chunk = std::min<int>(candidates[i], P->n_angles);
+    layout_workspace(P);
+    need = std::max(need, P->ws_bytes);
+  }
+  P->chunk = chunk0;
+  layout_workspace(P);
+  if (ws_bytes < need)
+    return fail(HOLO_ERR_WORKSPACE_TOO_SMALL, "holo_plan_autotune: workspace needs " +
+                                                  std::to_string(need) + " bytes, got " +
+                                                  std::to_string(ws_bytes));
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HOLO_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(HOLO_ERR_HIP, "holo_plan_autotune: hipEventCreate failed");
+  }
+  auto grad = [&]() {
+    return run(P, kGrad, u, q, 0, P->n_angles, nullptr, nullptr, amp, amp_ref, F, g_u, g_q, ws,
+               ws_bytes, stream);
+  };
+  // One untimed gradient first (device tables, code load), then one timed
+  // gradient per candidate; the fastest becomes the plan's chunk.
+  int best = chunk0;
+  float best_ms = 0.f;
+  s = grad();
+  for (int i = 0; i < n_cand && s == HOLO_OK; ++i) {
+    P->chunk = std::min<int>(candidates[i], P->n_angles);
+    layout_workspace(P);
+    float ms = 0.f;
+    if (hipEventRecord(e0, st) != hipSuccess) { s = fail(HOLO_ERR_HIP, "hipEventRecord"); break; }
+    s = grad();
+    if (s != HOLO_OK) break;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      s = fail(HOLO_ERR_HIP, "holo_plan_autotune: event timing failed");
+      break;
+    }
+    if (times_ms) times_ms[i] = ms;
+    if (i == 0 || ms < best_ms) {
+      best_ms = ms;
+      best = P->chunk;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  P->chunk = s == HOLO_OK ? best : chunk0;
+  layout_workspace(P);
+  if (s == HOLO_OK) *best_chunk = best;
+  return s;
 }
 
 extern "C" holo_status holo_plan_set_functional(holo_plan* P, int32_t functional) {

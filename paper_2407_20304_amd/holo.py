@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libholo.so")
 # Every symbol declared in include/holo.h.
 EXPORTS = (
     "holo_plan_create", "holo_plan_destroy", "holo_workspace_bytes", "holo_plan_set_functional",
+    "holo_plan_set_chunk", "holo_plan_get_chunk", "holo_plan_autotune",
     "holo_fwd", "holo_adj", "holo_objective", "holo_grad",
     "holo_grad_object", "holo_grad_probe",
     "holo_probe_init", "holo_cg_workspace_bytes", "holo_cg",
@@ -68,6 +69,9 @@ def lib():
     L.holo_plan_destroy.argtypes = [P]
     L.holo_workspace_bytes.argtypes = [P, POINTER(c_size_t)]
     L.holo_plan_set_functional.argtypes = [P, c_int32]
+    L.holo_plan_set_chunk.argtypes = [P, c_int32]
+    L.holo_plan_get_chunk.argtypes = [P, POINTER(c_int32)]
+    L.holo_plan_autotune.argtypes = [P, P, P, P, P, P, P, P, P, c_int32, P, c_size_t, P, P, P]
     L.holo_fwd.argtypes = [P, P, P, c_int32, c_int32, P, P, c_size_t, P]
     L.holo_adj.argtypes = [P, P, P, c_int32, c_int32, P, P, P, P, c_size_t, P]
     L.holo_objective.argtypes = [P, P, P, P, P, P, P, c_size_t, P]
@@ -162,6 +166,82 @@ class Plan:
         if self._ws is None or self._ws.device != torch.device(device):
             self._ws = torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=device)
         return self._ws
+
+    @property
+    def chunk(self):
+        c = c_int32()
+        _check(lib().holo_plan_get_chunk(self._h, ctypes.byref(c)))
+        return int(c.value)
+
+    def set_chunk(self, chunk):
+        """Angles per chunk; updates workspace_bytes (the workspace is
+        reallocated on the next call if it grew)."""
+        _check(lib().holo_plan_set_chunk(self._h, c_int32(int(chunk))))
+        self._refresh_workspace_size()
+
+    def _refresh_workspace_size(self):
+        n = c_size_t()
+        _check(lib().holo_workspace_bytes(self._h, ctypes.byref(n)))
+        self.workspace_bytes = int(n.value)
+        if self._ws is not None and self._ws.numel() < self.workspace_bytes:
+            self._ws = None
+
+    def tune_key(self, device):
+        import torch
+        return "%dx%dx%d_%dangles_%dplanes:%s" % (
+            self.H, self.W, self.W, self.n_angles, self.n_dist,
+            torch.cuda.get_device_name(torch.device(device)))
+
+    def autotune(self, u, q, amp, amp_ref, candidates=(16, 32, 64, 128), cache=None,
+                 stream=None):
+        """Choose the chunk size by timing one gradient per candidate
+        (holo_plan_autotune).  With `cache` (a JSON file path; default the
+        HOLO_TUNE_CACHE environment variable, if set) a result stored for
+        this geometry and device is reused without timing, and a new result
+        is stored.  Returns (chunk, {candidate: ms} or None when cached)."""
+        import json
+        import torch
+        self._check_data(u, q, amp, amp_ref)
+        cache = cache or os.environ.get("HOLO_TUNE_CACHE")
+        key = self.tune_key(u.device)
+        cands = sorted({max(int(c), 1) for c in candidates})
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                entry = json.load(f).get(key)
+            if entry is not None and int(entry["chunk"]) in cands:
+                self.set_chunk(int(entry["chunk"]))
+                return int(entry["chunk"]), None
+        chunk0 = self.chunk
+        need = 0
+        for c in cands:
+            self.set_chunk(c)
+            need = max(need, self.workspace_bytes)
+        self.set_chunk(chunk0)
+        ws = torch.empty(need, dtype=torch.uint8, device=u.device)
+        F = torch.empty((1,), dtype=torch.float64, device=u.device)
+        g_u, g_q = torch.empty_like(u), torch.empty_like(q)
+        arr = (c_int32 * len(cands))(*cands)
+        times = (c_float * len(cands))()
+        best = c_int32()
+        _check(lib().holo_plan_autotune(self._h, _ptr(u), _ptr(q), _ptr(amp), _ptr(amp_ref),
+                                        _ptr(F), _ptr(g_u), _ptr(g_q), arr, c_int32(len(cands)),
+                                        _ptr(ws), c_size_t(ws.numel()), ctypes.byref(best),
+                                        times, _stream(stream)))
+        del ws, g_u, g_q
+        self._ws = None
+        self._refresh_workspace_size()
+        result = {c: float(t) for c, t in zip(cands, times)}
+        if cache:
+            data = {}
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    data = json.load(f)
+            data[key] = {"chunk": int(best.value), "ms": {str(c): t for c, t in result.items()}}
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(data, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return int(best.value), result
 
     FUNCTIONALS = {"amplitude": 0, "intensity": 1}
 

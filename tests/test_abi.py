@@ -95,6 +95,34 @@ def test_null_arguments_return_invalid_argument():
     p.close()
 
 
+def test_chunk_and_autotune_validate_on_the_host():
+    L = holo.lib()
+    p = make_plan(chunk=4)
+    c = ctypes.c_int32()
+    assert L.holo_plan_get_chunk(p._h, ctypes.byref(c)) == 0 and c.value == 4
+    assert L.holo_plan_set_chunk(None, 8) == 1
+    ws4 = p.workspace_bytes
+    p.set_chunk(8)
+    assert p.chunk == 8 and p.workspace_bytes > ws4
+    p.set_chunk(100)                      # clamped to n_angles
+    assert p.chunk == 10
+    # a chunk below the largest forward angle group (>= 1) is rejected
+    assert L.holo_plan_set_chunk(p._h, 0) == 1
+    assert L.holo_plan_set_chunk(p._h, -5) == 1
+    buf = ctypes.c_void_p(1)
+    best = ctypes.c_int32()
+    cands = (ctypes.c_int32 * 2)(4, 8)
+    args = [p._h, buf, buf, buf, buf, buf, buf, buf]
+    assert L.holo_plan_autotune(None, *args[1:], cands, 2, buf, 1 << 40, ctypes.byref(best), None, None) == 1
+    assert L.holo_plan_autotune(*args, cands, 0, buf, 1 << 40, ctypes.byref(best), None, None) == 1
+    assert L.holo_plan_autotune(*args, None, 2, buf, 1 << 40, ctypes.byref(best), None, None) == 1
+    bad = (ctypes.c_int32 * 2)(0, 8)
+    assert L.holo_plan_autotune(*args, bad, 2, buf, 1 << 40, ctypes.byref(best), None, None) == 1
+    assert p.chunk == 10                  # a rejected call leaves the plan as it was
+    assert L.holo_plan_autotune(*args, cands, 2, buf, 16, ctypes.byref(best), None, None) == 3
+    p.close()
+
+
 def test_functional_switch_validates_on_the_host():
     L = holo.lib()
     p = make_plan()

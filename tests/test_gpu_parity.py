@@ -152,6 +152,27 @@ def test_intensity_functional_parity(small):
     assert abs(F2.item() - Fo2) / Fo2 < TOL
 
 
+def test_autotune_chunk_and_cache(small, tmp_path):
+    """The chunk autotuner times one gradient per candidate, keeps the
+    fastest, and the tuned plan's gradient still matches the oracle; a
+    second call with the same cache file reuses the stored choice."""
+    say("autotune chunk 64^3, 12 angles, candidates 4, 6, 12")
+    u, q, amp, amp_ref = PB.to_gpu(small)
+    plan = PB.gpu_plan(small)
+    cache = str(tmp_path / "tune.json")
+    best, times = plan.autotune(u, q, amp, amp_ref, candidates=(4, 6, 12), cache=cache)
+    assert best in (4, 6, 12) and plan.chunk == best
+    assert set(times) == {4, 6, 12} and all(t > 0 for t in times.values())
+    assert times[best] == min(times.values())
+    F, g_u, g_q = plan.holo_grad(u, q, amp, amp_ref)
+    Fo, guo, gqo = PB.oracle_grad(small)
+    assert abs(F.item() - Fo) / Fo < TOL
+    assert rel(g_u.cpu().numpy(), guo) < TOL and rel(g_q.cpu().numpy(), gqo) < TOL
+    plan2 = PB.gpu_plan(small)
+    best2, times2 = plan2.autotune(u, q, amp, amp_ref, candidates=(4, 6, 12), cache=cache)
+    assert best2 == best and times2 is None and plan2.chunk == best
+
+
 def test_repeat_calls_are_bitwise_identical(small):
     say("determinism")
     u, q, amp, amp_ref = PB.to_gpu(small)
