@@ -30,8 +30,8 @@ FLOP_PER_LERP = 8               # 2 taps x (re, im) x fused multiply-add
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean over the launches of
 # one gradient evaluation), each scaled by what the same counter reads for a
 # 1 GiB device-to-device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  The
-# figures hold for the library sources they were taken on (SHA-256 over the
-# csrc files); after any change to those sources the field reports null.
+# figures hold for the kernel sources they were taken on (SHA-256 over
+# KERNEL_SOURCES); after any change to those the field reports null.
 TRAFFIC = {
     "k_radon_fwd": {"fetch_kib": 16718983.70, "write_kib": 1248190.17,
                     "fetch_scale": 2.0, "write_scale": 1.0,
@@ -43,14 +43,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Sources the dominant kernel is built from (its body, the shared constants
+# and launch helpers, and the FFT header compiled into the same unit).
+KERNEL_SOURCES = ("holo_kernels.hip", "holo_internal.hpp", "fft_lds.hpp")
+
+
 def csrc_sha256():
-    import glob
     import hashlib
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2407_20304_amd", "csrc", "*"))):
-        if p.endswith((".hip", ".hpp", ".cpp", ".h")):
-            with open(p, "rb") as f:
-                h.update(f.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2407_20304_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()
 
 
@@ -210,6 +213,9 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy before the timed region "
                          "(a known-size reference for HBM traffic counters)")
+    ap.add_argument("--tune", action="store_true",
+                    help="choose the chunk size with the autotuner (candidates 16, 32, 64, 128) "
+                         "before timing; the default keeps the workload's chunk of 64")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip timing the plain unfused form (the speed-up denominator)")
     ap.add_argument("--solver", type=int, default=0, metavar="ITERS",
@@ -254,6 +260,11 @@ def main():
         log("calibration copy: 1 GiB read + 1 GiB written")
 
     plan = holo.Plan.for_workload(wl)
+    tuned = None
+    if args.tune:
+        best, times = plan.autotune(u, q, amp, amp_ref, candidates=(16, 32, 64, 128))
+        tuned = {"chunk": best, "ms": times}
+        log("autotune: chunk %d (%s)" % (best, times))
     if args.solver > 0:
         solver_bench(args, wl, plan, u, amp, amp_ref)
         return
@@ -318,7 +329,7 @@ def main():
         "vs_baseline": None,
         "dtype": "c64",
         "data": "synthetic",
-        "config": {"workload": wl.name, "volume": [H, W, W], "n_angles": N, "chunk": wl.chunk,
+        "config": {"workload": wl.name, "volume": [H, W, W], "n_angles": N, "chunk": plan.chunk,
                    "n_dist": nd, "detector": [H, W], "parallelism": "single GPU"},
         "objective": Fv,
         "frame_stage_GBps": frame_gbs,
@@ -326,6 +337,8 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
     }
+    if tuned is not None:
+        result["autotune"] = tuned
     if not args.no_plain:
         result["plain"] = plain_bench(wl, u, q, amp, amp_ref, F, g_u, g_q, K / elapsed)
         result["vs_plain"] = result["plain"]["speedup"]

@@ -498,6 +498,70 @@ def holo_cg(u0, q0, amp, amp_ref, geom: Geometry, iters, step0):
 
 
 # ---------------------------------------------------------------------------
+# Hierarchical binning and upsampling (Sec. 4, the speed-up schedule:
+# iterate on binned data, move the result to a grid twice as dense, continue
+# with less binning).  Readings:
+#   M1  binning by b averages the intensities of b x b detector pixels; for
+#       amplitude data a_b = sqrt(mean a^2);
+#   M2  the binned problem is the same dimensionless model on pixels b times
+#       larger: N_F0 -> b^2 N_F0 (N_F0 = Delta^2 / (lambda zeta_0)),
+#       kappa -> b kappa (phase per voxel of path), H -> H / b, W -> W / b,
+#       shifts -> shifts / b; angles, m~_j and m0 are unchanged;
+#   M3  moving to a grid f times denser replicates every cell (f^3 voxels of
+#       the volume, f^2 pixels of a frame).
+# ---------------------------------------------------------------------------
+
+def bin_frames(d: np.ndarray, b: int, amplitude: bool = True) -> np.ndarray:
+    """M1 on the last two axes (sizes divisible by b)."""
+    d = np.asarray(d, dtype=np.float64)
+    H, W = d.shape[-2:]
+    x = d * d if amplitude else d
+    m = x.reshape(d.shape[:-2] + (H // b, b, W // b, b)).mean(axis=(-3, -1))
+    return np.sqrt(m) if amplitude else m
+
+
+def upsample_frame(q: np.ndarray, f: int) -> np.ndarray:
+    """M3 for a frame (last two axes)."""
+    return np.repeat(np.repeat(q, f, axis=-2), f, axis=-1)
+
+
+def upsample_volume(u: np.ndarray, f: int) -> np.ndarray:
+    """M3 for a volume [z][y][x]."""
+    return np.repeat(np.repeat(np.repeat(u, f, axis=0), f, axis=1), f, axis=2)
+
+
+def level_geometry(geom: Geometry, b: int) -> Geometry:
+    """M2: the geometry of the problem binned by b."""
+    return Geometry(H=geom.H // b, W=geom.W // b, theta=geom.theta, mag_rel=geom.mag_rel,
+                    m0=geom.m0, fresnel0=geom.fresnel0 * b * b, kappa=geom.kappa * b,
+                    shift=None if geom.shift is None else geom.shift / b)
+
+
+def multires_cg(amp, amp_ref, geom: Geometry, schedule):
+    """The hierarchical schedule: for each (b, iters, step0) in order (b
+    decreasing, each dividing the one before), bin the data by b (M1),
+    start from the previous level's result moved to the denser grid (M3) --
+    or, at the first level, from u = 0 and the back-propagated reference --
+    and run `iters` conjugate-gradient iterations on the level's geometry
+    (M2).  Returns the final (u, q) and each level's objective history."""
+    u = q = None
+    prev = None
+    hists = []
+    for b, iters, step0 in schedule:
+        g = level_geometry(geom, b)
+        a, ar = bin_frames(amp, b), bin_frames(amp_ref, b)
+        if u is None:
+            u = np.zeros((g.H, g.W, g.W), np.complex128)
+            q = probe_init(ar, g.fresnel0)
+        else:
+            u, q = upsample_volume(u, prev // b), upsample_frame(q, prev // b)
+        u, q, hist, _, _ = holo_cg(u, q, a, ar, g, iters, step0)
+        hists.append(hist)
+        prev = b
+    return u, q, hists
+
+
+# ---------------------------------------------------------------------------
 # Error metric used by the parity tests
 # ---------------------------------------------------------------------------
 

@@ -535,3 +535,67 @@ def test_dai_yuan_direction_identity():
     g0 = (np.ones(3, complex),)
     eta, beta = O.dai_yuan_direction(g0, g0, (np.ones(3, complex),))
     assert beta == 0.0 and np.allclose(eta[0], -1.0)
+
+
+# ---------------------------------------------------------------------------
+# Hierarchical binning (readings M1-M3)
+# ---------------------------------------------------------------------------
+
+def test_binning_inverts_replication_and_keeps_intensity():
+    rng = np.random.default_rng(31)
+    a = np.abs(crandn(rng, 3, 2, 8, 12))
+    for f in (2, 4):
+        up = O.upsample_frame(a, f)
+        np.testing.assert_allclose(O.bin_frames(up, f), a, rtol=1e-14)
+        np.testing.assert_allclose(O.bin_frames(up ** 2, f, amplitude=False), a ** 2, rtol=1e-14)
+    # mean of the intensities: the total intensity shrinks by exactly b^2
+    d = a ** 2
+    assert O.bin_frames(d, 2, amplitude=False).sum() * 4 == pytest.approx(d.sum(), rel=1e-14)
+    assert O.bin_frames(a, 2) ** 2 == pytest.approx(O.bin_frames(d, 2, amplitude=False), rel=1e-14)
+
+
+@pytest.mark.parametrize("theta", [0.0, np.pi / 2])
+def test_coarse_phase_equals_fine_phase_of_the_replicated_volume(theta):
+    # At theta = 0 (pi/2) a ray sum is a plain sum along y (x): the
+    # replicated volume's sums are f times the coarse sums, replicated, and
+    # kappa scaled by f (M2) makes the transmittances identical.
+    rng = np.random.default_rng(32)
+    g = O.Geometry(H=16, W=16, theta=[theta], mag_rel=[1.0], kappa=40.0)
+    for f in (2, 4):
+        gc = O.level_geometry(g, f)
+        u = 1e-3 * (rng.uniform(0, 1, (gc.H, gc.W, gc.W)) + 0.01j * rng.uniform(0, 1, (gc.H, gc.W, gc.W)))
+        psi_c = O.transmittance(u, theta, gc.kappa)
+        psi_f = O.transmittance(O.upsample_volume(u, f), theta, g.kappa)
+        np.testing.assert_allclose(psi_f, O.upsample_frame(psi_c, f), rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("b", [2, 4])
+def test_coarse_propagation_samples_the_same_physical_wave(b):
+    # A Gaussian of physical width s0 pixels sampled on pixels b times
+    # larger and propagated with N_F0 b^2 (M2) equals the fine closed form
+    # at the coarse sample points: the b^2 scaling is the Fresnel number's.
+    n, s0, nf, rho = 256, 16.0, 0.01, 0.6
+    alpha = rho / nf
+    nc = n // b
+    y = (np.arange(nc)[:, None] - nc / 2) * b
+    x = (np.arange(nc)[None, :] - nc / 2) * b
+    fc = np.exp(-(x ** 2 + y ** 2) / (2 * s0 ** 2))
+    s2 = s0 ** 2 + 1j * alpha / (2 * np.pi)
+    exact = (s0 ** 2 / s2) * np.exp(-(x ** 2 + y ** 2) / (2 * s2))
+    np.testing.assert_allclose(O.propagate(fc, rho, nf * b * b), exact, atol=1e-10)
+
+
+def test_level_geometry_identity_and_schedule_runs():
+    g = O.Geometry(H=8, W=16, theta=[0.2, 1.0, 2.4], mag_rel=[1.0, 1.08, 1.25, 1.5],
+                   m0=300.0, fresnel0=0.05, kappa=40.0)
+    g1 = O.level_geometry(g, 1)
+    assert (g1.H, g1.W, g1.fresnel0, g1.kappa) == (g.H, g.W, g.fresnel0, g.kappa)
+    rng = np.random.default_rng(33)
+    u_true = 1e-3 * rng.uniform(0, 1, (8, 16, 16)) * (1 + 0.01j)
+    q_true = 1 + 0.05 * crandn(rng, 8, 16)
+    amp = np.abs(O.forward(u_true, q_true, g))
+    amp_ref = np.abs(O.propagate(q_true, 1.0, g.fresnel0))
+    u, q, hists = O.multires_cg(amp, amp_ref, g, [(2, 3, 1e-3), (1, 3, 1e-3)])
+    assert u.shape == (8, 16, 16) and q.shape == (8, 16)
+    for h in hists:
+        assert all(b <= a for a, b in zip(h, h[1:]))
