@@ -223,6 +223,31 @@ holo_status holo_cg(holo_plan* plan, holo_c64* u, holo_c64* q,
                     void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Hierarchical schedule (Sec. 4): iterate on binned data, move the result to
+ * a grid twice as dense, continue with less binning.  A problem binned by b
+ * is the same model on pixels b times larger: H/b x W/b detector,
+ * W/b x W/b x H/b volume, fresnel0 * b^2, kappa * b, shifts / b.
+ * ------------------------------------------------------------------------- */
+
+/* out[f][y][x] = mean of in[f] over the b x b block (y b .. y b + b - 1,
+ * x b .. x b + b - 1), summed in double; with `amplitude` != 0 the data are
+ * amplitudes and out = sqrt(mean in^2) (intensities are averaged).  in
+ * [n_frames][H][W] float, out [n_frames][H/b][W/b] float (device).
+ * Errors: INVALID_ARGUMENT (NULL, sizes < 1, b not dividing H and W, out
+ * aliasing in for b > 1). */
+holo_status holo_bin_frames(const float* in, int64_t n_frames, int32_t H, int32_t W, int32_t b,
+                            int32_t amplitude, float* out, void* stream);
+
+/* Move complex frames [n_frames][H][W] (or a volume [H][W][W]) to the grid
+ * f times denser by replication: out[n][f H][f W] with out[.][y][x] =
+ * in[.][y / f][x / f] (the volume also along z: out[f H][f W][f W]).
+ * Errors: INVALID_ARGUMENT (NULL, sizes or f < 1, out aliasing in). */
+holo_status holo_upsample_frames(const holo_c64* in, int64_t n_frames, int32_t H, int32_t W,
+                                 int32_t f, holo_c64* out, void* stream);
+holo_status holo_upsample_volume(const holo_c64* in, int32_t H, int32_t W, int32_t f,
+                                 holo_c64* out, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Batched independent single-angle retrievals (Eq. 10 and Eq. 11 with one
  * projection, psi the unknown, own probe and reference per instance).
  *

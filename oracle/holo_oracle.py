@@ -485,7 +485,7 @@ def probe_init(amp_ref, fresnel0) -> np.ndarray:
     return propagate(np.asarray(amp_ref, dtype=np.complex128), -1.0, fresnel0)
 
 
-def holo_cg(u0, q0, amp, amp_ref, geom: Geometry, iters, step0):
+def holo_cg(u0, q0, amp, amp_ref, geom: Geometry, iters, step0, line_search=None):
     """`iters` Dai-Yuan CG iterations on the joint objective F(u, q)."""
     f = lambda x: objective(x[0], x[1], amp, amp_ref, geom)
 
@@ -493,7 +493,7 @@ def holo_cg(u0, q0, amp, amp_ref, geom: Geometry, iters, step0):
         F, gu, gq = gradient(x[0], x[1], amp, amp_ref, geom)
         return F, (gu, gq)
 
-    (u, q), hist, steps, halv = cg_dai_yuan(f, grad, (u0, q0), iters, step0)
+    (u, q), hist, steps, halv = cg_dai_yuan(f, grad, (u0, q0), iters, step0, line_search)
     return u, q, hist, steps, halv
 
 
@@ -537,7 +537,7 @@ def level_geometry(geom: Geometry, b: int) -> Geometry:
                     shift=None if geom.shift is None else geom.shift / b)
 
 
-def multires_cg(amp, amp_ref, geom: Geometry, schedule):
+def multires_cg(amp, amp_ref, geom: Geometry, schedule, line_search=None):
     """The hierarchical schedule: for each (b, iters, step0) in order (b
     decreasing, each dividing the one before), bin the data by b (M1),
     start from the previous level's result moved to the denser grid (M3) --
@@ -555,7 +555,7 @@ def multires_cg(amp, amp_ref, geom: Geometry, schedule):
             q = probe_init(ar, g.fresnel0)
         else:
             u, q = upsample_volume(u, prev // b), upsample_frame(q, prev // b)
-        u, q, hist, _, _ = holo_cg(u, q, a, ar, g, iters, step0)
+        u, q, hist, _, _ = holo_cg(u, q, a, ar, g, iters, step0, line_search)
         hists.append(hist)
         prev = b
     return u, q, hists

@@ -25,6 +25,7 @@ EXPORTS = (
     "holo_fwd", "holo_adj", "holo_objective", "holo_grad",
     "holo_grad_object", "holo_grad_probe",
     "holo_probe_init", "holo_cg_workspace_bytes", "holo_cg",
+    "holo_bin_frames", "holo_upsample_frames", "holo_upsample_volume",
     "holo2d_plan_create", "holo2d_plan_destroy", "holo2d_offsets", "holo2d_workspace_bytes",
     "holo2d_fwd", "holo2d_objective", "holo2d_grad",
     "holo_timing_enable", "holo_timing_read", "holo_last_error",
@@ -79,6 +80,9 @@ def lib():
     L.holo_grad_object.argtypes = [P, P, P, P, P, P, P, P, c_size_t, P]
     L.holo_grad_probe.argtypes = [P, P, P, P, P, P, P, P, c_size_t, P]
     L.holo_probe_init.argtypes = [P, P, P, P]
+    L.holo_bin_frames.argtypes = [P, ctypes.c_int64, c_int32, c_int32, c_int32, c_int32, P, P]
+    L.holo_upsample_frames.argtypes = [P, ctypes.c_int64, c_int32, c_int32, c_int32, P, P]
+    L.holo_upsample_volume.argtypes = [P, c_int32, c_int32, c_int32, P, P]
     L.holo_cg_workspace_bytes.argtypes = [P, POINTER(c_size_t)]
     L.holo_cg.argtypes = [P, P, P, P, P, c_int32, c_double, P, P, P, P, c_size_t, P]
     L.holo2d_plan_create.argtypes = [c_int32, POINTER(c_int32), c_int32, POINTER(c_double),
@@ -113,6 +117,43 @@ def _stream(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return c_void_p(stream.cuda_stream)
+
+
+def bin_frames(t, b, amplitude=True, stream=None):
+    """holo_bin_frames on a contiguous float32 GPU tensor [..., H, W]."""
+    import torch
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.dim() < 2:
+        raise ValueError("bin_frames needs a contiguous float32 GPU tensor [..., H, W]")
+    H, W = t.shape[-2:]
+    n = t.numel() // (H * W)
+    out = torch.empty(t.shape[:-2] + (H // b, W // b), dtype=torch.float32, device=t.device)
+    _check(lib().holo_bin_frames(_ptr(t), n, H, W, int(b), 1 if amplitude else 0, _ptr(out),
+                                 _stream(stream)))
+    return out
+
+
+def upsample_frames(t, f, stream=None):
+    """holo_upsample_frames on a contiguous complex64 GPU tensor [..., H, W]."""
+    import torch
+    if t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous() or t.dim() < 2:
+        raise ValueError("upsample_frames needs a contiguous complex64 GPU tensor [..., H, W]")
+    H, W = t.shape[-2:]
+    n = t.numel() // (H * W)
+    out = torch.empty(t.shape[:-2] + (H * f, W * f), dtype=torch.complex64, device=t.device)
+    _check(lib().holo_upsample_frames(_ptr(t), n, H, W, int(f), _ptr(out), _stream(stream)))
+    return out
+
+
+def upsample_volume(t, f, stream=None):
+    """holo_upsample_volume on a contiguous complex64 GPU tensor [H, W, W]."""
+    import torch
+    if t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous() or t.dim() != 3 \
+            or t.shape[1] != t.shape[2]:
+        raise ValueError("upsample_volume needs a contiguous complex64 GPU tensor [H, W, W]")
+    H, W = t.shape[0], t.shape[1]
+    out = torch.empty((H * f, W * f, W * f), dtype=torch.complex64, device=t.device)
+    _check(lib().holo_upsample_volume(_ptr(t), H, W, int(f), _ptr(out), _stream(stream)))
+    return out
 
 
 class Plan:

@@ -123,6 +123,20 @@ def test_chunk_and_autotune_validate_on_the_host():
     p.close()
 
 
+def test_binning_entry_points_validate_on_the_host():
+    L = holo.lib()
+    buf, buf2 = ctypes.c_void_p(1), ctypes.c_void_p(2)
+    assert L.holo_bin_frames(None, 1, 8, 8, 2, 1, buf2, None) == 1
+    assert L.holo_bin_frames(buf, 0, 8, 8, 2, 1, buf2, None) == 1
+    assert L.holo_bin_frames(buf, 1, 8, 6, 4, 1, buf2, None) == 1   # 4 does not divide 6
+    assert L.holo_bin_frames(buf, 1, 8, 8, 0, 1, buf2, None) == 1
+    assert L.holo_bin_frames(buf, 1, 8, 8, 2, 1, buf, None) == 1    # aliasing
+    assert L.holo_upsample_frames(buf, 1, 8, 8, 0, buf2, None) == 1
+    assert L.holo_upsample_frames(buf, 1, 8, 8, 2, buf, None) == 1
+    assert L.holo_upsample_volume(None, 8, 8, 2, buf2, None) == 1
+    assert L.holo_upsample_volume(buf, 8, 0, 2, buf2, None) == 1
+
+
 def test_functional_switch_validates_on_the_host():
     L = holo.lib()
     p = make_plan()
