@@ -800,8 +800,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
   const int L = xcd_logical(blockIdx.x, gridDim.x);
   const int nt = W / 16;
   const int x0 = (L % nt) * 16, y0 = ((L / nt) % nt) * 16;
-  const int dx = threadIdx.x & 15, dy = threadIdx.x >> 4;
-  const int x = x0 + dx, y = y0 + dy;
+  // thread: voxel pair (x, x + 1), x = x0 + 2 px, row y0 + dy, and the 8
+  // slices of slice group sg of the block
+  const int px = threadIdx.x & 7, dy = (threadIdx.x >> 3) & 15, sg = threadIdx.x >> 7;
+  const int x = x0 + 2 * px, y = y0 + dy;
   const int z0 = (L / (nt * nt)) * ZT;
   const double X0 = (double)x0 - g.cW, X1 = X0 + 15.0;
   const double Y0 = (double)y0 - g.cW, Y1 = Y0 + 15.0;
@@ -860,10 +862,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
           : "memory", "m0");
   };
 
-  float ax[ZT], ay[ZT];
-  float ox[ZT], oy[ZT];
+  constexpr int ZS = ZT / 2;                        // slices per thread
+  float ax[2][ZS], ay[2][ZS];
+  float ox[2][ZS], oy[2][ZS];
 #pragma unroll
-  for (int i = 0; i < ZT; ++i) { ax[i] = ay[i] = 0.f; ox[i] = oy[i] = 0.f; }
+  for (int v = 0; v < 2; ++v)
+#pragma unroll
+    for (int i = 0; i < ZS; ++i) { ax[v][i] = ay[v][i] = 0.f; ox[v][i] = oy[v][i] = 0.f; }
 
   const int ng = (K + NA - 1) / NA;
   constexpr int GPW = TW / NA;                      // groups per set-up window
@@ -887,54 +892,66 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
     const int slot = (k0 / TW) & 1, base = k0 % TW;
     const float2* gb = tile + (gi % NBUF) * GF2;
     for (int a = 0; a < na; ++a) {
+      // the pair's fractional bins q and q + cos; every bin with a nonzero
+      // weight for either voxel (|i - q| < h <= 1) is one of jm .. jm + 2,
+      // jm = floor(min of the two), and its weight is the footprint
+      // max(0, 1 - |i - q| / h) / h = max(0, 1/h - |i - q| / h^2)
       const float ih = s_ih[slot][base + a], ih2 = s_ih2[slot][base + a];
-      const float qr = fmaf((float)dy, s_s[slot][base + a],
-                            fmaf((float)dx, s_c[slot][base + a], s_f0[slot][base + a]));
-      const float fl = floorf(qr);
-      const float fr = qr - fl;
-      const float w0 = fmaxf(0.0f, fmaf(-fr, ih2, ih));
-      const float w1 = fmaxf(0.0f, fmaf(fr - 1.0f, ih2, ih));
-      const int j0 = min(max((int)fl, 0), SEG - 2);
-      // two bases, 8 slices apart: each slice's tap pair is then one read
-      // at an immediate offset (the offset field spans 8 slice rows)
-      int hi_idx = a * ZT * SEG + j0 + 8 * SEG;
-      asm volatile("" : "+v"(hi_idx));                 // keep it a base of its own
-      const float2* tpl = gb + a * ZT * SEG + j0;
-      const float2* tph = gb + hi_idx;
-      auto tap = [&](int i) {
-        const float2* t = (i < 8 ? tpl : tph) + (i & 7) * SEG;
-        const float2 v0 = t[0], v1 = t[1];
-        return make_float4(v0.x, v0.y, v1.x, v1.y);
-      };
-      // software pipeline: the taps of slice i + LA are requested before
-      // slice i is accumulated, so LA + 1 LDS reads are in flight
+      const float c = s_c[slot][base + a];
+      const float qa = fmaf((float)dy, s_s[slot][base + a],
+                            fmaf((float)(2 * px), c, s_f0[slot][base + a]));
+      const float qb = qa + c;
+      const float fl = floorf(fminf(qa, qb));
+      const int jm = min(max((int)fl, 0), SEG - 3);
+      float wt[2][3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float bin = (float)(jm + k);        // the bins actually read
+        wt[0][k] = fmaxf(0.0f, fmaf(-fabsf(bin - qa), ih2, ih));
+        wt[1][k] = fmaxf(0.0f, fmaf(-fabsf(bin - qb), ih2, ih));
+      }
+      const float2* tp = gb + a * ZT * SEG + sg * ZS * SEG + jm;
+      // software pipeline: the three bins of slice i + LA are requested
+      // before slice i is accumulated
       constexpr int LA = 3;
-      static_assert(ZT == 16, "two bases of 8 slices");
-      float4 v[ZT];
+      static_assert(ZS == 8, "slice group");
+      float2 r[ZS][3];
+      auto fetch = [&](int i) {
+        const float2* t = tp + i * SEG;
+        r[i][0] = t[0];
+        r[i][1] = t[1];
+        r[i][2] = t[2];
+      };
 #pragma unroll
-      for (int i = 0; i < LA; ++i) v[i] = tap(i);
+      for (int i = 0; i < LA; ++i) fetch(i);
 #pragma unroll
-      for (int i = 0; i < ZT; ++i) {
-        if (i + LA < ZT) v[i + LA] = tap(i + LA);
-        ax[i] = fmaf(w1, v[i].z, fmaf(w0, v[i].x, ax[i]));
-        ay[i] = fmaf(w1, v[i].w, fmaf(w0, v[i].y, ay[i]));
+      for (int i = 0; i < ZS; ++i) {
+        if (i + LA < ZS) fetch(i + LA);
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          ax[v][i] = fmaf(wt[v][2], r[i][2].x, fmaf(wt[v][1], r[i][1].x, fmaf(wt[v][0], r[i][0].x, ax[v][i])));
+          ay[v][i] = fmaf(wt[v][2], r[i][2].y, fmaf(wt[v][1], r[i][1].y, fmaf(wt[v][0], r[i][0].y, ay[v][i])));
+        }
       }
     }
     // two-level single-precision sums: partials of up to 8 NA angles are
     // added into the outer sums
     if ((gi & 7) == 7 || gi + 1 >= ng) {
 #pragma unroll
-      for (int i = 0; i < ZT; ++i) {
-        ox[i] += ax[i];
-        oy[i] += ay[i];
-        ax[i] = ay[i] = 0.f;
-      }
+      for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int i = 0; i < ZS; ++i) {
+          ox[v][i] += ax[v][i];
+          oy[v][i] += ay[v][i];
+          ax[v][i] = ay[v][i] = 0.f;
+        }
     }
   }
   const size_t WW = (size_t)W * W;
 #pragma unroll
-  for (int i = 0; i < ZT; ++i) {
-    gu[(size_t)(z0 + i) * WW + (size_t)y * W + x] = make_float2(ox[i], oy[i]);
+  for (int i = 0; i < ZS; ++i) {
+    float4* o = reinterpret_cast<float4*>(gu + (size_t)(z0 + sg * ZS + i) * WW + (size_t)y * W + x);
+    *o = make_float4(ox[0][i], oy[0][i], ox[1][i], oy[1][i]);
   }
 }
 
