@@ -105,12 +105,15 @@ class Geometry:
     fresnel0: float = 0.01      # N_F0 of the first plane
     kappa: float = 4667.35      # phase per unit u per voxel of path
     shift: Optional[np.ndarray] = None   # (n_angles, n_dist, 2) = (t_y, t_x) px
+    probe_shift: Optional[np.ndarray] = None   # (n_angles, n_dist, 2) = (s_y, s_x) px
 
     def __post_init__(self):
         self.theta = np.asarray(self.theta, dtype=np.float64)
         self.mag_rel = np.asarray(self.mag_rel, dtype=np.float64)
         if self.shift is not None:
             self.shift = np.asarray(self.shift, dtype=np.float64)
+        if self.probe_shift is not None:
+            self.probe_shift = np.asarray(self.probe_shift, dtype=np.float64)
 
     @property
     def n_angles(self):
@@ -124,6 +127,11 @@ class Geometry:
         if self.shift is None:
             return 0.0, 0.0
         return float(self.shift[k, j, 0]), float(self.shift[k, j, 1])
+
+    def s(self, k, j):
+        if self.probe_shift is None:
+            return 0.0, 0.0
+        return float(self.probe_shift[k, j, 0]), float(self.probe_shift[k, j, 1])
 
 
 # ---------------------------------------------------------------------------
@@ -264,6 +272,38 @@ def transmittance(u: np.ndarray, theta: float, kappa: float) -> np.ndarray:
     return np.exp(1j * kappa * radon(u, theta))
 
 
+def circular_shift_matrix(n: int, shift: float) -> np.ndarray:
+    """n x n matrix of the circular linear-interpolation shift along one
+    axis (reading R23): (S f)[i] = f sampled at i - shift, indices mod n."""
+    src = np.arange(n, dtype=np.float64) - shift
+    i0 = np.floor(src).astype(np.int64)
+    w = src - i0
+    S = np.zeros((n, n))
+    S[np.arange(n), i0 % n] += 1.0 - w
+    S[np.arange(n), (i0 + 1) % n] += w
+    return S
+
+
+def probe_shift_op(f: np.ndarray, sy: float, sx: float) -> np.ndarray:
+    """S_s f on the last two axes (Eq. 9 with probe shifts, reading R23)."""
+    H, W = f.shape[-2:]
+    return circular_shift_matrix(H, sy) @ f @ circular_shift_matrix(W, sx).T
+
+
+def probe_shift_op_T(g: np.ndarray, sy: float, sx: float) -> np.ndarray:
+    """S_s^T, the literal transpose of `probe_shift_op`."""
+    H, W = g.shape[-2:]
+    return circular_shift_matrix(H, sy).T @ g @ circular_shift_matrix(W, sx)
+
+
+def probe_frames(q: np.ndarray, geom: Geometry, k: int):
+    """Q_kj = D_{rho_probe_j}(S_{s_kj} q): the probe at sample plane j for
+    angle k (Eq. 9, shifting then propagating, as written)."""
+    _, rho_p = distances(geom.m0, geom.mag_rel)
+    return [propagate(probe_shift_op(q, *geom.s(k, j)), r, geom.fresnel0)
+            for j, r in enumerate(rho_p)]
+
+
 def probes(q: np.ndarray, geom: Geometry):
     """Q_j = D_{rho_probe_j} q: the probe at sample plane j (Eq. 8)."""
     _, rho_p = distances(geom.m0, geom.mag_rel)
@@ -294,6 +334,8 @@ def forward(u: np.ndarray, q: np.ndarray, geom: Geometry, ks=None) -> np.ndarray
     Q = probes(q, geom)
     out = np.zeros((len(ks), geom.n_dist, geom.H, geom.W), dtype=np.complex128)
     for a, k in enumerate(ks):
+        if geom.probe_shift is not None:
+            Q = probe_frames(q, geom, k)
         psi = transmittance(u, geom.theta[k], geom.kappa)
         for j in range(geom.n_dist):
             phi = transmit(psi, geom.mag_rel[j], *geom.t(k, j))
@@ -336,7 +378,10 @@ def gradient(u, q, amp, amp_ref, geom: Geometry, with_reference=True,
     F = 0.0
     G = [np.zeros((geom.H, geom.W), np.complex128) for _ in range(geom.n_dist)]
     g_u = np.zeros(u.shape, np.complex128)
+    g_q = np.zeros((geom.H, geom.W), np.complex128)
     for k in range(geom.n_angles):
+        if geom.probe_shift is not None:
+            Q = probe_frames(q, geom, k)
         psi = transmittance(u, geom.theta[k], geom.kappa)
         g_psi = np.zeros_like(psi)
         for j in range(geom.n_dist):
@@ -346,11 +391,15 @@ def gradient(u, q, amp, amp_ref, geom: Geometry, with_reference=True,
             Fk, r = RESIDUALS[functional](v, amp[k, j])
             F += Fk
             w = propagate(r, -rho_d[j], geom.fresnel0)
-            G[j] += np.conj(phi) * w
+            if geom.probe_shift is None:
+                G[j] += np.conj(phi) * w
+            else:   # Q_kj = D S q: back through D, then S^T
+                g_q += probe_shift_op_T(propagate(np.conj(phi) * w, -rho_p[j], geom.fresnel0),
+                                        *geom.s(k, j))
             g_psi += resample_T(np.conj(Q[j]) * w, geom.mag_rel[j], ty, tx)
         h = -1j * geom.kappa * np.conj(psi) * g_psi
         g_u += radon_T(h, geom.theta[k], geom.W)
-    g_q = sum(propagate(G[j], -rho_p[j], geom.fresnel0) for j in range(geom.n_dist))
+    g_q = g_q + sum(propagate(G[j], -rho_p[j], geom.fresnel0) for j in range(geom.n_dist))
     if with_reference:
         Fr, gr = reference_term(q, amp_ref, geom.fresnel0, functional)
         F += Fr
@@ -370,17 +419,24 @@ def adjoint(u, q, w_frames, geom: Geometry, ks=None):
     Q = probes(q, geom)
     G = [np.zeros((geom.H, geom.W), np.complex128) for _ in range(geom.n_dist)]
     g_u = np.zeros(u.shape, np.complex128)
+    g_q = np.zeros((geom.H, geom.W), np.complex128)
     for a, k in enumerate(ks):
+        if geom.probe_shift is not None:
+            Q = probe_frames(q, geom, k)
         psi = transmittance(u, geom.theta[k], geom.kappa)
         g_psi = np.zeros_like(psi)
         for j in range(geom.n_dist):
             ty, tx = geom.t(k, j)
             phi = transmit(psi, geom.mag_rel[j], ty, tx)
             wb = propagate(w_frames[a, j], -rho_d[j], geom.fresnel0)
-            G[j] += np.conj(phi) * wb
+            if geom.probe_shift is None:
+                G[j] += np.conj(phi) * wb
+            else:
+                g_q += probe_shift_op_T(propagate(np.conj(phi) * wb, -rho_p[j], geom.fresnel0),
+                                        *geom.s(k, j))
             g_psi += resample_T(np.conj(Q[j]) * wb, geom.mag_rel[j], ty, tx)
         g_u += radon_T(-1j * geom.kappa * np.conj(psi) * g_psi, geom.theta[k], geom.W)
-    g_q = sum(propagate(G[j], -rho_p[j], geom.fresnel0) for j in range(geom.n_dist))
+    g_q = g_q + sum(propagate(G[j], -rho_p[j], geom.fresnel0) for j in range(geom.n_dist))
     return g_u, g_q
 
 
@@ -534,7 +590,8 @@ def level_geometry(geom: Geometry, b: int) -> Geometry:
     """M2: the geometry of the problem binned by b."""
     return Geometry(H=geom.H // b, W=geom.W // b, theta=geom.theta, mag_rel=geom.mag_rel,
                     m0=geom.m0, fresnel0=geom.fresnel0 * b * b, kappa=geom.kappa * b,
-                    shift=None if geom.shift is None else geom.shift / b)
+                    shift=None if geom.shift is None else geom.shift / b,
+                    probe_shift=None if geom.probe_shift is None else geom.probe_shift / b)
 
 
 def multires_cg(amp, amp_ref, geom: Geometry, schedule, line_search=None):

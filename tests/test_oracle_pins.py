@@ -599,3 +599,59 @@ def test_level_geometry_identity_and_schedule_runs():
     assert u.shape == (8, 16, 16) and q.shape == (8, 16)
     for h in hists:
         assert all(b <= a for a, b in zip(h, h[1:]))
+
+
+# ---------------------------------------------------------------------------
+# Probe shifts s_kj (Eq. 9, reading R23: circular linear-interpolation shift)
+# ---------------------------------------------------------------------------
+
+def test_probe_shift_operator_identities():
+    rng = np.random.default_rng(51)
+    f = crandn(rng, 12, 20)
+    # an integer shift is a circular roll
+    np.testing.assert_allclose(O.probe_shift_op(f, 3.0, -5.0), np.roll(f, (3, -5), axis=(0, 1)),
+                               atol=1e-14)
+    # the transpose is the shift by -s (both are circulant)
+    g = crandn(rng, 12, 20)
+    for sy, sx in ((0.3, -1.7), (2.25, 0.5)):
+        np.testing.assert_allclose(O.probe_shift_op_T(g, sy, sx), O.probe_shift_op(g, -sy, -sx),
+                                   atol=1e-13)
+        # and it commutes with the Fresnel propagator, so D S q = S D q
+        np.testing.assert_allclose(O.propagate(O.probe_shift_op(f, sy, sx), 0.7, 0.05),
+                                   O.probe_shift_op(O.propagate(f, 0.7, 0.05), sy, sx), atol=1e-12)
+        # a half-pixel shift averages neighbours
+        h = O.probe_shift_op(f, 0.0, 0.5)
+        np.testing.assert_allclose(h, 0.5 * (f + np.roll(f, 1, axis=1)), atol=1e-14)
+
+
+def test_probe_shifts_central_differences_and_zero_shift():
+    geom, u, q, amp, amp_ref = tiny_problem(seed=52)
+    rng = np.random.default_rng(53)
+    geom0 = O.Geometry(H=geom.H, W=geom.W, theta=geom.theta, mag_rel=geom.mag_rel, m0=geom.m0,
+                       fresnel0=geom.fresnel0, kappa=geom.kappa, shift=geom.shift,
+                       probe_shift=np.zeros((geom.n_angles, geom.n_dist, 2)))
+    F0 = O.objective(u, q, amp, amp_ref, geom)
+    assert O.objective(u, q, amp, amp_ref, geom0) == pytest.approx(F0, rel=1e-13)
+    gs = O.Geometry(H=geom.H, W=geom.W, theta=geom.theta, mag_rel=geom.mag_rel, m0=geom.m0,
+                    fresnel0=geom.fresnel0, kappa=geom.kappa, shift=geom.shift,
+                    probe_shift=rng.uniform(-2.5, 2.5, (geom.n_angles, geom.n_dist, 2)))
+    F, gu, gq = O.gradient(u, q, amp, amp_ref, gs)
+    assert F == pytest.approx(O.objective(u, q, amp, amp_ref, gs), rel=1e-12)
+    assert abs(F - F0) > 1e-6 * F0          # the shifts change the model
+    for trial in range(3):
+        du = 1e-4 * crandn(rng, *u.shape)
+        dq = 1e-2 * crandn(rng, *q.shape)
+        for (a, b) in ((du, 0 * dq), (0 * du, dq)):
+            eps = 1e-3
+            fd = (O.objective(u + eps * a, q + eps * b, amp, amp_ref, gs)
+                  - O.objective(u - eps * a, q - eps * b, amp, amp_ref, gs)) / (2 * eps)
+            an = np.real(np.vdot(gu, a)) + np.real(np.vdot(gq, b))
+            assert an == pytest.approx(fd, rel=1e-6, abs=1e-9 * abs(F))
+    # the adjoint with w = r reproduces the gradient without the reference term
+    v = O.forward(u, q, gs)
+    r = np.stack([np.stack([O._residual(v[k, j], amp[k, j])[1] for j in range(gs.n_dist)])
+                  for k in range(gs.n_angles)])
+    au, aq = O.adjoint(u, q, r, gs)
+    _, gu2, gq2 = O.gradient(u, q, amp, amp_ref, gs, with_reference=False)
+    np.testing.assert_allclose(au, gu2, atol=1e-12 * np.abs(gu2).max())
+    np.testing.assert_allclose(aq, gq2, atol=1e-12 * np.abs(gq2).max())
