@@ -107,6 +107,17 @@ holo_status holo_plan_destroy(holo_plan* plan);
 /* Bytes of device workspace every compute call of this plan needs. */
 holo_status holo_workspace_bytes(const holo_plan* plan, size_t* bytes);
 
+/* Probe shifts s_kj of Eq. (9): Q_kj = D_{rho_probe_j}(S_{s_kj} q) with S_s
+ * the shift by s = (s_y, s_x) pixels, f sampled at (y - s_y, x - s_x) with
+ * linear interpolation on the periodic H x W grid (so S_s commutes with the
+ * propagators and the kernels shift Q_j = D_{rho_probe_j} q directly).
+ * `shifts` is host memory [n_angles][n_dist][2], copied; NULL removes the
+ * shifts.  Setting shifts grows the workspace by chunk * n_dist frames
+ * (query holo_workspace_bytes again).  Errors: INVALID_ARGUMENT (NULL plan,
+ * non-finite shift).  Host-only; the device copy is refreshed by the next
+ * compute call. */
+holo_status holo_plan_set_probe_shifts(holo_plan* plan, const float* shifts);
+
 /* Angles per chunk (the frames of one chunk are formed, back-propagated and
  * dropped before the next; the workspace grows with it).  set_chunk changes
  * the plan's workspace size (query holo_workspace_bytes again); chunks below

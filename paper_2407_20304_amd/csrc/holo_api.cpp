@@ -51,6 +51,8 @@ struct holo_plan {
   double m0 = 0, fresnel0 = 0, kappa = 0;
   std::vector<double> theta, mag;
   std::vector<float> shift;                 // empty = no shifts
+  std::vector<float> pshift;                // probe shifts, empty = none
+  bool pshift_dirty = false;                // device copy older than pshift
   std::vector<double> ang;                  // [n_angles][kAngleStride]
   std::vector<float2> twW, twH, chirpW, chirpH;
   bool any_xwalk = false;
@@ -65,7 +67,7 @@ struct holo_plan {
   void* d_tables = nullptr;
   int device = -1;
   size_t off_twW = 0, off_twH = 0, off_chW = 0, off_chH = 0, off_ang = 0, off_shift = 0,
-         off_groups = 0;
+         off_groups = 0, off_pshift = 0, table_bytes = 0, off_Pbuf = 0;
   // timing diagnostics
   bool timing = false;
   std::vector<hipEvent_t> ev_free;
@@ -145,6 +147,8 @@ static void layout_workspace(holo_plan* P) {
   P->n_fpart = tiles * (1 + (size_t)P->n_angles * P->nd);
   // cost partials, then the reduction's stage-one sums
   P->off_F = o;   o = align_up(o + (P->n_fpart + kReduceParts) * sizeof(double));
+  // with probe shifts: conj(phi) w of every frame of a chunk
+  P->off_Pbuf = o; o = align_up(o + (P->pshift.empty() ? 0 : fr * P->chunk * P->nd));
   P->ws_bytes = o;
 }
 
@@ -258,6 +262,9 @@ extern "C" holo_status holo_plan_create(const holo_geom* geom, holo_plan** out) 
     P->off_ang = t;   t = align_up(t + P->ang.size() * sizeof(double));
     P->off_shift = t; t = align_up(t + P->shift.size() * sizeof(float));
     P->off_groups = t; t = align_up(t + P->groups.size() * sizeof(int2));
+    // probe shifts (room for all of them, filled when set)
+    P->off_pshift = t; t = align_up(t + (size_t)P->n_angles * P->nd * 2 * sizeof(float));
+    P->table_bytes = t + 256;
   } catch (const std::bad_alloc&) {
     delete P;
     return fail(HOLO_ERR_OUT_OF_HOST_MEMORY, "holo_plan_create: out of host memory");
@@ -353,9 +360,13 @@ holo_status ensure_tables(holo_plan* P) {
     if (dev != P->device)
       return fail(HOLO_ERR_INVALID_ARGUMENT, "plan tables live on device " + std::to_string(P->device) +
                                                  ", current device is " + std::to_string(dev));
+    if (P->pshift_dirty && !P->pshift.empty())
+      HOLO_HIP(hipMemcpy((char*)P->d_tables + P->off_pshift, P->pshift.data(),
+                         P->pshift.size() * sizeof(float), hipMemcpyHostToDevice));
+    P->pshift_dirty = false;
     return HOLO_OK;
   }
-  const size_t bytes = P->off_groups + align_up(P->groups.size() * sizeof(int2)) + 256;
+  const size_t bytes = P->table_bytes;
   void* d = nullptr;
   HOLO_HIP(hipMalloc(&d, bytes));
   char* b = (char*)d;
@@ -370,12 +381,14 @@ holo_status ensure_tables(holo_plan* P) {
   if (e == hipSuccess) e = put(P->off_ang, P->ang.data(), P->ang.size() * sizeof(double));
   if (e == hipSuccess) e = put(P->off_shift, P->shift.data(), P->shift.size() * sizeof(float));
   if (e == hipSuccess) e = put(P->off_groups, P->groups.data(), P->groups.size() * sizeof(int2));
+  if (e == hipSuccess) e = put(P->off_pshift, P->pshift.data(), P->pshift.size() * sizeof(float));
   if (e != hipSuccess) {
     (void)hipFree(d);
     return hip_fail(e, "uploading plan tables");
   }
   P->d_tables = d;
   P->device = dev;
+  P->pshift_dirty = false;
   return HOLO_OK;
 }
 
@@ -396,6 +409,7 @@ DevGeom make_geom(const holo_plan* P) {
   g.chirpH = (const float2*)(b + P->off_chH);
   g.shift = P->shift.empty() ? nullptr : (const float*)(b + P->off_shift);
   g.functional = P->functional;
+  g.pshift = P->pshift.empty() ? nullptr : (const float*)(b + P->off_pshift);
   return g;
 }
 
@@ -430,6 +444,7 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
   float2* X = (float2*)(wsb + P->off_X);
   float2* S = (float2*)(wsb + P->off_S);
   double* Fpart = (double*)(wsb + P->off_F);
+  float2* Pbuf = P->pshift.empty() ? nullptr : (float2*)(wsb + P->off_Pbuf);
   const double* d_ang = (const double*)((const char*)P->d_tables + P->off_ang);
   const int tiles = W / cols_per_wg(H);
 
@@ -514,8 +529,12 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
     }
     if ((mode == kGrad || mode == kAdj) && frames_back) {
       HOLO_HIP(timed(P, HOLO_K_PASS_C, st, [&] {
-        return launch_pass_c(g, X, psi, Q, Gacc, want_gq ? 1 : 0, c0, Kc, st);
+        return launch_pass_c(g, X, psi, Q, Gacc, Pbuf, want_gq ? 1 : 0, c0, Kc, st);
       }));
+      if (want_gq && Pbuf)
+        HOLO_HIP(timed(P, HOLO_K_PASS_C, st, [&] {
+          return launch_probe_shift_acc(g, Gacc, Pbuf, c0, Kc, st);
+        }));
       if (want_gu)
         HOLO_HIP(timed(P, HOLO_K_PASS_D, st, [&] {
           return launch_pass_d(g, X, psi, S + (size_t)(c0 - k0) * H * sino_row(W), c0, Kc, st);
@@ -783,6 +802,22 @@ extern "C" holo_status holo_cg(holo_plan* P, holo_c64* u_, holo_c64* q_, const f
   }
 #undef HOLO_TRY
   HOLO_HIP(hipStreamSynchronize(st));
+  return HOLO_OK;
+}
+
+extern "C" holo_status holo_plan_set_probe_shifts(holo_plan* P, const float* shifts) {
+  if (!P) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_set_probe_shifts: plan is NULL");
+  const size_t n = (size_t)P->n_angles * P->nd * 2;
+  if (shifts) {
+    for (size_t i = 0; i < n; ++i)
+      if (!std::isfinite(shifts[i]))
+        return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_set_probe_shifts: shifts must be finite");
+    P->pshift.assign(shifts, shifts + n);
+  } else {
+    P->pshift.clear();
+  }
+  P->pshift_dirty = true;
+  layout_workspace(P);
   return HOLO_OK;
 }
 

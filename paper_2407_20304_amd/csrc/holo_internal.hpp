@@ -34,6 +34,7 @@ struct DevGeom {
   const float2* chirpH;      // [3 nd + 1][H] transfer factors, times 1/H
   const float* shift;        // [n_angles][nd][2] (t_y, t_x) or nullptr
   int functional;            // 0: amplitude residual (F2), 1: intensity (F1)
+  const float* pshift;       // [n_angles][nd][2] (s_y, s_x) probe shifts or nullptr
 };
 
 // Transfer-function table rows: detector step of plane j, probe step of
@@ -94,7 +95,11 @@ hipError_t launch_pass_a(const DevGeom& g, const float2* psi, const float2* Q, f
 hipError_t launch_pass_b(const DevGeom& g, int mode, const float2* src, float2* X,
                          const float* amp, double* Fpart, int Kc, hipStream_t st);
 hipError_t launch_pass_c(const DevGeom& g, float2* X, const float2* psi, const float2* Q,
-                         float2* G, int accumulate, int k_first, int Kc, hipStream_t st);
+                         float2* G, float2* Pbuf, int accumulate, int k_first, int Kc,
+                         hipStream_t st);
+// G_j += sum_k S_{-s_kj}(Pbuf[k][j]) for the Kc angles of a chunk (probe shifts).
+hipError_t launch_probe_shift_acc(const DevGeom& g, float2* G, const float2* Pbuf, int k_first,
+                                  int Kc, hipStream_t st);
 hipError_t launch_pass_d(const DevGeom& g, const float2* X, const float2* psi, float2* S,
                          int k_first, int Kc, hipStream_t st);
 hipError_t launch_radon_fwd(const DevGeom& g, const float2* ub, const float2* uTb, float2* psi,

@@ -138,11 +138,34 @@ __device__ __forceinline__ void shift_of(const DevGeom& g, int kglob, int j, dou
   }
 }
 
+// Probe shifts (Eq. 9): S_s f is f sampled at (y - s_y, x - s_x) with linear
+// interpolation on the periodic grid.  Circular shifts commute with the
+// Fresnel propagator, so the shifted probe at plane j is S_s applied to
+// Q_j = D_{rho_probe_j} q, and S_s^T = S_{-s}.
+__device__ __forceinline__ float2 sample_circ(const float2* __restrict__ f, int H, int W,
+                                              double yy, double xx) {
+  // positions reduced onto [0, n] first, so any finite shift indexes in range
+  yy -= (double)H * floor(yy / (double)H);
+  xx -= (double)W * floor(xx / (double)W);
+  const double fy = floor(yy), fx = floor(xx);
+  const float wy = (float)(yy - fy), wx = (float)(xx - fx);
+  int y0 = (int)fy % H, x0 = (int)fx % W;
+  y0 += y0 < 0 ? H : 0;
+  x0 += x0 < 0 ? W : 0;
+  const int y1 = y0 + 1 == H ? 0 : y0 + 1, x1 = x0 + 1 == W ? 0 : x0 + 1;
+  const float2 a = f[(size_t)y0 * W + x0], b = f[(size_t)y0 * W + x1];
+  const float2 c = f[(size_t)y1 * W + x0], d = f[(size_t)y1 * W + x1];
+  const float w00 = (1.f - wy) * (1.f - wx), w01 = (1.f - wy) * wx, w10 = wy * (1.f - wx),
+              w11 = wy * wx;
+  return make_float2(w00 * a.x + w01 * b.x + w10 * c.x + w11 * d.x,
+                     w00 * a.y + w01 * b.y + w10 * c.y + w11 * d.y);
+}
+
 // ---------------------------------------------------------------------------
 // Row kernels (lines of length W along the detector columns)
 // ---------------------------------------------------------------------------
 
-template <int W>
+template <int W, bool PS>   // PS: probe shifts set
 __global__ __launch_bounds__(kThreads) void k_pass_a(const float2* __restrict__ psi,
                                                      const float2* __restrict__ Q,
                                                      float2* __restrict__ X, DevGeom g,
@@ -163,12 +186,18 @@ __global__ __launch_bounds__(kThreads) void k_pass_a(const float2* __restrict__ 
   const AxisTaps tyt = fwd_taps(g.cH, m, ty, z, g.H);
   const float2* psik = psi + (size_t)k * g.H * W;
   const float2* Qrow = Q + ((size_t)j * g.H + z) * W;
+  const float* ps = PS ? g.pshift + ((size_t)(k_first + k) * g.nd + j) * 2 : nullptr;
   float2* L = s_line[line];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int s = lt + e * TL;
     const AxisTaps txt = fwd_taps(g.cW, m, tx, s, W);
-    L[rowpos<TL>(lp, lt, e)] = cmul(Qrow[s], sample_phi(psik, W, tyt, txt));
+    float2 qv;
+    if constexpr (PS)
+      qv = sample_circ(Q + (size_t)j * g.H * W, g.H, W, (double)z - ps[0], (double)s - ps[1]);
+    else
+      qv = Qrow[s];
+    L[rowpos<TL>(lp, lt, e)] = cmul(qv, sample_phi(psik, W, tyt, txt));
   }
   fft<W, TL, false, true>(L, s_tw, lt);
   const float2* ch = g.chirpW + (size_t)chirp_det(j) * W;
@@ -186,11 +215,12 @@ __global__ __launch_bounds__(kThreads) void k_pass_a(const float2* __restrict__ 
   }
 }
 
-template <int W>
+template <int W, bool PS>   // PS: probe shifts set
 __global__ __launch_bounds__(kThreads) void k_pass_c(float2* __restrict__ X,
                                                      const float2* __restrict__ psi,
                                                      const float2* __restrict__ Q,
-                                                     float2* __restrict__ G, DevGeom g,
+                                                     float2* __restrict__ G,
+                                                     float2* __restrict__ Pbuf, DevGeom g,
                                                      int accumulate, int k_first, int Kc) {
   constexpr int TL = rows_tl(W), LPW = rows_lpw(W), E = W / TL;
   __shared__ float2 s_tw[W];
@@ -223,6 +253,7 @@ __global__ __launch_bounds__(kThreads) void k_pass_c(float2* __restrict__ X,
     shift_of(g, k_first + k, j, ty, tx);
     const AxisTaps tyt = fwd_taps(g.cH, m, ty, z, g.H);
     const float2* psik = psi + (size_t)k * g.H * W;
+    const float* ps = PS ? g.pshift + ((size_t)(k_first + k) * g.nd + j) * 2 : nullptr;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int s = lt + e * TL;
@@ -231,13 +262,22 @@ __global__ __launch_bounds__(kThreads) void k_pass_c(float2* __restrict__ X,
         const AxisTaps txt = fwd_taps(g.cW, m, tx, s, W);
         const float2 phi = sample_phi(psik, W, tyt, txt);
         const float2 t = cmulc(w, phi);  // conj(phi) w
-        gacc[e].x += t.x;
-        gacc[e].y += t.y;
+        if constexpr (PS) {              // shifted probes: summed after the chunk
+          Pbuf[(((size_t)k * g.nd + j) * g.H + z) * W + s] = t;
+        } else {
+          gacc[e].x += t.x;
+          gacc[e].y += t.y;
+        }
       }
-      row[s] = cmulc(w, Qrow[s]);        // conj(Q_j) w
+      float2 qv;
+      if constexpr (PS)
+        qv = sample_circ(Q + (size_t)j * g.H * W, g.H, W, (double)z - ps[0], (double)s - ps[1]);
+      else
+        qv = Qrow[s];
+      row[s] = cmulc(w, qv);             // conj(Q_kj) w
     }
   }
-  if (accumulate) {
+  if (accumulate && !PS) {
     float2* grow = G + ((size_t)j * g.H + z) * W;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -1071,7 +1111,13 @@ hipError_t launch_pass_a(const DevGeom& g, const float2* psi, const float2* Q, f
                          int k_first, int Kc, hipStream_t st) {
   const dim3 grid(g.H / rows_per_wg(g.W), Kc * g.nd);
   switch (g.W) {
-#define CASE(N) case N: k_pass_a<N><<<grid, kThreads, 0, st>>>(psi, Q, X, g, k_first); break;
+#define CASE(N)                                                                 \
+  case N:                                                                       \
+    if (g.pshift)                                                               \
+      k_pass_a<N, true><<<grid, kThreads, 0, st>>>(psi, Q, X, g, k_first);      \
+    else                                                                        \
+      k_pass_a<N, false><<<grid, kThreads, 0, st>>>(psi, Q, X, g, k_first);     \
+    break;
     HOLO_FOR_SIZES(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -1110,11 +1156,19 @@ hipError_t launch_pass_b(const DevGeom& g, int mode, const float2* src, float2* 
 }
 
 hipError_t launch_pass_c(const DevGeom& g, float2* X, const float2* psi, const float2* Q,
-                         float2* G, int accumulate, int k_first, int Kc, hipStream_t st) {
+                         float2* G, float2* Pbuf, int accumulate, int k_first, int Kc,
+                         hipStream_t st) {
   const dim3 grid(g.H / rows_per_wg(g.W), g.nd);
   switch (g.W) {
-#define CASE(N) \
-  case N: k_pass_c<N><<<grid, kThreads, 0, st>>>(X, psi, Q, G, g, accumulate, k_first, Kc); break;
+#define CASE(N)                                                                            \
+  case N:                                                                                  \
+    if (g.pshift)                                                                          \
+      k_pass_c<N, true><<<grid, kThreads, 0, st>>>(X, psi, Q, G, Pbuf, g, accumulate,       \
+                                                   k_first, Kc);                            \
+    else                                                                                   \
+      k_pass_c<N, false><<<grid, kThreads, 0, st>>>(X, psi, Q, G, nullptr, g, accumulate,   \
+                                                    k_first, Kc);                           \
+    break;
     HOLO_FOR_SIZES(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -1126,6 +1180,36 @@ hipError_t launch_pass_d(const DevGeom& g, const float2* X, const float2* psi, f
                          int k_first, int Kc, hipStream_t st) {
   const dim3 grid((g.H / 16) * (sino_row(g.W) / 16), Kc);
   k_pass_d<<<grid, kThreads, 0, st>>>(X, psi, S, g, k_first);
+  return hipGetLastError();
+}
+
+// G_j[y][x] += sum over the chunk's angles k of Pbuf[k][j] sampled at
+// (y + s_y, x + s_x): the transposed probe shift S_{-s_kj}.
+__global__ __launch_bounds__(kThreads) void k_probe_shift_acc(float2* __restrict__ G,
+                                                              const float2* __restrict__ Pbuf,
+                                                              DevGeom g, int k_first, int Kc) {
+  const size_t HW = (size_t)g.H * g.W;
+  const int j = blockIdx.y;
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < HW;
+       i += (size_t)gridDim.x * kThreads) {
+    const int y = (int)(i / g.W), x = (int)(i % g.W);
+    float2 acc = G[(size_t)j * HW + i];
+    for (int k = 0; k < Kc; ++k) {
+      const float* ps = g.pshift + ((size_t)(k_first + k) * g.nd + j) * 2;
+      const float2 v = sample_circ(Pbuf + ((size_t)k * g.nd + j) * HW, g.H, g.W,
+                                   (double)y + ps[0], (double)x + ps[1]);
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    G[(size_t)j * HW + i] = acc;
+  }
+}
+
+hipError_t launch_probe_shift_acc(const DevGeom& g, float2* G, const float2* Pbuf, int k_first,
+                                  int Kc, hipStream_t st) {
+  const size_t HW = (size_t)g.H * g.W;
+  const unsigned gx = (unsigned)std::min<size_t>((HW + kThreads - 1) / kThreads, 4096);
+  k_probe_shift_acc<<<dim3(gx, g.nd), kThreads, 0, st>>>(G, Pbuf, g, k_first, Kc);
   return hipGetLastError();
 }
 

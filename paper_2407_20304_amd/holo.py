@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libholo.so")
 EXPORTS = (
     "holo_plan_create", "holo_plan_destroy", "holo_workspace_bytes", "holo_plan_set_functional",
     "holo_plan_set_chunk", "holo_plan_get_chunk", "holo_plan_autotune",
+    "holo_plan_set_probe_shifts",
     "holo_fwd", "holo_adj", "holo_objective", "holo_grad",
     "holo_grad_object", "holo_grad_probe",
     "holo_probe_init", "holo_cg_workspace_bytes", "holo_cg",
@@ -71,6 +72,7 @@ def lib():
     L.holo_workspace_bytes.argtypes = [P, POINTER(c_size_t)]
     L.holo_plan_set_functional.argtypes = [P, c_int32]
     L.holo_plan_set_chunk.argtypes = [P, c_int32]
+    L.holo_plan_set_probe_shifts.argtypes = [P, P]
     L.holo_plan_get_chunk.argtypes = [P, POINTER(c_int32)]
     L.holo_plan_autotune.argtypes = [P, P, P, P, P, P, P, P, P, c_int32, P, c_size_t, P, P, P]
     L.holo_fwd.argtypes = [P, P, P, c_int32, c_int32, P, P, c_size_t, P]
@@ -218,6 +220,20 @@ class Plan:
         """Angles per chunk; updates workspace_bytes (the workspace is
         reallocated on the next call if it grew)."""
         _check(lib().holo_plan_set_chunk(self._h, c_int32(int(chunk))))
+        self._refresh_workspace_size()
+
+    def set_probe_shifts(self, shifts):
+        """Probe shifts s_kj, an (n_angles, n_dist, 2) array of (s_y, s_x)
+        pixels, or None to remove them; updates workspace_bytes."""
+        if shifts is None:
+            _check(lib().holo_plan_set_probe_shifts(self._h, None))
+            self._pshift = None
+        else:
+            a = np.ascontiguousarray(shifts, dtype=np.float32)
+            if a.shape != (self.n_angles, self.n_dist, 2):
+                raise ValueError("probe shifts must have shape (n_angles, n_dist, 2)")
+            _check(lib().holo_plan_set_probe_shifts(self._h, a.ctypes.data_as(c_void_p)))
+            self._pshift = a
         self._refresh_workspace_size()
 
     def _refresh_workspace_size(self):

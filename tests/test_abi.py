@@ -137,6 +137,23 @@ def test_binning_entry_points_validate_on_the_host():
     assert L.holo_upsample_volume(buf, 8, 0, 2, buf2, None) == 1
 
 
+def test_probe_shifts_validate_and_grow_the_workspace():
+    L = holo.lib()
+    p = make_plan(chunk=4)
+    ws0 = p.workspace_bytes
+    assert L.holo_plan_set_probe_shifts(None, None) == 1
+    bad = np.zeros((10, 4, 2), np.float32)
+    bad[3, 1, 0] = np.nan
+    assert L.holo_plan_set_probe_shifts(p._h, bad.ctypes.data_as(ctypes.c_void_p)) == 1
+    p.set_probe_shifts(np.ones((10, 4, 2), np.float32))
+    assert p.workspace_bytes == ws0 + 4 * 4 * 64 * 64 * 8   # chunk x n_dist frames
+    with pytest.raises(ValueError):
+        p.set_probe_shifts(np.ones((10, 3, 2)))
+    p.set_probe_shifts(None)
+    assert p.workspace_bytes == ws0
+    p.close()
+
+
 def test_functional_switch_validates_on_the_host():
     L = holo.lib()
     p = make_plan()
