@@ -582,7 +582,9 @@ def test_coarse_propagation_samples_the_same_physical_wave(b):
     fc = np.exp(-(x ** 2 + y ** 2) / (2 * s0 ** 2))
     s2 = s0 ** 2 + 1j * alpha / (2 * np.pi)
     exact = (s0 ** 2 / s2) * np.exp(-(x ** 2 + y ** 2) / (2 * s2))
-    np.testing.assert_allclose(O.propagate(fc, rho, nf * b * b), exact, atol=1e-10)
+    gc = O.level_geometry(O.Geometry(H=n, W=n, theta=[0.0], mag_rel=[1.0], fresnel0=nf), b)
+    assert (gc.H, gc.W) == (nc, nc)
+    np.testing.assert_allclose(O.propagate(fc, rho, gc.fresnel0), exact, atol=1e-10)
 
 
 def test_level_geometry_identity_and_schedule_runs():
