@@ -138,8 +138,25 @@ template <bool INV> struct Dft<8, INV> {
   }
 };
 
+// Ordering between the phases of a transform.  WAVE: each line is owned by
+// threads of a single wavefront.  A wavefront's LDS accesses are performed
+// in issue order, so a wavefront-scope fence (which only stops the compiler
+// from moving accesses across it) orders them for every lane of the line;
+// the other wavefronts of the workgroup go on without waiting.  Otherwise a
+// workgroup barrier.
+template <bool WAVE>
+__device__ __forceinline__ void fft_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // One Stockham stage on `line` (LDS), executed by TL threads (thread lt).
-template <int N, int TL, int R, int P, bool INV, bool PADDED>
+template <int N, int TL, int R, int P, bool INV, bool PADDED, bool WAVE>
 __device__ __forceinline__ void fft_stage(float2* line, const float2* tw, int lt) {
   constexpr int NB = N / R;
   constexpr int IT = (NB + TL - 1) / TL;
@@ -168,7 +185,7 @@ __device__ __forceinline__ void fft_stage(float2* line, const float2* tw, int lt
       }
     }
   }
-  __syncthreads();
+  fft_sync<WAVE>();
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int i = lt + it * TL;
@@ -194,14 +211,14 @@ __device__ __forceinline__ void fft_stage(float2* line, const float2* tw, int lt
       }
     }
   }
-  __syncthreads();
+  fft_sync<WAVE>();
 }
 
-template <int N, int TL, bool INV, bool PADDED, int S>
+template <int N, int TL, bool INV, bool PADDED, bool WAVE, int S>
 __device__ __forceinline__ void fft_stages(float2* line, const float2* tw, int lt) {
   if constexpr (S < fft_nstages(N)) {
-    fft_stage<N, TL, fft_radix(N, S), fft_pstride(N, S), INV, PADDED>(line, tw, lt);
-    fft_stages<N, TL, INV, PADDED, S + 1>(line, tw, lt);
+    fft_stage<N, TL, fft_radix(N, S), fft_pstride(N, S), INV, PADDED, WAVE>(line, tw, lt);
+    fft_stages<N, TL, INV, PADDED, WAVE, S + 1>(line, tw, lt);
   }
 }
 
@@ -209,11 +226,15 @@ __device__ __forceinline__ void fft_stages(float2* line, const float2* tw, int l
 // All threads of the workgroup must call it (it synchronises); the line must
 // be fully written before the call.  PADDED: the line is stored padded
 // (element n at fpi(n), fft_line_len(N) elements), otherwise plain.  `tw`
-// holds the N twiddles.
-template <int N, int TL, bool INV, bool PADDED = false>
+// holds the N twiddles.  WAVE (each line owned by one wavefront, TL <= 64):
+// the transform synchronises only within the wavefront, so LDS data written
+// by other wavefronts (the twiddles, a tile loaded across lines) must be
+// behind a workgroup barrier before the call.
+template <int N, int TL, bool INV, bool PADDED = false, bool WAVE = false>
 __device__ __forceinline__ void fft(float2* line, const float2* tw, int lt) {
-  __syncthreads();
-  fft_stages<N, TL, INV, PADDED, 0>(line, tw, lt);
+  static_assert(!WAVE || (TL <= 64 && 64 % TL == 0), "wavefront-owned lines");
+  fft_sync<WAVE>();
+  fft_stages<N, TL, INV, PADDED, WAVE, 0>(line, tw, lt);
 }
 
 }  // namespace holo

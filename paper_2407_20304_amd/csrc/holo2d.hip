@@ -161,14 +161,18 @@ __device__ __forceinline__ void b_rows_body(const B2Args& A, const B2Item& it, f
 #pragma unroll
     for (int e = 0; e < E; ++e) L[lt + e * TL] = r[lt + e * TL];
   }
-  fft<N, TL, false>(L, s_tw, lt);
+  // A line within one wavefront synchronises only there (s_tw is behind
+  // the barrier).
+  constexpr bool WL = TL <= 64;
+  if constexpr (WL) __syncthreads();
+  fft<N, TL, false, false, WL>(L, s_tw, lt);
   const float2* ch = in.chirp + (size_t)chirp * N;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int s = lt + e * TL;
     L[s] = conj ? cmulc(L[s], ch[s]) : cmul(L[s], ch[s]);
   }
-  fft<N, TL, true>(L, s_tw, lt);
+  fft<N, TL, true, false, WL>(L, s_tw, lt);
   float2* o = dst + (size_t)z * N;
   if (A.mode == kB2RowsC) {
     const double m = A.mag[j];
@@ -269,9 +273,13 @@ __device__ __forceinline__ void b_cols_body(const B2Args& A, const B2Item& it, f
     col0[cc * (N + 1) + zz] = frame[(size_t)zz * N + s0 + cc];
   }
   const float2* ch = in.chirp + (size_t)chirp * N;
-  fft<N, TLc, false>(Lc, s_tw, lt);
+  // Each column lies within one wavefront: the transforms synchronise only
+  // there, behind one barrier for the tile and s_tw.
+  constexpr bool WL = TLc <= 64;
+  if constexpr (WL) __syncthreads();
+  fft<N, TLc, false, false, WL>(Lc, s_tw, lt);
   for (int zz = lt; zz < N; zz += TLc) Lc[zz] = conj ? cmulc(Lc[zz], ch[zz]) : cmul(Lc[zz], ch[zz]);
-  fft<N, TLc, true>(Lc, s_tw, lt);
+  fft<N, TLc, true, false, WL>(Lc, s_tw, lt);
   __syncthreads();
   if (amp) {
     double acc = 0.0;
@@ -285,9 +293,9 @@ __device__ __forceinline__ void b_cols_body(const B2Args& A, const B2Item& it, f
     __syncthreads();
   }
   if (adj_after) {
-    fft<N, TLc, false>(Lc, s_tw, lt);
+    fft<N, TLc, false, false, WL>(Lc, s_tw, lt);
     for (int zz = lt; zz < N; zz += TLc) Lc[zz] = cmulc(Lc[zz], ch[zz]);
-    fft<N, TLc, true>(Lc, s_tw, lt);
+    fft<N, TLc, true, false, WL>(Lc, s_tw, lt);
     __syncthreads();
   }
   if (A.mode == kB2ColsB && A.amp && !A.want_grad) return;  // objective only

@@ -31,8 +31,15 @@ typedef float f4a8 __attribute__((ext_vector_type(4), aligned(8)));
 
 constexpr int kThreads = 256;
 
+// Threads per row line.  From W = 1024 on a line spans two or more
+// wavefronts: one wavefront per 1024-point line would need a private LDS
+// line per wavefront, which halves the waves per CU, and that costs more in
+// the row passes than their workgroup barriers.
 __host__ __device__ constexpr int rows_tl(int W) { return fft_row_threads(W); }
-__host__ __device__ constexpr int rows_lpw(int W) { return kThreads / fft_row_threads(W); }
+__host__ __device__ constexpr int rows_lpw(int W) { return kThreads / rows_tl(W); }
+// Lines (rows, or columns of a column tile) whose TL threads lie in one
+// wavefront: their transforms need no workgroup barrier.
+__host__ __device__ constexpr bool wave_lines(int TL) { return TL <= 64; }
 __host__ __device__ constexpr int cols_tc(int H) { return H >= 2048 ? 4 : (H >= 1024 ? 8 : 16); }
 // Pitch of one column line in the column kernels' LDS tile: the padded line
 // plus 4, so that the tile loads (8 columns x 4 rows per LDS pass) hit
@@ -199,14 +206,15 @@ __global__ __launch_bounds__(kThreads) void k_pass_a(const float2* __restrict__ 
       qv = Qrow[s];
     L[rowpos<TL>(lp, lt, e)] = cmul(qv, sample_phi(psik, W, tyt, txt));
   }
-  fft<W, TL, false, true>(L, s_tw, lt);
+  if constexpr (wave_lines(TL)) __syncthreads();   // s_tw
+  fft<W, TL, false, true, wave_lines(TL)>(L, s_tw, lt);
   const float2* ch = g.chirpW + (size_t)chirp_det(j) * W;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int s = lt + e * TL;
     L[rowpos<TL>(lp, lt, e)] = cmul(L[rowpos<TL>(lp, lt, e)], ch[s]);
   }
-  fft<W, TL, true, true>(L, s_tw, lt);
+  fft<W, TL, true, true, wave_lines(TL)>(L, s_tw, lt);
   float2* out = X + ((size_t)f * g.H + z) * W;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -237,18 +245,19 @@ __global__ __launch_bounds__(kThreads) void k_pass_c(float2* __restrict__ X,
   float2 gacc[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) gacc[e] = make_float2(0.f, 0.f);
+  if constexpr (wave_lines(TL)) __syncthreads();   // s_tw
 
   for (int k = 0; k < Kc; ++k) {
     float2* row = X + (((size_t)k * g.nd + j) * g.H + z) * W;
 #pragma unroll
     for (int e = 0; e < E; ++e) L[rowpos<TL>(lp, lt, e)] = row[lt + e * TL];
-    fft<W, TL, false, true>(L, s_tw, lt);
+    fft<W, TL, false, true, wave_lines(TL)>(L, s_tw, lt);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int s = lt + e * TL;
       L[rowpos<TL>(lp, lt, e)] = cmulc(L[rowpos<TL>(lp, lt, e)], ch[s]);
     }
-    fft<W, TL, true, true>(L, s_tw, lt);
+    fft<W, TL, true, true, wave_lines(TL)>(L, s_tw, lt);
     double ty, tx;
     shift_of(g, k_first + k, j, ty, tx);
     const AxisTaps tyt = fwd_taps(g.cH, m, ty, z, g.H);
@@ -302,14 +311,15 @@ __global__ __launch_bounds__(kThreads) void k_rows_prop(PropJobs jobs, DevGeom g
   float2* L = s_line[line];
 #pragma unroll
   for (int e = 0; e < E; ++e) L[rowpos<TL>(lp, lt, e)] = in[lt + e * TL];
-  fft<W, TL, false, true>(L, s_tw, lt);
+  if constexpr (wave_lines(TL)) __syncthreads();   // s_tw
+  fft<W, TL, false, true, wave_lines(TL)>(L, s_tw, lt);
   const float2* ch = g.chirpW + (size_t)jb.chirp * W;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int s = lt + e * TL;
     L[rowpos<TL>(lp, lt, e)] = jb.conj ? cmulc(L[rowpos<TL>(lp, lt, e)], ch[s]) : cmul(L[rowpos<TL>(lp, lt, e)], ch[s]);
   }
-  fft<W, TL, true, true>(L, s_tw, lt);
+  fft<W, TL, true, true, wave_lines(TL)>(L, s_tw, lt);
   float2* out = jb.dst + (size_t)z * W;
 #pragma unroll
   for (int e = 0; e < E; ++e) out[lt + e * TL] = L[rowpos<TL>(lp, lt, e)];
@@ -413,10 +423,12 @@ __global__ __launch_bounds__(kColThreads) void k_pass_b(const float2* __restrict
   for (int r = 0; r < NPT; ++r) l0[r * LSTEP] = t[r];
   float2* Lc = s_col[c];
   const float2* ch = g.chirpH + (size_t)chirp_det(j) * H;
+  constexpr bool WL = wave_lines(TLc);
   if (MODE != kColAdj) {
-    fft<H, TLc, false, true>(Lc, s_tw, lt);
+    if constexpr (WL) __syncthreads();   // tile and s_tw
+    fft<H, TLc, false, true, WL>(Lc, s_tw, lt);
     for (int zz = lt; zz < H; zz += TLc) Lc[fpi(zz)] = cmul(Lc[fpi(zz)], ch[zz]);
-    fft<H, TLc, true, true>(Lc, s_tw, lt);
+    fft<H, TLc, true, true, WL>(Lc, s_tw, lt);
     __syncthreads();
   }
   if (kResidual) {
@@ -435,9 +447,10 @@ __global__ __launch_bounds__(kColThreads) void k_pass_b(const float2* __restrict
     block_sum_store<kColThreads>(acc, Fpart + (size_t)f * ntiles + tile);
   }
   if (MODE == kColGrad || MODE == kColAdj) {
-    fft<H, TLc, false, true>(Lc, s_tw, lt);
+    if constexpr (WL) __syncthreads();   // tile (residual or load) and s_tw
+    fft<H, TLc, false, true, WL>(Lc, s_tw, lt);
     for (int zz = lt; zz < H; zz += TLc) Lc[fpi(zz)] = cmulc(Lc[fpi(zz)], ch[zz]);
-    fft<H, TLc, true, true>(Lc, s_tw, lt);
+    fft<H, TLc, true, true, WL>(Lc, s_tw, lt);
     __syncthreads();
   }
   if (MODE != kColObj) {
@@ -466,9 +479,11 @@ __global__ __launch_bounds__(kColThreads) void k_cols_prop(PropJobs jobs, double
   }
   float2* L = s_col[c];
   const float2* ch = g.chirpH + (size_t)jb.chirp * H;
-  fft<H, TLc, false, true>(L, s_tw, lt);
+  constexpr bool WL = wave_lines(TLc);
+  if constexpr (WL) __syncthreads();   // tile and s_tw
+  fft<H, TLc, false, true, WL>(L, s_tw, lt);
   for (int zz = lt; zz < H; zz += TLc) L[fpi(zz)] = jb.conj ? cmulc(L[fpi(zz)], ch[zz]) : cmul(L[fpi(zz)], ch[zz]);
-  fft<H, TLc, true, true>(L, s_tw, lt);
+  fft<H, TLc, true, true, WL>(L, s_tw, lt);
   __syncthreads();
   if (jb.amp) {
     double acc = 0.0;
@@ -494,16 +509,21 @@ __global__ __launch_bounds__(kColThreads) void k_cols_prop(PropJobs jobs, double
 // chain rule through psi = exp(i kappa p).
 // ---------------------------------------------------------------------------
 
+// Angles per pass-D workgroup: without object shifts the taps do not depend
+// on the angle, so they are formed once for all of them.
+constexpr int kPassDAngles = 4;
+
 __global__ __launch_bounds__(kThreads) void k_pass_d(const float2* __restrict__ X,
                                                      const float2* __restrict__ psi,
                                                      float2* __restrict__ S, DevGeom g,
-                                                     int k_first) {
+                                                     int k_first, int Kc) {
   // A workgroup covers 16 rows x 16 padded bins, bins fastest, of the
   // sinogram S[k][z][kAdjPad + s] (rows padded by kAdjPad zero bins on each
-  // side).  Workgroups over the padding write its zeros.  The transposed
-  // resampling is separable, so its taps are formed once per workgroup: per
-  // plane, the three row taps of each of the 16 rows and the three column
-  // taps of each of the 16 bins.
+  // side) for kPassDAngles consecutive angles.  Workgroups over the padding
+  // write its zeros.  The transposed resampling is separable, so its taps
+  // are formed once per workgroup (once per angle with shifts): per plane,
+  // the three row taps of each of the 16 rows and the three column taps of
+  // each of the 16 bins.
   constexpr int SC = 16, ZR = kThreads / SC;
   static_assert(kMaxDist * 2 * SC <= kThreads, "one tap set per thread");
   __shared__ int s_d[kMaxDist][2 * SC][3];
@@ -514,59 +534,65 @@ __global__ __launch_bounds__(kThreads) void k_pass_d(const float2* __restrict__ 
   const int r = threadIdx.x / SC, c = threadIdx.x % SC;
   const int z = z0 + r, sp = sp0 + c;
   const int s = sp - kAdjPad;
-  const int k = blockIdx.y;
-  if ((int)threadIdx.x < g.nd * 2 * SC) {
-    // thread (j, e): plane j; e < 16 the taps of row z0 + e, else those of
-    // bin sp0 + e - 16 (none for bins in the padding)
-    const int j = threadIdx.x / (2 * SC), e = threadIdx.x % (2 * SC);
-    double ty, tx;
-    shift_of(g, k_first + k, j, ty, tx);
-    const double m = g.mag[j];
-    AdjTaps t;
-    if (e < SC) {
-      t = adj_taps(g.cH, m, ty, z0 + e, H);
-    } else {
-      const int sb = sp0 + e - SC - kAdjPad;
-      if (sb >= 0 && sb < W) {
-        t = adj_taps(g.cW, m, tx, sb, W);
-      } else {
+  const bool inside = s >= 0 && s < W;
+  const int kb = blockIdx.y * kPassDAngles, ke = min(kb + kPassDAngles, Kc);
+  for (int k = kb; k < ke; ++k) {
+    if (k == kb || g.shift) {   // uniform over the workgroup
+      if (k != kb) __syncthreads();   // the previous angle's taps are read
+      if ((int)threadIdx.x < g.nd * 2 * SC) {
+        // thread (j, e): plane j; e < 16 the taps of row z0 + e, else those
+        // of bin sp0 + e - 16 (none for bins in the padding)
+        const int j = threadIdx.x / (2 * SC), e = threadIdx.x % (2 * SC);
+        double ty, tx;
+        shift_of(g, k_first + k, j, ty, tx);
+        const double m = g.mag[j];
+        AdjTaps t;
+        if (e < SC) {
+          t = adj_taps(g.cH, m, ty, z0 + e, H);
+        } else {
+          const int sb = sp0 + e - SC - kAdjPad;
+          if (sb >= 0 && sb < W) {
+            t = adj_taps(g.cW, m, tx, sb, W);
+          } else {
 #pragma unroll
-        for (int q = 0; q < 3; ++q) { t.d[q] = 0; t.w[q] = 0.f; }
+            for (int q = 0; q < 3; ++q) { t.d[q] = 0; t.w[q] = 0.f; }
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) { s_d[j][e][q] = t.d[q]; s_w[j][e][q] = t.w[q]; }
       }
+      __syncthreads();
     }
+    float2* out = S + ((size_t)k * H + z) * Wp + sp;
+    if (!inside) {
+      *out = make_float2(0.f, 0.f);
+      continue;
+    }
+    float ax = 0.f, ay = 0.f;
+    for (int j = 0; j < g.nd; ++j) {
+      const float2* Xj = X + ((size_t)k * g.nd + j) * H * W;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) { s_d[j][e][q] = t.d[q]; s_w[j][e][q] = t.w[q]; }
-  }
-  __syncthreads();
-  float2* out = S + ((size_t)k * H + z) * Wp + sp;
-  if (s < 0 || s >= W) {
-    *out = make_float2(0.f, 0.f);
-    return;
-  }
-  float ax = 0.f, ay = 0.f;
-  for (int j = 0; j < g.nd; ++j) {
-    const float2* Xj = X + ((size_t)k * g.nd + j) * H * W;
+      for (int a = 0; a < 3; ++a) {
+        const float wz = s_w[j][r][a];
+        const float2* Xr = Xj + (size_t)s_d[j][r][a] * W;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const float wz = s_w[j][r][a];
-      const float2* Xr = Xj + (size_t)s_d[j][r][a] * W;
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        const float wt = wz * s_w[j][SC + c][b];
-        if (wt != 0.0f) {
-          const float2 v = Xr[s_d[j][SC + c][b]];
-          ax += wt * v.x;
-          ay += wt * v.y;
+        for (int b = 0; b < 3; ++b) {
+          const float wt = wz * s_w[j][SC + c][b];
+          if (wt != 0.0f) {
+            const float2 v = Xr[s_d[j][SC + c][b]];
+            ax += wt * v.x;
+            ay += wt * v.y;
+          }
         }
       }
     }
+    const float2 ps = psi[((size_t)k * H + z) * W + s];
+    // conj(psi) g
+    const float cx = ps.x * ax + ps.y * ay;
+    const float cy = ps.x * ay - ps.y * ax;
+    // -i kappa (cx + i cy) = kappa cy - i kappa cx
+    *out = make_float2(g.kappa * cy, -g.kappa * cx);
   }
-  const float2 ps = psi[((size_t)k * H + z) * W + s];
-  // conj(psi) g
-  const float cx = ps.x * ax + ps.y * ay;
-  const float cy = ps.x * ay - ps.y * ax;
-  // -i kappa (cx + i cy) = kappa cy - i kappa cx
-  *out = make_float2(g.kappa * cy, -g.kappa * cx);
 }
 
 // Z-blocked copies of the volume for the ray sums: ub[z / ZT][y][P + x][z % ZT]
@@ -1178,8 +1204,8 @@ hipError_t launch_pass_c(const DevGeom& g, float2* X, const float2* psi, const f
 
 hipError_t launch_pass_d(const DevGeom& g, const float2* X, const float2* psi, float2* S,
                          int k_first, int Kc, hipStream_t st) {
-  const dim3 grid((g.H / 16) * (sino_row(g.W) / 16), Kc);
-  k_pass_d<<<grid, kThreads, 0, st>>>(X, psi, S, g, k_first);
+  const dim3 grid((g.H / 16) * (sino_row(g.W) / 16), (Kc + kPassDAngles - 1) / kPassDAngles);
+  k_pass_d<<<grid, kThreads, 0, st>>>(X, psi, S, g, k_first, Kc);
   return hipGetLastError();
 }
 
