@@ -334,17 +334,18 @@ __global__ __launch_bounds__(kT2) void k2_gather(B2Args A, const B2Item* __restr
   for (int j = 0; j < A.nd; ++j) {
     const double m = A.mag[j];
     const BAdj rz = b_adj_taps(c, m, z, n), rs = b_adj_taps(c, m, s, n);
+    // With m >= 1 at most two adjacent candidates of an axis carry weight:
+    // (0, 1) if candidate 0 does, else (1, 2).  Four unconditional loads.
+    const int az = rz.w[0] != 0.0f ? 0 : 1, as = rs.w[0] != 0.0f ? 0 : 1;
     const float2* Xj = A.X + in.off * A.nd + j * fr;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < 2; ++a) {
 #pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        const float wt = rz.w[a] * rs.w[b];
-        if (wt != 0.0f) {
-          const float2 v = Xj[(size_t)rz.d[a] * n + rs.d[b]];
-          ax += wt * v.x;
-          ay += wt * v.y;
-        }
+      for (int b = 0; b < 2; ++b) {
+        const float wt = rz.w[az + a] * rs.w[as + b];
+        const float2 v = Xj[(size_t)rz.d[az + a] * n + rs.d[as + b]];   // in range
+        ax += wt * v.x;
+        ay += wt * v.y;
       }
     }
     const float2 gj = A.G[in.off * A.nd + j * fr + p];

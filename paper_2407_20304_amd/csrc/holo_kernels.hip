@@ -522,12 +522,15 @@ __global__ __launch_bounds__(kThreads) void k_pass_d(const float2* __restrict__ 
   // side) for kPassDAngles consecutive angles.  Workgroups over the padding
   // write its zeros.  The transposed resampling is separable, so its taps
   // are formed once per workgroup (once per angle with shifts): per plane,
-  // the three row taps of each of the 16 rows and the three column taps of
-  // each of the 16 bins.
+  // the row taps of each of the 16 rows and the column taps of each of the
+  // 16 bins.  Of the three candidates of an axis at most two adjacent ones
+  // carry weight (the magnifications are >= 1, so the forward samples of
+  // neighbouring destinations are at least one pixel apart), and only those
+  // two are kept: four unconditional loads per plane and pixel.
   constexpr int SC = 16, ZR = kThreads / SC;
   static_assert(kMaxDist * 2 * SC <= kThreads, "one tap set per thread");
-  __shared__ int s_d[kMaxDist][2 * SC][3];
-  __shared__ float s_w[kMaxDist][2 * SC][3];
+  __shared__ int s_d[kMaxDist][2 * SC][2];
+  __shared__ float s_w[kMaxDist][2 * SC][2];
   const int H = g.H, W = g.W, Wp = sino_row(W);
   const int nsb = Wp / SC;
   const int z0 = (blockIdx.x / nsb) * ZR, sp0 = (blockIdx.x % nsb) * SC;
@@ -558,8 +561,11 @@ __global__ __launch_bounds__(kThreads) void k_pass_d(const float2* __restrict__ 
             for (int q = 0; q < 3; ++q) { t.d[q] = 0; t.w[q] = 0.f; }
           }
         }
+        // the weighted pair: (0, 1) if candidate 0 has weight (candidate 2,
+        // two destinations further on, then has none), else (1, 2)
+        const int e0 = t.w[0] != 0.0f ? 0 : 1;
 #pragma unroll
-        for (int q = 0; q < 3; ++q) { s_d[j][e][q] = t.d[q]; s_w[j][e][q] = t.w[q]; }
+        for (int q = 0; q < 2; ++q) { s_d[j][e][q] = t.d[e0 + q]; s_w[j][e][q] = t.w[e0 + q]; }
       }
       __syncthreads();
     }
@@ -572,17 +578,15 @@ __global__ __launch_bounds__(kThreads) void k_pass_d(const float2* __restrict__ 
     for (int j = 0; j < g.nd; ++j) {
       const float2* Xj = X + ((size_t)k * g.nd + j) * H * W;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
+      for (int a = 0; a < 2; ++a) {
         const float wz = s_w[j][r][a];
         const float2* Xr = Xj + (size_t)s_d[j][r][a] * W;
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
+        for (int b = 0; b < 2; ++b) {
           const float wt = wz * s_w[j][SC + c][b];
-          if (wt != 0.0f) {
-            const float2 v = Xr[s_d[j][SC + c][b]];
-            ax += wt * v.x;
-            ay += wt * v.y;
-          }
+          const float2 v = Xr[s_d[j][SC + c][b]];   // in range; weight 0 if unused
+          ax += wt * v.x;
+          ay += wt * v.y;
         }
       }
     }
