@@ -9,8 +9,9 @@
 // registers, synchronises, and writes in place, so one LDS line per transform
 // suffices.
 //
-// Lengths are 2^a (radices 8, then 4 or 2) and 3 * 2^a (one radix-3 stage
-// first).  Twiddles come from a table tw[m] = exp(-2 pi i m / N) built in
+// Lengths are 2^a (radices 8, then 4 or 2; a plan ending in 4, 4 ends in
+// one radix-16 stage instead when the line has N / 16 threads) and 3 * 2^a
+// (one radix-3 stage first).  Twiddles come from a table tw[m] = exp(-2 pi i m / N) built in
 // double precision on the host and staged in LDS by the caller.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -45,6 +46,23 @@ __host__ __device__ constexpr int fft_radix(int N, int s) {
 
 __host__ __device__ constexpr int fft_pstride(int N, int s) {
   return s == 0 ? 1 : fft_pstride(N, s - 1) * fft_radix(N, s - 1);
+}
+
+// Plans for a given number of threads per line.  A power of two whose
+// radix plan ends in {4, 4} ends in one radix-16 stage instead when that
+// stage has exactly one butterfly per thread (N / 16 == TL): one LDS round
+// trip fewer per transform, no idle threads.
+__host__ __device__ constexpr bool fft_use16(int N, int TL) {
+  return !fft_has3(N) && fft_log2m(N) % 3 == 1 && fft_log2m(N) >= 4 && N / 16 == TL;
+}
+__host__ __device__ constexpr int fft_nstages_tl(int N, int TL) {
+  return fft_nstages(N) - (fft_use16(N, TL) ? 1 : 0);
+}
+__host__ __device__ constexpr int fft_radix_tl(int N, int TL, int s) {
+  return fft_use16(N, TL) && s == fft_nstages_tl(N, TL) - 1 ? 16 : fft_radix(N, s);
+}
+__host__ __device__ constexpr int fft_pstride_tl(int N, int TL, int s) {
+  return s == 0 ? 1 : fft_pstride_tl(N, TL, s - 1) * fft_radix_tl(N, TL, s - 1);
 }
 
 // Threads that share one line in the row kernels: a power of two near N/8.
@@ -155,6 +173,42 @@ __device__ __forceinline__ void fft_sync() {
   }
 }
 
+// 16-point DFT as 4 x 4: x[4 n1 + n2] -> 4-point DFTs over n1, twiddles
+// W16^(n2 k1), 4-point DFTs over n2 -> X[k1 + 4 k2].
+template <bool INV> struct Dft<16, INV> {
+  // W16^m = exp(-+2 pi i m / 16) for the products m = n2 k1 that occur
+  __device__ __forceinline__ static float2 w16(int m) {
+    const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;
+    const float r = 0.70710678118654752440f;
+    float2 w = m == 1 ? make_float2(c1, -s1)
+             : m == 2 ? make_float2(r, -r)
+             : m == 3 ? make_float2(s1, -c1)
+             : m == 4 ? make_float2(0.0f, -1.0f)
+             : m == 6 ? make_float2(-r, -r)
+                      : make_float2(-c1, s1);   // m == 9
+    if (INV) w.y = -w.y;
+    return w;
+  }
+  __device__ __forceinline__ static void run(float2* v) {
+    float2 a[4][4];   // a[n2][k1]
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      float2 t[4] = {v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]};
+      Dft<4, INV>::run(t);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1)
+        a[n2][k1] = (n2 == 0 || k1 == 0) ? t[k1] : cmul(t[k1], w16(n2 * k1));
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      float2 t[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+      Dft<4, INV>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+    }
+  }
+};
+
 // One Stockham stage on `line` (LDS), executed by TL threads (thread lt).
 template <int N, int TL, int R, int P, bool INV, bool PADDED, bool WAVE>
 __device__ __forceinline__ void fft_stage(float2* line, const float2* tw, int lt) {
@@ -216,8 +270,9 @@ __device__ __forceinline__ void fft_stage(float2* line, const float2* tw, int lt
 
 template <int N, int TL, bool INV, bool PADDED, bool WAVE, int S>
 __device__ __forceinline__ void fft_stages(float2* line, const float2* tw, int lt) {
-  if constexpr (S < fft_nstages(N)) {
-    fft_stage<N, TL, fft_radix(N, S), fft_pstride(N, S), INV, PADDED, WAVE>(line, tw, lt);
+  if constexpr (S < fft_nstages_tl(N, TL)) {
+    fft_stage<N, TL, fft_radix_tl(N, TL, S), fft_pstride_tl(N, TL, S), INV, PADDED, WAVE>(line, tw,
+                                                                                         lt);
     fft_stages<N, TL, INV, PADDED, WAVE, S + 1>(line, tw, lt);
   }
 }

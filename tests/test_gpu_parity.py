@@ -113,6 +113,7 @@ def test_objective_and_grad_parity(small):
     (128, 256, 9, 4, True),        # rectangular, ragged last chunk
     (192, 192, 7, 3, True),        # radix-3 FFT lengths
     (64, 384, 5, 2, False),
+    (1024, 64, 3, 2, True),        # 1024-point columns: one wavefront each, radix-16 stage
 ])
 def test_grad_parity_shapes(H, W, n, chunk, shifts):
     say("grad parity", H, W, n, chunk, shifts)
