@@ -452,8 +452,11 @@ def holo2d_forward(psi, q, mag_rel, m0, fresnel0):
         for j in range(len(mag_rel))])
 
 
-def holo2d_gradient(psi, q, amp, amp_ref, mag_rel, m0, fresnel0):
-    """F2 of one projection with its own probe: F, g_psi, g_q (Eq. 10/11)."""
+def holo2d_gradient(psi, q, amp, amp_ref, mag_rel, m0, fresnel0, functional="amplitude"):
+    """F2 of one projection with its own probe: F, g_psi, g_q (Eq. 10/11);
+    functional="intensity" takes F1 (Eq. 9) instead, amp and amp_ref then
+    holding intensities."""
+    residual = RESIDUALS[functional]
     rho_d, rho_p = distances(m0, mag_rel)
     F = 0.0
     g_psi = np.zeros(psi.shape, np.complex128)
@@ -462,12 +465,12 @@ def holo2d_gradient(psi, q, amp, amp_ref, mag_rel, m0, fresnel0):
         Qj = propagate(q, rho_p[j], fresnel0)
         phi = transmit(psi, mag_rel[j])
         v = propagate(Qj * phi, rho_d[j], fresnel0)
-        Fj, r = _residual(v, amp[j])
+        Fj, r = residual(v, amp[j])
         F += Fj
         w = propagate(r, -rho_d[j], fresnel0)
         g_psi += resample_T(np.conj(Qj) * w, mag_rel[j])
         g_q += propagate(np.conj(phi) * w, -rho_p[j], fresnel0)
-    Fr, gr = reference_term(q, amp_ref, fresnel0)
+    Fr, gr = reference_term(q, amp_ref, fresnel0, functional)
     return F + Fr, g_psi, g_q + gr
 
 

@@ -382,11 +382,15 @@ def test_adjoint_is_the_jacobian_transpose():
     assert abs(lhs - rhs) < 1e-6 * abs(lhs)
 
 
-def test_holo2d_matches_joint_model_single_angle():
+@pytest.mark.parametrize("functional", ["amplitude", "intensity"])
+def test_holo2d_matches_joint_model_single_angle(functional):
     geom, u, q, amp, amp_ref = tiny_problem(seed=18, n_angles=1, shifts=False)
+    if functional == "intensity":   # F1 takes intensities
+        amp, amp_ref = amp ** 2, amp_ref ** 2
     psi = O.transmittance(u, geom.theta[0], geom.kappa)
-    F2, gpsi, gq2 = O.holo2d_gradient(psi, q, amp[0], amp_ref, geom.mag_rel, geom.m0, geom.fresnel0)
-    F, gu, gq = O.gradient(u, q, amp, amp_ref, geom)
+    F2, gpsi, gq2 = O.holo2d_gradient(psi, q, amp[0], amp_ref, geom.mag_rel, geom.m0, geom.fresnel0,
+                                      functional=functional)
+    F, gu, gq = O.gradient(u, q, amp, amp_ref, geom, functional=functional)
     assert F2 == pytest.approx(F, rel=1e-12)
     np.testing.assert_allclose(gq2, gq, atol=1e-10 * np.max(np.abs(gq)))
     # chain rule of the joint model
@@ -395,14 +399,15 @@ def test_holo2d_matches_joint_model_single_angle():
                                atol=1e-10 * np.max(np.abs(gu)))
 
 
-def test_holo2d_central_differences():
+@pytest.mark.parametrize("functional", ["amplitude", "intensity"])
+def test_holo2d_central_differences(functional):
     rng = np.random.default_rng(19)
     n = 24
     psi = np.exp(1j * 0.5 * rng.uniform(0, 1, (n, n)))
     q = 1 + 0.1 * crandn(rng, n, n)
     amp = np.abs(1 + 0.2 * crandn(rng, 4, n, n))
     amp_ref = np.abs(1 + 0.2 * crandn(rng, n, n))
-    args = ([1.0, 1.08, 1.25, 1.5], 300.0, 0.02)
+    args = ([1.0, 1.08, 1.25, 1.5], 300.0, 0.02, functional)
     F, gpsi, gq = O.holo2d_gradient(psi, q, amp, amp_ref, *args)
     dpsi, dq = 1e-2 * crandn(rng, n, n), 1e-2 * crandn(rng, n, n)
     eps = 1e-3
