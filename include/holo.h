@@ -282,6 +282,12 @@ holo_status holo2d_plan_create(int32_t n_inst, const int32_t* sizes, int32_t n_d
                                const double* mag_rel, double m0, double fresnel0,
                                holo2d_plan** out);
 holo_status holo2d_plan_destroy(holo2d_plan* plan);
+/* The functional holo2d_objective and holo2d_grad evaluate, as
+ * holo_plan_set_functional: HOLO_FUNCTIONAL_AMPLITUDE (default, F2 of
+ * Eq. 10) or HOLO_FUNCTIONAL_INTENSITY (F1 of Eq. 9; amp and amp_ref then
+ * hold intensities).  Errors: INVALID_ARGUMENT (NULL plan, unknown value).
+ * Host-only. */
+holo_status holo2d_plan_set_functional(holo2d_plan* plan, int32_t functional);
 /* offsets[n_inst] (elements) and total T of the packed layout. */
 holo_status holo2d_offsets(const holo2d_plan* plan, int64_t* offsets, int64_t* total);
 holo_status holo2d_workspace_bytes(const holo2d_plan* plan, size_t* bytes);

@@ -209,7 +209,16 @@ __global__ __launch_bounds__(kT2) void k2_rows(B2Args A, const B2Item* __restric
 // Columns
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ double b_residual(float2& v, float a) {
+// Amplitude functional (F2): r = 2 (v - a v/|v|) in place (v/|v| := 0 at
+// |v| = 0), returns (|v| - a)^2.  Intensity functional (F1, `a` is then the
+// intensity d): r = 4 (|v|^2 - d) v, returns (|v|^2 - d)^2.
+__device__ __forceinline__ double b_residual(float2& v, float a, int functional) {
+  if (functional) {
+    const double e = (double)fmaf(v.x, v.x, v.y * v.y) - (double)a;
+    const float sc = 4.0f * (float)e;
+    v = make_float2(sc * v.x, sc * v.y);
+    return e * e;
+  }
   const float av = sqrtf(v.x * v.x + v.y * v.y);
   const double d = (double)av - (double)a;
   const float sc = av > 0.0f ? 2.0f * (1.0f - a / av) : 2.0f;
@@ -286,7 +295,7 @@ __device__ __forceinline__ void b_cols_body(const B2Args& A, const B2Item& it, f
     for (int i = threadIdx.x; i < N * TC; i += kT2) {
       const int zz = i / TC, cc = i % TC;
       float2 v = col0[cc * (N + 1) + zz];
-      acc += b_residual(v, amp[(size_t)zz * N + s0 + cc]);
+      acc += b_residual(v, amp[(size_t)zz * N + s0 + cc], A.functional);
       col0[cc * (N + 1) + zz] = v;
     }
     b_block_sum(acc, A.Fpart + it.slot);

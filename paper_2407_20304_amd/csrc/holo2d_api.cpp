@@ -28,6 +28,7 @@ struct ItemList {
 
 struct holo2d_plan {
   int n_inst = 0, nd = 0;
+  int functional = 0;                     // holo_functional
   double m0 = 0, fresnel0 = 0;
   std::vector<double> mag;
   std::vector<int> sizes;
@@ -194,6 +195,15 @@ extern "C" holo_status holo2d_plan_create(int32_t n_inst, const int32_t* sizes, 
   return HOLO_OK;
 }
 
+extern "C" holo_status holo2d_plan_set_functional(holo2d_plan* P, int32_t functional) {
+  if (!P) return fail2(HOLO_ERR_INVALID_ARGUMENT, "holo2d_plan_set_functional: NULL plan");
+  if (functional != HOLO_FUNCTIONAL_AMPLITUDE && functional != HOLO_FUNCTIONAL_INTENSITY)
+    return fail2(HOLO_ERR_INVALID_ARGUMENT,
+                 "holo2d_plan_set_functional: functional must be 0 (amplitude) or 1 (intensity)");
+  P->functional = functional;
+  return HOLO_OK;
+}
+
 extern "C" holo_status holo2d_plan_destroy(holo2d_plan* P) {
   if (!P) return HOLO_OK;
   if (P->d_tables) {
@@ -293,6 +303,7 @@ holo_status b2_run(holo2d_plan* P, B2Run run, const holo_c64* psi, const holo_c6
   auto items = [&](const ItemList& L) { return (const B2Item*)(tb + L.off); };
   B2Args A{};
   A.nd = P->nd;
+  A.functional = P->functional;
   for (int j = 0; j < P->nd; ++j) A.mag[j] = P->mag[j];
   A.inst = (const B2Inst*)(tb + P->off_inst);
   A.psi = (const float2*)psi;

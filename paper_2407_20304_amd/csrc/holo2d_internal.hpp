@@ -24,6 +24,7 @@ enum B2Mode {
 
 struct B2Args {
   int mode, nd, want_grad, want_ref;
+  int functional;          // 0: amplitude (F2), 1: intensity (F1)
   double mag[8];
   const B2Inst* inst;
   const float2* psi;

@@ -28,7 +28,7 @@ EXPORTS = (
     "holo_probe_init", "holo_cg_workspace_bytes", "holo_cg",
     "holo_bin_frames", "holo_upsample_frames", "holo_upsample_volume",
     "holo2d_plan_create", "holo2d_plan_destroy", "holo2d_offsets", "holo2d_workspace_bytes",
-    "holo2d_fwd", "holo2d_objective", "holo2d_grad",
+    "holo2d_plan_set_functional", "holo2d_fwd", "holo2d_objective", "holo2d_grad",
     "holo_timing_enable", "holo_timing_read", "holo_last_error",
 )
 
@@ -90,6 +90,7 @@ def lib():
     L.holo2d_plan_create.argtypes = [c_int32, POINTER(c_int32), c_int32, POINTER(c_double),
                                      c_double, c_double, POINTER(c_void_p)]
     L.holo2d_plan_destroy.argtypes = [P]
+    L.holo2d_plan_set_functional.argtypes = [P, c_int32]
     L.holo2d_offsets.argtypes = [P, POINTER(ctypes.c_int64), POINTER(ctypes.c_int64)]
     L.holo2d_workspace_bytes.argtypes = [P, POINTER(c_size_t)]
     L.holo2d_fwd.argtypes = [P, P, P, P, P, c_size_t, P]
@@ -477,6 +478,13 @@ class Plan2D:
         _check(lib().holo2d_workspace_bytes(h, ctypes.byref(n)))
         self.workspace_bytes = int(n.value)
         self._ws = None
+        self.functional = "amplitude"
+
+    def set_functional(self, name):
+        """"amplitude" (F2, default; amp = sqrt(d)) or "intensity" (F1; amp
+        and amp_ref then hold the intensities d)."""
+        _check(lib().holo2d_plan_set_functional(self._h, c_int32(Plan.FUNCTIONALS[name])))
+        self.functional = name
 
     def close(self):
         if getattr(self, "_h", None):

@@ -165,6 +165,13 @@ def test_functional_switch_validates_on_the_host():
     p.set_functional("intensity")
     assert p.functional == "intensity"
     p.close()
+    q = holo.Plan2D([128, 64], [1.0, 1.25], 300.0, 0.01)
+    assert L.holo2d_plan_set_functional(None, 0) == 1
+    assert L.holo2d_plan_set_functional(q._h, 2) == 1
+    assert L.holo2d_plan_set_functional(q._h, 1) == 0
+    q.set_functional("amplitude")
+    assert q.functional == "amplitude"
+    q.close()
 
 
 def test_solver_entry_points_validate_on_the_host():

@@ -35,10 +35,11 @@ def make_instances(sizes, config=2):
     return out
 
 
-def run_batch(sizes, inst):
+def run_batch(sizes, inst, functional="amplitude"):
     import torch
     from paper_2407_20304_amd import holo
     plan = holo.Plan2D(sizes, synth.MAG_REL, synth.M0, synth.FRESNEL0)
+    plan.set_functional(functional)
     dev = torch.device("cuda:0")
     psi = plan.pack([x[0] for x in inst], device=dev)
     q = plan.pack([x[1] for x in inst], device=dev)
@@ -95,3 +96,23 @@ def test_96_instances_batch_equals_single_instances():
                                          synth.MAG_REL, synth.M0, synth.FRESNEL0)
         assert abs(F[i] - F0) / F0 < TOL
         assert O.rel_err(gpsi[i].numpy(), gp0) < TOL and O.rel_err(gq[i].numpy(), gq0) < TOL
+
+
+def test_intensity_functional_against_oracle():
+    # F1 (Eq. 9): the same instances with intensities in place of amplitudes
+    sizes = [256, 64, 1024, 192]
+    say("batch F1 parity, sizes", sizes)
+    inst = [(ps, q, (a.astype(np.float64) ** 2).astype(np.float32),
+             (ar.astype(np.float64) ** 2).astype(np.float32))
+            for ps, q, a, ar in make_instances(sizes)]
+    plan, F, Fo, gpsi, gq, _ = run_batch(sizes, inst, functional="intensity")
+    assert np.array_equal(F, Fo)
+    for i, (ps, q, d, dr) in enumerate(inst):
+        F0, gp0, gq0 = O.holo2d_gradient(ps.astype(np.complex128), q.astype(np.complex128),
+                                         d.astype(np.float64), dr.astype(np.float64),
+                                         synth.MAG_REL, synth.M0, synth.FRESNEL0,
+                                         functional="intensity")
+        eF = abs(F[i] - F0) / F0
+        ep, eq = O.rel_err(gpsi[i].numpy(), gp0), O.rel_err(gq[i].numpy(), gq0)
+        say("  inst %d n=%d: F %.1e g_psi %.1e g_q %.1e" % (i, sizes[i], eF, ep, eq))
+        assert max(eF, ep, eq) < TOL
