@@ -202,6 +202,57 @@ def solver_bench(args, wl, plan, u, amp, amp_ref):
     print(json.dumps(result), flush=True)
 
 
+def batch2d_bench(steps=20, warmup=3):
+    """The batched single-angle workload: 96 independent problems with the
+    seeded size mix (128 to 512 px, 4 planes, own probe and reference each).
+    One call of holo2d_grad evaluates every instance's objective and both
+    gradients.  Reports calls per second (HIP events on the launch stream)
+    and the HBM rate against the compulsory bytes: psi, q, amp and amp_ref
+    read, g_psi and g_q written (8 + 8 + 4 nd + 4 + 8 + 8 bytes per pixel)."""
+    import torch
+    from paper_2407_20304_amd import holo, synth
+    sizes = synth.batch_sizes()
+    nd = len(synth.MAG_REL)
+    plan = holo.Plan2D(sizes, synth.MAG_REL, synth.M0, synth.FRESNEL0)
+    dev = torch.device("cuda:0")
+    sd = lambda role, i: synth.seed_of(2, role) + 100 * i
+    psi = plan.pack([synth.phase_object_2d(n, sd(4, i)) for i, n in enumerate(sizes)], device=dev)
+    q = plan.pack([synth.probe(n, n, sd(5, i)) for i, n in enumerate(sizes)], device=dev)
+    amp = plan.pack([synth.synthetic_amplitudes(1, nd, n, n, sd(9, i), device=dev)[0].cpu().numpy()
+                     for i, n in enumerate(sizes)], planes=True, device=dev)
+    amp_ref = plan.pack([synth.synthetic_amplitudes(1, 1, n, n, sd(9, i) + 500, device=dev)[0, 0]
+                         .cpu().numpy() for i, n in enumerate(sizes)], device=dev)
+    F = torch.empty(plan.n_inst, dtype=torch.float64, device=dev)
+    g_psi, g_q = torch.empty_like(psi), torch.empty_like(q)
+    for _ in range(warmup):
+        plan.holo2d_grad(psi, q, amp, amp_ref, F=F, g_psi=g_psi, g_q=g_q)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        plan.holo2d_grad(psi, q, amp, amp_ref, F=F, g_psi=g_psi, g_q=g_q)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    if not bool(torch.isfinite(F).all()):
+        raise RuntimeError("batched objective is not finite")
+    T = plan.total
+    compulsory = T * (8 + 8 + 4 * nd + 4 + 8 + 8)
+    # FFT flops at 5 N log2 N per N-point transform: a propagation D is two
+    # 2-D transforms of n^2 points (20 n^2 log2 n); per instance 4 per plane
+    # (probe, forward field, its adjoint, probe-gradient adjoint) and 2 for
+    # the reference term
+    fft_flop = sum((4 * nd + 2) * 20 * n * n * math.log2(n) for n in sizes)
+    res = {"workload": "batch96_mixed", "instances": plan.n_inst,
+           "sizes": {str(n): sizes.count(n) for n in sorted(set(sizes))}, "pixels": T,
+           "n_dist": nd, "calls": steps, "ms_per_call": ms, "calls_per_s": 1e3 / ms,
+           "compulsory_bytes": compulsory, "GBps": compulsory / (ms * 1e-3) / 1e9,
+           "hbm_frac": compulsory / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+           "fft_flop": fft_flop, "fft_TFLOPs": fft_flop / (ms * 1e-3) / 1e12}
+    plan.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -222,6 +273,11 @@ def main():
                     help="instead of the gradient step, time ITERS conjugate-gradient "
                          "iterations (holo_cg) from u and the back-propagated reference probe "
                          "and print their own JSON line")
+    ap.add_argument("--batch2d", action="store_true",
+                    help="time only the batched single-angle workload (96 instances) and print "
+                         "its own JSON line")
+    ap.add_argument("--no-batch2d", action="store_true",
+                    help="leave the batched single-angle workload out of the default line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one MI355X: the path runs on a single GPU "
@@ -236,6 +292,13 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     holo.lib()  # fails loudly if the HIP library is missing
+    if args.batch2d:
+        res = batch2d_bench()
+        res.update({"metric": "batched single-angle gradient calls/s", "value": res["calls_per_s"],
+                    "unit": "calls/s", "n_gpus": 1, "higher_is_better": True, "dtype": "c64",
+                    "data": "synthetic"})
+        print(json.dumps(res), flush=True)
+        return
     dev = torch.device("cuda:0")
     wl = synth.WORKLOADS[args.workload]
     H, W, N, nd = wl.H, wl.W, wl.n_angles, len(wl.mag_rel)
@@ -342,6 +405,9 @@ def main():
     if not args.no_plain:
         result["plain"] = plain_bench(wl, u, q, amp, amp_ref, F, g_u, g_q, K / elapsed)
         result["vs_plain"] = result["plain"]["speedup"]
+    if not args.no_batch2d:
+        log("batched single-angle workload")
+        result["batch2d"] = batch2d_bench()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         result["cpu_baseline"] = cpu_baseline(wl, u, q_np, amp, amp_ref.cpu().numpy(),
