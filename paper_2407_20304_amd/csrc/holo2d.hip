@@ -22,7 +22,12 @@ constexpr int kT2 = 256;
 
 __host__ __device__ constexpr int b_rows_tl(int n) { return fft_row_threads(n); }
 __host__ __device__ constexpr int b_rows_lpw(int n) { return kT2 / fft_row_threads(n); }
-__host__ __device__ constexpr int b_cols_tc(int n) { return n >= 1024 ? 8 : 16; }
+// Columns per column-pass workgroup: 8 from 384 on, so that the tile of a
+// batch whose instances are at most 512 px fits 37 KB of LDS (four
+// workgroups per CU instead of two).
+__host__ __device__ constexpr int b_cols_tc(int n) { return n >= 384 ? 8 : 16; }
+// LDS of one column workgroup of size n: twiddles plus the padded tile.
+__host__ __device__ constexpr int b_cols_lds(int n) { return n + b_cols_tc(n) * (n + 1); }
 
 int b2_rows_per_wg(int n) { return b_rows_lpw(n); }
 int b2_cols_per_wg(int n) { return b_cols_tc(n); }
@@ -35,7 +40,12 @@ bool b2_size_supported(int n) {
 
 // LDS budget shared by every specialisation (twiddles + lines / columns).
 constexpr int kRowLds = 1024 + 3072;          // float2 elements
-constexpr int kColLds = 1024 + 8 * 1025;
+// column-kernel LDS (float2) for batches up to 512 px and with 1024 px
+constexpr int kColLdsSmall = b_cols_lds(512), kColLdsLarge = b_cols_lds(1024);
+static_assert(b_cols_lds(384) <= kColLdsSmall && b_cols_lds(256) <= kColLdsSmall &&
+                  b_cols_lds(192) <= kColLdsSmall && b_cols_lds(128) <= kColLdsSmall &&
+                  b_cols_lds(64) <= kColLdsSmall,
+              "small column LDS covers every size up to 512");
 
 __device__ __forceinline__ double b_src_pos(double c, double m, int idx) {
   return c + m * ((double)idx - c);
@@ -314,11 +324,17 @@ __device__ __forceinline__ void b_cols_body(const B2Args& A, const B2Item& it, f
   }
 }
 
+// LDS: the host launches the small instantiation only for batches whose
+// largest instance is at most 512 px.
+template <int LDS>
 __global__ __launch_bounds__(kT2) void k2_cols(B2Args A, const B2Item* __restrict__ items) {
-  __shared__ float2 lds[kColLds];
+  __shared__ float2 lds[LDS];
   const B2Item it = items[blockIdx.x];
   switch (A.inst[it.inst].n) {
-#define CASE(N) case N: b_cols_body<N>(A, it, lds); break;
+#define CASE(N) \
+  case N:       \
+    if constexpr (b_cols_lds(N) <= LDS) b_cols_body<N>(A, it, lds); \
+    break;
     CASE(64) CASE(128) CASE(192) CASE(256) CASE(384) CASE(512) CASE(1024)
 #undef CASE
     default: break;
@@ -382,7 +398,10 @@ hipError_t launch_b2_rows(const B2Args& A, const B2Item* items, int n, hipStream
 
 hipError_t launch_b2_cols(const B2Args& A, const B2Item* items, int n, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  k2_cols<<<n, kT2, 0, st>>>(A, items);
+  if (A.max_n <= 512)
+    k2_cols<kColLdsSmall><<<n, kT2, 0, st>>>(A, items);
+  else
+    k2_cols<kColLdsLarge><<<n, kT2, 0, st>>>(A, items);
   return hipGetLastError();
 }
 

@@ -304,6 +304,7 @@ holo_status b2_run(holo2d_plan* P, B2Run run, const holo_c64* psi, const holo_c6
   B2Args A{};
   A.nd = P->nd;
   A.functional = P->functional;
+  A.max_n = P->dsizes.back();
   for (int j = 0; j < P->nd; ++j) A.mag[j] = P->mag[j];
   A.inst = (const B2Inst*)(tb + P->off_inst);
   A.psi = (const float2*)psi;

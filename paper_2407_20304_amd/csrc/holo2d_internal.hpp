@@ -25,6 +25,7 @@ enum B2Mode {
 struct B2Args {
   int mode, nd, want_grad, want_ref;
   int functional;          // 0: amplitude (F2), 1: intensity (F1)
+  int max_n;               // largest instance size of the batch
   double mag[8];
   const B2Inst* inst;
   const float2* psi;

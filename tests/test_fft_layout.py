@@ -161,5 +161,5 @@ def test_which_kernels_take_the_radix16_plan():
         pairs.add(("rows", n, pow2_floor(n // 8)))
         pairs.add(("cols", n, 512 // (4 if n >= 2048 else 8 if n >= 1024 else 16)))
         if n <= 1024:
-            pairs.add(("cols2d", n, 256 // (8 if n >= 1024 else 16)))
+            pairs.add(("cols2d", n, 256 // (8 if n >= 384 else 16)))
     assert {(k, n, tl) for k, n, tl in pairs if use16(n, tl)} == {("cols", 1024, 64)}
