@@ -26,8 +26,11 @@ __host__ __device__ constexpr int b_rows_lpw(int n) { return kT2 / fft_row_threa
 // batch whose instances are at most 512 px fits 37 KB of LDS (four
 // workgroups per CU instead of two).
 __host__ __device__ constexpr int b_cols_tc(int n) { return n >= 384 ? 8 : 16; }
-// LDS of one column workgroup of size n: twiddles plus the padded tile.
-__host__ __device__ constexpr int b_cols_lds(int n) { return n + b_cols_tc(n) * (n + 1); }
+// Pitch of one column line of the tile: the padded line plus 4, so that the
+// tile loads (columns of consecutive threads at one row) spread over banks.
+__host__ __device__ constexpr int b_col_pitch(int n) { return fft_line_len(n) + 4; }
+// LDS of one column workgroup of size n: twiddles plus the tile.
+__host__ __device__ constexpr int b_cols_lds(int n) { return n + b_cols_tc(n) * b_col_pitch(n); }
 
 int b2_rows_per_wg(int n) { return b_rows_lpw(n); }
 int b2_cols_per_wg(int n) { return b_cols_tc(n); }
@@ -110,9 +113,11 @@ __device__ __forceinline__ BAdj b_adj_taps(double c, double m, int idx, int n) {
 template <int N>
 __device__ __forceinline__ void b_rows_body(const B2Args& A, const B2Item& it, float2* lds) {
   constexpr int TL = b_rows_tl(N), LPW = b_rows_lpw(N), E = N / TL;
+  static_assert(N + LPW * fft_line_len(N) <= kRowLds, "row lines fit the LDS");
   float2* s_tw = lds;
   const int line = threadIdx.x / TL, lt = threadIdx.x % TL;
-  float2* L = lds + N + line * N;
+  // lines stored padded (element s at fpi(s)): conflict-free FFT stages
+  float2* L = lds + N + line * fft_line_len(N);
   const B2Inst in = A.inst[it.inst];
   for (int i = threadIdx.x; i < N; i += kT2) s_tw[i] = in.tw[i];
   const int z = it.line0 + line;
@@ -164,25 +169,25 @@ __device__ __forceinline__ void b_rows_body(const B2Args& A, const B2Item& it, f
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int s = lt + e * TL;
-      L[s] = cmul(Qr[s], b_phi(psi, N, ty, b_fwd_taps(c, m, s, N)));
+      L[fpi(s)] = cmul(Qr[s], b_phi(psi, N, ty, b_fwd_taps(c, m, s, N)));
     }
   } else {
     const float2* r = src + (size_t)z * N;
 #pragma unroll
-    for (int e = 0; e < E; ++e) L[lt + e * TL] = r[lt + e * TL];
+    for (int e = 0; e < E; ++e) L[fpi(lt + e * TL)] = r[lt + e * TL];
   }
   // A line within one wavefront synchronises only there (s_tw is behind
   // the barrier).
   constexpr bool WL = TL <= 64;
   if constexpr (WL) __syncthreads();
-  fft<N, TL, false, false, WL>(L, s_tw, lt);
+  fft<N, TL, false, true, WL>(L, s_tw, lt);
   const float2* ch = in.chirp + (size_t)chirp * N;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int s = lt + e * TL;
-    L[s] = conj ? cmulc(L[s], ch[s]) : cmul(L[s], ch[s]);
+    L[fpi(s)] = conj ? cmulc(L[fpi(s)], ch[s]) : cmul(L[fpi(s)], ch[s]);
   }
-  fft<N, TL, true, false, WL>(L, s_tw, lt);
+  fft<N, TL, true, true, WL>(L, s_tw, lt);
   float2* o = dst + (size_t)z * N;
   if (A.mode == kB2RowsC) {
     const double m = A.mag[j];
@@ -193,13 +198,13 @@ __device__ __forceinline__ void b_rows_body(const B2Args& A, const B2Item& it, f
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int s = lt + e * TL;
-      const float2 w = L[s];
+      const float2 w = L[fpi(s)];
       Gr[s] = cmulc(w, b_phi(psi, N, ty, b_fwd_taps(c, m, s, N)));
       o[s] = cmulc(w, Qr[s]);
     }
   } else {
 #pragma unroll
-    for (int e = 0; e < E; ++e) o[lt + e * TL] = L[lt + e * TL];
+    for (int e = 0; e < E; ++e) o[lt + e * TL] = L[fpi(lt + e * TL)];
   }
   (void)LPW;
 }
@@ -253,8 +258,10 @@ __device__ __forceinline__ void b_cols_body(const B2Args& A, const B2Item& it, f
   constexpr int TC = b_cols_tc(N), TLc = kT2 / TC;
   float2* s_tw = lds;
   const int cidx = threadIdx.x / TLc, lt = threadIdx.x % TLc;
+  // column lines stored padded (element zz at fpi(zz)), pitch b_col_pitch
+  constexpr int CP = b_col_pitch(N);
   float2* col0 = lds + N;
-  float2* Lc = col0 + cidx * (N + 1);
+  float2* Lc = col0 + cidx * CP;
   const B2Inst in = A.inst[it.inst];
   for (int i = threadIdx.x; i < N; i += kT2) s_tw[i] = in.tw[i];
   const size_t fr = (size_t)N * N;
@@ -289,38 +296,39 @@ __device__ __forceinline__ void b_cols_body(const B2Args& A, const B2Item& it, f
   }
   for (int i = threadIdx.x; i < N * TC; i += kT2) {
     const int zz = i / TC, cc = i % TC;
-    col0[cc * (N + 1) + zz] = frame[(size_t)zz * N + s0 + cc];
+    col0[cc * CP + fpi(zz)] = frame[(size_t)zz * N + s0 + cc];
   }
   const float2* ch = in.chirp + (size_t)chirp * N;
   // Each column lies within one wavefront: the transforms synchronise only
   // there, behind one barrier for the tile and s_tw.
   constexpr bool WL = TLc <= 64;
   if constexpr (WL) __syncthreads();
-  fft<N, TLc, false, false, WL>(Lc, s_tw, lt);
-  for (int zz = lt; zz < N; zz += TLc) Lc[zz] = conj ? cmulc(Lc[zz], ch[zz]) : cmul(Lc[zz], ch[zz]);
-  fft<N, TLc, true, false, WL>(Lc, s_tw, lt);
+  fft<N, TLc, false, true, WL>(Lc, s_tw, lt);
+  for (int zz = lt; zz < N; zz += TLc)
+    Lc[fpi(zz)] = conj ? cmulc(Lc[fpi(zz)], ch[zz]) : cmul(Lc[fpi(zz)], ch[zz]);
+  fft<N, TLc, true, true, WL>(Lc, s_tw, lt);
   __syncthreads();
   if (amp) {
     double acc = 0.0;
     for (int i = threadIdx.x; i < N * TC; i += kT2) {
       const int zz = i / TC, cc = i % TC;
-      float2 v = col0[cc * (N + 1) + zz];
+      float2 v = col0[cc * CP + fpi(zz)];
       acc += b_residual(v, amp[(size_t)zz * N + s0 + cc], A.functional);
-      col0[cc * (N + 1) + zz] = v;
+      col0[cc * CP + fpi(zz)] = v;
     }
     b_block_sum(acc, A.Fpart + it.slot);
     __syncthreads();
   }
   if (adj_after) {
-    fft<N, TLc, false, false, WL>(Lc, s_tw, lt);
-    for (int zz = lt; zz < N; zz += TLc) Lc[zz] = cmulc(Lc[zz], ch[zz]);
-    fft<N, TLc, true, false, WL>(Lc, s_tw, lt);
+    fft<N, TLc, false, true, WL>(Lc, s_tw, lt);
+    for (int zz = lt; zz < N; zz += TLc) Lc[fpi(zz)] = cmulc(Lc[fpi(zz)], ch[zz]);
+    fft<N, TLc, true, true, WL>(Lc, s_tw, lt);
     __syncthreads();
   }
   if (A.mode == kB2ColsB && A.amp && !A.want_grad) return;  // objective only
   for (int i = threadIdx.x; i < N * TC; i += kT2) {
     const int zz = i / TC, cc = i % TC;
-    frame[(size_t)zz * N + s0 + cc] = col0[cc * (N + 1) + zz];
+    frame[(size_t)zz * N + s0 + cc] = col0[cc * CP + fpi(zz)];
   }
 }
 
