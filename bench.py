@@ -35,7 +35,7 @@ FLOP_PER_LERP = 8               # 2 taps x (re, im) x fused multiply-add
 TRAFFIC = {
     "k_radon_fwd": {"fetch_kib": 15932943.35, "write_kib": 1246930.94,
                     "fetch_scale": 2.0, "write_scale": 1.0,
-                    "sources_sha256": "735d50bd6e181a7ad28a74aef5017f3c0ce11e01fb4316410033bc96dc05a8ca"},
+                    "sources_sha256": "1be59e656a75ba7ecda887041f954fff4dcdb0a09b7cc439ddb7892aac786588"},
 }
 
 

@@ -13,9 +13,10 @@
 //              bin, each thread owns 2 slices x 8 bins), fused
 //              exp(i kappa p) epilogue
 //   radon_adj  transpose as a triangle-footprint gather over all angles
-//              (lanes = a 16 x 16 voxel tile, each thread owns kAdjZT
-//              slices), sinogram segments staged in LDS per angle group
-//              by LDS-direct loads
+//              (a workgroup per 16 x 16 voxel tile and kAdjZT slices, each
+//              thread a voxel pair along x and kAdjZT / 2 slices),
+//              sinogram segments staged in LDS per angle group by
+//              LDS-direct loads
 // Positions and interpolation weights are formed in double precision (or as
 // single-precision offsets of a few bins from double-precision bases); field
 // arithmetic is single precision; costs and long ray sums are carried in
@@ -836,14 +837,15 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
     }
 }
 
-// Transpose.  A workgroup owns a 16 x 16 voxel tile (one voxel per thread)
-// and kAdjZT slices (per thread) and loops over all angles in groups of
-// kAdjNA (one wave loads each angle of a group): the kAdjSeg bins of each
-// slice that the tile projects onto are copied straight from the sinogram
-// into LDS, [angle][slice][bin], by LDS-direct loads two groups ahead of use
-// (three group buffers), then every thread gathers its two taps per slice.
-// The lanes of a wave read different bins of one 256-byte bin row: no bank
-// conflicts.  Sinogram rows are zero-padded by kAdjPad bins, so a segment
+// Transpose.  A workgroup owns a 16 x 16 voxel tile and kAdjZT slices; a
+// thread owns a voxel pair along x and half of the slices (kAdjZT / 2).  It
+// loops over all angles in groups of kAdjNA (one wave loads each angle of a
+// group): the kAdjSeg bins of each slice that the tile projects onto are
+// copied straight from the sinogram into LDS, [angle][slice][bin], by
+// LDS-direct loads one group ahead of use (two group buffers); per slice a
+// thread then reads the three consecutive bins that carry both voxels'
+// weights.  The lanes of a wave read different bins of one 256-byte bin
+// row: no bank conflicts.  Sinogram rows are zero-padded by kAdjPad bins, so a segment
 // is read without bounds checks.  A voxel projecting to fractional bin q
 // takes max(0, 1 - |i - q| / h) / h of bin i (h = max(|cos|, |sin|)) --
 // exactly the weight Joseph's interpolation gave it.
