@@ -20,6 +20,12 @@ paper by eye:
   * Sec. 2, Eq. (14)  R_k, the Radon transform at angle theta_k.
   * Appendix A, the Fresnel kernel P_Z and D_Z psi = psi * P_Z.
 
+For problems too large for the NumPy loops (hundreds of angles on 256^3 to
+1024^3 volumes) the same Joseph sums and transpose are available from
+oracle/joseph.c (plain C loops in double precision, built by
+oracle/build_oracle.py) through `radon_set` and `radon_T_set`; the pins hold
+both implementations to the same facts.
+
 Dimensionless units (one length unit = one detector pixel after the data
 rescaling):  the Fresnel number of the first plane is N_F0 = Delta^2 /
 (lambda zeta_0), every propagation distance is a multiple rho of zeta_0, and
@@ -69,6 +75,8 @@ Array layouts (the same ones the C ABI uses):
 
 from __future__ import annotations
 
+import ctypes
+import os
 from dataclasses import dataclass, field
 from typing import Optional, Sequence
 
@@ -363,17 +371,46 @@ def objective(u, q, amp, amp_ref, geom: Geometry, functional: str = "amplitude")
     return F + reference_term(q, amp_ref, geom.fresnel0, functional)[0]
 
 
+def _angle_terms(psi, k, Q, amp_k, geom: Geometry, functional: str = "amplitude"):
+    """The frame stage of one angle k, given psi_k: forward to v_kj, residual
+    r_kj (Eq. 11), w_kj = D_{-rho}(r_kj) (D* = D_{-z}), probe part
+    conj(phi_kj) w_kj (display after Eq. 11), object part
+    B^T(conj(Q_j) w_kj) (L* of Eq. 11).
+
+    Returns (F_k, g_psi_k, G_k, gq_k): G_k[j] = conj(phi_kj) w_kj when there
+    are no probe shifts (summed over k and propagated back by the caller),
+    else None and gq_k = sum_j S^T D_{-rho_probe_j}(conj(phi_kj) w_kj)."""
+    rho_d, rho_p = distances(geom.m0, geom.mag_rel)
+    F = 0.0
+    g_psi = np.zeros_like(psi)
+    G = [] if geom.probe_shift is None else None
+    gq = None if geom.probe_shift is None else np.zeros((geom.H, geom.W), np.complex128)
+    for j in range(geom.n_dist):
+        ty, tx = geom.t(k, j)
+        phi = transmit(psi, geom.mag_rel[j], ty, tx)
+        v = propagate(Q[j] * phi, rho_d[j], geom.fresnel0)
+        Fk, r = RESIDUALS[functional](v, amp_k[j])
+        F += Fk
+        w = propagate(r, -rho_d[j], geom.fresnel0)
+        if G is not None:
+            G.append(np.conj(phi) * w)
+        else:   # Q_kj = D S q: back through D, then S^T
+            gq += probe_shift_op_T(propagate(np.conj(phi) * w, -rho_p[j], geom.fresnel0),
+                                   *geom.s(k, j))
+        g_psi += resample_T(np.conj(Q[j]) * w, geom.mag_rel[j], ty, tx)
+    return F, g_psi, G, gq
+
+
 def gradient(u, q, amp, amp_ref, geom: Geometry, with_reference=True,
              functional: str = "amplitude"):
     """F, g_u, g_q of the joint objective (F2, or F1 with
     functional="intensity").
 
-    Per angle: forward to v_kj, residual r_kj (Eq. 11), w_kj = D_{-rho}(r_kj)
-    (D* = D_{-z}), probe part conj(phi_kj) w_kj (display after Eq. 11),
-    object part B^T(conj(Q_j) w_kj) (L* of Eq. 11), chain rule through the
-    exponential and R^T (reading R5).
+    Per angle: psi_k, the frame stage `_angle_terms`, then the chain rule
+    through the exponential and R^T (reading R5); after all angles the probe
+    parts go back through D_{-rho_probe_j} and the reference term is added.
     """
-    rho_d, rho_p = distances(geom.m0, geom.mag_rel)
+    _, rho_p = distances(geom.m0, geom.mag_rel)
     Q = probes(q, geom)
     F = 0.0
     G = [np.zeros((geom.H, geom.W), np.complex128) for _ in range(geom.n_dist)]
@@ -383,20 +420,13 @@ def gradient(u, q, amp, amp_ref, geom: Geometry, with_reference=True,
         if geom.probe_shift is not None:
             Q = probe_frames(q, geom, k)
         psi = transmittance(u, geom.theta[k], geom.kappa)
-        g_psi = np.zeros_like(psi)
-        for j in range(geom.n_dist):
-            ty, tx = geom.t(k, j)
-            phi = transmit(psi, geom.mag_rel[j], ty, tx)
-            v = propagate(Q[j] * phi, rho_d[j], geom.fresnel0)
-            Fk, r = RESIDUALS[functional](v, amp[k, j])
-            F += Fk
-            w = propagate(r, -rho_d[j], geom.fresnel0)
-            if geom.probe_shift is None:
-                G[j] += np.conj(phi) * w
-            else:   # Q_kj = D S q: back through D, then S^T
-                g_q += probe_shift_op_T(propagate(np.conj(phi) * w, -rho_p[j], geom.fresnel0),
-                                        *geom.s(k, j))
-            g_psi += resample_T(np.conj(Q[j]) * w, geom.mag_rel[j], ty, tx)
+        Fk, g_psi, Gk, gqk = _angle_terms(psi, k, Q, amp[k], geom, functional)
+        F += Fk
+        if Gk is not None:
+            for j in range(geom.n_dist):
+                G[j] += Gk[j]
+        else:
+            g_q += gqk
         h = -1j * geom.kappa * np.conj(psi) * g_psi
         g_u += radon_T(h, geom.theta[k], geom.W)
     g_q = g_q + sum(propagate(G[j], -rho_p[j], geom.fresnel0) for j in range(geom.n_dist))
@@ -634,3 +664,134 @@ def rel_err(x, ref) -> float:
     if den == 0.0:
         return float(num)
     return float(num / den)
+
+
+def max_rel_err(x, ref) -> float:
+    """max |x - ref| / max |ref| over all elements, in float64 (0 if both
+    are zero): a wrong value where |ref| is small, which the L2 metric can
+    hide, shows here."""
+    x = np.asarray(x, dtype=np.complex128)
+    ref = np.asarray(ref, dtype=np.complex128)
+    den = float(np.max(np.abs(ref))) if ref.size else 0.0
+    num = float(np.max(np.abs(x - ref))) if ref.size else 0.0
+    if den == 0.0:
+        return num
+    return num / den
+
+
+# ---------------------------------------------------------------------------
+# Problems too large for the NumPy ray sums (hundreds of angles, 256^3 to
+# 1024^3 volumes): the same Joseph sums and transpose from oracle/joseph.c
+# (plain C loops in double precision, slices in parallel), and the frame
+# stage of several angles at once on a thread pool (NumPy's FFTs and
+# products release the interpreter lock).  Same definitions, same steps.
+# ---------------------------------------------------------------------------
+
+_JOSEPH_LIB = None
+JOSEPH_SO = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libjoseph_oracle.so")
+
+
+def _joseph():
+    global _JOSEPH_LIB
+    if _JOSEPH_LIB is None:
+        if not os.path.exists(JOSEPH_SO):
+            raise RuntimeError("oracle/libjoseph_oracle.so is not built (oracle/build_oracle.py)")
+        L = ctypes.CDLL(JOSEPH_SO)
+        P, I = ctypes.c_void_p, ctypes.c_int
+        L.joseph_radon.argtypes = [P, I, I, P, I, I, I, P]
+        L.joseph_radon_T.argtypes = [P, I, P, I, I, P]
+        L.joseph_radon.restype = L.joseph_radon_T.restype = I
+        _JOSEPH_LIB = L
+    return _JOSEPH_LIB
+
+
+def radon_set(u, thetas, z0: int = 0, nz: Optional[int] = None) -> np.ndarray:
+    """p[k, z, i] = (R_{theta_k} u)[z0 + z, i] -- `radon` at every angle of
+    `thetas` for the slices z0 .. z0 + nz - 1, computed by joseph.c.
+
+    u is (H, W, W); it is read as complex64 (the inputs of the comparisons
+    are single-precision values), every sum is formed in double."""
+    u = np.ascontiguousarray(u, dtype=np.complex64)
+    H, W, _ = u.shape
+    nz = H - z0 if nz is None else nz
+    th = np.ascontiguousarray(thetas, dtype=np.float64).ravel()
+    p = np.empty((len(th), nz, W), np.complex128)
+    rc = _joseph().joseph_radon(u.ctypes.data, H, W, th.ctypes.data, len(th), z0, nz,
+                                p.ctypes.data)
+    if rc != 0:
+        raise RuntimeError("joseph_radon failed (%d)" % rc)
+    return p
+
+
+def radon_T_set(h, thetas, W: int) -> np.ndarray:
+    """sum_k R_{theta_k}^T h[k] -- `radon_T` of every angle, summed, for the
+    nz slices of h (n, nz, W); returns (nz, W, W) complex128."""
+    h = np.ascontiguousarray(h, dtype=np.complex128)
+    n, nz, W2 = h.shape
+    assert W2 == W
+    th = np.ascontiguousarray(thetas, dtype=np.float64).ravel()
+    assert len(th) == n
+    g = np.empty((nz, W, W), np.complex128)
+    rc = _joseph().joseph_radon_T(h.ctypes.data, W, th.ctypes.data, n, nz, g.ctypes.data)
+    if rc != 0:
+        raise RuntimeError("joseph_radon_T failed (%d)" % rc)
+    return g
+
+
+def _pool_map(fn, items, threads):
+    from concurrent.futures import ThreadPoolExecutor
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1), ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(fn, items))
+
+
+def forward_many(u, q, geom: Geometry, threads: int = 8) -> np.ndarray:
+    """`forward` for all angles: ray sums from joseph.c, then the frames of
+    each angle (psi_k, phi_kj = M S psi_k, v_kj = D_{rho_det_j}(Q_j phi_kj))."""
+    rho_d, _ = distances(geom.m0, geom.mag_rel)
+    p = radon_set(u, geom.theta)
+
+    def one(k):
+        Q = probe_frames(q, geom, k) if geom.probe_shift is not None else probes(q, geom)
+        psi = np.exp(1j * geom.kappa * p[k])
+        return np.stack([propagate(Q[j] * transmit(psi, geom.mag_rel[j], *geom.t(k, j)),
+                                   rho_d[j], geom.fresnel0) for j in range(geom.n_dist)])
+
+    return np.stack(_pool_map(one, range(geom.n_angles), threads))
+
+
+def gradient_projection_domain(u, q, amp, amp_ref, geom: Geometry, threads: int = 8,
+                               functional: str = "amplitude"):
+    """`gradient` up to its last step: returns (F, h, g_q) with
+    h[k] = -i kappa conj(psi_k) g_psi_k, so that g_u = sum_k R_k^T h[k]
+    (`radon_T_set(h, geom.theta, W)`, slab by slab for large volumes).
+
+    The ray sums come from joseph.c; the frame stage `_angle_terms` of each
+    angle runs on a thread pool; F and the probe parts are summed in angle
+    order."""
+    _, rho_p = distances(geom.m0, geom.mag_rel)
+    p = radon_set(u, geom.theta)
+    Q0 = probes(q, geom)
+
+    def one(k):
+        Q = probe_frames(q, geom, k) if geom.probe_shift is not None else Q0
+        psi = np.exp(1j * geom.kappa * p[k])
+        Fk, g_psi, Gk, gqk = _angle_terms(psi, k, Q, amp[k], geom, functional)
+        p[k] = -1j * geom.kappa * np.conj(psi) * g_psi      # h_k replaces p_k
+        return Fk, Gk, gqk
+
+    F = 0.0
+    G = [np.zeros((geom.H, geom.W), np.complex128) for _ in range(geom.n_dist)]
+    g_q = np.zeros((geom.H, geom.W), np.complex128)
+    batch = max(1, threads)
+    for k0 in range(0, geom.n_angles, batch):
+        for Fk, Gk, gqk in _pool_map(one, range(k0, min(k0 + batch, geom.n_angles)), threads):
+            F += Fk
+            if Gk is not None:
+                for j in range(geom.n_dist):
+                    G[j] += Gk[j]
+            else:
+                g_q += gqk
+    g_q = g_q + sum(propagate(G[j], -rho_p[j], geom.fresnel0) for j in range(geom.n_dist))
+    Fr, gr = reference_term(q, amp_ref, geom.fresnel0, functional)
+    return F + Fr, p, g_q + gr

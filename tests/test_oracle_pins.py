@@ -138,31 +138,55 @@ def footprint_radon(u, theta):
     return p
 
 
+def _radon_c(u, theta):
+    return O.radon_set(np.asarray(u, np.complex64), [theta])[0]
+
+
+def _radon_T_c(p, theta, W):
+    return O.radon_T_set(np.asarray(p)[None], [theta], W)
+
+
+# The NumPy loops and the C loops of joseph.c (used for the large checks)
+# are held to the same pins; inputs are complex64 values (what joseph.c
+# reads), widened.
+RADON = {"numpy": (O.radon, O.radon_T), "c": (_radon_c, _radon_T_c)}
+
+
+def c64_values(x):
+    return np.asarray(x).astype(np.complex64).astype(np.complex128)
+
+
+@pytest.mark.parametrize("impl", sorted(RADON))
 @pytest.mark.parametrize("theta", [0.0, 0.3, math.pi / 4, 1.1, 2.0, 2.9])
-def test_radon_matches_brute_force_footprint(theta):
+def test_radon_matches_brute_force_footprint(theta, impl):
+    radon, _ = RADON[impl]
     rng = np.random.default_rng(3)
-    u = crandn(rng, 3, 12, 12)
-    np.testing.assert_allclose(O.radon(u, theta), footprint_radon(u, theta), atol=1e-12)
+    u = c64_values(crandn(rng, 3, 12, 12))
+    np.testing.assert_allclose(radon(u, theta), footprint_radon(u, theta), atol=1e-12)
 
 
-def test_radon_axis_sums():
+@pytest.mark.parametrize("impl", sorted(RADON))
+def test_radon_axis_sums(impl):
+    radon, _ = RADON[impl]
     rng = np.random.default_rng(4)
-    u = crandn(rng, 5, 16, 16)
+    u = c64_values(crandn(rng, 5, 16, 16))
     # theta = 0: bins along x, rays along y
-    np.testing.assert_allclose(O.radon(u, 0.0), u.sum(axis=1), atol=1e-12)
+    np.testing.assert_allclose(radon(u, 0.0), u.sum(axis=1), atol=1e-12)
     # theta = pi/2: bins along y, rays along x
-    np.testing.assert_allclose(O.radon(u, math.pi / 2), u.sum(axis=2), atol=1e-12)
+    np.testing.assert_allclose(radon(u, math.pi / 2), u.sum(axis=2), atol=1e-12)
 
 
-def test_radon_point_voxel_lands_on_its_projection():
+@pytest.mark.parametrize("impl", sorted(RADON))
+def test_radon_point_voxel_lands_on_its_projection(impl):
     # A single voxel at (x, y) = (5, -7) lands on the two bins around
     # s = x cos + y sin, the nearer one taking the larger weight.
+    radon, _ = RADON[impl]
     W = 32
     u = np.zeros((1, W, W))
     ix, iy = 21, 9
     u[0, iy, ix] = 1.0
     for theta in (0.2, 0.9, 1.7, 2.6):
-        p = O.radon(u, theta)[0].real
+        p = radon(u, theta)[0].real
         s = (ix - W / 2) * math.cos(theta) + (iy - W / 2) * math.sin(theta)
         f = W / 2 + s
         lo = int(math.floor(f))
@@ -172,9 +196,11 @@ def test_radon_point_voxel_lands_on_its_projection():
         assert p[near] >= p[far]
 
 
-def test_radon_uniform_ball_chords():
+@pytest.mark.parametrize("impl", sorted(RADON))
+def test_radon_uniform_ball_chords(impl):
     # A centred ball of radius r: every ray at offset s through slice z
     # crosses 2 sqrt(r^2 - s^2 - z^2) voxels, at every angle.
+    radon, _ = RADON[impl]
     W, H, r = 96, 9, 40.0
     z = np.arange(H)[:, None, None] - H / 2
     y = np.arange(W)[None, :, None] - W / 2
@@ -182,7 +208,7 @@ def test_radon_uniform_ball_chords():
     u = ((x ** 2 + y ** 2 + (z * 4.0) ** 2) <= r * r).astype(float)
     s = np.arange(W) - W / 2
     for theta in (0.0, 0.35, math.pi / 4, 1.3, 2.2):
-        p = O.radon(u, theta)
+        p = radon(u, theta)
         for iz in range(H):
             zz = (iz - H / 2) * 4.0
             chord = 2 * np.sqrt(np.maximum(r * r - s ** 2 - zz ** 2, 0.0))
@@ -194,14 +220,31 @@ def test_radon_uniform_ball_chords():
             assert np.mean(err[inner] / chord[inner]) <= 0.02
 
 
+@pytest.mark.parametrize("impl", sorted(RADON))
 @pytest.mark.parametrize("theta", [0.1, math.pi / 4, math.pi / 2, 1.9, 3.0])
-def test_radon_adjoint(theta):
+def test_radon_adjoint(theta, impl):
+    radon, radon_T = RADON[impl]
     rng = np.random.default_rng(5)
-    u = crandn(rng, 4, 20, 20)
+    u = c64_values(crandn(rng, 4, 20, 20))
     p = crandn(rng, 4, 20)
-    lhs = np.vdot(p, O.radon(u, theta))
-    rhs = np.vdot(O.radon_T(p, theta, 20), u)
+    lhs = np.vdot(p, radon(u, theta))
+    rhs = np.vdot(radon_T(p, theta, 20), u)
     assert abs(lhs - rhs) < 1e-11 * abs(lhs)
+
+
+def test_radon_set_sums_angles_and_slabs():
+    # the many-angle C entry points: slab offsets select the right slices and
+    # the transpose sums over the angles
+    rng = np.random.default_rng(6)
+    th = [0.2, 1.0, 2.5]
+    u = c64_values(crandn(rng, 6, 16, 16))
+    p = O.radon_set(u, th, z0=2, nz=3)
+    for k, t in enumerate(th):
+        np.testing.assert_allclose(p[k], footprint_radon(u[2:5], t), atol=1e-12)
+    h = crandn(rng, 3, 6, 16)
+    g = O.radon_T_set(h, th, 16)
+    lhs = sum(np.vdot(h[k], footprint_radon(u, th[k])) for k in range(3))
+    assert abs(np.vdot(g, u) - lhs) < 1e-11 * abs(lhs)
 
 
 # ---------------------------------------------------------------------------
@@ -662,3 +705,86 @@ def test_probe_shifts_central_differences_and_zero_shift():
     _, gu2, gq2 = O.gradient(u, q, amp, amp_ref, gs, with_reference=False)
     np.testing.assert_allclose(au, gu2, atol=1e-12 * np.abs(gu2).max())
     np.testing.assert_allclose(aq, gq2, atol=1e-12 * np.abs(gq2).max())
+
+
+# ---------------------------------------------------------------------------
+# The single-angle forward model and the error metrics of the parity tests
+# ---------------------------------------------------------------------------
+
+def test_holo2d_forward_is_the_joint_forward_at_one_angle():
+    # Eq. (8) with one projection: the batched single-angle model fed the
+    # transmittance exp(i kappa R u) of an angle is the joint model's forward
+    # field of that angle (no shifts: the single-angle problems have none).
+    geom, u, q, _, _ = tiny_problem(seed=21, n_angles=3, shifts=False)
+    v = O.forward(u, q, geom)
+    for k in range(3):
+        psi = O.transmittance(u, geom.theta[k], geom.kappa)
+        v2 = O.holo2d_forward(psi, q, geom.mag_rel, geom.m0, geom.fresnel0)
+        np.testing.assert_allclose(v2, v[k], atol=1e-12 * np.max(np.abs(v[k])))
+    # and with psi = 1 (no object) every plane holds the propagated probe D_1 q
+    v1 = O.holo2d_forward(np.ones((geom.H, geom.W), complex), q, geom.mag_rel, geom.m0,
+                          geom.fresnel0)
+    ref = O.propagate(q, 1.0, geom.fresnel0)
+    for j in range(4):
+        np.testing.assert_allclose(v1[j], ref, atol=1e-12)
+
+
+def test_error_metrics_on_hand_computed_cases():
+    # rel_err = ||x - ref||_2 / ||ref||_2: ref = (3, 4i) has norm 5, the
+    # difference (2, -i) has norm sqrt 5 (and x itself norm sqrt 34, so a
+    # metric normalised by x instead of ref fails)
+    ref = np.array([3.0, 4.0j])
+    x = np.array([5.0, 3.0j])
+    assert O.rel_err(x, ref) == pytest.approx(math.sqrt(5.0) / 5.0, rel=1e-15)
+    assert O.rel_err(ref, ref) == 0.0
+    # both zero: 0; ref zero: the absolute norm of x
+    assert O.rel_err(np.zeros(3), np.zeros(3)) == 0.0
+    assert O.rel_err(np.array([3.0, 4.0]), np.zeros(2)) == pytest.approx(5.0)
+    # float32 inputs are compared in float64 (no rounding of the difference)
+    a = np.array([1.0, 1.0 + 2.0 ** -20], np.float32)
+    b = np.array([1.0, 1.0], np.float64)
+    assert O.rel_err(a, b) == pytest.approx(2.0 ** -20 / math.sqrt(2.0), rel=1e-12)
+    # max_rel_err = max |x - ref| / max |ref|: one wrong small element that
+    # the L2 metric dilutes over many large ones
+    ref = np.full(10000, 1.0 + 0j)
+    ref[7] = 1e-3
+    x = ref.copy()
+    x[7] = 2e-3 + 1e-3j
+    assert O.max_rel_err(x, ref) == pytest.approx(math.sqrt(2.0) * 1e-3, rel=1e-12)
+    assert O.rel_err(x, ref) == pytest.approx(math.sqrt(2.0) * 1e-3 / math.sqrt(9999 + 1e-6),
+                                              rel=1e-9)
+    assert O.max_rel_err(np.zeros(4), np.zeros(4)) == 0.0
+
+
+# ---------------------------------------------------------------------------
+# The large-problem path (C ray sums, threaded frame stage) computes the
+# same objective and gradients as the plain loops
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("functional", ["amplitude", "intensity"])
+@pytest.mark.parametrize("shifts", [False, True])
+def test_projection_domain_gradient_equals_the_plain_loops(shifts, functional):
+    geom, u, q, amp, amp_ref = tiny_problem(seed=23, shifts=shifts)
+    u = c64_values(u)           # what joseph.c reads
+    if functional == "intensity":
+        amp, amp_ref = amp ** 2, amp_ref ** 2
+    F, gu, gq = O.gradient(u, q, amp, amp_ref, geom, functional=functional)
+    F2, h, gq2 = O.gradient_projection_domain(u, q, amp, amp_ref, geom, threads=3,
+                                              functional=functional)
+    gu2 = O.radon_T_set(h, geom.theta, geom.W)
+    assert F2 == pytest.approx(F, rel=1e-12)
+    assert O.rel_err(gu2, gu) < 1e-12 and O.rel_err(gq2, gq) < 1e-12
+    v = O.forward(u, q, geom)
+    assert O.rel_err(O.forward_many(u, q, geom, threads=2), v) < 1e-13
+
+
+def test_projection_domain_gradient_with_probe_shifts():
+    geom, u, q, amp, amp_ref = tiny_problem(seed=24, shifts=True)
+    u = c64_values(u)
+    rng = np.random.default_rng(25)
+    geom.probe_shift = rng.uniform(-2.0, 2.0, (geom.n_angles, geom.n_dist, 2))
+    F, gu, gq = O.gradient(u, q, amp, amp_ref, geom)
+    F2, h, gq2 = O.gradient_projection_domain(u, q, amp, amp_ref, geom, threads=2)
+    assert F2 == pytest.approx(F, rel=1e-12)
+    assert O.rel_err(O.radon_T_set(h, geom.theta, geom.W), gu) < 1e-12
+    assert O.rel_err(gq2, gq) < 1e-12
