@@ -329,6 +329,17 @@ holo_status holo_timing_enable(holo_plan* plan, int32_t on);
 holo_status holo_timing_read(holo_plan* plan, int32_t kernel_class,
                              double* total_ms, int64_t* launches);
 
+/* The angle groups of the forward ray sums (diagnostics): consecutive
+ * angles of one walk direction, at most 4, never crossing a chunk, whose
+ * rays share one staged column window per (block of 16 bins, row); the
+ * plan forms them so that every tap of every row lies at least one column
+ * inside its window.  Writes *n_groups and, for i < min(capacity,
+ * *n_groups), the first angle and the angle count of group i.  Errors:
+ * INVALID_ARGUMENT (NULL plan or n_groups; NULL first or count with
+ * capacity > 0).  Host-only. */
+holo_status holo_plan_ray_groups(const holo_plan* plan, int32_t* first, int32_t* count,
+                                 int32_t capacity, int32_t* n_groups);
+
 /* Message describing the last non-OK status returned on this thread. */
 const char* holo_last_error(void);
 

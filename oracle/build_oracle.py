@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libjoseph_oracle.so")
 
 def build(verbose=True):
     tmp = LIB + ".tmp"
-    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-Wall", "-Wextra",
+    cmd = ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-Wall", "-Wextra",
            "-o", tmp, SRC, "-lm"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

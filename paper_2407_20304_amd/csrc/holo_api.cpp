@@ -103,11 +103,16 @@ static void build_twiddles(std::vector<float2>& out, int n) {
 static bool is_finite(double x) { return std::isfinite(x); }
 
 // Can angles [a, b) share the staged row windows of the forward ray sums?
-// The window of a (bin block, row) must span at most kFwdSeg - 4 columns
-// between the lowest and highest tap (the kernel adds one column of margin
-// below and reads one tap to the right; the rest covers rounding).  Tap
-// positions are affine in bin and row, so the extremes sit at the block's
-// end bins and at the first and last row.
+// For each (bin block, row) the window starts one column below the lowest
+// tap, floor(mn) - 1.  Tap positions are affine in bin and row, so over the
+// group's angles and the block's end bins the highest tap mx is convex in
+// the row and the lowest mn concave: their span mx - mn is largest at the
+// first or the last row.  A span of at most kFwdSeg - 4 there keeps every
+// tap of every row below column kFwdSeg - 2 of its window
+// (mx - floor(mn) + 1 < kFwdSeg - 2): the tap and its right neighbour stay
+// inside the staged kFwdSeg columns, and the kernel's clamp of the tap base
+// (to at most kFwdSeg - 1.01 for the highest tap) only ever acts on windows
+// moved into the zero padding.
 static bool fwd_group_fits(const holo_plan* P, int a, int b) {
   const int W = P->W;
   for (int sb = 0; sb < W; sb += kFwdNB) {
@@ -121,7 +126,7 @@ static bool fwd_group_fits(const holo_plan* P, int a, int b) {
           mx = std::fmax(mx, f);
         }
       }
-      if (std::floor(mx) - std::floor(mn) > kFwdSeg - 4) return false;
+      if (mx - mn > (double)(kFwdSeg - 4)) return false;
     }
   }
   return true;
@@ -908,6 +913,21 @@ extern "C" holo_status holo_plan_autotune(holo_plan* P, const holo_c64* u, const
   layout_workspace(P);
   if (s == HOLO_OK) *best_chunk = best;
   return s;
+}
+
+extern "C" holo_status holo_plan_ray_groups(const holo_plan* P, int32_t* first, int32_t* count,
+                                            int32_t capacity, int32_t* n_groups) {
+  if (!P || !n_groups)
+    return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_ray_groups: plan or n_groups is NULL");
+  *n_groups = (int32_t)P->groups.size();
+  if (capacity > 0 && (!first || !count))
+    return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_ray_groups: first or count is NULL");
+  const int n = std::min<int>(capacity, (int)P->groups.size());
+  for (int i = 0; i < n; ++i) {
+    first[i] = P->groups[i].x;
+    count[i] = P->groups[i].y;
+  }
+  return HOLO_OK;
 }
 
 extern "C" holo_status holo_plan_set_functional(holo_plan* P, int32_t functional) {

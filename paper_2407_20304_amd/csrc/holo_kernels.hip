@@ -703,12 +703,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
   const double B = aw[kB], D = aw[kD];
   const double fA = aw[kA] + (double)s0 * B;
   const float Bf = (float)B;
-  // Range of the per-row base that keeps every tap of the thread's bins
-  // inside the staged window.  Inside the volume the host's grouping already
-  // guarantees it (so the clamp changes nothing there); a window moved into
-  // the zero padding reads zeros wherever the taps land.
+  // Range of the per-row base that keeps every tap of the thread's bins and
+  // its right neighbour inside the staged window.  Inside the volume the
+  // host's grouping keeps every tap below column SEG - 2, so the clamp
+  // changes nothing there; a window moved into the zero padding reads zeros
+  // wherever the taps land.
   const float span = (float)(BPT - 1) * Bf;
-  const float rel_lo = fmaxf(0.0f, -span), rel_hi = (float)(SEG - 2) - fmaxf(0.0f, span) - 0.01f;
+  const float rel_lo = fmaxf(0.0f, -span), rel_hi = (float)(SEG - 1) - fmaxf(0.0f, span) - 0.01f;
 
   // window start of every row: lowest tap over the group's angles and the
   // block's end bins, minus one column of margin for rounding
@@ -786,7 +787,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
       constexpr int LA = 2;
       float4 v[BPT][2];
       auto fetch_bin = [&](int b) {
-        const float q = fmaf((float)b, Bf, rel);          // >= 0, < SEG - 2
+        const float q = fmaf((float)b, Bf, rel);          // >= 0, < SEG - 1
         const float2* tp = tr + (int)q * ZT;             // truncation = floor here
 #pragma unroll
         for (int m = 0; m < 2; ++m) {

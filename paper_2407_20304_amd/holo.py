@@ -29,7 +29,7 @@ EXPORTS = (
     "holo_bin_frames", "holo_upsample_frames", "holo_upsample_volume",
     "holo2d_plan_create", "holo2d_plan_destroy", "holo2d_offsets", "holo2d_workspace_bytes",
     "holo2d_plan_set_functional", "holo2d_fwd", "holo2d_objective", "holo2d_grad",
-    "holo_timing_enable", "holo_timing_read", "holo_last_error",
+    "holo_timing_enable", "holo_timing_read", "holo_plan_ray_groups", "holo_last_error",
 )
 
 KERNEL_CLASSES = ("radon_fwd", "radon_adj", "pass_a", "pass_b", "pass_c", "pass_d", "probe",
@@ -98,6 +98,7 @@ def lib():
     L.holo2d_grad.argtypes = [P, P, P, P, P, P, P, P, P, c_size_t, P]
     L.holo_timing_enable.argtypes = [P, c_int32]
     L.holo_timing_read.argtypes = [P, c_int32, POINTER(c_double), POINTER(ctypes.c_int64)]
+    L.holo_plan_ray_groups.argtypes = [P, P, P, c_int32, POINTER(c_int32)]
     for name in EXPORTS[:-1]:
         getattr(L, name).restype = c_int32
     L.holo_last_error.restype = c_char_p
@@ -446,6 +447,15 @@ class Plan:
             _check(lib().holo_timing_read(self._h, i, ctypes.byref(ms), ctypes.byref(n)))
             out[name] = (ms.value, int(n.value))
         return out
+
+    def ray_groups(self):
+        """[(first angle, count)] of the forward ray sums' angle groups."""
+        n = c_int32()
+        _check(lib().holo_plan_ray_groups(self._h, None, None, 0, ctypes.byref(n)))
+        first = (c_int32 * max(n.value, 1))()
+        count = (c_int32 * max(n.value, 1))()
+        _check(lib().holo_plan_ray_groups(self._h, first, count, n.value, ctypes.byref(n)))
+        return [(int(first[i]), int(count[i])) for i in range(n.value)]
 
     def _check_data(self, u, q, amp, amp_ref):
         import torch

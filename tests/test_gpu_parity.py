@@ -1,7 +1,9 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
-Tolerance: 1e-5 relative L2 error on the objective and on each gradient and
-field, the bar the single-precision path is held to."""
+Tolerance: 1e-5 relative error on the objective, and on each gradient and
+field both 1e-5 relative L2 error and 1e-5 max-abs error over the largest
+magnitude (tests/problems.py: assert_close), the bar the single-precision
+path is held to."""
 
 import sys
 
@@ -52,7 +54,7 @@ def test_zero_object_fields_are_the_propagated_probe(H, W):
     ref = O.propagate(PB.c128(q), 1.0, synth.FRESNEL0)
     for k in range(3):
         for j in range(4):
-            assert rel(v[k, j], ref) < TOL, (k, j, rel(v[k, j], ref))
+            PB.assert_close(v[k, j], ref, "v[%d,%d] %dx%d" % (k, j, H, W))
 
 
 # ---------------------------------------------------------------------------
@@ -73,7 +75,7 @@ def test_fwd_parity(small):
     plan = PB.gpu_plan(small)
     v = plan.holo_fwd(u, q, 2, 11).cpu().numpy()
     ref = O.forward(PB.c128(small.u), PB.c128(small.q), small.geom, ks=range(2, 11))
-    assert rel(v, ref) < TOL, rel(v, ref)
+    PB.assert_close(v, ref, "v")
 
 
 def test_adj_parity(small):
@@ -85,8 +87,8 @@ def test_adj_parity(small):
     w = (rng.standard_normal((7, 4, 64, 64)) + 1j * rng.standard_normal((7, 4, 64, 64))).astype(np.complex64)
     gu, gq = plan.holo_adj(u, q, torch.from_numpy(w).cuda(), 3, 10)
     ru, rq = O.adjoint(PB.c128(small.u), PB.c128(small.q), PB.c128(w), small.geom, ks=range(3, 10))
-    assert rel(gu.cpu().numpy(), ru) < TOL, rel(gu.cpu().numpy(), ru)
-    assert rel(gq.cpu().numpy(), rq) < TOL, rel(gq.cpu().numpy(), rq)
+    PB.assert_close(gu.cpu().numpy(), ru, "gu")
+    PB.assert_close(gq.cpu().numpy(), rq, "gq")
 
 
 def test_objective_and_grad_parity(small):
@@ -98,8 +100,8 @@ def test_objective_and_grad_parity(small):
     F, gu, gq = plan.holo_grad(u, q, amp, amp_ref)
     assert abs(Fo - F0) / F0 < TOL
     assert abs(F.item() - F0) / F0 < TOL
-    assert rel(gu.cpu().numpy(), gu0) < TOL, rel(gu.cpu().numpy(), gu0)
-    assert rel(gq.cpu().numpy(), gq0) < TOL, rel(gq.cpu().numpy(), gq0)
+    PB.assert_close(gu.cpu().numpy(), gu0, "gu")
+    PB.assert_close(gq.cpu().numpy(), gq0, "gq")
     # the object-only and probe-only entry points agree with the joint one
     F1, gu1 = plan.holo_grad_object(u, q, amp, amp_ref)
     F2, gq2 = plan.holo_grad_probe(u, q, amp, amp_ref)
@@ -123,8 +125,8 @@ def test_grad_parity_shapes(H, W, n, chunk, shifts):
     F0, gu0, gq0 = PB.oracle_grad(p)
     F, gu, gq = plan.holo_grad(u, q, amp, amp_ref)
     assert abs(F.item() - F0) / F0 < TOL, (F.item(), F0)
-    assert rel(gu.cpu().numpy(), gu0) < TOL, rel(gu.cpu().numpy(), gu0)
-    assert rel(gq.cpu().numpy(), gq0) < TOL, rel(gq.cpu().numpy(), gq0)
+    PB.assert_close(gu.cpu().numpy(), gu0, "gu")
+    PB.assert_close(gq.cpu().numpy(), gq0, "gq")
 
 
 def test_intensity_functional_parity(small):
@@ -144,8 +146,8 @@ def test_intensity_functional_parity(small):
     Fr, gur, gqr = O.gradient(PB.c128(small.u), PB.c128(small.q), d64, dr64, small.geom,
                               functional="intensity")
     assert abs(F.item() - Fr) / Fr < TOL and abs(Fo.item() - Fr) / Fr < TOL
-    assert rel(g_u.cpu().numpy(), gur) < TOL, rel(g_u.cpu().numpy(), gur)
-    assert rel(g_q.cpu().numpy(), gqr) < TOL, rel(g_q.cpu().numpy(), gqr)
+    PB.assert_close(g_u.cpu().numpy(), gur, "g_u")
+    PB.assert_close(g_q.cpu().numpy(), gqr, "g_q")
     # and back to the amplitude functional on the same plan
     plan.set_functional("amplitude")
     F2, _, _ = plan.holo_grad(u, q, amp, amp_ref)
@@ -168,7 +170,8 @@ def test_autotune_chunk_and_cache(small, tmp_path):
     F, g_u, g_q = plan.holo_grad(u, q, amp, amp_ref)
     Fo, guo, gqo = PB.oracle_grad(small)
     assert abs(F.item() - Fo) / Fo < TOL
-    assert rel(g_u.cpu().numpy(), guo) < TOL and rel(g_q.cpu().numpy(), gqo) < TOL
+    PB.assert_close(g_u.cpu().numpy(), guo, "g_u")
+    PB.assert_close(g_q.cpu().numpy(), gqo, "g_q")
     plan2 = PB.gpu_plan(small)
     best2, times2 = plan2.autotune(u, q, amp, amp_ref, candidates=(4, 6, 12), cache=cache)
     assert best2 == best and times2 is None and plan2.chunk == best
@@ -189,17 +192,18 @@ def test_probe_shift_parity(small):
     plan.set_probe_shifts(ps)
     v = plan.holo_fwd(u, q, 0, 4).cpu().numpy()
     vref = O.forward(PB.c128(small.u), PB.c128(small.q), gs, ks=range(4))
-    assert rel(v, vref) < TOL, rel(v, vref)
+    PB.assert_close(v, vref, "v")
     F, g_u, g_q = plan.holo_grad(u, q, amp, amp_ref)
     Fr, gur, gqr = O.gradient(PB.c128(small.u), PB.c128(small.q), small.amp.astype(np.float64),
                               small.amp_ref.astype(np.float64), gs)
     assert abs(F.item() - Fr) / Fr < TOL
-    assert rel(g_u.cpu().numpy(), gur) < TOL, rel(g_u.cpu().numpy(), gur)
-    assert rel(g_q.cpu().numpy(), gqr) < TOL, rel(g_q.cpu().numpy(), gqr)
+    PB.assert_close(g_u.cpu().numpy(), gur, "g_u")
+    PB.assert_close(g_q.cpu().numpy(), gqr, "g_q")
     plan.set_probe_shifts(None)
     F0, gu0, gq0 = plan.holo_grad(u, q, amp, amp_ref)
     Fo, guo, gqo = PB.oracle_grad(small)
-    assert abs(F0.item() - Fo) / Fo < TOL and rel(gq0.cpu().numpy(), gqo) < TOL
+    assert abs(F0.item() - Fo) / Fo < TOL
+    PB.assert_close(gq0.cpu().numpy(), gqo, "g_q without probe shifts")
 
 
 def test_repeat_calls_are_bitwise_identical(small):
@@ -225,7 +229,7 @@ def test_fwd_parity_fine_angles_across_walk_switch():
     v = plan.holo_fwd(u, q).cpu().numpy()
     ref = O.forward(PB.c128(p.u), PB.c128(p.q), p.geom)
     for k in range(len(deg)):
-        assert rel(v[k], ref[k]) < TOL, (deg[k], rel(v[k], ref[k]))
+        PB.assert_close(v[k], ref[k], "v at %.1f deg" % deg[k])
 
 
 def test_dense_volume_with_poisoned_workspace():
@@ -247,10 +251,10 @@ def test_dense_volume_with_poisoned_workspace():
     v = plan.holo_fwd(u, q).cpu().numpy()
     ref = O.forward(PB.c128(u_np), PB.c128(p.q), p.geom)
     for k in range(len(deg)):
-        assert rel(v[k], ref[k]) < TOL, (deg[k], rel(v[k], ref[k]))
+        PB.assert_close(v[k], ref[k], "v at %.1f deg" % deg[k])
     w = (rng.standard_normal(v.shape) + 1j * rng.standard_normal(v.shape)).astype(np.complex64)
     plan.workspace(u.device).fill_(255)
     gu, gq = plan.holo_adj(u, q, torch.from_numpy(w).cuda())
     ru, rq = O.adjoint(PB.c128(u_np), PB.c128(p.q), PB.c128(w), p.geom)
-    assert rel(gu.cpu().numpy(), ru) < TOL, rel(gu.cpu().numpy(), ru)
-    assert rel(gq.cpu().numpy(), rq) < TOL, rel(gq.cpu().numpy(), rq)
+    PB.assert_close(gu.cpu().numpy(), ru, "gu")
+    PB.assert_close(gq.cpu().numpy(), rq, "gq")
