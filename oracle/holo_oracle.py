@@ -761,16 +761,19 @@ def forward_many(u, q, geom: Geometry, threads: int = 8) -> np.ndarray:
 
 
 def gradient_projection_domain(u, q, amp, amp_ref, geom: Geometry, threads: int = 8,
-                               functional: str = "amplitude"):
+                               functional: str = "amplitude", progress=None):
     """`gradient` up to its last step: returns (F, h, g_q) with
     h[k] = -i kappa conj(psi_k) g_psi_k, so that g_u = sum_k R_k^T h[k]
     (`radon_T_set(h, geom.theta, W)`, slab by slab for large volumes).
 
     The ray sums come from joseph.c; the frame stage `_angle_terms` of each
     angle runs on a thread pool; F and the probe parts are summed in angle
-    order."""
+    order.  `progress(message)`, if given, is called after the ray sums and
+    after each batch of angles."""
     _, rho_p = distances(geom.m0, geom.mag_rel)
     p = radon_set(u, geom.theta)
+    if progress:
+        progress("ray sums of %d angles done" % geom.n_angles)
     Q0 = probes(q, geom)
 
     def one(k):
@@ -792,6 +795,8 @@ def gradient_projection_domain(u, q, amp, amp_ref, geom: Geometry, threads: int 
                     G[j] += Gk[j]
             else:
                 g_q += gqk
+        if progress:
+            progress("frames of angles %d-%d done" % (k0, min(k0 + batch, geom.n_angles) - 1))
     g_q = g_q + sum(propagate(G[j], -rho_p[j], geom.fresnel0) for j in range(geom.n_dist))
     Fr, gr = reference_term(q, amp_ref, geom.fresnel0, functional)
     return F + Fr, p, g_q + gr

@@ -123,8 +123,9 @@ def strided_subset_parity(name):
     geom = O.Geometry(H=wl.H, W=wl.W, theta=theta, mag_rel=wl.mag_rel, m0=wl.m0,
                       fresnel0=wl.fresnel0, kappa=wl.kappa)
     t = time.time()
-    F0, h, gq0 = O.gradient_projection_domain(u_np, q_np.astype(np.complex128), amp_np,
-                                              amp_ref_np, geom, threads=PB.oracle_threads())
+    F0, h, gq0 = O.gradient_projection_domain(
+        u_np, q_np.astype(np.complex128), amp_np, amp_ref_np, geom, threads=PB.oracle_threads(),
+        progress=lambda m: say("  oracle: %s (%.1f s)" % (m, time.time() - t)))
     say("  oracle forward + frames %.1f s" % (time.time() - t))
     del u_np
     PB.assert_close_scalar(F, F0)
