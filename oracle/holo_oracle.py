@@ -471,6 +471,70 @@ def adjoint(u, q, w_frames, geom: Geometry, ks=None):
 
 
 # ---------------------------------------------------------------------------
+# The conventional functional with division by the reference image (Sec. 3,
+# Eq. 16): no probe, one independent functional per projection
+# ---------------------------------------------------------------------------
+#
+# Reading F1 (flat field): Eq. 16 compares |D(S psi_k)|^2 with the square
+# root of the flat-field-corrected data; amplitudes are taken on both sides
+# (the data are square roots, as in F2).  The plane-j field is the model of
+# Eq. 8 with q = 1 -- the paper's own remark that q = 1 turns its cone-beam
+# model into the conventional one -- so psi is demagnified and shifted per
+# plane exactly as in the joint model, and the data a_kj = sqrt(d_kj / d^r)
+# are given on the computational grid (their rescaling is preprocessing, as
+# R6).  There is no probe and no reference term.
+
+def conventional_objective(u, amp, geom: Geometry) -> float:
+    """sum_k sum_j || |D_{rho'_j}(M_j S_{t_kj} psi_k)| - a_kj ||^2 with
+    psi_k = exp(i kappa R_k u)."""
+    rho_d, _ = distances(geom.m0, geom.mag_rel)
+    F = 0.0
+    for k in range(geom.n_angles):
+        psi = transmittance(u, geom.theta[k], geom.kappa)
+        for j in range(geom.n_dist):
+            v = propagate(transmit(psi, geom.mag_rel[j], *geom.t(k, j)), rho_d[j], geom.fresnel0)
+            F += float(np.sum((np.abs(v) - amp[k, j]) ** 2))
+    return F
+
+
+def conventional_gradient(u, amp, geom: Geometry):
+    """F and g_u of `conventional_objective`: per plane the residual
+    r = 2(v - a v/|v|) (v/|v| := 0 at |v| = 0), back through D_{-rho'_j}
+    and the transposed resampling, then the chain rule through exp and R^T."""
+    rho_d, _ = distances(geom.m0, geom.mag_rel)
+    F = 0.0
+    g_u = np.zeros(u.shape, np.complex128)
+    for k in range(geom.n_angles):
+        psi = transmittance(u, geom.theta[k], geom.kappa)
+        g_psi = np.zeros_like(psi)
+        for j in range(geom.n_dist):
+            ty, tx = geom.t(k, j)
+            v = propagate(transmit(psi, geom.mag_rel[j], ty, tx), rho_d[j], geom.fresnel0)
+            av = np.abs(v)
+            F += float(np.sum((av - amp[k, j]) ** 2))
+            unit = np.divide(v, av, out=np.zeros_like(v), where=av > 0)
+            w = propagate(2.0 * (v - amp[k, j] * unit), -rho_d[j], geom.fresnel0)
+            g_psi += resample_T(w, geom.mag_rel[j], ty, tx)
+        g_u += radon_T(-1j * geom.kappa * np.conj(psi) * g_psi, geom.theta[k], geom.W)
+    return F, g_u
+
+
+def holo2d_conventional_gradient(psi, amp, mag_rel, m0, fresnel0):
+    """Eq. 16 for one projection with psi the unknown: F and g_psi."""
+    rho_d, _ = distances(m0, mag_rel)
+    F = 0.0
+    g_psi = np.zeros(psi.shape, np.complex128)
+    for j in range(len(mag_rel)):
+        v = propagate(transmit(psi, mag_rel[j]), rho_d[j], fresnel0)
+        av = np.abs(v)
+        F += float(np.sum((av - amp[j]) ** 2))
+        unit = np.divide(v, av, out=np.zeros_like(v), where=av > 0)
+        w = propagate(2.0 * (v - amp[j] * unit), -rho_d[j], fresnel0)
+        g_psi += resample_T(w, mag_rel[j])
+    return F, g_psi
+
+
+# ---------------------------------------------------------------------------
 # Single-angle multi-distance retrieval (psi is the unknown; Eq. 10, N_theta=1)
 # ---------------------------------------------------------------------------
 

@@ -788,3 +788,82 @@ def test_projection_domain_gradient_with_probe_shifts():
     assert F2 == pytest.approx(F, rel=1e-12)
     assert O.rel_err(O.radon_T_set(h, geom.theta, geom.W), gu) < 1e-12
     assert O.rel_err(gq2, gq) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# The conventional functional with division by the reference (Eq. 16)
+# ---------------------------------------------------------------------------
+
+def test_conventional_functional_central_differences():
+    geom, u, _, amp, _ = tiny_problem(seed=31)
+    F, gu = O.conventional_gradient(u, amp, geom)
+    assert F == pytest.approx(O.conventional_objective(u, amp, geom), rel=1e-12)
+    rng = np.random.default_rng(32)
+    for trial in range(4):
+        du = 1e-4 * crandn(rng, *u.shape)
+        eps = 1e-3
+        fd = (O.conventional_objective(u + eps * du, amp, geom)
+              - O.conventional_objective(u - eps * du, amp, geom)) / (2 * eps)
+        assert np.real(np.vdot(gu, du)) == pytest.approx(fd, rel=1e-6, abs=1e-9 * abs(F))
+
+
+def test_conventional_functional_is_the_joint_model_with_unit_probe():
+    # the paper's remark: q = 1 turns the cone-beam model with probe into the
+    # conventional one; the conventional functional has no reference term
+    geom, u, _, amp, amp_ref = tiny_problem(seed=33)
+    ones = np.ones((geom.H, geom.W), complex)
+    F, gu = O.conventional_gradient(u, amp, geom)
+    Fj, guj, _ = O.gradient(u, ones, amp, amp_ref, geom, with_reference=False)
+    assert F == pytest.approx(Fj, rel=1e-12)
+    np.testing.assert_allclose(gu, guj, atol=1e-12 * np.max(np.abs(gu)))
+
+
+def test_conventional_functional_separates_over_projections():
+    # one independent functional per projection (the remark after Eq. 16)
+    geom, u, _, amp, _ = tiny_problem(seed=34)
+    F, gu = O.conventional_gradient(u, amp, geom)
+    Fs, gs = 0.0, np.zeros_like(gu)
+    for k in range(geom.n_angles):
+        gk = O.Geometry(H=geom.H, W=geom.W, theta=geom.theta[k:k + 1], mag_rel=geom.mag_rel,
+                        m0=geom.m0, fresnel0=geom.fresnel0, kappa=geom.kappa,
+                        shift=geom.shift[k:k + 1])
+        Fk, guk = O.conventional_gradient(u, amp[k:k + 1], gk)
+        Fs += Fk
+        gs += guk
+    assert F == pytest.approx(Fs, rel=1e-12)
+    np.testing.assert_allclose(gu, gs, atol=1e-12 * np.max(np.abs(gu)))
+
+
+def test_conventional_functional_vanishes_on_its_own_data_and_plane_wave_case():
+    geom, u, _, _, _ = tiny_problem(seed=35)
+    rd, _ = O.distances(geom.m0, geom.mag_rel)
+    amp = np.zeros((geom.n_angles, geom.n_dist, geom.H, geom.W))
+    for k in range(geom.n_angles):
+        psi = np.exp(1j * geom.kappa * O.radon(u, geom.theta[k]))
+        for j in range(geom.n_dist):
+            # written out: D_rho'(1 + B(psi - 1)) with B from the interpolation
+            # matrices, no probe
+            Ay = O.interp_matrix(geom.H, geom.mag_rel[j], geom.t(k, j)[0])
+            Ax = O.interp_matrix(geom.W, geom.mag_rel[j], geom.t(k, j)[1])
+            amp[k, j] = np.abs(O.propagate(1.0 + Ay @ (psi - 1.0) @ Ax.T, rd[j], geom.fresnel0))
+    F, gu = O.conventional_gradient(u, amp, geom)
+    assert F < 1e-24 and np.max(np.abs(gu)) < 1e-9
+    # one plane, m~ = 1, no shift: the textbook parallel-beam |D psi| (Eq. 3)
+    g1 = O.Geometry(H=geom.H, W=geom.W, theta=geom.theta[:1], mag_rel=[1.0], m0=geom.m0,
+                    fresnel0=geom.fresnel0, kappa=geom.kappa)
+    a = np.abs(1 + 0.2 * crandn(np.random.default_rng(36), 1, 1, geom.H, geom.W))
+    psi = np.exp(1j * geom.kappa * O.radon(u, geom.theta[0]))
+    v = O.propagate(psi, O.distances(geom.m0, [1.0])[0][0], geom.fresnel0)
+    assert O.conventional_objective(u, a, g1) == pytest.approx(
+        np.sum((np.abs(v) - a[0, 0]) ** 2), rel=1e-12)
+
+
+def test_holo2d_conventional_matches_the_tomographic_form_at_one_angle():
+    geom, u, _, amp, _ = tiny_problem(seed=37, n_angles=1, shifts=False)
+    psi = O.transmittance(u, geom.theta[0], geom.kappa)
+    F2, gpsi = O.holo2d_conventional_gradient(psi, amp[0], geom.mag_rel, geom.m0, geom.fresnel0)
+    F, gu = O.conventional_gradient(u, amp, geom)
+    assert F2 == pytest.approx(F, rel=1e-12)
+    h = -1j * geom.kappa * np.conj(psi) * gpsi
+    np.testing.assert_allclose(O.radon_T(h, geom.theta[0], geom.W), gu,
+                               atol=1e-10 * np.max(np.abs(gu)))
