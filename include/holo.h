@@ -304,6 +304,28 @@ holo_status holo2d_grad(holo2d_plan* plan, const holo_c64* psi, const holo_c64* 
                         holo_c64* g_psi, holo_c64* g_q, void* ws, size_t ws_bytes,
                         void* stream);
 
+/* holo2d_grad for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * no workspace argument, and the call performs no hipMalloc, hipFree or
+ * other allocation.  The plan's constant tables and the workspace are placed
+ * in one static device array of HOLO2D_SCRATCH_MAX_BYTES per GPU, which the
+ * library holds from its load until the process ends; each call rewrites
+ * the tables there (stream-ordered before its kernels).  The caller still
+ * passes every input and output (device pointers, as holo2d_grad; F, g_psi
+ * and g_q may each be NULL).  Results equal holo2d_grad's.
+ * All calls on one GPU share that GPU's array: calls that overlap on one GPU
+ * (different streams or threads without ordering between them) race and
+ * give wrong results; calls ordered on one stream are safe.
+ * holo2d_noalloc_bytes gives the bytes a plan needs in the array.
+ * Errors: INVALID_ARGUMENT (NULL plan, psi, q, amp or amp_ref),
+ * WORKSPACE_TOO_SMALL (the plan needs more than HOLO2D_SCRATCH_MAX_BYTES;
+ * returned before any device work), HIP. */
+#define HOLO2D_SCRATCH_MAX_BYTES (128u << 20)
+holo_status holo2d_noalloc_bytes(const holo2d_plan* plan, size_t* bytes);
+holo_status holo2d_grad_noalloc(holo2d_plan* plan, const holo_c64* psi, const holo_c64* q,
+                                const float* amp, const float* amp_ref, double* F,
+                                holo_c64* g_psi, holo_c64* g_q, void* stream);
+
 /* Kernel classes for the timing diagnostics below. */
 enum {
   HOLO_K_RADON_FWD = 0,  /* ray sums + exp, one launch per angle chunk          */

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -47,6 +48,9 @@ struct holo2d_plan {
   int device = -1;
   // workspace (bytes)
   size_t ws_Q = 0, ws_P = 0, ws_X = 0, ws_G = 0, ws_F = 0, ws_bytes = 0;
+  // table image of holo2d_grad_noalloc, built for the static array's address
+  std::vector<char> noalloc_image;
+  const void* noalloc_base = nullptr;
 };
 
 static holo_status fail2(holo_status s, const std::string& m) { return holo::set_last_error(s, m); }
@@ -239,24 +243,17 @@ namespace {
                                                          hipGetErrorString(e_)); \
   } while (0)
 
-holo_status b2_tables(holo2d_plan* P) {
-  int dev = -1;
-  B2_HIP(hipGetDevice(&dev));
-  if (P->d_tables) {
-    if (dev != P->device)
-      return fail2(HOLO_ERR_INVALID_ARGUMENT, "plan tables live on another device");
-    return HOLO_OK;
-  }
-  std::vector<char> h(P->table_bytes, 0);
+// The device image of a plan's constant tables (twiddles, transfer rows,
+// instance descriptors, work items, cost-slot ranges) for tables placed at
+// device address `base`: the instance descriptors hold pointers into it.
+void b2_table_image(const holo2d_plan* P, const char* base, std::vector<char>& h) {
+  h.assign(P->table_bytes, 0);
   for (size_t d = 0; d < P->dsizes.size(); ++d) {
     std::copy((const char*)P->tw[d].data(), (const char*)(P->tw[d].data() + P->tw[d].size()),
               h.data() + P->off_tw[d]);
     std::copy((const char*)P->chirp[d].data(),
               (const char*)(P->chirp[d].data() + P->chirp[d].size()), h.data() + P->off_chirp[d]);
   }
-  void* d = nullptr;
-  B2_HIP(hipMalloc(&d, P->table_bytes));
-  char* base = (char*)d;
   std::vector<B2Inst> inst(P->n_inst);
   for (int i = 0; i < P->n_inst; ++i) {
     const size_t k = std::lower_bound(P->dsizes.begin(), P->dsizes.end(), P->sizes[i]) -
@@ -268,13 +265,27 @@ holo_status b2_tables(holo2d_plan* P) {
   }
   std::copy((const char*)inst.data(), (const char*)(inst.data() + inst.size()),
             h.data() + P->off_inst);
-  for (ItemList* L : {&P->rows_probe, &P->rows_probe_noref, &P->rows_ref, &P->rows_nd,
-                      &P->cols_probe, &P->cols_probe_noref, &P->cols_ref, &P->cols_nd,
-                      &P->gather})
+  for (const ItemList* L : {&P->rows_probe, &P->rows_probe_noref, &P->rows_ref, &P->rows_nd,
+                            &P->cols_probe, &P->cols_probe_noref, &P->cols_ref, &P->cols_nd,
+                            &P->gather})
     std::copy((const char*)L->items.data(), (const char*)(L->items.data() + L->items.size()),
               h.data() + L->off);
   std::copy((const char*)P->ranges.data(), (const char*)(P->ranges.data() + P->ranges.size()),
             h.data() + P->off_ranges);
+}
+
+holo_status b2_tables(holo2d_plan* P) {
+  int dev = -1;
+  B2_HIP(hipGetDevice(&dev));
+  if (P->d_tables) {
+    if (dev != P->device)
+      return fail2(HOLO_ERR_INVALID_ARGUMENT, "plan tables live on another device");
+    return HOLO_OK;
+  }
+  void* d = nullptr;
+  B2_HIP(hipMalloc(&d, P->table_bytes));
+  std::vector<char> h;
+  b2_table_image(P, (const char*)d, h);
   hipError_t e = hipMemcpy(d, h.data(), P->table_bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(d);
@@ -287,19 +298,12 @@ holo_status b2_tables(holo2d_plan* P) {
 
 enum B2Run { kB2Fwd, kB2Obj, kB2Grad };
 
-holo_status b2_run(holo2d_plan* P, B2Run run, const holo_c64* psi, const holo_c64* q,
-                   const float* amp, const float* amp_ref, holo_c64* v_out, double* F,
-                   holo_c64* g_psi, holo_c64* g_q, void* ws, size_t ws_bytes, void* stream) {
-  if (!psi || !q) return fail2(HOLO_ERR_INVALID_ARGUMENT, "psi or q is NULL");
-  if (!ws) return fail2(HOLO_ERR_INVALID_ARGUMENT, "workspace is NULL");
-  if (ws_bytes < P->ws_bytes)
-    return fail2(HOLO_ERR_WORKSPACE_TOO_SMALL, "workspace needs " + std::to_string(P->ws_bytes) +
-                                                   " bytes, got " + std::to_string(ws_bytes));
-  holo_status ts = b2_tables(P);
-  if (ts != HOLO_OK) return ts;
-  hipStream_t st = (hipStream_t)stream;
-  char* w = (char*)ws;
-  const char* tb = (const char*)P->d_tables;
+// Enqueue the passes of one call.  `tb` holds the plan's device tables (as
+// laid out by b2_table_image for that address), `w` the workspace.
+holo_status b2_launch(holo2d_plan* P, B2Run run, const char* tb, char* w, const holo_c64* psi,
+                      const holo_c64* q, const float* amp, const float* amp_ref,
+                      holo_c64* v_out, double* F, holo_c64* g_psi, holo_c64* g_q,
+                      hipStream_t st) {
   auto items = [&](const ItemList& L) { return (const B2Item*)(tb + L.off); };
   B2Args A{};
   A.nd = P->nd;
@@ -357,6 +361,20 @@ holo_status b2_run(holo2d_plan* P, B2Run run, const holo_c64* psi, const holo_c6
   return HOLO_OK;
 }
 
+holo_status b2_run(holo2d_plan* P, B2Run run, const holo_c64* psi, const holo_c64* q,
+                   const float* amp, const float* amp_ref, holo_c64* v_out, double* F,
+                   holo_c64* g_psi, holo_c64* g_q, void* ws, size_t ws_bytes, void* stream) {
+  if (!psi || !q) return fail2(HOLO_ERR_INVALID_ARGUMENT, "psi or q is NULL");
+  if (!ws) return fail2(HOLO_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  if (ws_bytes < P->ws_bytes)
+    return fail2(HOLO_ERR_WORKSPACE_TOO_SMALL, "workspace needs " + std::to_string(P->ws_bytes) +
+                                                   " bytes, got " + std::to_string(ws_bytes));
+  holo_status ts = b2_tables(P);
+  if (ts != HOLO_OK) return ts;
+  return b2_launch(P, run, (const char*)P->d_tables, (char*)ws, psi, q, amp, amp_ref, v_out, F,
+                   g_psi, g_q, (hipStream_t)stream);
+}
+
 }  // namespace
 
 extern "C" holo_status holo2d_fwd(holo2d_plan* P, const holo_c64* psi, const holo_c64* q,
@@ -381,4 +399,75 @@ extern "C" holo_status holo2d_grad(holo2d_plan* P, const holo_c64* psi, const ho
                                    void* stream) {
   if (!P || !amp || !amp_ref) return fail2(HOLO_ERR_INVALID_ARGUMENT, "holo2d_grad: NULL argument");
   return b2_run(P, kB2Grad, psi, q, amp, amp_ref, nullptr, F, g_psi, g_q, ws, ws_bytes, stream);
+}
+
+// ---------------------------------------------------------------------------
+// holo2d_grad without allocation: the plan's tables and the workspace live in
+// one static device array per GPU.
+// ---------------------------------------------------------------------------
+
+// Each GPU holds its own copy from the library's load until the process
+// ends.  Host code never uses this name as an address: the device address of
+// the current GPU's copy comes from hipGetSymbolAddress (scratch_address).
+static __device__ __align__(256) unsigned char scratch[HOLO2D_SCRATCH_MAX_BYTES];
+
+namespace {
+
+constexpr size_t kScratchBytes = size_t(HOLO2D_SCRATCH_MAX_BYTES);
+constexpr int kMaxDevices = 64;
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+holo_status scratch_address(void** out) {
+  int dev = -1;
+  B2_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail2(HOLO_ERR_INVALID_ARGUMENT, "holo2d_grad_noalloc: device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail2(HOLO_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                     hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return HOLO_OK;
+}
+
+}  // namespace
+
+extern "C" holo_status holo2d_noalloc_bytes(const holo2d_plan* P, size_t* bytes) {
+  if (!P || !bytes) return fail2(HOLO_ERR_INVALID_ARGUMENT, "holo2d_noalloc_bytes: NULL argument");
+  *bytes = al(P->table_bytes) + P->ws_bytes;
+  return HOLO_OK;
+}
+
+extern "C" holo_status holo2d_grad_noalloc(holo2d_plan* P, const holo_c64* psi, const holo_c64* q,
+                                           const float* amp, const float* amp_ref, double* F,
+                                           holo_c64* g_psi, holo_c64* g_q, void* stream) {
+  if (!P || !psi || !q || !amp || !amp_ref)
+    return fail2(HOLO_ERR_INVALID_ARGUMENT, "holo2d_grad_noalloc: NULL argument");
+  const size_t need = al(P->table_bytes) + P->ws_bytes;
+  if (need > kScratchBytes)
+    return fail2(HOLO_ERR_WORKSPACE_TOO_SMALL,
+                 "holo2d_grad_noalloc: the plan needs " + std::to_string(need) +
+                     " bytes of scratch, the static array holds " + std::to_string(kScratchBytes) +
+                     " (use holo2d_grad with a caller workspace)");
+  void* base = nullptr;
+  holo_status s = scratch_address(&base);
+  if (s != HOLO_OK) return s;
+  char* tb = (char*)base;
+  // Tables first: every call rewrites them (another plan's call may have
+  // left its own there), ordered on the stream before this call's kernels.
+  if (P->noalloc_base != base) {
+    b2_table_image(P, tb, P->noalloc_image);
+    P->noalloc_base = base;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  B2_HIP(hipMemcpyAsync(tb, P->noalloc_image.data(), P->table_bytes, hipMemcpyHostToDevice, st));
+  return b2_launch(P, kB2Grad, tb, tb + al(P->table_bytes), psi, q, amp, amp_ref, nullptr, F,
+                   g_psi, g_q, st);
 }

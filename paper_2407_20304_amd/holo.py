@@ -29,6 +29,7 @@ EXPORTS = (
     "holo_bin_frames", "holo_upsample_frames", "holo_upsample_volume",
     "holo2d_plan_create", "holo2d_plan_destroy", "holo2d_offsets", "holo2d_workspace_bytes",
     "holo2d_plan_set_functional", "holo2d_fwd", "holo2d_objective", "holo2d_grad",
+    "holo2d_noalloc_bytes", "holo2d_grad_noalloc",
     "holo_timing_enable", "holo_timing_read", "holo_plan_ray_groups", "holo_last_error",
 )
 
@@ -96,6 +97,8 @@ def lib():
     L.holo2d_fwd.argtypes = [P, P, P, P, P, c_size_t, P]
     L.holo2d_objective.argtypes = [P, P, P, P, P, P, P, c_size_t, P]
     L.holo2d_grad.argtypes = [P, P, P, P, P, P, P, P, P, c_size_t, P]
+    L.holo2d_noalloc_bytes.argtypes = [P, POINTER(c_size_t)]
+    L.holo2d_grad_noalloc.argtypes = [P, P, P, P, P, P, P, P, P]
     L.holo_timing_enable.argtypes = [P, c_int32]
     L.holo_timing_read.argtypes = [P, c_int32, POINTER(c_double), POINTER(ctypes.c_int64)]
     L.holo_plan_ray_groups.argtypes = [P, P, P, c_int32, POINTER(c_int32)]
@@ -576,6 +579,30 @@ class Plan2D:
         _check(lib().holo2d_grad(self._h, _ptr(psi), _ptr(q), _ptr(amp), _ptr(amp_ref), _ptr(F),
                                  _ptr(g_psi), _ptr(g_q), _ptr(ws), c_size_t(ws.numel()),
                                  _stream(stream)))
+        return F, g_psi, g_q
+
+    def noalloc_bytes(self):
+        """Bytes of the library's static scratch array that
+        holo2d_grad_noalloc needs for this plan."""
+        n = c_size_t()
+        _check(lib().holo2d_noalloc_bytes(self._h, ctypes.byref(n)))
+        return int(n.value)
+
+    def holo2d_grad_noalloc(self, psi, q, amp, amp_ref, F, g_psi, g_q, stream=None):
+        """holo2d_grad through the allocation-free entry point: the library
+        allocates nothing (its static scratch array holds the tables and the
+        workspace); the outputs are the caller's preallocated tensors (F,
+        g_psi, g_q; each may be None)."""
+        import torch
+        self._chk_data(psi, q, amp, amp_ref)
+        if g_psi is not None:
+            self._chk(g_psi, False, "g_psi", torch.complex64)
+        if g_q is not None:
+            self._chk(g_q, False, "g_q", torch.complex64)
+        if F is not None and (F.dtype != torch.float64 or not F.is_cuda or F.numel() != self.n_inst):
+            raise ValueError("F must be a float64 GPU tensor of %d elements" % self.n_inst)
+        _check(lib().holo2d_grad_noalloc(self._h, _ptr(psi), _ptr(q), _ptr(amp), _ptr(amp_ref),
+                                         _ptr(F), _ptr(g_psi), _ptr(g_q), _stream(stream)))
         return F, g_psi, g_q
 
     def _chk_data(self, psi, q, amp, amp_ref):

@@ -241,3 +241,22 @@ def test_batch_plan_offsets_and_validation():
     assert L.holo2d_grad(q._h, buf, buf, buf, buf, buf, buf, buf, buf, 8, None) == 3
     assert L.holo2d_fwd(q._h, buf, buf, None, buf, 1 << 40, None) == 1
     q.close()
+
+
+def test_noalloc_batch_gradient_validates_on_the_host():
+    # the batch of the benchmark needs more than the static scratch array:
+    # rejected with WORKSPACE_TOO_SMALL before any device work
+    L = holo.lib()
+    sizes = [512] * 96
+    big = holo.Plan2D(sizes, [1.0, 1.08, 1.25, 1.5], 300.0, 0.01)
+    assert big.noalloc_bytes() > (128 << 20)
+    buf = ctypes.c_void_p(1)
+    assert L.holo2d_grad_noalloc(big._h, buf, buf, buf, buf, buf, buf, buf, None) == 3
+    assert b"static array" in L.holo_last_error()
+    small = holo.Plan2D([128, 64], [1.0, 1.08, 1.25, 1.5], 300.0, 0.01)
+    assert big.workspace_bytes < big.noalloc_bytes()
+    assert 0 < small.noalloc_bytes() < (128 << 20)
+    assert L.holo2d_grad_noalloc(small._h, None, buf, buf, buf, buf, buf, buf, None) == 1
+    assert L.holo2d_grad_noalloc(None, buf, buf, buf, buf, buf, buf, buf, None) == 1
+    big.close()
+    small.close()
