@@ -3,7 +3,7 @@
  * (libholo_plain.so).
  *
  * These are the deliberately simple forms of the ray-sum projector R_theta
- * (Sec. 4, Eq. 14) and of its adjoint R_theta^* (the back-projection of the
+ * (Sec. 2, Eq. 14) and of its adjoint R_theta^* (the back-projection of the
  * tomography step, Eq. 15), used only as the comparison baseline for the
  * fused library: one thread per ray or per voxel, every tap read from
  * global memory, one launch per angle.  They compute the same Joseph
