@@ -49,6 +49,21 @@ in the design notes of the repository):
      g_u = sum_k R_k^T(-i kappa conj(psi_k) g_psi_k).
   R6 Data are given directly as amplitudes a = sqrt(d~) on the computational
      grid (the m0^2 M_{1/m0} rescaling is the identity there).
+  F1 The Fourier-slice discretisation of R_k (an option of the geometry,
+     projector = "fourier"): the Fourier slice theorem evaluated exactly on
+     the slice's discrete-time Fourier transform at W + 1 frequencies
+     m (cos, sin), the two Nyquist terms at half weight, inverted at the W
+     bins; equivalently p[i] = sum u[y, x] D_W(s_i - (x' cos + y' sin)) with
+     the periodic sinc D_W(d) = sin(pi d) / (W tan(pi d / W)).  No path
+     factor.  Without it (projector = "joseph") reading R1 holds.
+  P1 Padded propagation (an option of the geometry, pad = 2): D_Z is a
+     convolution over the whole plane, the fields are known on the H x W
+     grid only and are taken as zero outside; each propagation sets the
+     field in the centre of a 2H x 2W grid, applies that grid's transfer
+     function (same pixel size) and cuts the centre out again.  Every
+     propagation of the model (probe, detector, reference, adjoints) is
+     padded when the option is set; its adjoint is the padded propagation
+     by -rho.  Without it (pad = 1) reading R2 holds.
 
 The solver around the gradient (Sec. 2, the CG iteration with the
 Dai-Yuan formula, Eq. (12)-(13), and the initial probe):
@@ -114,6 +129,8 @@ class Geometry:
     kappa: float = 4667.35      # phase per unit u per voxel of path
     shift: Optional[np.ndarray] = None   # (n_angles, n_dist, 2) = (t_y, t_x) px
     probe_shift: Optional[np.ndarray] = None   # (n_angles, n_dist, 2) = (s_y, s_x) px
+    pad: int = 1                # 1: periodic propagation; 2: padded (reading P1)
+    projector: str = "joseph"   # R_k: "joseph" (reading R1) or "fourier" (reading F1)
 
     def __post_init__(self):
         self.theta = np.asarray(self.theta, dtype=np.float64)
@@ -157,9 +174,23 @@ def transfer(n: int, rho: float, fresnel0: float) -> np.ndarray:
     return np.exp(-1j * np.pi * rho * k * k / (fresnel0 * n * n))
 
 
-def propagate(f: np.ndarray, rho: float, fresnel0: float) -> np.ndarray:
-    """D_rho f on the last two axes (reading R2)."""
+def propagate(f: np.ndarray, rho: float, fresnel0: float, pad: int = 1) -> np.ndarray:
+    """D_rho f on the last two axes (reading R2).
+
+    With pad > 1, the padded propagation (reading P1): D_Z is a convolution
+    over the whole plane (Appendix A), and the field is known on the H x W
+    grid only; it is taken as zero outside, set in the centre of a grid pad
+    times larger in each direction (same pixel size), propagated there with
+    that grid's transfer function, and the centre H x W is cut out.  Its
+    adjoint is the same with -rho (cutting out is the transpose of setting
+    in)."""
     H, W = f.shape[-2:]
+    if pad > 1:
+        H2, W2 = pad * H, pad * W
+        y0, x0 = (H2 - H) // 2, (W2 - W) // 2
+        g = np.zeros(f.shape[:-2] + (H2, W2), dtype=np.complex128)
+        g[..., y0:y0 + H, x0:x0 + W] = f
+        return propagate(g, rho, fresnel0)[..., y0:y0 + H, x0:x0 + W]
     h = transfer(H, rho, fresnel0)[:, None] * transfer(W, rho, fresnel0)[None, :]
     return np.fft.ifft2(np.fft.fft2(f) * h)
 
@@ -237,6 +268,66 @@ def radon_T(p: np.ndarray, theta: float, W: int) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
+# Fourier-slice discretisation of R_k (reading F1)
+#
+# The Fourier slice theorem: the 1-D Fourier transform of the projection at
+# angle theta is the 2-D Fourier transform of the slice along the line
+# through the origin at that angle.  Evaluated exactly on a slice's
+# discrete-time Fourier transform F(xi) = sum u[y, x] e^{-2 pi i xi.(x', y')/W}
+# at the W + 1 frequencies xi = m (cos, sin), m = -W/2 .. W/2 (the two
+# Nyquist terms at half weight, so that R stays a real operator), and
+# inverted with the W-point inverse DFT at the bins s_i = i - W/2, it gives
+#   p[i] = sum_{y,x} u[y, x] D_W(s_i - (x' cos + y' sin)),
+#   D_W(d) = (1/W) sum_m c_m e^{2 pi i m d / W} = sin(pi d) / (W tan(pi d / W)),
+# D_W(0) = 1: the line integrals of the slice's trigonometric interpolant.
+# No path factor appears (the integral has unit speed along the line).
+# ---------------------------------------------------------------------------
+
+def periodic_sinc(d, W: int) -> np.ndarray:
+    """D_W(d) = sin(pi d) / (W tan(pi d / W)) for even W, 1 where d is a
+    multiple of W."""
+    d = np.asarray(d, dtype=np.float64)
+    out = np.ones_like(d)
+    t = np.tan(np.pi * d / W)
+    nz = np.abs(np.sin(np.pi * d / W)) > 1e-14
+    out[nz] = np.sin(np.pi * d[nz]) / (W * t[nz])
+    return out
+
+
+def fourier_slice_matrix(W: int, theta: float) -> np.ndarray:
+    """The (W, W*W) matrix of the Fourier-slice projection of one slice:
+    entry [i, y*W + x] = D_W(s_i - (x' cos(theta) + y' sin(theta)))."""
+    c = W // 2
+    xs = np.arange(W, dtype=np.float64) - c
+    t = (xs[None, :] * np.cos(theta) + xs[:, None] * np.sin(theta)).ravel()   # [y, x]
+    s = np.arange(W, dtype=np.float64) - c
+    return periodic_sinc(s[:, None] - t[None, :], W)
+
+
+def radon_fourier(u: np.ndarray, theta: float) -> np.ndarray:
+    """p[z, i] of every slice of u (H, W, W) at one angle (reading F1)."""
+    H, W, _ = u.shape
+    A = fourier_slice_matrix(W, theta)
+    return u.reshape(H, W * W) @ A.T
+
+
+def radon_fourier_T(p: np.ndarray, theta: float, W: int) -> np.ndarray:
+    """Transpose of `radon_fourier`: p (H, W) -> (H, W, W)."""
+    A = fourier_slice_matrix(W, theta)
+    return (p @ A).reshape(p.shape[0], W, W)
+
+
+def project(u: np.ndarray, theta: float, projector: str = "joseph") -> np.ndarray:
+    """R_theta u with the chosen discretisation."""
+    return radon_fourier(u, theta) if projector == "fourier" else radon(u, theta)
+
+
+def project_T(p: np.ndarray, theta: float, W: int, projector: str = "joseph") -> np.ndarray:
+    """R_theta^T p with the chosen discretisation."""
+    return radon_fourier_T(p, theta, W) if projector == "fourier" else radon_T(p, theta, W)
+
+
+# ---------------------------------------------------------------------------
 # Demagnification and shift M_{1/m~} S_t (reading R3)
 # ---------------------------------------------------------------------------
 
@@ -275,9 +366,9 @@ def transmit(psi: np.ndarray, mag: float, ty: float = 0.0, tx: float = 0.0):
 # The joint model and its objective/gradient
 # ---------------------------------------------------------------------------
 
-def transmittance(u: np.ndarray, theta: float, kappa: float) -> np.ndarray:
+def transmittance(u: np.ndarray, theta: float, kappa: float, projector: str = "joseph") -> np.ndarray:
     """psi_k = exp(i kappa R_k u) (Sec. 5, Eq. 17)."""
-    return np.exp(1j * kappa * radon(u, theta))
+    return np.exp(1j * kappa * project(u, theta, projector))
 
 
 def circular_shift_matrix(n: int, shift: float) -> np.ndarray:
@@ -308,14 +399,14 @@ def probe_frames(q: np.ndarray, geom: Geometry, k: int):
     """Q_kj = D_{rho_probe_j}(S_{s_kj} q): the probe at sample plane j for
     angle k (Eq. 9, shifting then propagating, as written)."""
     _, rho_p = distances(geom.m0, geom.mag_rel)
-    return [propagate(probe_shift_op(q, *geom.s(k, j)), r, geom.fresnel0)
+    return [propagate(probe_shift_op(q, *geom.s(k, j)), r, geom.fresnel0, geom.pad)
             for j, r in enumerate(rho_p)]
 
 
 def probes(q: np.ndarray, geom: Geometry):
     """Q_j = D_{rho_probe_j} q: the probe at sample plane j (Eq. 8)."""
     _, rho_p = distances(geom.m0, geom.mag_rel)
-    return [propagate(q, r, geom.fresnel0) for r in rho_p]
+    return [propagate(q, r, geom.fresnel0, geom.pad) for r in rho_p]
 
 
 def _residual(v: np.ndarray, a: np.ndarray):
@@ -344,21 +435,21 @@ def forward(u: np.ndarray, q: np.ndarray, geom: Geometry, ks=None) -> np.ndarray
     for a, k in enumerate(ks):
         if geom.probe_shift is not None:
             Q = probe_frames(q, geom, k)
-        psi = transmittance(u, geom.theta[k], geom.kappa)
+        psi = transmittance(u, geom.theta[k], geom.kappa, geom.projector)
         for j in range(geom.n_dist):
             phi = transmit(psi, geom.mag_rel[j], *geom.t(k, j))
-            out[a, j] = propagate(Q[j] * phi, rho_d[j], geom.fresnel0)
+            out[a, j] = propagate(Q[j] * phi, rho_d[j], geom.fresnel0, geom.pad)
     return out
 
 
 def reference_term(q: np.ndarray, amp_ref: np.ndarray, fresnel0: float,
-                   functional: str = "amplitude"):
+                   functional: str = "amplitude", pad: int = 1):
     """|| |D_1 q| - sqrt(d~r) ||^2 (or, for the intensity functional,
     || |D_1 q|^2 - d~r ||^2 with amp_ref holding d~r) and its probe gradient
     D_{-1}(r_ref)."""
-    P = propagate(q, 1.0, fresnel0)
+    P = propagate(q, 1.0, fresnel0, pad)
     F, r = RESIDUALS[functional](P, amp_ref)
-    return F, propagate(r, -1.0, fresnel0)
+    return F, propagate(r, -1.0, fresnel0, pad)
 
 
 def objective(u, q, amp, amp_ref, geom: Geometry, functional: str = "amplitude") -> float:
@@ -368,7 +459,7 @@ def objective(u, q, amp, amp_ref, geom: Geometry, functional: str = "amplitude")
     v = forward(u, q, geom)
     F = sum(RESIDUALS[functional](v[k, j], amp[k, j])[0]
             for k in range(v.shape[0]) for j in range(v.shape[1]))
-    return F + reference_term(q, amp_ref, geom.fresnel0, functional)[0]
+    return F + reference_term(q, amp_ref, geom.fresnel0, functional, geom.pad)[0]
 
 
 def _angle_terms(psi, k, Q, amp_k, geom: Geometry, functional: str = "amplitude"):
@@ -388,14 +479,14 @@ def _angle_terms(psi, k, Q, amp_k, geom: Geometry, functional: str = "amplitude"
     for j in range(geom.n_dist):
         ty, tx = geom.t(k, j)
         phi = transmit(psi, geom.mag_rel[j], ty, tx)
-        v = propagate(Q[j] * phi, rho_d[j], geom.fresnel0)
+        v = propagate(Q[j] * phi, rho_d[j], geom.fresnel0, geom.pad)
         Fk, r = RESIDUALS[functional](v, amp_k[j])
         F += Fk
-        w = propagate(r, -rho_d[j], geom.fresnel0)
+        w = propagate(r, -rho_d[j], geom.fresnel0, geom.pad)
         if G is not None:
             G.append(np.conj(phi) * w)
         else:   # Q_kj = D S q: back through D, then S^T
-            gq += probe_shift_op_T(propagate(np.conj(phi) * w, -rho_p[j], geom.fresnel0),
+            gq += probe_shift_op_T(propagate(np.conj(phi) * w, -rho_p[j], geom.fresnel0, geom.pad),
                                    *geom.s(k, j))
         g_psi += resample_T(np.conj(Q[j]) * w, geom.mag_rel[j], ty, tx)
     return F, g_psi, G, gq
@@ -419,7 +510,7 @@ def gradient(u, q, amp, amp_ref, geom: Geometry, with_reference=True,
     for k in range(geom.n_angles):
         if geom.probe_shift is not None:
             Q = probe_frames(q, geom, k)
-        psi = transmittance(u, geom.theta[k], geom.kappa)
+        psi = transmittance(u, geom.theta[k], geom.kappa, geom.projector)
         Fk, g_psi, Gk, gqk = _angle_terms(psi, k, Q, amp[k], geom, functional)
         F += Fk
         if Gk is not None:
@@ -428,10 +519,10 @@ def gradient(u, q, amp, amp_ref, geom: Geometry, with_reference=True,
         else:
             g_q += gqk
         h = -1j * geom.kappa * np.conj(psi) * g_psi
-        g_u += radon_T(h, geom.theta[k], geom.W)
-    g_q = g_q + sum(propagate(G[j], -rho_p[j], geom.fresnel0) for j in range(geom.n_dist))
+        g_u += project_T(h, geom.theta[k], geom.W, geom.projector)
+    g_q = g_q + sum(propagate(G[j], -rho_p[j], geom.fresnel0, geom.pad) for j in range(geom.n_dist))
     if with_reference:
-        Fr, gr = reference_term(q, amp_ref, geom.fresnel0, functional)
+        Fr, gr = reference_term(q, amp_ref, geom.fresnel0, functional, geom.pad)
         F += Fr
         g_q = g_q + gr
     return F, g_u, g_q
@@ -453,20 +544,21 @@ def adjoint(u, q, w_frames, geom: Geometry, ks=None):
     for a, k in enumerate(ks):
         if geom.probe_shift is not None:
             Q = probe_frames(q, geom, k)
-        psi = transmittance(u, geom.theta[k], geom.kappa)
+        psi = transmittance(u, geom.theta[k], geom.kappa, geom.projector)
         g_psi = np.zeros_like(psi)
         for j in range(geom.n_dist):
             ty, tx = geom.t(k, j)
             phi = transmit(psi, geom.mag_rel[j], ty, tx)
-            wb = propagate(w_frames[a, j], -rho_d[j], geom.fresnel0)
+            wb = propagate(w_frames[a, j], -rho_d[j], geom.fresnel0, geom.pad)
             if geom.probe_shift is None:
                 G[j] += np.conj(phi) * wb
             else:
-                g_q += probe_shift_op_T(propagate(np.conj(phi) * wb, -rho_p[j], geom.fresnel0),
+                g_q += probe_shift_op_T(propagate(np.conj(phi) * wb, -rho_p[j], geom.fresnel0, geom.pad),
                                         *geom.s(k, j))
             g_psi += resample_T(np.conj(Q[j]) * wb, geom.mag_rel[j], ty, tx)
-        g_u += radon_T(-1j * geom.kappa * np.conj(psi) * g_psi, geom.theta[k], geom.W)
-    g_q = g_q + sum(propagate(G[j], -rho_p[j], geom.fresnel0) for j in range(geom.n_dist))
+        g_u += project_T(-1j * geom.kappa * np.conj(psi) * g_psi, geom.theta[k], geom.W,
+                         geom.projector)
+    g_q = g_q + sum(propagate(G[j], -rho_p[j], geom.fresnel0, geom.pad) for j in range(geom.n_dist))
     return g_u, g_q
 
 
@@ -490,9 +582,10 @@ def conventional_objective(u, amp, geom: Geometry) -> float:
     rho_d, _ = distances(geom.m0, geom.mag_rel)
     F = 0.0
     for k in range(geom.n_angles):
-        psi = transmittance(u, geom.theta[k], geom.kappa)
+        psi = transmittance(u, geom.theta[k], geom.kappa, geom.projector)
         for j in range(geom.n_dist):
-            v = propagate(transmit(psi, geom.mag_rel[j], *geom.t(k, j)), rho_d[j], geom.fresnel0)
+            v = propagate(transmit(psi, geom.mag_rel[j], *geom.t(k, j)), rho_d[j], geom.fresnel0,
+                          geom.pad)
             F += float(np.sum((np.abs(v) - amp[k, j]) ** 2))
     return F
 
@@ -505,17 +598,18 @@ def conventional_gradient(u, amp, geom: Geometry):
     F = 0.0
     g_u = np.zeros(u.shape, np.complex128)
     for k in range(geom.n_angles):
-        psi = transmittance(u, geom.theta[k], geom.kappa)
+        psi = transmittance(u, geom.theta[k], geom.kappa, geom.projector)
         g_psi = np.zeros_like(psi)
         for j in range(geom.n_dist):
             ty, tx = geom.t(k, j)
-            v = propagate(transmit(psi, geom.mag_rel[j], ty, tx), rho_d[j], geom.fresnel0)
+            v = propagate(transmit(psi, geom.mag_rel[j], ty, tx), rho_d[j], geom.fresnel0, geom.pad)
             av = np.abs(v)
             F += float(np.sum((av - amp[k, j]) ** 2))
             unit = np.divide(v, av, out=np.zeros_like(v), where=av > 0)
-            w = propagate(2.0 * (v - amp[k, j] * unit), -rho_d[j], geom.fresnel0)
+            w = propagate(2.0 * (v - amp[k, j] * unit), -rho_d[j], geom.fresnel0, geom.pad)
             g_psi += resample_T(w, geom.mag_rel[j], ty, tx)
-        g_u += radon_T(-1j * geom.kappa * np.conj(psi) * g_psi, geom.theta[k], geom.W)
+        g_u += project_T(-1j * geom.kappa * np.conj(psi) * g_psi, geom.theta[k], geom.W,
+                         geom.projector)
     return F, g_u
 
 
@@ -632,10 +726,10 @@ def cg_dai_yuan(f, grad, x0, iters, step0, line_search=None):
     return x, hist, steps, halv
 
 
-def probe_init(amp_ref, fresnel0) -> np.ndarray:
+def probe_init(amp_ref, fresnel0, pad: int = 1) -> np.ndarray:
     """Initial probe (C4): q0 = D_{-1}(sqrt(d~r)), the reference amplitude
     with zero phase propagated back to sample plane 0."""
-    return propagate(np.asarray(amp_ref, dtype=np.complex128), -1.0, fresnel0)
+    return propagate(np.asarray(amp_ref, dtype=np.complex128), -1.0, fresnel0, pad)
 
 
 def holo_cg(u0, q0, amp, amp_ref, geom: Geometry, iters, step0, line_search=None):
@@ -809,17 +903,27 @@ def _pool_map(fn, items, threads):
         return list(ex.map(fn, items))
 
 
+def _ray_sums_all(u, geom: Geometry) -> np.ndarray:
+    """p[k] = R_k u for every angle: joseph.c for Joseph's sums, the dense
+    Fourier-slice matrices otherwise."""
+    if geom.projector == "fourier":
+        u = np.asarray(u, dtype=np.complex64).astype(np.complex128)
+        return np.stack([radon_fourier(u, th) for th in geom.theta])
+    return radon_set(u, geom.theta)
+
+
 def forward_many(u, q, geom: Geometry, threads: int = 8) -> np.ndarray:
     """`forward` for all angles: ray sums from joseph.c, then the frames of
     each angle (psi_k, phi_kj = M S psi_k, v_kj = D_{rho_det_j}(Q_j phi_kj))."""
     rho_d, _ = distances(geom.m0, geom.mag_rel)
-    p = radon_set(u, geom.theta)
+    p = _ray_sums_all(u, geom)
 
     def one(k):
         Q = probe_frames(q, geom, k) if geom.probe_shift is not None else probes(q, geom)
         psi = np.exp(1j * geom.kappa * p[k])
         return np.stack([propagate(Q[j] * transmit(psi, geom.mag_rel[j], *geom.t(k, j)),
-                                   rho_d[j], geom.fresnel0) for j in range(geom.n_dist)])
+                                   rho_d[j], geom.fresnel0, geom.pad)
+                         for j in range(geom.n_dist)])
 
     return np.stack(_pool_map(one, range(geom.n_angles), threads))
 
@@ -835,7 +939,7 @@ def gradient_projection_domain(u, q, amp, amp_ref, geom: Geometry, threads: int 
     order.  `progress(message)`, if given, is called after the ray sums and
     after each batch of angles."""
     _, rho_p = distances(geom.m0, geom.mag_rel)
-    p = radon_set(u, geom.theta)
+    p = _ray_sums_all(u, geom)
     if progress:
         progress("ray sums of %d angles done" % geom.n_angles)
     Q0 = probes(q, geom)
@@ -861,6 +965,6 @@ def gradient_projection_domain(u, q, amp, amp_ref, geom: Geometry, threads: int 
                 g_q += gqk
         if progress:
             progress("frames of angles %d-%d done" % (k0, min(k0 + batch, geom.n_angles) - 1))
-    g_q = g_q + sum(propagate(G[j], -rho_p[j], geom.fresnel0) for j in range(geom.n_dist))
-    Fr, gr = reference_term(q, amp_ref, geom.fresnel0, functional)
+    g_q = g_q + sum(propagate(G[j], -rho_p[j], geom.fresnel0, geom.pad) for j in range(geom.n_dist))
+    Fr, gr = reference_term(q, amp_ref, geom.fresnel0, functional, geom.pad)
     return F + Fr, p, g_q + gr

@@ -867,3 +867,242 @@ def test_holo2d_conventional_matches_the_tomographic_form_at_one_angle():
     h = -1j * geom.kappa * np.conj(psi) * gpsi
     np.testing.assert_allclose(O.radon_T(h, geom.theta[0], geom.W), gu,
                                atol=1e-10 * np.max(np.abs(gu)))
+
+
+# ---------------------------------------------------------------------------
+# Padded propagation (reading P1)
+# ---------------------------------------------------------------------------
+
+def _edge_gaussians(H, W, s0, s2):
+    """Two Gaussians of width s0 near opposite edges (bottom-left and
+    top-right) and their exact propagation by convolution with the Fresnel
+    kernel over the whole plane: (s0^2 / s2) exp(-|x - c|^2 / 2 s2)."""
+    y = np.arange(H)[:, None].astype(float)
+    x = np.arange(W)[None, :].astype(float)
+    f = np.zeros((H, W), complex)
+    exact = np.zeros((H, W), complex)
+    for (cy, cx, a) in ((H - 20.0, 20.0, 1.0), (18.0, W - 22.0, 0.5 - 0.3j)):
+        r2 = (x - cx) ** 2 + (y - cy) ** 2
+        f += a * np.exp(-r2 / (2 * s0 ** 2))
+        exact += a * (s0 ** 2 / s2) * np.exp(-r2 / (2 * s2))
+    return f, exact
+
+
+@pytest.mark.parametrize("rho", [1.885, -1.3])
+def test_padded_propagation_matches_the_whole_plane_convolution_near_the_edges(rho):
+    # A field near the grid's edges spreads across them: the padded
+    # propagation equals the convolution over the whole plane (the field
+    # being zero outside the grid) on every pixel, while the periodic one
+    # wraps the spread around to the opposite edges.
+    H, W, s0, nf = 64, 96, 3.0, 0.01
+    alpha = rho / nf
+    s2 = s0 ** 2 + 1j * alpha / (2 * np.pi)
+    f, exact = _edge_gaussians(H, W, s0, s2)
+    padded = O.propagate(f, rho, nf, pad=2)
+    assert np.max(np.abs(padded - exact)) < 1e-9
+    periodic = O.propagate(f, rho, nf)
+    assert np.max(np.abs(periodic - exact)) > 1e-2
+
+
+def test_padded_propagation_adjoint_contraction_and_pad_one():
+    rng = np.random.default_rng(5)
+    f, g = crandn(rng, 24, 40), crandn(rng, 24, 40)
+    a, nf = 0.9, 0.01
+    Df = O.propagate(f, a, nf, pad=2)
+    lhs = np.vdot(g, Df)
+    rhs = np.vdot(O.propagate(g, -a, nf, pad=2), f)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    # cutting out loses energy; setting in and cutting out with no
+    # propagation is the identity
+    assert np.linalg.norm(Df) < np.linalg.norm(f)
+    np.testing.assert_allclose(O.propagate(f, 0.0, nf, pad=2), f, atol=1e-13)
+    np.testing.assert_array_equal(O.propagate(f, a, nf, pad=1), O.propagate(f, a, nf))
+    # and it is not the periodic propagation
+    assert np.max(np.abs(Df - O.propagate(f, a, nf))) > 1e-3
+
+
+def _padded(geom):
+    geom.pad = 2
+    return geom
+
+
+def test_padded_model_central_differences():
+    geom, u, q, amp, amp_ref = tiny_problem(seed=31)
+    geom = _padded(geom)
+    F, gu, gq = O.gradient(u, q, amp, amp_ref, geom)
+    assert F == pytest.approx(O.objective(u, q, amp, amp_ref, geom), rel=1e-12)
+    geom1, *_ = tiny_problem(seed=31)
+    assert abs(F - O.objective(u, q, amp, amp_ref, geom1)) > 1e-6 * F
+    rng = np.random.default_rng(32)
+    for trial in range(3):
+        du = 1e-4 * crandn(rng, *u.shape)
+        dq = 1e-2 * crandn(rng, *q.shape)
+        eps = 1e-3
+        Fp = O.objective(u + eps * du, q + eps * dq, amp, amp_ref, geom)
+        Fm = O.objective(u - eps * du, q - eps * dq, amp, amp_ref, geom)
+        fd = (Fp - Fm) / (2 * eps)
+        an = np.real(np.vdot(gu, du)) + np.real(np.vdot(gq, dq))
+        assert an == pytest.approx(fd, rel=1e-6, abs=1e-9 * abs(F))
+
+
+def test_padded_model_adjoint_is_the_jacobian_transpose():
+    geom, u, q, _, _ = tiny_problem(seed=33)
+    geom = _padded(geom)
+    rng = np.random.default_rng(34)
+    du, dq = 1e-3 * crandn(rng, *u.shape), 1e-1 * crandn(rng, *q.shape)
+    w = crandn(rng, geom.n_angles, 4, geom.H, geom.W)
+    eps = 1e-4
+    Jx = (O.forward(u + eps * du, q + eps * dq, geom)
+          - O.forward(u - eps * du, q - eps * dq, geom)) / (2 * eps)
+    gu, gq = O.adjoint(u, q, w, geom)
+    lhs = np.vdot(w, Jx)
+    rhs = np.vdot(gu, du) + np.vdot(gq, dq)
+    assert abs(lhs - rhs) < 1e-6 * abs(lhs)
+
+
+def test_padded_projection_domain_gradient_equals_the_plain_loops():
+    geom, u, q, amp, amp_ref = tiny_problem(seed=35)
+    geom = _padded(geom)
+    F, gu, gq = O.gradient(u, q, amp, amp_ref, geom)
+    F2, h, gq2 = O.gradient_projection_domain(u.astype(np.complex64), q, amp, amp_ref, geom,
+                                              threads=2)
+    gu2 = O.radon_T_set(h, geom.theta, geom.W)
+    u32 = u.astype(np.complex64).astype(np.complex128)
+    F3, gu3, gq3 = O.gradient(u32, q, amp, amp_ref, geom)
+    assert F2 == pytest.approx(F3, rel=1e-12)
+    np.testing.assert_allclose(gu2, gu3, rtol=0, atol=1e-10 * np.abs(gu3).max())
+    np.testing.assert_allclose(gq2, gq3, rtol=0, atol=1e-10 * np.abs(gq3).max())
+
+
+# ---------------------------------------------------------------------------
+# Fourier-slice projector (reading F1)
+# ---------------------------------------------------------------------------
+
+def test_periodic_sinc_is_the_half_weighted_dirichlet_sum():
+    # D_W(d) = (1/W) sum_{m=-W/2}^{W/2} c_m e^{2 pi i m d / W}, c = 1/2 at
+    # the two Nyquist terms: the closed form against the sum itself
+    for W in (8, 16, 64):
+        d = np.linspace(-1.7 * W, 1.7 * W, 397)
+        m = np.arange(-W // 2, W // 2 + 1)
+        c = np.ones(len(m))
+        c[0] = c[-1] = 0.5
+        direct = (c[None, :] * np.exp(2j * np.pi * m[None, :] * d[:, None] / W)).sum(axis=1) / W
+        assert np.max(np.abs(direct.imag)) < 1e-12
+        np.testing.assert_allclose(O.periodic_sinc(d, W), direct.real, atol=1e-12)
+        # interpolating: 1 at 0 (and at multiples of W), 0 at the other integers
+        k = np.arange(-2 * W, 2 * W + 1)
+        np.testing.assert_allclose(O.periodic_sinc(k, W), (k % W == 0).astype(float), atol=1e-12)
+
+
+def test_fourier_slice_equals_the_dtft_along_the_line():
+    # The matrix form against the definition it restates: the slice's DTFT
+    # at m (cos, sin), Nyquist terms halved, inverse DFT at the bins
+    rng = np.random.default_rng(41)
+    W = 16
+    f = crandn(rng, W, W)
+    c = W // 2
+    xs = np.arange(W) - c
+    for th in (0.0, 0.37, 1.1, 2.5):
+        m = np.arange(-W // 2, W // 2 + 1)
+        t = xs[None, :] * np.cos(th) + xs[:, None] * np.sin(th)
+        F = np.array([np.sum(f * np.exp(-2j * np.pi * mm * t / W)) for mm in m])
+        cm = np.ones(len(m))
+        cm[0] = cm[-1] = 0.5
+        s = np.arange(W) - c
+        p_def = (cm[None, :] * F[None, :] * np.exp(2j * np.pi * m[None, :] * s[:, None] / W)).sum(1) / W
+        p = O.radon_fourier(f[None], th)[0]
+        np.testing.assert_allclose(p, p_def, atol=1e-12)
+
+
+def test_fourier_slice_axis_sums_and_real():
+    rng = np.random.default_rng(42)
+    u = crandn(rng, 3, 24, 24)
+    np.testing.assert_allclose(O.radon_fourier(u, 0.0), u.sum(axis=1), atol=1e-12)
+    np.testing.assert_allclose(O.radon_fourier(u, np.pi / 2), u.sum(axis=2), atol=1e-12)
+    r = rng.standard_normal((2, 24, 24))
+    assert np.max(np.abs(np.imag(O.radon_fourier(r.astype(complex), 0.83)))) < 1e-12
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.31, np.pi / 4, 1.3, 2.2, 3.0])
+def test_fourier_slice_projects_a_gaussian_exactly(theta):
+    # A Gaussian blob (width 3 px, off centre) is band-limited to double
+    # precision: its projection is sqrt(2 pi) sigma exp(-(s - s_c)^2 / 2 sigma^2)
+    # at every angle, s_c the projection of its centre.
+    W, sg = 64, 3.0
+    cy, cx = 7.3, -9.6
+    xs = np.arange(W) - W // 2
+    g = np.exp(-((xs[None, :] - cx) ** 2 + (xs[:, None] - cy) ** 2) / (2 * sg ** 2))
+    p = O.radon_fourier(g[None].astype(complex), theta)[0]
+    sc = cx * np.cos(theta) + cy * np.sin(theta)
+    s = np.arange(W) - W // 2
+    exact = np.sqrt(2 * np.pi) * sg * np.exp(-(s - sc) ** 2 / (2 * sg ** 2))
+    assert np.max(np.abs(p - exact)) < 1e-9 * exact.max()
+    if theta not in (0.0,):
+        # Joseph's linear interpolation is not exact for it
+        pj = O.radon(g[None].astype(complex), theta)[0]
+        assert np.max(np.abs(pj - exact)) > 1e-4 * exact.max()
+
+
+@pytest.mark.parametrize("theta", [0.4, 1.9])
+def test_fourier_slice_adjoint(theta):
+    rng = np.random.default_rng(43)
+    u, p = crandn(rng, 2, 20, 20), crandn(rng, 2, 20)
+    lhs = np.vdot(p, O.radon_fourier(u, theta))
+    rhs = np.vdot(O.radon_fourier_T(p, theta, 20), u)
+    assert abs(lhs - rhs) < 1e-11 * abs(lhs)
+
+
+def test_fourier_slice_ball_chords_and_closeness_to_joseph():
+    # a voxelised ball: chords 2 sqrt(r^2 - s^2) within the discretisation
+    # error (the same gate as Joseph's), and the two discretisations agree
+    # to within a few per cent on it
+    # (near the rim the chord has unbounded slope: the gate is on the inner
+    # half, as for Joseph's sums)
+    W, r = 64, 20.0
+    xs = np.arange(W) - W // 2
+    ball = ((xs[None, :] ** 2 + xs[:, None] ** 2) <= r * r).astype(complex)
+    s = np.arange(W) - W // 2
+    exact = 2 * np.sqrt(np.maximum(r * r - s * s, 0.0))
+    inner = exact > 0.5 * exact.max()
+    for th in (0.2, 0.9, 1.6, 2.7):
+        p = O.radon_fourier(ball[None], th)[0].real
+        err = np.abs(p - exact)
+        assert np.mean(err[inner] / exact[inner]) < 0.02 and err[inner].max() <= 2.0
+        pj = O.radon(ball[None], th)[0].real
+        assert np.linalg.norm(p - pj) / np.linalg.norm(pj) < 0.02
+
+
+def _fourier(geom):
+    geom.projector = "fourier"
+    return geom
+
+
+def test_fourier_model_central_differences_and_adjoint():
+    geom, u, q, amp, amp_ref = tiny_problem(seed=45)
+    geom = _fourier(geom)
+    F, gu, gq = O.gradient(u, q, amp, amp_ref, geom)
+    assert F == pytest.approx(O.objective(u, q, amp, amp_ref, geom), rel=1e-12)
+    rng = np.random.default_rng(46)
+    for trial in range(3):
+        du = 1e-4 * crandn(rng, *u.shape)
+        dq = 1e-2 * crandn(rng, *q.shape)
+        eps = 1e-3
+        Fp = O.objective(u + eps * du, q + eps * dq, amp, amp_ref, geom)
+        Fm = O.objective(u - eps * du, q - eps * dq, amp, amp_ref, geom)
+        an = np.real(np.vdot(gu, du)) + np.real(np.vdot(gq, dq))
+        assert an == pytest.approx((Fp - Fm) / (2 * eps), rel=1e-6, abs=1e-9 * abs(F))
+    du, dq = 1e-3 * crandn(rng, *u.shape), 1e-1 * crandn(rng, *q.shape)
+    w = crandn(rng, geom.n_angles, 4, geom.H, geom.W)
+    eps = 1e-4
+    Jx = (O.forward(u + eps * du, q + eps * dq, geom)
+          - O.forward(u - eps * du, q - eps * dq, geom)) / (2 * eps)
+    au, aq = O.adjoint(u, q, w, geom)
+    lhs = np.vdot(w, Jx)
+    assert abs(lhs - (np.vdot(au, du) + np.vdot(aq, dq))) < 1e-6 * abs(lhs)
+    F2, h, gq2 = O.gradient_projection_domain(u, q, amp, amp_ref, geom, threads=2)
+    u32 = u.astype(np.complex64).astype(np.complex128)
+    F3, gu3, gq3 = O.gradient(u32, q, amp, amp_ref, geom)
+    assert F2 == pytest.approx(F3, rel=1e-12)
+    np.testing.assert_allclose(gq2, gq3, rtol=0, atol=1e-10 * np.abs(gq3).max())
+    gu2 = sum(O.radon_fourier_T(h[k], geom.theta[k], geom.W) for k in range(geom.n_angles))
+    np.testing.assert_allclose(gu2, gu3, rtol=0, atol=1e-10 * np.abs(gu3).max())
