@@ -140,8 +140,8 @@ holo_status holo_plan_autotune(holo_plan* plan, const holo_c64* u, const holo_c6
                                int32_t n_cand, void* ws, size_t ws_bytes,
                                int32_t* best_chunk, float* times_ms, void* stream);
 
-/* The least-squares functional that holo_objective, holo_grad*, holo_cg
- * (and the residual they form) evaluate on this plan.
+/* The least-squares functional that holo_fwd, holo_adj, holo_objective,
+ * holo_grad*, holo_cg (and the residual they form) evaluate on this plan.
  *   AMPLITUDE (default): F2 of Eq. (10),
  *     sum || |v_kj| - a_kj ||^2 + || |D_1 q| - a_ref ||^2,
  *     amp and amp_ref hold the amplitudes a = sqrt(d~).
@@ -149,12 +149,63 @@ holo_status holo_plan_autotune(holo_plan* plan, const holo_c64* u, const holo_c6
  *     sum || |v_kj|^2 - d~_kj ||^2 + || |D_1 q|^2 - d~r ||^2,
  *     amp and amp_ref then hold the intensities d~ themselves; the residual
  *     is 4 (|v|^2 - d~) v.
+ *   CONVENTIONAL: the flat-field functional of Eq. (16), the model with
+ *     the probe replaced by 1 (Sec. 2: q = 1 gives the conventional form)
+ *     and no reference term,
+ *     sum || |D_{rho_det_j}(M_{1/m~_j} S_{t_kj} psi_k)| - a_kj ||^2,
+ *     amp holding sqrt(d_kj / d^r) (data divided by the reference image).
+ *     q and amp_ref must still be non-NULL but are not read, g_q is
+ *     written as 0 (F does not depend on q), holo_fwd gives the probe-free
+ *     fields and holo_cg leaves q unchanged.
  * Errors: INVALID_ARGUMENT (NULL plan, unknown value).  Host-only. */
 typedef enum {
   HOLO_FUNCTIONAL_AMPLITUDE = 0,
-  HOLO_FUNCTIONAL_INTENSITY = 1
+  HOLO_FUNCTIONAL_INTENSITY = 1,
+  HOLO_FUNCTIONAL_CONVENTIONAL = 2
 } holo_functional;
 holo_status holo_plan_set_functional(holo_plan* plan, int32_t functional);
+
+/* Propagation on a padded grid (Appendix A: D_Z is a convolution over the
+ * whole plane).  pad = 1 (default): every propagation is the transfer
+ * function on the periodic H x W grid.  pad = 2: every propagation of the
+ * model (probe to plane j, plane j to the detector, the reference, and
+ * their adjoints, also in holo_probe_init) sets the field in the centre of
+ * a 2H x 2W grid with zeros outside, applies that grid's transfer function
+ * (same pixel size) and keeps the centre H x W: the fields are taken as zero
+ * outside the field of view instead of periodic.  The frame stages then run
+ * as separate elementwise, row and column launches (slower than the fused
+ * passes of pad = 1).  The workspace size does not change.  Probe shifts
+ * are not taken with pad = 2: they are applied to the propagated probe,
+ * which equals shifting before the propagation only on the periodic grid.
+ * Errors: INVALID_ARGUMENT (NULL plan, pad not 1 or 2, pad = 2 on a plan
+ * with probe shifts, and holo_plan_set_probe_shifts on a padded plan),
+ * UNSUPPORTED_SIZE (pad = 2 with det_rows or det_cols above 1024).
+ * Host-only. */
+holo_status holo_plan_set_padding(holo_plan* plan, int32_t pad);
+
+/* The discretisation of the ray sums R_k (Eq. 14 names the Radon transform
+ * only).
+ *   JOSEPH (default): the ray-driven sums of the header above.
+ *   FOURIER: the Fourier slice theorem evaluated on each slice's
+ *     discrete-time Fourier transform, F(xi) = sum u[z][y][x]
+ *     exp(-2 pi i xi.(x', y') / W), at xi = m (cos, sin), m = -W/2 .. W/2
+ *     (the two Nyquist samples averaged), inverted by the W-point DFT at the
+ *     bins s = i - W/2; equivalently p[i] = sum u D_W(s_i - (x' cos +
+ *     y' sin)) with D_W(d) = sin(pi d) / (W tan(pi d / W)): line integrals
+ *     of each slice's trigonometric interpolant, no path factor.  Evaluated
+ *     by gridding on a twice-oversampled frequency grid (8-tap kernel,
+ *     approximation error a few 1e-8 relative) with O(W^2 log W + N_theta W)
+ *     work per slice instead of O(N_theta W^2).  Its transpose is the exact
+ *     transpose of the same computation.  Needs det_cols <= 1024; grows the
+ *     workspace by 8 grids of (2W)^2 and 8 N_theta (W + 2) samples (query
+ *     holo_workspace_bytes again).
+ * Errors: INVALID_ARGUMENT (NULL plan, unknown value), UNSUPPORTED_SIZE
+ * (FOURIER with det_cols above 1024).  Host-only. */
+typedef enum {
+  HOLO_PROJECTOR_JOSEPH = 0,
+  HOLO_PROJECTOR_FOURIER = 1
+} holo_projector;
+holo_status holo_plan_set_projector(holo_plan* plan, int32_t projector);
 
 /* Forward model: v_kj for the angles k0 <= k < k1 (Eq. 8 with Eq. 17). */
 holo_status holo_fwd(holo_plan* plan, const holo_c64* u, const holo_c64* q,

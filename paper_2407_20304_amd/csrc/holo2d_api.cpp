@@ -2,6 +2,7 @@
 // (holo2d_* in include/holo.h).
 #include "../../include/holo.h"
 #include "holo2d_internal.hpp"
+#include "holo_internal.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -201,9 +202,11 @@ extern "C" holo_status holo2d_plan_create(int32_t n_inst, const int32_t* sizes, 
 
 extern "C" holo_status holo2d_plan_set_functional(holo2d_plan* P, int32_t functional) {
   if (!P) return fail2(HOLO_ERR_INVALID_ARGUMENT, "holo2d_plan_set_functional: NULL plan");
-  if (functional != HOLO_FUNCTIONAL_AMPLITUDE && functional != HOLO_FUNCTIONAL_INTENSITY)
+  if (functional != HOLO_FUNCTIONAL_AMPLITUDE && functional != HOLO_FUNCTIONAL_INTENSITY &&
+      functional != HOLO_FUNCTIONAL_CONVENTIONAL)
     return fail2(HOLO_ERR_INVALID_ARGUMENT,
-                 "holo2d_plan_set_functional: functional must be 0 (amplitude) or 1 (intensity)");
+                 "holo2d_plan_set_functional: functional must be 0 (amplitude), 1 (intensity) or "
+                 "2 (conventional)");
   P->functional = functional;
   return HOLO_OK;
 }
@@ -305,9 +308,12 @@ holo_status b2_launch(holo2d_plan* P, B2Run run, const char* tb, char* w, const 
                       holo_c64* v_out, double* F, holo_c64* g_psi, holo_c64* g_q,
                       hipStream_t st) {
   auto items = [&](const ItemList& L) { return (const B2Item*)(tb + L.off); };
+  // The conventional functional: the model with q = 1 and no reference
+  // term (amplitude residual); F does not depend on q, so g_q = 0.
+  const bool conv = P->functional == HOLO_FUNCTIONAL_CONVENTIONAL;
   B2Args A{};
   A.nd = P->nd;
-  A.functional = P->functional;
+  A.functional = P->functional == HOLO_FUNCTIONAL_INTENSITY ? 1 : 0;
   A.max_n = P->dsizes.back();
   for (int j = 0; j < P->nd; ++j) A.mag[j] = P->mag[j];
   A.inst = (const B2Inst*)(tb + P->off_inst);
@@ -319,21 +325,29 @@ holo_status b2_launch(holo2d_plan* P, B2Run run, const char* tb, char* w, const 
   A.X = run == kB2Fwd ? (float2*)v_out : (float2*)(w + P->ws_X);
   A.G = (float2*)(w + P->ws_G);
   A.Fpart = (double*)(w + P->ws_F);
-  const bool want_ref = run != kB2Fwd;
+  const bool want_ref = run != kB2Fwd && !conv;
   const bool grad = run == kB2Grad && (g_psi || g_q);
+  const bool want_gq = grad && g_q && !conv;
   A.want_ref = want_ref ? 1 : 0;
   A.want_grad = grad ? 1 : 0;
   A.g_psi = (float2*)g_psi;
-  A.g_q = (float2*)g_q;
+  A.g_q = want_gq ? (float2*)g_q : nullptr;
 
   // probe stage
-  A.mode = kB2RowsProbe;
-  const ItemList& rp = want_ref ? P->rows_probe : P->rows_probe_noref;
-  B2_HIP(launch_b2_rows(A, items(rp), (int)rp.items.size(), st));
-  A.mode = kB2ColsProbe;
-  const ItemList& cp = want_ref ? P->cols_probe : P->cols_probe_noref;
-  B2_HIP(launch_b2_cols(A, items(cp), (int)cp.items.size(), st));
-  if (grad && g_q) {
+  if (conv) {
+    B2_HIP(launch_fill(A.Q, (size_t)P->total * P->nd, make_float2(1.f, 0.f), st));
+    // the reference's cost slots stay zero (a double 0 is all-zero bits)
+    if (run != kB2Fwd) B2_HIP(launch_fill_zero((float2*)A.Fpart, (size_t)P->n_slots, st));
+    if (grad && g_q) B2_HIP(launch_fill_zero((float2*)g_q, (size_t)P->total, st));
+  } else {
+    A.mode = kB2RowsProbe;
+    const ItemList& rp = want_ref ? P->rows_probe : P->rows_probe_noref;
+    B2_HIP(launch_b2_rows(A, items(rp), (int)rp.items.size(), st));
+    A.mode = kB2ColsProbe;
+    const ItemList& cp = want_ref ? P->cols_probe : P->cols_probe_noref;
+    B2_HIP(launch_b2_cols(A, items(cp), (int)cp.items.size(), st));
+  }
+  if (want_gq) {
     A.mode = kB2RowsRef;
     B2_HIP(launch_b2_rows(A, items(P->rows_ref), (int)P->rows_ref.items.size(), st));
     A.mode = kB2ColsRef;
@@ -348,7 +362,7 @@ holo_status b2_launch(holo2d_plan* P, B2Run run, const char* tb, char* w, const 
   if (grad) {
     A.mode = kB2RowsC;
     B2_HIP(launch_b2_rows(A, items(P->rows_nd), (int)P->rows_nd.items.size(), st));
-    if (g_q) {
+    if (want_gq) {
       A.mode = kB2RowsGq;
       B2_HIP(launch_b2_rows(A, items(P->rows_nd), (int)P->rows_nd.items.size(), st));
       A.mode = kB2ColsGq;
@@ -356,7 +370,7 @@ holo_status b2_launch(holo2d_plan* P, B2Run run, const char* tb, char* w, const 
     }
     B2_HIP(launch_b2_gather(A, items(P->gather), (int)P->gather.items.size(), st));
   }
-  if (F && want_ref)
+  if (F && run != kB2Fwd)
     B2_HIP(launch_b2_reduce(A.Fpart, (const int2*)(tb + P->off_ranges), P->n_inst, F, st));
   return HOLO_OK;
 }

@@ -55,6 +55,18 @@ struct holo_plan {
   bool pshift_dirty = false;                // device copy older than pshift
   std::vector<double> ang;                  // [n_angles][kAngleStride]
   std::vector<float2> twW, twH, chirpW, chirpH;
+  // padded propagation (reading P1): 1 = periodic, 2 = padded; the tables
+  // of lengths 2W and 2H exist when both edges are at most 1024
+  int pad = 1;
+  std::vector<float2> tw2W, tw2H, chirp2W, chirp2H;
+  // Fourier-slice projector (reading F1): HOLO_PROJECTOR_*, and its tables
+  // (built when W <= 1024): 1 / kernel transform, angles sorted modulo pi,
+  // first sorted position of every angle bin
+  int projector = HOLO_PROJECTOR_JOSEPH;
+  std::vector<float> fs_dinv;
+  std::vector<int> fs_sorted, fs_bins;
+  size_t off_fsdinv = 0, off_fssorted = 0, off_fsbins = 0;
+  size_t off_fsG = 0, off_fsA = 0;
   bool any_xwalk = false;
   // forward ray-sum angle groups: consecutive angles of one walk direction
   // whose staged row windows fit (first, count); group_of[k] = group index
@@ -68,6 +80,7 @@ struct holo_plan {
   int device = -1;
   size_t off_twW = 0, off_twH = 0, off_chW = 0, off_chH = 0, off_ang = 0, off_shift = 0,
          off_groups = 0, off_pshift = 0, table_bytes = 0, off_Pbuf = 0;
+  size_t off_tw2W = 0, off_tw2H = 0, off_ch2W = 0, off_ch2H = 0;
   // timing diagnostics
   bool timing = false;
   std::vector<hipEvent_t> ev_free;
@@ -101,6 +114,51 @@ static void build_twiddles(std::vector<float2>& out, int n) {
 }
 
 static bool is_finite(double x) { return std::isfinite(x); }
+
+// Fourier-slice tables.  The gridding kernel exp(beta (sqrt(1 - (2x/KW)^2) - 1))
+// on |x| < KW/2 has the transform phihat(k) = int phi(x) cos(2 pi k x / M) dx
+// (M = 2W grid points); with x = (KW/2) sin(t) the integrand is smooth, and
+// Simpson's rule on t in [0, pi/2] gives it to double precision.
+static double fs_beta() { return 2.3 * kFsWidth; }
+
+static void build_fs_tables(holo_plan* P) {
+  const int W = P->W;
+  const double M = 2.0 * W, h = 0.5 * kFsWidth, beta = fs_beta();
+  const int n = 4096;                           // Simpson intervals (even)
+  P->fs_dinv.resize(W);
+  for (int x = 0; x < W; ++x) {
+    const double k = (double)(x - W / 2);
+    double acc = 0.0;
+    for (int i = 0; i <= n; ++i) {
+      const double t = 0.5 * M_PI * i / n;
+      const double f = std::exp(beta * (std::cos(t) - 1.0)) * std::cos(2.0 * M_PI * k * h * std::sin(t) / M) *
+                       h * std::cos(t);
+      acc += f * ((i == 0 || i == n) ? 1.0 : (i % 2 ? 4.0 : 2.0));
+    }
+    const double phihat = 2.0 * acc * (0.5 * M_PI / n) / 3.0;   // both halves
+    P->fs_dinv[x] = (float)(1.0 / phihat);
+  }
+  // angles sorted by theta mod pi, and the first sorted position of every
+  // bin [b pi / B, (b + 1) pi / B)
+  std::vector<double> tm(P->n_angles);
+  for (int k = 0; k < P->n_angles; ++k) {
+    double t = std::fmod(P->theta[k], M_PI);
+    if (t < 0) t += M_PI;
+    if (t >= M_PI) t -= M_PI;
+    tm[k] = t;
+  }
+  P->fs_sorted.resize(P->n_angles);
+  for (int k = 0; k < P->n_angles; ++k) P->fs_sorted[k] = k;
+  std::stable_sort(P->fs_sorted.begin(), P->fs_sorted.end(),
+                   [&](int a, int b) { return tm[a] < tm[b]; });
+  P->fs_bins.assign(kFsBins + 1, P->n_angles);
+  int pos = 0;
+  for (int b = 0; b <= kFsBins; ++b) {
+    const double lo = M_PI * b / kFsBins;
+    while (pos < P->n_angles && tm[P->fs_sorted[pos]] < lo) ++pos;
+    P->fs_bins[b] = b == kFsBins ? P->n_angles : pos;
+  }
+}
 
 // Can angles [a, b) share the staged row windows of the forward ray sums?
 // For each (bin block, row) the window starts one column below the lowest
@@ -148,12 +206,21 @@ static void layout_workspace(holo_plan* P) {
   P->off_X = o;   o = align_up(o + fr * P->chunk * P->nd);
   // sinogram rows carry kAdjPad zero bins on each side
   P->off_S = o;   o = align_up(o + (size_t)P->H * sino_row(P->W) * sizeof(float2) * P->n_angles);
-  const size_t tiles = (size_t)P->W / cols_per_wg(P->H);
+  // column tiles per frame: the padded column pass has at least as many
+  // as the periodic one, so one size serves both
+  const size_t tiles = (size_t)std::max(P->W / cols_per_wg(P->H),
+                                        P->chirp2W.empty() ? 0 : pad_col_tiles(P->H, P->W));
   P->n_fpart = tiles * (1 + (size_t)P->n_angles * P->nd);
   // cost partials, then the reduction's stage-one sums
   P->off_F = o;   o = align_up(o + (P->n_fpart + kReduceParts) * sizeof(double));
   // with probe shifts: conj(phi) w of every frame of a chunk
   P->off_Pbuf = o; o = align_up(o + (P->pshift.empty() ? 0 : fr * P->chunk * P->nd));
+  // Fourier-slice projector: the grids of one slab and its polar samples
+  const bool fs = P->projector == HOLO_PROJECTOR_FOURIER;
+  const size_t M = 2 * (size_t)P->W;
+  P->off_fsG = o; o = align_up(o + (fs ? (size_t)kFsSlab * M * M * sizeof(float2) : 0));
+  P->off_fsA = o;
+  o = align_up(o + (fs ? (size_t)kFsSlab * P->n_angles * (P->W + 2) * sizeof(float2) : 0));
   P->ws_bytes = o;
 }
 
@@ -255,6 +322,15 @@ extern "C" holo_status holo_plan_create(const holo_geom* geom, holo_plan** out) 
     build_chirp(P->chirpH, P->H, rhos, P->fresnel0);
     build_twiddles(P->twW, P->W);
     build_twiddles(P->twH, P->H);
+    if (pad_size_supported(P->H) && pad_size_supported(P->W)) {
+      build_chirp(P->chirp2W, 2 * P->W, rhos, P->fresnel0);
+      build_chirp(P->chirp2H, 2 * P->H, rhos, P->fresnel0);
+      build_twiddles(P->tw2H, 2 * P->H);
+    }
+    if (fs_size_supported(P->W)) {
+      build_twiddles(P->tw2W, 2 * P->W);
+      build_fs_tables(P);
+    }
 
     layout_workspace(P);
 
@@ -269,6 +345,13 @@ extern "C" holo_status holo_plan_create(const holo_geom* geom, holo_plan** out) 
     P->off_groups = t; t = align_up(t + P->groups.size() * sizeof(int2));
     // probe shifts (room for all of them, filled when set)
     P->off_pshift = t; t = align_up(t + (size_t)P->n_angles * P->nd * 2 * sizeof(float));
+    P->off_tw2W = t;  t = align_up(t + P->tw2W.size() * sizeof(float2));
+    P->off_tw2H = t;  t = align_up(t + P->tw2H.size() * sizeof(float2));
+    P->off_ch2W = t;  t = align_up(t + P->chirp2W.size() * sizeof(float2));
+    P->off_ch2H = t;  t = align_up(t + P->chirp2H.size() * sizeof(float2));
+    P->off_fsdinv = t;  t = align_up(t + P->fs_dinv.size() * sizeof(float));
+    P->off_fssorted = t; t = align_up(t + P->fs_sorted.size() * sizeof(int));
+    P->off_fsbins = t;  t = align_up(t + P->fs_bins.size() * sizeof(int));
     P->table_bytes = t + 256;
   } catch (const std::bad_alloc&) {
     delete P;
@@ -387,6 +470,13 @@ holo_status ensure_tables(holo_plan* P) {
   if (e == hipSuccess) e = put(P->off_shift, P->shift.data(), P->shift.size() * sizeof(float));
   if (e == hipSuccess) e = put(P->off_groups, P->groups.data(), P->groups.size() * sizeof(int2));
   if (e == hipSuccess) e = put(P->off_pshift, P->pshift.data(), P->pshift.size() * sizeof(float));
+  if (e == hipSuccess) e = put(P->off_tw2W, P->tw2W.data(), P->tw2W.size() * sizeof(float2));
+  if (e == hipSuccess) e = put(P->off_tw2H, P->tw2H.data(), P->tw2H.size() * sizeof(float2));
+  if (e == hipSuccess) e = put(P->off_ch2W, P->chirp2W.data(), P->chirp2W.size() * sizeof(float2));
+  if (e == hipSuccess) e = put(P->off_ch2H, P->chirp2H.data(), P->chirp2H.size() * sizeof(float2));
+  if (e == hipSuccess) e = put(P->off_fsdinv, P->fs_dinv.data(), P->fs_dinv.size() * sizeof(float));
+  if (e == hipSuccess) e = put(P->off_fssorted, P->fs_sorted.data(), P->fs_sorted.size() * sizeof(int));
+  if (e == hipSuccess) e = put(P->off_fsbins, P->fs_bins.data(), P->fs_bins.size() * sizeof(int));
   if (e != hipSuccess) {
     (void)hipFree(d);
     return hip_fail(e, "uploading plan tables");
@@ -413,8 +503,14 @@ DevGeom make_geom(const holo_plan* P) {
   g.chirpW = (const float2*)(b + P->off_chW);
   g.chirpH = (const float2*)(b + P->off_chH);
   g.shift = P->shift.empty() ? nullptr : (const float*)(b + P->off_shift);
-  g.functional = P->functional;
+  // the conventional functional has the amplitude residual
+  g.functional = P->functional == HOLO_FUNCTIONAL_INTENSITY ? 1 : 0;
   g.pshift = P->pshift.empty() ? nullptr : (const float*)(b + P->off_pshift);
+  const bool tabs = !P->chirp2W.empty();
+  g.tw2W = P->tw2W.empty() ? nullptr : (const float2*)(b + P->off_tw2W);
+  g.tw2H = tabs ? (const float2*)(b + P->off_tw2H) : nullptr;
+  g.chirp2W = tabs ? (const float2*)(b + P->off_ch2W) : nullptr;
+  g.chirp2H = tabs ? (const float2*)(b + P->off_ch2H) : nullptr;
   return g;
 }
 
@@ -451,15 +547,60 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
   double* Fpart = (double*)(wsb + P->off_F);
   float2* Pbuf = P->pshift.empty() ? nullptr : (float2*)(wsb + P->off_Pbuf);
   const double* d_ang = (const double*)((const char*)P->d_tables + P->off_ang);
-  const int tiles = W / cols_per_wg(H);
+  const bool padded = P->pad == 2;
+  const int tiles = padded ? pad_col_tiles(H, W) : W / cols_per_wg(H);
+  // a padded propagation over `n` frames (see PadJob)
+  auto pj = [&](const float2* src, float2* dst, long long step, int n, int chirp0, int cmod,
+                int conj, int pmode, const float* a, int fslot0) {
+    PadJob jb;
+    jb.src = src;
+    jb.dst = dst;
+    jb.amp = a;
+    jb.src_step = step;
+    jb.nframes = n;
+    jb.chirp0 = chirp0;
+    jb.cmod = cmod;
+    jb.conj = conj;
+    jb.mode = pmode;
+    jb.fslot0 = fslot0;
+    return jb;
+  };
+  const long long hw = (long long)HW;
 
+  // The conventional functional is the model with q = 1 and no reference
+  // term: F does not depend on q, so g_q = 0.
+  const bool conv = P->functional == HOLO_FUNCTIONAL_CONVENTIONAL;
   const bool want_F = (mode == kObj || mode == kGrad) && F;
-  const bool want_gq = (mode == kAdj || mode == kGrad) && gq;
+  const bool want_gq = (mode == kAdj || mode == kGrad) && gq && !conv;
   const bool want_gu = (mode == kAdj || mode == kGrad) && gu;
-  const bool with_ref = (mode == kObj || mode == kGrad);
+  const bool with_ref = (mode == kObj || mode == kGrad) && !conv;
 
   // Probe stage.
-  {
+  if (conv) {
+    HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] {
+      return launch_fill(Q, nd * HW, make_float2(1.f, 0.f), st);
+    }));
+    if ((mode == kAdj || mode == kGrad) && gq)
+      HOLO_HIP(timed(P, HOLO_K_OTHER, st, [&] { return launch_fill_zero(gq, HW, st); }));
+  } else if (padded) {
+    const int cp = chirp_probe(nd, 0), cr = chirp_ref(nd);
+    const PadJob rq = pj(q, Q, 0, nd, cp, nd, 0, 0, nullptr, 0);
+    const PadJob cq = pj(Q, Q, hw, nd, cp, nd, 0, 0, nullptr, 0);
+    HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_rows_pad(g, rq, st); }));
+    HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_cols_pad(g, cq, Fpart, st); }));
+    if (with_ref) {
+      // the reference field, its residual (cost slots 0 .. tiles - 1) and,
+      // for the probe gradient, its adjoint propagation
+      const PadJob rr = pj(q, Pref, 0, 1, cr, 1, 0, 0, nullptr, 0);
+      const PadJob cr2 = pj(Pref, Pref, hw, 1, cr, 1, 0, want_gq ? 1 : 2, amp_ref, 0);
+      HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_rows_pad(g, rr, st); }));
+      HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_cols_pad(g, cr2, Fpart, st); }));
+      if (want_gq) {
+        const PadJob ra = pj(Pref, Pref, hw, 1, cr, 1, 1, 0, nullptr, 0);
+        HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_rows_pad(g, ra, st); }));
+      }
+    }
+  } else {
     PropJobs rj{}, cj{};
     for (int j = 0; j < nd; ++j) {
       rj.job[rj.n++] = PropJob{q, Q + j * HW, nullptr, chirp_probe(nd, j), 0, 0};
@@ -479,11 +620,36 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
       HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_cols_prop(g, c2, Fpart, st); }));
     }
   }
-  bool xwalk = false;
-  for (int k = k0; k < k1; ++k) xwalk |= P->ang[(size_t)k * kAngleStride + kBranch] != 0.0;
-  HOLO_HIP(timed(P, HOLO_K_OTHER, st, [&] {
-    return launch_block_volume(g, u, ub, xwalk ? uTb : nullptr, st);
-  }));
+  // Fourier-slice projector: psi of every angle of the call into the
+  // sinogram buffer now, slab by slab; the chunks copy theirs from there
+  const bool fs = P->projector == HOLO_PROJECTOR_FOURIER;
+  FsArgs fa{};
+  float2* fsG = (float2*)(wsb + P->off_fsG);
+  float2* fsA = (float2*)(wsb + P->off_fsA);
+  const int Wp = sino_row(W);
+  if (fs) {
+    const char* tb = (const char*)P->d_tables;
+    fa.K = k1 - k0;
+    fa.k0 = k0;
+    fa.n_angles = P->n_angles;
+    fa.beta = (float)fs_beta();
+    fa.dinv = (const float*)(tb + P->off_fsdinv);
+    fa.ang = d_ang;
+    fa.sorted_k = (const int*)(tb + P->off_fssorted);
+    fa.bin_first = (const int*)(tb + P->off_fsbins);
+    for (int z0 = 0; z0 < H; z0 += kFsSlab) {
+      const int nz = std::min(kFsSlab, H - z0);
+      HOLO_HIP(timed(P, HOLO_K_RADON_FWD, st, [&] {
+        return launch_fs_forward_slab(g, fa, u + (size_t)z0 * W * W, fsG, S, z0, nz, st);
+      }));
+    }
+  } else {
+    bool xwalk = false;
+    for (int k = k0; k < k1; ++k) xwalk |= P->ang[(size_t)k * kAngleStride + kBranch] != 0.0;
+    HOLO_HIP(timed(P, HOLO_K_OTHER, st, [&] {
+      return launch_block_volume(g, u, ub, xwalk ? uTb : nullptr, st);
+    }));
+  }
   if (want_gq) HOLO_HIP(timed(P, HOLO_K_OTHER, st, [&] { return launch_fill_zero(Gacc, nd * HW, st); }));
 
   const bool frames_back = want_gq || want_gu;
@@ -501,11 +667,58 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
     if (c1 == c0) c1 = std::min(c0 + P->chunk, k1);
     const int Kc = c1 - c0;
     const int gfirst = P->group_of[c0], glast = P->group_of[c1 - 1];
-    HOLO_HIP(timed(P, HOLO_K_RADON_FWD, st, [&] {
-      return launch_radon_fwd(g, ub, uTb, psi, d_ang, d_groups, gfirst, glast - gfirst + 1, c0, c1,
-                              st);
-    }));
+    if (fs) {
+      HOLO_HIP(timed(P, HOLO_K_OTHER, st, [&] {
+        return launch_copy_rows(S + (size_t)(c0 - k0) * H * Wp + kAdjPad, Wp, psi, (size_t)Kc * H,
+                                W, st);
+      }));
+    } else {
+      HOLO_HIP(timed(P, HOLO_K_RADON_FWD, st, [&] {
+        return launch_radon_fwd(g, ub, uTb, psi, d_ang, d_groups, gfirst, glast - gfirst + 1, c0,
+                                c1, st);
+      }));
+    }
     double* Fc = Fpart + (size_t)tiles * (1 + (size_t)(c0 - k0) * nd);
+    if (padded) {
+      // the unfused sequence: elementwise pass A, padded rows, padded
+      // columns (with the residual and the adjoint columns), padded adjoint
+      // rows, elementwise pass C
+      const int nf = Kc * nd;
+      float2* F0 = mode == kFwd ? v_out + (size_t)(c0 - k0) * nd * HW : X;
+      if (mode != kAdj) {
+        HOLO_HIP(timed(P, HOLO_K_PASS_A, st, [&] {
+          return launch_frames_x(g, psi, Q, F0, c0, Kc, st);
+        }));
+        const PadJob rf = pj(F0, F0, hw, nf, chirp_det(0), nd, 0, 0, nullptr, 0);
+        HOLO_HIP(timed(P, HOLO_K_PASS_A, st, [&] { return launch_rows_pad(g, rf, st); }));
+      }
+      PadJob cf;
+      if (mode == kFwd) {
+        cf = pj(F0, F0, hw, nf, chirp_det(0), nd, 0, 0, nullptr, 0);
+      } else if (mode == kAdj) {
+        cf = pj(w_in + (size_t)(c0 - k0) * nd * HW, X, hw, nf, chirp_det(0), nd, 1, 0, nullptr, 0);
+      } else {
+        cf = pj(X, X, hw, nf, chirp_det(0), nd, 0, frames_back ? 1 : 2,
+                amp + (size_t)c0 * nd * HW, (int)(Fc - Fpart));
+      }
+      HOLO_HIP(timed(P, HOLO_K_PASS_B, st, [&] { return launch_cols_pad(g, cf, Fpart, st); }));
+      if ((mode == kGrad || mode == kAdj) && frames_back) {
+        const PadJob ra = pj(X, X, hw, nf, chirp_det(0), nd, 1, 0, nullptr, 0);
+        HOLO_HIP(timed(P, HOLO_K_PASS_C, st, [&] { return launch_rows_pad(g, ra, st); }));
+        HOLO_HIP(timed(P, HOLO_K_PASS_C, st, [&] {
+          return launch_frames_c(g, X, psi, Q, Gacc, Pbuf, want_gq ? 1 : 0, c0, Kc, st);
+        }));
+        if (want_gq && Pbuf)
+          HOLO_HIP(timed(P, HOLO_K_PASS_C, st, [&] {
+            return launch_probe_shift_acc(g, Gacc, Pbuf, c0, Kc, st);
+          }));
+        if (want_gu)
+          HOLO_HIP(timed(P, HOLO_K_PASS_D, st, [&] {
+            return launch_pass_d(g, X, psi, S + (size_t)(c0 - k0) * H * sino_row(W), c0, Kc, st);
+          }));
+      }
+      continue;
+    }
     switch (mode) {
       case kFwd: {
         float2* v = v_out + (size_t)(c0 - k0) * nd * HW;
@@ -546,26 +759,44 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
         }));
     }
   }
-  if (want_gu)
+  if (want_gu && fs) {
+    for (int z0 = 0; z0 < H; z0 += kFsSlab) {
+      const int nz = std::min(kFsSlab, H - z0);
+      HOLO_HIP(timed(P, HOLO_K_RADON_ADJ, st, [&] {
+        return launch_fs_adjoint_slab(g, fa, S, fsA, fsG, gu + (size_t)z0 * W * W, z0, nz, st);
+      }));
+    }
+  } else if (want_gu) {
     HOLO_HIP(timed(P, HOLO_K_RADON_ADJ, st, [&] {
       return launch_radon_adj(g, S, gu, d_ang + (size_t)k0 * kAngleStride, k1 - k0, st);
     }));
+  }
   if (want_gq) {
-    PropJobs rj{}, cj{};
-    for (int j = 0; j < nd; ++j) {
-      rj.job[rj.n++] = PropJob{Gacc + j * HW, Gacc + j * HW, nullptr, chirp_probe(nd, j), 1, 0};
-      cj.job[cj.n++] = PropJob{Gacc + j * HW, Gacc + j * HW, nullptr, chirp_probe(nd, j), 1, 0};
+    if (padded) {
+      const int cp = chirp_probe(nd, 0);
+      const PadJob rg = pj(Gacc, Gacc, hw, nd, cp, nd, 1, 0, nullptr, 0);
+      const PadJob cg = pj(Gacc, Gacc, hw, nd, cp, nd, 1, 0, nullptr, 0);
+      HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_rows_pad(g, rg, st); }));
+      HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_cols_pad(g, cg, Fpart, st); }));
+    } else {
+      PropJobs rj{}, cj{};
+      for (int j = 0; j < nd; ++j) {
+        rj.job[rj.n++] = PropJob{Gacc + j * HW, Gacc + j * HW, nullptr, chirp_probe(nd, j), 1, 0};
+        cj.job[cj.n++] = PropJob{Gacc + j * HW, Gacc + j * HW, nullptr, chirp_probe(nd, j), 1, 0};
+      }
+      HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_rows_prop(g, rj, st); }));
+      HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_cols_prop(g, cj, Fpart, st); }));
     }
-    HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_rows_prop(g, rj, st); }));
-    HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_cols_prop(g, cj, Fpart, st); }));
     HOLO_HIP(timed(P, HOLO_K_OTHER, st, [&] {
       return launch_sum_frames(Gacc, nd, with_ref ? Pref : nullptr, gq, HW, st);
     }));
   }
   if (want_F) {
-    const size_t n = (size_t)tiles * (1 + (size_t)(k1 - k0) * nd);
+    // the first `tiles` slots hold the reference term's cost
+    const size_t first = with_ref ? 0 : (size_t)tiles;
+    const size_t n = (size_t)tiles * (1 + (size_t)(k1 - k0) * nd) - first;
     HOLO_HIP(timed(P, HOLO_K_OTHER, st, [&] {
-      return launch_reduce_sum(Fpart, n, Fpart + P->n_fpart, F, st);
+      return launch_reduce_sum(Fpart + first, n, Fpart + P->n_fpart, F, st);
     }));
   }
   return HOLO_OK;
@@ -682,6 +913,12 @@ extern "C" holo_status holo_probe_init(holo_plan* P, const float* amp_ref, holo_
   HOLO_HIP(timed(P, HOLO_K_PROBE, st,
                  [&] { return launch_real_to_c64(amp_ref, q, (size_t)P->H * P->W, st); }));
   // D_{-1}: the reference step with the conjugate transfer, rows then columns
+  if (P->pad == 2) {
+    PadJob jb{q, q, nullptr, (long long)P->H * P->W, 1, chirp_ref(P->nd), 1, 1, 0, 0};
+    HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_rows_pad(g, jb, st); }));
+    HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_cols_pad(g, jb, nullptr, st); }));
+    return HOLO_OK;
+  }
   PropJobs rj{}, cj{};
   rj.job[rj.n++] = PropJob{q, q, nullptr, chirp_ref(P->nd), 1, 0};
   cj.job[cj.n++] = PropJob{q, q, nullptr, chirp_ref(P->nd), 1, 0};
@@ -813,6 +1050,9 @@ extern "C" holo_status holo_cg(holo_plan* P, holo_c64* u_, holo_c64* q_, const f
 extern "C" holo_status holo_plan_set_probe_shifts(holo_plan* P, const float* shifts) {
   if (!P) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_set_probe_shifts: plan is NULL");
   const size_t n = (size_t)P->n_angles * P->nd * 2;
+  if (shifts && P->pad == 2)
+    return fail(HOLO_ERR_INVALID_ARGUMENT,
+                "holo_plan_set_probe_shifts: padded propagation does not take probe shifts");
   if (shifts) {
     for (size_t i = 0; i < n; ++i)
       if (!std::isfinite(shifts[i]))
@@ -930,9 +1170,36 @@ extern "C" holo_status holo_plan_ray_groups(const holo_plan* P, int32_t* first, 
   return HOLO_OK;
 }
 
+extern "C" holo_status holo_plan_set_projector(holo_plan* P, int32_t projector) {
+  if (!P) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_set_projector: plan is NULL");
+  if (projector != HOLO_PROJECTOR_JOSEPH && projector != HOLO_PROJECTOR_FOURIER)
+    return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_set_projector: unknown projector");
+  if (projector == HOLO_PROJECTOR_FOURIER && P->fs_dinv.empty())
+    return fail(HOLO_ERR_UNSUPPORTED_SIZE,
+                "holo_plan_set_projector: the Fourier-slice projector needs det_cols <= 1024");
+  P->projector = projector;
+  layout_workspace(P);
+  return HOLO_OK;
+}
+
+extern "C" holo_status holo_plan_set_padding(holo_plan* P, int32_t pad) {
+  if (!P) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_set_padding: plan is NULL");
+  if (pad != 1 && pad != 2)
+    return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_set_padding: pad must be 1 or 2");
+  if (pad == 2 && P->chirp2W.empty())
+    return fail(HOLO_ERR_UNSUPPORTED_SIZE,
+                "holo_plan_set_padding: padded propagation needs det_rows and det_cols <= 1024");
+  if (pad == 2 && !P->pshift.empty())
+    return fail(HOLO_ERR_INVALID_ARGUMENT,
+                "holo_plan_set_padding: padded propagation does not take probe shifts");
+  P->pad = pad;
+  return HOLO_OK;
+}
+
 extern "C" holo_status holo_plan_set_functional(holo_plan* P, int32_t functional) {
   if (!P) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_set_functional: plan is NULL");
-  if (functional != HOLO_FUNCTIONAL_AMPLITUDE && functional != HOLO_FUNCTIONAL_INTENSITY)
+  if (functional != HOLO_FUNCTIONAL_AMPLITUDE && functional != HOLO_FUNCTIONAL_INTENSITY &&
+      functional != HOLO_FUNCTIONAL_CONVENTIONAL)
     return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_set_functional: unknown functional");
   P->functional = functional;
   return HOLO_OK;

@@ -33,8 +33,45 @@ struct DevGeom {
   const float2* chirpW;      // [3 nd + 1][W] transfer factors, times 1/W
   const float2* chirpH;      // [3 nd + 1][H] transfer factors, times 1/H
   const float* shift;        // [n_angles][nd][2] (t_y, t_x) or nullptr
-  int functional;            // 0: amplitude residual (F2), 1: intensity (F1)
+  int functional;            // residual: 0 amplitude (F2 and the conventional
+                             // functional), 1 intensity (F1)
   const float* pshift;       // [n_angles][nd][2] (s_y, s_x) probe shifts or nullptr
+  // padded propagation (lines set in the centre of lines twice as long):
+  // twiddles and transfer rows of lengths 2W and 2H, or nullptr
+  const float2* tw2W;        // [2W]
+  const float2* tw2H;        // [2H]
+  const float2* chirp2W;     // [2 nd + 1][2W], times 1/(2W)
+  const float2* chirp2H;     // [2 nd + 1][2H], times 1/(2H)
+};
+
+// Fourier-slice projector (holo_fs.hip): gridding kernel taps per axis,
+// slices per slab, and the bins of the transpose's angle-window table.
+constexpr int kFsWidth = 8;
+constexpr int kFsSlab = 8;
+constexpr int kFsBins = 4096;
+struct FsArgs {
+  int K, k0;                 // the call's angles: plan angles k0 .. k0 + K - 1
+  int n_angles;              // plan angles
+  float beta;                // kernel shape exp(beta (sqrt(1 - (2x/KW)^2) - 1))
+  const float* dinv;         // [W] 1 / (Fourier transform of the kernel) at x - W/2
+  const double* ang;         // plan angle table (kAngleStride doubles per angle)
+  const int* sorted_k;       // [n_angles] plan angles sorted by theta mod pi
+  const int* bin_first;      // [kFsBins + 1] first sorted position at or past bin b
+};
+
+// One padded propagation over a set of frames (H x W each): frame f reads
+// src + f * src_step and writes dst + f * H * W; its transfer row is
+// chirp0 + f % cmod (conjugated when conj).  Rows apply the transfer only.
+// Columns: mode 0 the transfer only; mode 1 the transfer, the residual
+// against amp + f * H * W (cost into Fpart[fslot0 + f * ntiles + tile]) and
+// then the conjugate transfer; mode 2 the transfer and the residual's cost
+// only (nothing written).
+struct PadJob {
+  const float2* src;
+  float2* dst;
+  const float* amp;
+  long long src_step;
+  int nframes, chirp0, cmod, conj, mode, fslot0;
 };
 
 // Transfer-function table rows: detector step of plane j, probe step of
@@ -92,6 +129,29 @@ hipError_t launch_rows_prop(const DevGeom& g, const PropJobs& jobs, hipStream_t 
 hipError_t launch_cols_prop(const DevGeom& g, const PropJobs& jobs, double* Fpart, hipStream_t st);
 hipError_t launch_pass_a(const DevGeom& g, const float2* psi, const float2* Q, float2* X,
                          int k_first, int Kc, hipStream_t st);
+// Padded propagation (row and column halves) and the elementwise parts of
+// passes A and C that surround it when the plan propagates padded.
+bool pad_size_supported(int n);
+int pad_col_tiles(int H, int W);  // column tiles per frame of the padded column pass
+hipError_t launch_rows_pad(const DevGeom& g, const PadJob& jb, hipStream_t st);
+hipError_t launch_cols_pad(const DevGeom& g, const PadJob& jb, double* Fpart, hipStream_t st);
+// Fourier-slice forward of slices z0 .. z0 + nz - 1 (nz <= kFsSlab): psi of
+// every angle of the call into S[k][z][kAdjPad + s]; and its transpose from
+// h in S into g_u of those slices.  G: kFsSlab grids of (2W)^2; A:
+// kFsSlab * K * (W + 2) polar samples.
+bool fs_size_supported(int W);
+hipError_t launch_fs_forward_slab(const DevGeom& g, const FsArgs& f, const float2* u_slab,
+                                  float2* G, float2* S, int z0, int nz, hipStream_t st);
+hipError_t launch_fs_adjoint_slab(const DevGeom& g, const FsArgs& f, const float2* S,
+                                  float2* A, float2* G, float2* gu_slab, int z0, int nz,
+                                  hipStream_t st);
+hipError_t launch_copy_rows(const float2* src, size_t src_pitch, float2* dst, size_t rows,
+                            int W, hipStream_t st);
+hipError_t launch_frames_x(const DevGeom& g, const float2* psi, const float2* Q, float2* X,
+                           int k_first, int Kc, hipStream_t st);
+hipError_t launch_frames_c(const DevGeom& g, float2* X, const float2* psi, const float2* Q,
+                           float2* G, float2* Pbuf, int accumulate, int k_first, int Kc,
+                           hipStream_t st);
 hipError_t launch_pass_b(const DevGeom& g, int mode, const float2* src, float2* X,
                          const float* amp, double* Fpart, int Kc, hipStream_t st);
 hipError_t launch_pass_c(const DevGeom& g, float2* X, const float2* psi, const float2* Q,
@@ -110,6 +170,7 @@ hipError_t launch_radon_adj(const DevGeom& g, const float2* S, float2* gu, const
 hipError_t launch_block_volume(const DevGeom& g, const float2* u, float2* ub, float2* uTb,
                                hipStream_t st);
 hipError_t launch_fill_zero(float2* p, size_t n, hipStream_t st);
+hipError_t launch_fill(float2* p, size_t n, float2 value, hipStream_t st);
 hipError_t launch_sum_frames(const float2* G, int nd, const float2* extra, float2* out,
                              size_t n, hipStream_t st);
 // Deterministic two-stage sum of n doubles; `scratch` holds kReduceParts.

@@ -9,8 +9,8 @@
 //   pass D  pixels:  g_psi = sum_j B^T X_j (gather), h = -i kappa conj(psi) g_psi
 // Ray sums (bound by VALU and LDS operand delivery):
 //   radon_fwd  Joseph ray sums, angle groups sharing row windows staged in
-//              LDS by LDS-direct loads (lanes = consecutive slices of one
-//              bin, each thread owns 2 slices x 8 bins), fused
+//              LDS by LDS-direct loads (16 lanes cover the 64 slices of one
+//              bin group, each thread owns 4 slices x 4 bins), fused
 //              exp(i kappa p) epilogue
 //   radon_adj  transpose as a triangle-footprint gather over all angles
 //              (a workgroup per 16 x 16 voxel tile and kAdjZT slices, each
@@ -506,6 +506,183 @@ __global__ __launch_bounds__(kColThreads) void k_cols_prop(PropJobs jobs, double
 }
 
 // ---------------------------------------------------------------------------
+// Padded propagation: a line of n samples is set in the centre of a line of
+// 2n (zeros outside), transformed there with the 2n-point transfer row, and
+// the centre n samples are kept.  Rows and columns are separable halves of
+// the padded 2-D propagation (the setting-in and cutting-out of one axis
+// commute with the other axis' transform).
+// ---------------------------------------------------------------------------
+
+bool pad_size_supported(int n) { return fft_size_supported(n) && n <= 1024; }
+int pad_col_tiles(int H, int W) { return W / cols_tc(2 * H); }
+
+template <int W>
+__global__ __launch_bounds__(kThreads) void k_rows_pad(PadJob jb, DevGeom g) {
+  constexpr int N2 = 2 * W, TL = rows_tl(N2), LPW = rows_lpw(N2), E = N2 / TL;
+  constexpr int OFF = W / 2;
+  __shared__ float2 s_tw[N2];
+  __shared__ float2 s_line[LPW][fft_line_len(N2)];
+  const int line = threadIdx.x / TL, lt = threadIdx.x % TL;
+  const int z = blockIdx.x * LPW + line;
+  const int f = blockIdx.y;
+  for (int i = threadIdx.x; i < N2; i += kThreads) s_tw[i] = g.tw2W[i];
+  const float2* in = jb.src + (size_t)f * jb.src_step + (size_t)z * W;
+  float2* L = s_line[line];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int n = lt + e * TL;
+    L[fpi(n)] = (n >= OFF && n < OFF + W) ? in[n - OFF] : make_float2(0.f, 0.f);
+  }
+  if constexpr (wave_lines(TL)) __syncthreads();   // s_tw
+  fft<N2, TL, false, true, wave_lines(TL)>(L, s_tw, lt);
+  const float2* ch = g.chirp2W + (size_t)(jb.chirp0 + f % jb.cmod) * N2;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int n = lt + e * TL;
+    L[fpi(n)] = jb.conj ? cmulc(L[fpi(n)], ch[n]) : cmul(L[fpi(n)], ch[n]);
+  }
+  fft<N2, TL, true, true, wave_lines(TL)>(L, s_tw, lt);
+  float2* out = jb.dst + (size_t)f * g.H * W + (size_t)z * W;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int n = lt + e * TL;
+    if (n >= OFF && n < OFF + W) out[n - OFF] = L[fpi(n)];
+  }
+}
+
+template <int H>
+__global__ __launch_bounds__(kColThreads) void k_cols_pad(PadJob jb, double* __restrict__ Fpart,
+                                                          DevGeom g, int ntiles) {
+  constexpr int N2 = 2 * H, TC = cols_tc(N2), TLc = kColThreads / TC;
+  constexpr int OFF = H / 2;
+  __shared__ float2 s_tw[N2];
+  __shared__ float2 s_col[TC][col_pitch(N2)];
+  const int c = threadIdx.x / TLc, lt = threadIdx.x % TLc;
+  const int W = g.W;
+  const int tile = blockIdx.x % ntiles, f = blockIdx.x / ntiles;
+  const int s0 = tile * TC;
+  const size_t HW = (size_t)H * W;
+  for (int i = threadIdx.x; i < N2; i += kColThreads) s_tw[i] = g.tw2H[i];
+  const float2* in = jb.src + (size_t)f * jb.src_step + s0;
+  for (int i = threadIdx.x; i < N2 * TC; i += kColThreads) {
+    const int zz = i / TC, cc = i % TC;
+    s_col[cc][fpi(zz)] = (zz >= OFF && zz < OFF + H) ? in[(size_t)(zz - OFF) * W + cc]
+                                                     : make_float2(0.f, 0.f);
+  }
+  float2* L = s_col[c];
+  const float2* ch = g.chirp2H + (size_t)(jb.chirp0 + f % jb.cmod) * N2;
+  constexpr bool WL = wave_lines(TLc);
+  const bool cj = jb.mode == 0 && jb.conj;
+  if constexpr (WL) __syncthreads();   // tile and s_tw
+  fft<N2, TLc, false, true, WL>(L, s_tw, lt);
+  for (int zz = lt; zz < N2; zz += TLc) L[fpi(zz)] = cj ? cmulc(L[fpi(zz)], ch[zz]) : cmul(L[fpi(zz)], ch[zz]);
+  fft<N2, TLc, true, true, WL>(L, s_tw, lt);
+  __syncthreads();
+  if (jb.mode != 0) {
+    // residual on the kept centre; the rest is cleared before the adjoint
+    double acc = 0.0;
+    const float* a = jb.amp + (size_t)f * HW + s0;
+    for (int i = threadIdx.x; i < N2 * TC; i += kColThreads) {
+      const int zz = i / TC, cc = i % TC;
+      float2 v = make_float2(0.f, 0.f);
+      if (zz >= OFF && zz < OFF + H) {
+        v = s_col[cc][fpi(zz)];
+        acc += residual(v, a[(size_t)(zz - OFF) * W + cc], g.functional);
+      }
+      s_col[cc][fpi(zz)] = v;
+    }
+    block_sum_store<kColThreads>(acc, Fpart + jb.fslot0 + (size_t)f * ntiles + tile);
+    if (jb.mode == 2) return;
+    if constexpr (WL) __syncthreads();
+    fft<N2, TLc, false, true, WL>(L, s_tw, lt);
+    for (int zz = lt; zz < N2; zz += TLc) L[fpi(zz)] = cmulc(L[fpi(zz)], ch[zz]);
+    fft<N2, TLc, true, true, WL>(L, s_tw, lt);
+    __syncthreads();
+  }
+  float2* out = jb.dst + (size_t)f * HW + s0;
+  for (int i = threadIdx.x; i < H * TC; i += kColThreads) {
+    const int zz = i / TC, cc = i % TC;
+    out[(size_t)zz * W + cc] = s_col[cc][fpi(zz + OFF)];
+  }
+}
+
+// x_kj = Q_kj phi_kj for every pixel of a chunk's frames (pass A without
+// its row transform).
+__global__ __launch_bounds__(kThreads) void k_frames_x(const float2* __restrict__ psi,
+                                                       const float2* __restrict__ Q,
+                                                       float2* __restrict__ X, DevGeom g,
+                                                       int k_first, int Kc) {
+  const size_t HW = (size_t)g.H * g.W;
+  const size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= HW * Kc * g.nd) return;
+  const size_t fidx = i / HW;
+  const int p = (int)(i % HW);
+  const int z = p / g.W, s = p % g.W;
+  const int k = (int)(fidx / g.nd), j = (int)(fidx % g.nd);
+  double ty, tx;
+  shift_of(g, k_first + k, j, ty, tx);
+  const double m = g.mag[j];
+  const AxisTaps tyt = fwd_taps(g.cH, m, ty, z, g.H);
+  const AxisTaps txt = fwd_taps(g.cW, m, tx, s, g.W);
+  float2 qv;
+  if (g.pshift) {
+    const float* ps = g.pshift + ((size_t)(k_first + k) * g.nd + j) * 2;
+    qv = sample_circ(Q + (size_t)j * HW, g.H, g.W, (double)z - ps[0], (double)s - ps[1]);
+  } else {
+    qv = Q[(size_t)j * HW + p];
+  }
+  X[i] = cmul(qv, sample_phi(psi + (size_t)k * HW, g.W, tyt, txt));
+}
+
+// Pass C without its row transform: for every pixel of plane j, over the
+// chunk's angles, G_j += conj(phi) w (or conj(phi) w into Pbuf with probe
+// shifts) and X := conj(Q_kj) w.
+__global__ __launch_bounds__(kThreads) void k_frames_c(float2* __restrict__ X,
+                                                       const float2* __restrict__ psi,
+                                                       const float2* __restrict__ Q,
+                                                       float2* __restrict__ G,
+                                                       float2* __restrict__ Pbuf, DevGeom g,
+                                                       int accumulate, int k_first, int Kc) {
+  const size_t HW = (size_t)g.H * g.W;
+  const size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= HW * g.nd) return;
+  const int j = (int)(i / HW);
+  const int p = (int)(i % HW);
+  const int z = p / g.W, s = p % g.W;
+  const double m = g.mag[j];
+  float2 gacc = make_float2(0.f, 0.f);
+  for (int k = 0; k < Kc; ++k) {
+    float2* xp = X + ((size_t)k * g.nd + j) * HW + p;
+    const float2 w = *xp;
+    double ty, tx;
+    shift_of(g, k_first + k, j, ty, tx);
+    if (accumulate) {
+      const AxisTaps tyt = fwd_taps(g.cH, m, ty, z, g.H);
+      const AxisTaps txt = fwd_taps(g.cW, m, tx, s, g.W);
+      const float2 t = cmulc(w, sample_phi(psi + (size_t)k * HW, g.W, tyt, txt));
+      if (g.pshift) {
+        Pbuf[((size_t)k * g.nd + j) * HW + p] = t;
+      } else {
+        gacc.x += t.x;
+        gacc.y += t.y;
+      }
+    }
+    float2 qv;
+    if (g.pshift) {
+      const float* ps = g.pshift + ((size_t)(k_first + k) * g.nd + j) * 2;
+      qv = sample_circ(Q + (size_t)j * HW, g.H, g.W, (double)z - ps[0], (double)s - ps[1]);
+    } else {
+      qv = Q[(size_t)j * HW + p];
+    }
+    *xp = cmulc(w, qv);
+  }
+  if (accumulate && !g.pshift) {
+    const float2 v = G[i];
+    G[i] = make_float2(v.x + gacc.x, v.y + gacc.y);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Pass D: transpose of the demagnification, summed over planes, and the
 // chain rule through psi = exp(i kappa p).
 // ---------------------------------------------------------------------------
@@ -656,17 +833,18 @@ __global__ __launch_bounds__(kThreads) void k_block_volume(const float2* __restr
 
 // Forward.  A workgroup owns up to kFwdNA consecutive angles of one walk
 // direction (one wave per angle), kFwdNB consecutive bins and kFwdZT slices.
-// Within a wave, 32 consecutive lanes are 32 consecutive slices of one bin
-// and a thread takes 2 slices (32 apart) of 8 consecutive bins.  The
-// workgroup walks the rows of the volume one at a time: each row's column
-// window that all its rays cross (shared by the angles of the group) is
-// copied straight from memory into LDS, [column][slice], by LDS-direct
-// loads two rows ahead of use (three row buffers), so staging costs no
-// registers and no LDS writes by the waves.  A lane then reads its two taps
-// per slice; the 32 lanes of one LDS pass read 256 contiguous bytes, free
-// of bank conflicts.  Angles that walk along x read the x/y-transposed
-// volume, so both walk directions use the same code.  The host groups
-// angles so that every window fits.
+// Within a wave, 16 consecutive lanes cover the 64 slices of one group of 4
+// consecutive bins: lane l takes the slice pairs (2 (l % 16), + 1) and
+// (32 + 2 (l % 16), + 1), so one tap position and weight serve 4 slices and
+// each tap of a pair is one 16-byte LDS read.  The workgroup walks the rows
+// of the volume one at a time: each row's column window that all its rays
+// cross (shared by the angles of the group) is copied straight from memory
+// into LDS, [column][slice], by LDS-direct loads two rows ahead of use
+// (three row buffers), so staging costs no registers and no LDS writes by
+// the waves.  The 16 lanes of one LDS pass read the 256 contiguous bytes of
+// one column: free of bank conflicts.  Angles that walk along x read the
+// x/y-transposed volume, so both walk directions use the same code.  The
+// host groups angles so that every window fits.
 __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restrict__ u,
                                                          const float2* __restrict__ uT,  // z-blocked
                                                          float2* __restrict__ psi, DevGeom g,
@@ -674,17 +852,17 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
                                                          const int2* __restrict__ groups,
                                                          int g0, int ngroups, int c0, int c1) {
   constexpr int ZT = kFwdZT, NB = kFwdNB, SEG = kFwdSeg, ZB = kVolZB;
-  constexpr int BPT = NB / 2;                       // bins per thread
+  constexpr int BPT = NB / 4;                       // bins per thread
   constexpr int NBUF = 3;                           // row buffers (loads run 2 rows ahead)
   constexpr int ROWF2 = SEG * ZT;                   // float2 per staged row
   constexpr int LPW = ROWF2 / (4 * 128);            // LDS-direct loads (16 B per lane) per wave per row
-  static_assert(ZT == 64 && NB % 2 == 0 && LPW == 4 && kThreads == 256, "tiling");
+  constexpr int C4 = ZT / 2;                        // float4 per staged column
+  static_assert(ZT == 64 && NB == 16 && LPW == 4 && kThreads == 256, "tiling");
   __shared__ float4 tile4[NBUF * ROWF2 / 2];
   __shared__ short s_xl[kMaxW];
-  float2* tile = reinterpret_cast<float2*>(tile4);
   const int W = g.W, H = g.H;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int zl = lane & 31, bg = lane >> 5;
+  const int pz = lane & 15, bg = lane >> 4;
   // logical order: angle group fastest, then bin block, then slice block,
   // so the groups reading the same windows run together on one XCD
   const int L = xcd_logical(blockIdx.x, gridDim.x);
@@ -705,9 +883,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
   const float Bf = (float)B;
   // Range of the per-row base that keeps every tap of the thread's bins and
   // its right neighbour inside the staged window.  Inside the volume the
-  // host's grouping keeps every tap below column SEG - 2, so the clamp
-  // changes nothing there; a window moved into the zero padding reads zeros
-  // wherever the taps land.
+  // host's grouping keeps every tap at least one column inside the window,
+  // so the clamp changes nothing there; a window moved into the zero
+  // padding reads zeros wherever the taps land.
   const float span = (float)(BPT - 1) * Bf;
   const float rel_lo = fmaxf(0.0f, -span), rel_hi = (float)(SEG - 1) - fmaxf(0.0f, span) - 0.01f;
 
@@ -755,12 +933,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
           : "memory", "m0");
   };
 
-  float ax[BPT][2], ay[BPT][2];
-  double ox[BPT][2], oy[BPT][2];
+  // accumulators: [bin][slice e] with slice 32 (e / 2) + 2 pz + e % 2
+  float ax[BPT][4], ay[BPT][4];
+  double ox[BPT][4], oy[BPT][4];
 #pragma unroll
   for (int b = 0; b < BPT; ++b)
 #pragma unroll
-    for (int m = 0; m < 2; ++m) { ax[b][m] = ay[b][m] = 0.f; ox[b][m] = oy[b][m] = 0.0; }
+    for (int e = 0; e < 4; ++e) { ax[b][e] = ay[b][e] = 0.f; ox[b][e] = oy[b][e] = 0.0; }
 
   issue(0);
   if (W > 1) issue(1);
@@ -776,45 +955,46 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
     if (y + 2 < W) issue(y + 2);
     if (active) {
       // tap position of the thread's first bin relative to the window, in
-      // double precision; the other bins add b B (< NB / 2 * sqrt(2))
+      // double precision; the other bins add b B (< 4 sqrt(2))
       float rel = (float)(fA + (double)y * D - (double)s_xl[y]);
       rel = fminf(fmaxf(rel, rel_lo), rel_hi);
-      int tb = (y % NBUF) * ROWF2 + zl;
+      int tb = (y % NBUF) * (ROWF2 / 2) + pz;
       asm volatile("" : "+v"(tb));                     // one base register per row
-      const float2* tr = tile + tb;
-      // software pipeline: the taps of bin b + LA are requested before bin b
-      // is accumulated, so the reads of LA + 1 bins are in flight
-      constexpr int LA = 2;
-      float4 v[BPT][2];
+      const float4* tr = tile4 + tb;
+      // software pipeline: the taps of bin b + 1 are requested before bin b
+      // is accumulated
+      float4 v[BPT][2][2];                             // [bin][pair][tap]
       auto fetch_bin = [&](int b) {
         const float q = fmaf((float)b, Bf, rel);          // >= 0, < SEG - 1
-        const float2* tp = tr + (int)q * ZT;             // truncation = floor here
+        const float4* tp = tr + (int)q * C4;             // truncation = floor here
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          const float2 v0 = tp[32 * m], v1 = tp[ZT + 32 * m];
-          v[b][m] = make_float4(v0.x, v0.y, v1.x, v1.y);
+        for (int p = 0; p < 2; ++p) {
+          v[b][p][0] = tp[16 * p];
+          v[b][p][1] = tp[C4 + 16 * p];
         }
       };
-#pragma unroll
-      for (int b = 0; b < LA; ++b) fetch_bin(b);
+      fetch_bin(0);
 #pragma unroll
       for (int b = 0; b < BPT; ++b) {
-        if (b + LA < BPT) fetch_bin(b + LA);
+        if (b + 1 < BPT) fetch_bin(b + 1);
         const float w1 = __builtin_amdgcn_fractf(fmaf((float)b, Bf, rel)), w0 = 1.0f - w1;
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          ax[b][m] = fmaf(w1, v[b][m].z, fmaf(w0, v[b][m].x, ax[b][m]));
-          ay[b][m] = fmaf(w1, v[b][m].w, fmaf(w0, v[b][m].y, ay[b][m]));
+        for (int p = 0; p < 2; ++p) {
+          const float4 t0 = v[b][p][0], t1 = v[b][p][1];
+          ax[b][2 * p] = fmaf(w1, t1.x, fmaf(w0, t0.x, ax[b][2 * p]));
+          ay[b][2 * p] = fmaf(w1, t1.y, fmaf(w0, t0.y, ay[b][2 * p]));
+          ax[b][2 * p + 1] = fmaf(w1, t1.z, fmaf(w0, t0.z, ax[b][2 * p + 1]));
+          ay[b][2 * p + 1] = fmaf(w1, t1.w, fmaf(w0, t0.w, ay[b][2 * p + 1]));
         }
       }
       if ((y & 31) == 31) {
 #pragma unroll
         for (int b = 0; b < BPT; ++b)
 #pragma unroll
-          for (int m = 0; m < 2; ++m) {
-            ox[b][m] += (double)ax[b][m];
-            oy[b][m] += (double)ay[b][m];
-            ax[b][m] = ay[b][m] = 0.f;
+          for (int e = 0; e < 4; ++e) {
+            ox[b][e] += (double)ax[b][e];
+            oy[b][e] += (double)ay[b][e];
+            ax[b][e] = ay[b][e] = 0.f;
           }
       }
     }
@@ -824,18 +1004,25 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
   const double kap = (double)g.kappa;
   const double twopi = 6.283185307179586476925;
 #pragma unroll
-  for (int b = 0; b < BPT; ++b)
+  for (int e = 0; e < 4; ++e) {
+    float2 o[BPT];
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      const double px = (ox[b][m] + (double)ax[b][m]) * scale;
-      const double py = (oy[b][m] + (double)ay[b][m]) * scale;
+    for (int b = 0; b < BPT; ++b) {
+      const double px = (ox[b][e] + (double)ax[b][e]) * scale;
+      const double py = (oy[b][e] + (double)ay[b][e]) * scale;
       double ph = kap * px;
       ph -= twopi * rint(ph / twopi);
       float sn, cs;
       sincosf((float)ph, &sn, &cs);
       const float mag = expf((float)(-kap * py));
-      psi[((size_t)(k - c0) * H + z0 + zl + 32 * m) * W + s0 + b] = make_float2(mag * cs, mag * sn);
+      o[b] = make_float2(mag * cs, mag * sn);
     }
+    // the thread's 4 bins of one slice are 32 contiguous bytes
+    const int z = z0 + 32 * (e >> 1) + 2 * pz + (e & 1);
+    float4* dst = reinterpret_cast<float4*>(psi + ((size_t)(k - c0) * H + z) * W + s0);
+    dst[0] = make_float4(o[0].x, o[0].y, o[1].x, o[1].y);
+    dst[1] = make_float4(o[2].x, o[2].y, o[3].x, o[3].y);
+  }
 }
 
 // Transpose.  A workgroup owns a 16 x 16 voxel tile and kAdjZT slices; a
@@ -1028,10 +1215,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
   }
 }
 
-__global__ void k_fill_zero(float2* __restrict__ p, size_t n) {
+__global__ void k_fill(float2* __restrict__ p, size_t n, float2 value) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) p[i] = make_float2(0.f, 0.f);
+  for (; i < n; i += stride) p[i] = value;
 }
 
 __global__ void k_sum_frames(const float2* __restrict__ G, int nd, const float2* __restrict__ extra,
@@ -1137,6 +1324,71 @@ hipError_t launch_cols_prop(const DevGeom& g, const PropJobs& jobs, double* Fpar
 #undef CASE
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+#define HOLO_FOR_PAD_SIZES(X) X(64) X(128) X(192) X(256) X(384) X(512) X(1024)
+
+hipError_t launch_rows_pad(const DevGeom& g, const PadJob& jb, hipStream_t st) {
+  if (jb.nframes == 0) return hipSuccess;
+  if (!g.tw2W || !g.chirp2W) return hipErrorInvalidValue;
+  const dim3 grid(g.H / rows_lpw(2 * g.W), jb.nframes);
+  switch (g.W) {
+#define CASE(N) case N: k_rows_pad<N><<<grid, kThreads, 0, st>>>(jb, g); break;
+    HOLO_FOR_PAD_SIZES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cols_pad(const DevGeom& g, const PadJob& jb, double* Fpart, hipStream_t st) {
+  if (jb.nframes == 0) return hipSuccess;
+  if (!g.tw2H || !g.chirp2H || (jb.mode != 0 && (!jb.amp || !Fpart))) return hipErrorInvalidValue;
+  const int ntiles = pad_col_tiles(g.H, g.W);
+  const unsigned n = (unsigned)ntiles * (unsigned)jb.nframes;
+  switch (g.H) {
+#define CASE(N) case N: k_cols_pad<N><<<n, kColThreads, 0, st>>>(jb, Fpart, g, ntiles); break;
+    HOLO_FOR_PAD_SIZES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// dst[r][s] = src[r * src_pitch + s] for rows r < rows, s < W.
+__global__ __launch_bounds__(kThreads) void k_copy_rows(const float2* __restrict__ src,
+                                                        size_t src_pitch, float2* __restrict__ dst,
+                                                        size_t n, int W) {
+  const size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  dst[i] = src[(i / W) * src_pitch + i % W];
+}
+
+hipError_t launch_copy_rows(const float2* src, size_t src_pitch, float2* dst, size_t rows, int W,
+                            hipStream_t st) {
+  const size_t n = rows * (size_t)W;
+  if (n == 0) return hipSuccess;
+  k_copy_rows<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, st>>>(src, src_pitch, dst,
+                                                                              n, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_frames_x(const DevGeom& g, const float2* psi, const float2* Q, float2* X,
+                           int k_first, int Kc, hipStream_t st) {
+  const size_t n = (size_t)g.H * g.W * Kc * g.nd;
+  if (n == 0) return hipSuccess;
+  k_frames_x<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, st>>>(psi, Q, X, g, k_first,
+                                                                            Kc);
+  return hipGetLastError();
+}
+
+hipError_t launch_frames_c(const DevGeom& g, float2* X, const float2* psi, const float2* Q,
+                           float2* G, float2* Pbuf, int accumulate, int k_first, int Kc,
+                           hipStream_t st) {
+  const size_t n = (size_t)g.H * g.W * g.nd;
+  k_frames_c<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, st>>>(
+      X, psi, Q, G, Pbuf, g, accumulate, k_first, Kc);
   return hipGetLastError();
 }
 
@@ -1275,10 +1527,14 @@ static unsigned grid_for(size_t n) {
   return (unsigned)b;
 }
 
-hipError_t launch_fill_zero(float2* p, size_t n, hipStream_t st) {
+hipError_t launch_fill(float2* p, size_t n, float2 value, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  k_fill_zero<<<grid_for(n), kThreads, 0, st>>>(p, n);
+  k_fill<<<grid_for(n), kThreads, 0, st>>>(p, n, value);
   return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(float2* p, size_t n, hipStream_t st) {
+  return launch_fill(p, n, make_float2(0.f, 0.f), st);
 }
 
 hipError_t launch_sum_frames(const float2* G, int nd, const float2* extra, float2* out, size_t n,

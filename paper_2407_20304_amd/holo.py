@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libholo.so")
 EXPORTS = (
     "holo_plan_create", "holo_plan_destroy", "holo_workspace_bytes", "holo_plan_set_functional",
     "holo_plan_set_chunk", "holo_plan_get_chunk", "holo_plan_autotune",
-    "holo_plan_set_probe_shifts",
+    "holo_plan_set_probe_shifts", "holo_plan_set_padding", "holo_plan_set_projector",
     "holo_fwd", "holo_adj", "holo_objective", "holo_grad",
     "holo_grad_object", "holo_grad_probe",
     "holo_probe_init", "holo_cg_workspace_bytes", "holo_cg",
@@ -74,6 +74,8 @@ def lib():
     L.holo_plan_set_functional.argtypes = [P, c_int32]
     L.holo_plan_set_chunk.argtypes = [P, c_int32]
     L.holo_plan_set_probe_shifts.argtypes = [P, P]
+    L.holo_plan_set_padding.argtypes = [P, c_int32]
+    L.holo_plan_set_projector.argtypes = [P, c_int32]
     L.holo_plan_get_chunk.argtypes = [P, POINTER(c_int32)]
     L.holo_plan_autotune.argtypes = [P, P, P, P, P, P, P, P, P, c_int32, P, c_size_t, P, P, P]
     L.holo_fwd.argtypes = [P, P, P, c_int32, c_int32, P, P, c_size_t, P]
@@ -191,6 +193,8 @@ class Plan:
         _check(lib().holo_workspace_bytes(h, ctypes.byref(n)))
         self.workspace_bytes = int(n.value)
         self._ws = None
+        self.pad = 1
+        self.projector = "joseph"
 
     @classmethod
     def for_workload(cls, wl, theta=None, shift=None):
@@ -305,7 +309,22 @@ class Plan:
             os.replace(tmp, cache)
         return int(best.value), result
 
-    FUNCTIONALS = {"amplitude": 0, "intensity": 1}
+    FUNCTIONALS = {"amplitude": 0, "intensity": 1, "conventional": 2}
+
+    PROJECTORS = {"joseph": 0, "fourier": 1}
+
+    def set_projector(self, name):
+        """"joseph" (ray-driven sums, default) or "fourier" (Fourier-slice
+        gridding); updates workspace_bytes."""
+        _check(lib().holo_plan_set_projector(self._h, c_int32(self.PROJECTORS[name])))
+        self.projector = name
+        self._refresh_workspace_size()
+
+    def set_padding(self, pad):
+        """1: periodic propagation (default); 2: padded propagation (fields
+        zero outside the field of view, grids of 2H x 2W)."""
+        _check(lib().holo_plan_set_padding(self._h, c_int32(int(pad))))
+        self.pad = int(pad)
 
     def set_functional(self, name):
         """"amplitude" (F2, default; amp = sqrt(d)) or "intensity" (F1; amp

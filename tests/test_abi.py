@@ -158,8 +158,9 @@ def test_functional_switch_validates_on_the_host():
     L = holo.lib()
     p = make_plan()
     assert L.holo_plan_set_functional(None, 0) == 1
-    assert L.holo_plan_set_functional(p._h, 2) == 1
+    assert L.holo_plan_set_functional(p._h, 3) == 1
     assert L.holo_plan_set_functional(p._h, -1) == 1
+    assert L.holo_plan_set_functional(p._h, 2) == 0
     assert L.holo_plan_set_functional(p._h, 1) == 0
     assert L.holo_plan_set_functional(p._h, 0) == 0
     p.set_functional("intensity")
@@ -167,7 +168,8 @@ def test_functional_switch_validates_on_the_host():
     p.close()
     q = holo.Plan2D([128, 64], [1.0, 1.25], 300.0, 0.01)
     assert L.holo2d_plan_set_functional(None, 0) == 1
-    assert L.holo2d_plan_set_functional(q._h, 2) == 1
+    assert L.holo2d_plan_set_functional(q._h, 3) == 1
+    assert L.holo2d_plan_set_functional(q._h, 2) == 0
     assert L.holo2d_plan_set_functional(q._h, 1) == 0
     q.set_functional("amplitude")
     assert q.functional == "amplitude"
@@ -260,3 +262,45 @@ def test_noalloc_batch_gradient_validates_on_the_host():
     assert L.holo2d_grad_noalloc(None, buf, buf, buf, buf, buf, buf, buf, None) == 1
     big.close()
     small.close()
+
+
+def test_padding_switch_validates_on_the_host():
+    L = holo.lib()
+    p = make_plan()
+    assert L.holo_plan_set_padding(None, 2) == 1
+    assert L.holo_plan_set_padding(p._h, 3) == 1
+    assert L.holo_plan_set_padding(p._h, 0) == 1
+    n0 = p.workspace_bytes
+    p.set_padding(2)
+    assert p.pad == 2
+    n = ctypes.c_size_t()
+    assert L.holo_workspace_bytes(p._h, ctypes.byref(n)) == 0 and n.value == n0
+    # probe shifts are refused on a padded plan, and padding on a shifted one
+    sh = np.zeros((10, 4, 2), np.float32)
+    assert L.holo_plan_set_probe_shifts(p._h, sh.ctypes.data_as(ctypes.c_void_p)) == 1
+    p.set_padding(1)
+    p.set_probe_shifts(sh)
+    assert L.holo_plan_set_padding(p._h, 2) == 1
+    p.set_probe_shifts(None)
+    p.close()
+    big = make_plan(W=2048)          # 2W = 4096 exceeds the padded transforms
+    assert L.holo_plan_set_padding(big._h, 2) == 2
+    assert L.holo_plan_set_padding(big._h, 1) == 0
+    big.close()
+
+
+def test_projector_switch_validates_on_the_host():
+    L = holo.lib()
+    p = make_plan()
+    assert L.holo_plan_set_projector(None, 1) == 1
+    assert L.holo_plan_set_projector(p._h, 2) == 1
+    n0 = p.workspace_bytes
+    p.set_projector("fourier")
+    # 8 grids of (2W)^2 and 8 x n_angles x (W + 2) polar samples, complex64
+    assert p.workspace_bytes >= n0 + 8 * (2 * 64) ** 2 * 8 + 8 * 10 * 66 * 8
+    p.set_projector("joseph")
+    assert p.workspace_bytes == n0
+    p.close()
+    big = make_plan(W=2048)
+    assert L.holo_plan_set_projector(big._h, 1) == 2
+    big.close()

@@ -116,3 +116,24 @@ def test_intensity_functional_against_oracle():
         ep, eq = O.rel_err(gpsi[i].numpy(), gp0), O.rel_err(gq[i].numpy(), gq0)
         say("  inst %d n=%d: F %.1e g_psi %.1e g_q %.1e" % (i, sizes[i], eF, ep, eq))
         assert max(eF, ep, eq) < TOL
+
+
+def test_conventional_functional_against_oracle():
+    # Eq. (16): the model with q = 1 and no reference term; the amplitudes
+    # stand for sqrt(d / d^r).  g_q is exactly 0 and the forward fields are
+    # those of a unit probe.
+    sizes = [256, 64, 192, 128]
+    say("batch conventional functional parity, sizes", sizes)
+    inst = make_instances(sizes)
+    plan, F, Fo, gpsi, gq, v = run_batch(sizes, inst, functional="conventional")
+    assert np.array_equal(F, Fo)
+    for i, (ps, q, a, ar) in enumerate(inst):
+        F0, gp0 = O.holo2d_conventional_gradient(ps.astype(np.complex128), a.astype(np.float64),
+                                                  synth.MAG_REL, synth.M0, synth.FRESNEL0)
+        v0 = O.holo2d_forward(ps.astype(np.complex128), np.ones((sizes[i], sizes[i]), np.complex128),
+                              synth.MAG_REL, synth.M0, synth.FRESNEL0)
+        eF = abs(F[i] - F0) / F0
+        ep, ev = O.rel_err(gpsi[i].numpy(), gp0), O.rel_err(v[i].numpy(), v0)
+        say("  inst %d n=%d: F %.1e g_psi %.1e v %.1e" % (i, sizes[i], eF, ep, ev))
+        assert max(eF, ep, ev) < TOL
+        assert bool((gq[i] == 0).all())

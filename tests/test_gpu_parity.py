@@ -155,6 +155,121 @@ def test_intensity_functional_parity(small):
     assert abs(F2.item() - Fo2) / Fo2 < TOL
 
 
+def test_conventional_functional_parity(small):
+    """The flat-field functional of Eq. (16): the plan switched to the
+    model with q = 1 and no reference term; the data stand for sqrt(d / d^r).
+    F and g_u against the oracle's conventional functional, g_q exactly 0,
+    the forward fields equal the joint model's with a unit probe."""
+    import torch
+    say("conventional functional 64^3, 12 angles, shifts, chunk 5")
+    u, q, amp, amp_ref = PB.to_gpu(small)
+    plan = PB.gpu_plan(small)
+    plan.set_functional("conventional")
+    F, g_u, g_q = plan.holo_grad(u, q, amp, amp_ref)
+    Fo = plan.holo_objective(u, q, amp, amp_ref)
+    v = plan.holo_fwd(u, q, 2, 7)
+    Fr, gur = O.conventional_gradient(PB.c128(small.u), small.amp.astype(np.float64), small.geom)
+    PB.assert_close_scalar(F.item(), Fr)
+    PB.assert_close_scalar(Fo.item(), Fr, "F (objective call)")
+    PB.assert_close(g_u.cpu().numpy(), gur, "g_u")
+    assert bool((g_q == 0).all())
+    ones = np.ones_like(PB.c128(small.q))
+    vr = O.forward(PB.c128(small.u), ones, small.geom, ks=range(2, 7))
+    PB.assert_close(v.cpu().numpy(), vr, "v (unit probe)")
+    # and back to the amplitude functional on the same plan
+    plan.set_functional("amplitude")
+    F2, _, _ = plan.holo_grad(u, q, amp, amp_ref)
+    Fo2, _, _ = PB.oracle_grad(small)
+    PB.assert_close_scalar(F2.item(), Fo2, "F2 after switching back")
+
+
+@pytest.mark.parametrize("H,W,n_angles,chunk,_unused",
+                         [(64, 64, 12, 5, False), (128, 256, 9, 4, False), (1024, 64, 3, 2, False)])
+def test_padded_propagation_parity(H, W, n_angles, chunk, _unused):
+    from paper_2407_20304_amd import synth
+    """Every propagation on the 2H x 2W grid with the field zero outside
+    (reading P1): forward fields, objective, both gradients, the adjoint and
+    the initial probe against the oracle with the same padding; object
+    shifts (probe shifts are refused with padding)."""
+    import torch
+    say("padded propagation %dx%d, %d angles, chunk %d" % (H, W, n_angles, chunk))
+    p = PB.make_problem(H, W, n_angles, config=0, chunk=chunk, shifts=True)
+    p.geom.pad = 2
+    plan = PB.gpu_plan(p)
+    plan.set_padding(2)
+    u, q, amp, amp_ref = PB.to_gpu(p)
+    v = plan.holo_fwd(u, q, 1, n_angles).cpu().numpy()
+    ref = O.forward(PB.c128(p.u), PB.c128(p.q), p.geom, ks=range(1, n_angles))
+    PB.assert_close(v, ref, "v")
+    F, g_u, g_q = plan.holo_grad(u, q, amp, amp_ref)
+    Fo = plan.holo_objective(u, q, amp, amp_ref)
+    F0, gu0, gq0 = PB.oracle_grad(p)
+    PB.assert_close_scalar(F.item(), F0)
+    PB.assert_close_scalar(Fo.item(), F0, "F (objective call)")
+    PB.assert_close(g_u.cpu().numpy(), gu0, "g_u")
+    PB.assert_close(g_q.cpu().numpy(), gq0, "g_q")
+    rng = np.random.default_rng(5)
+    w = (rng.standard_normal(ref.shape) + 1j * rng.standard_normal(ref.shape)).astype(np.complex64)
+    au, aq = plan.holo_adj(u, q, torch.from_numpy(w).cuda(), 1, n_angles)
+    au0, aq0 = O.adjoint(PB.c128(p.u), PB.c128(p.q), w.astype(np.complex128), p.geom,
+                         ks=range(1, n_angles))
+    PB.assert_close(au.cpu().numpy(), au0, "adj g_u")
+    PB.assert_close(aq.cpu().numpy(), aq0, "adj g_q")
+    q0 = plan.holo_probe_init(amp_ref).cpu().numpy()
+    PB.assert_close(q0, O.probe_init(p.amp_ref.astype(np.float64), p.geom.fresnel0, pad=2),
+                    "probe init")
+    # the periodic propagation on the same plan gives the periodic result
+    plan.set_padding(1)
+    p.geom.pad = 1
+    F1, _, _ = plan.holo_grad(u, q, amp, amp_ref)
+    PB.assert_close_scalar(F1.item(), PB.oracle_grad(p)[0], "F periodic")
+
+
+@pytest.mark.parametrize("H,W,angles,chunk", [
+    (64, 64, "uniform12", 5),
+    (256, 128, "scattered9", 4),     # unsorted, beyond pi, repeated modulo pi
+    (64, 192, "uniform7", 3),
+])
+def test_fourier_slice_projector_parity(H, W, angles, chunk):
+    """The Fourier-slice discretisation of R_k (reading F1) by gridding on
+    the GPU against the oracle's exact sums: forward fields, objective, both
+    gradients and the adjoint."""
+    import torch
+    if angles == "scattered9":
+        theta = np.array([2.9, 0.1, 4.0, 1.3, np.pi / 2, 0.1 + np.pi, 5.5, 0.77, 3.05])
+    else:
+        n = int(angles[len("uniform"):])
+        theta = np.arange(n) * (np.pi / n)
+    say("fourier-slice projector %dx%d, angles %s, chunk %d" % (H, W, angles, chunk))
+    p = PB.make_problem(H, W, len(theta), config=0, chunk=chunk, theta=theta, shifts=True)
+    p.geom.projector = "fourier"
+    plan = PB.gpu_plan(p)
+    plan.set_projector("fourier")
+    u, q, amp, amp_ref = PB.to_gpu(p)
+    v = plan.holo_fwd(u, q, 1, len(theta)).cpu().numpy()
+    ref = O.forward(PB.c128(p.u), PB.c128(p.q), p.geom, ks=range(1, len(theta)))
+    PB.assert_close(v, ref, "v")
+    F, g_u, g_q = plan.holo_grad(u, q, amp, amp_ref)
+    Fo = plan.holo_objective(u, q, amp, amp_ref)
+    F0, gu0, gq0 = PB.oracle_grad(p)
+    PB.assert_close_scalar(F.item(), F0)
+    PB.assert_close_scalar(Fo.item(), F0, "F (objective call)")
+    PB.assert_close(g_u.cpu().numpy(), gu0, "g_u")
+    PB.assert_close(g_q.cpu().numpy(), gq0, "g_q")
+    rng = np.random.default_rng(6)
+    w = (rng.standard_normal(ref.shape) + 1j * rng.standard_normal(ref.shape)).astype(np.complex64)
+    au, aq = plan.holo_adj(u, q, torch.from_numpy(w).cuda(), 1, len(theta))
+    au0, aq0 = O.adjoint(PB.c128(p.u), PB.c128(p.q), w.astype(np.complex128), p.geom,
+                         ks=range(1, len(theta)))
+    PB.assert_close(au.cpu().numpy(), au0, "adj g_u")
+    PB.assert_close(aq.cpu().numpy(), aq0, "adj g_q")
+    # switching back gives Joseph's sums again
+    plan.set_projector("joseph")
+    p.geom.projector = "joseph"
+    F1, _, _ = plan.holo_grad(u, q, amp, amp_ref)
+    PB.assert_close_scalar(F1.item(), PB.oracle_grad(p)[0], "F with Joseph's sums")
+
+
 def test_autotune_chunk_and_cache(small, tmp_path):
     """The chunk autotuner times one gradient per candidate, keeps the
     fastest, and the tuned plan's gradient still matches the oracle; a
