@@ -74,47 +74,142 @@ def frame_bytes_model(wl, steps):
     return per_eval * steps
 
 
-def cpu_baseline(wl, u_gpu, q, amp_gpu, amp_ref, slab):
-    """Time the FP64 oracle on a bounded sample of the same workload: three
-    angles (a sixth, a half and five sixths of the way through, so both walk
-    directions appear), each with its ray sums and their transpose on a
-    `slab`-slice slab of the volume (scaled to all slices) plus its full
-    four-plane frame stage; the mean per angle is scaled to all angles."""
-    import numpy as np
-    from threadpoolctl import threadpool_limits
+_CPU = {}
+
+
+def _cpu_angle(k):
+    """One angle of the oracle sample in a worker process (single-threaded
+    NumPy): ray sums and their transpose on the slab, then the four-plane
+    frame stage of that angle at full detector size."""
     from oracle import holo_oracle as O
-    ks = [wl.n_angles // 6, wl.n_angles // 2, (5 * wl.n_angles) // 6]
-    z0 = wl.H // 2 - slab // 2
-    u_slab = u_gpu[z0:z0 + slab].cpu().numpy()
+    c = _CPU
+    theta = float(c["theta"][k])
+    t0 = time.perf_counter()
+    p = O.radon(c["u_slab"], theta)
+    O.radon_T(p, theta, c["W"])
+    t1 = time.perf_counter()
+    O.holo2d_gradient(c["psi"], c["q"], c["amp"][c["ks"].index(k)], c["a_ref"], c["mag_rel"],
+                      c["m0"], c["fresnel0"])
+    return t1 - t0, time.perf_counter() - t1
+
+
+def _cpu_init():
+    from threadpoolctl import threadpool_limits
+    _CPU["limits"] = threadpool_limits(1)
+
+
+def cpu_baseline_child(d):
+    """The oracle sample itself, in a process that never touches the GPU
+    (started by cpu_baseline): loads the sample from directory `d`, runs its
+    angles on a pool of worker processes and prints one JSON line."""
+    import multiprocessing as mp
+    import platform
+    import numpy as np
+    meta = json.load(open(os.path.join(d, "meta.json")))
+    for name in ("theta", "u_slab", "q", "a_ref", "amp", "mag_rel"):
+        _CPU[name] = np.load(os.path.join(d, name + ".npy"))
+    _CPU["ks"] = list(meta["ks"])
+    _CPU.update({k: meta[k] for k in ("W", "m0", "fresnel0")})
     rng = np.random.default_rng(0)
-    psi = np.exp(1j * rng.uniform(0, 1, (wl.H, wl.W)))
-    qc = q.astype(np.complex128)
-    a_ref = amp_ref.astype(np.float64)
-    t_ray = t_frame = 0.0
-    with threadpool_limits(1):
-        for k in ks:
-            theta = float(wl.theta[k])
-            amp_k = amp_gpu[k].cpu().numpy().astype(np.float64)
-            t0 = time.perf_counter()
-            p = O.radon(u_slab, theta)
-            O.radon_T(p, theta, wl.W)
-            t1 = time.perf_counter()
-            O.holo2d_gradient(psi, qc, amp_k, a_ref, wl.mag_rel, wl.m0, wl.fresnel0)
-            t2 = time.perf_counter()
-            t_ray += t1 - t0
-            t_frame += t2 - t1
-            log("  oracle angle %d: %.1f s" % (k, t2 - t0))
-    n = len(ks)
-    t_angle = (t_ray / n) * (wl.H / slab) + t_frame / n
-    t_eval = t_angle * wl.n_angles
+    _CPU["psi"] = np.exp(1j * rng.uniform(0, 1, (meta["H"], meta["W"])))
+    cores = max(1, min(16, len(os.sched_getaffinity(0)), len(_CPU["ks"])))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores, initializer=_cpu_init) as pool:
+        times = pool.map(_cpu_angle, _CPU["ks"])
+    wall = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except Exception:
+        model = platform.processor()
+    print(json.dumps({"times": times, "wall": wall, "cores": cores, "cpu": model,
+                      "numpy": np.__version__}), flush=True)
+
+
+def cpu_baseline(wl, u_gpu, q, amp_gpu, amp_ref, slab, n_sample=16):
+    """Time the FP64 oracle on a bounded sample of the same workload, on the
+    host's cores (one worker process per core, up to 16): `n_sample` angles of
+    the strided subset {floor(i N / n_sample)}, each with its ray sums and
+    their transpose on a `slab`-slice slab of the volume plus its full
+    four-plane frame stage.  The single-core seconds of the sample are scaled
+    to a whole evaluation (ray sums x H / slab, angles x N / n_sample) and
+    divided by the worker count (angles are independent).  The sample runs
+    in a child process that never touches the GPU."""
+    import shutil
+    import subprocess
+    import tempfile
+    import numpy as np
+    ks = [(i * wl.n_angles) // n_sample for i in range(n_sample)]
+    z0 = wl.H // 2 - slab // 2
+    d = tempfile.mkdtemp(prefix="holo_cpu_")
+    try:
+        np.save(os.path.join(d, "theta.npy"), np.asarray(wl.theta, dtype=np.float64))
+        np.save(os.path.join(d, "u_slab.npy"), u_gpu[z0:z0 + slab].cpu().numpy())
+        np.save(os.path.join(d, "q.npy"), q.astype(np.complex128))
+        np.save(os.path.join(d, "a_ref.npy"), amp_ref.astype(np.float64))
+        np.save(os.path.join(d, "amp.npy"), np.stack([amp_gpu[k].cpu().numpy() for k in ks])
+                .astype(np.float64))
+        np.save(os.path.join(d, "mag_rel.npy"), np.asarray(wl.mag_rel, dtype=np.float64))
+        json.dump({"ks": ks, "H": wl.H, "W": wl.W, "m0": wl.m0, "fresnel0": wl.fresnel0},
+                  open(os.path.join(d, "meta.json"), "w"))
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", d],
+                           capture_output=True, text=True, check=True)
+        out = json.loads(r.stdout.strip().splitlines()[-1])
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+    times, cores, wall = out["times"], out["cores"], out["wall"]
+    t_ray = sum(t[0] for t in times)
+    t_frame = sum(t[1] for t in times)
+    core_s = (t_ray * (wl.H / slab) + t_frame) * (wl.n_angles / n_sample)
+    t_eval = core_s / cores
+    log("  oracle sample: %d angles on %d workers in %.1f s wall" % (n_sample, cores, wall))
     return {
-        "value": 1.0 / t_eval, "unit": "gradient evals/s", "cores": 1, "kind": "oracle",
-        "sample": ("angles %s of %d: ray sums + transpose on a %d-slice slab (x%d to %d slices, "
-                   "%.1f s measured) and the 4-plane frame stage at %dx%d (%.1f s); mean per "
-                   "angle scaled x%d angles -> %.0f s per evaluation") %
-                  (ks, wl.n_angles, slab, wl.H // slab, wl.H, t_ray, wl.H, wl.W, t_frame,
-                   wl.n_angles, t_eval),
+        "value": 1.0 / t_eval, "unit": "gradient evals/s", "cores": cores, "kind": "oracle",
+        "cpu": out["cpu"], "numpy": out["numpy"],
+        "sample": ("%d angles of the strided subset {floor(i %d / %d)}, %d worker processes "
+                   "(%.1f s wall): ray sums + transpose on a %d-slice slab (%.1f core-s, "
+                   "extrapolated x%d to %d slices) and the 4-plane frame stage at %dx%d "
+                   "(%.1f core-s); extrapolated x%d/%d to all angles -> %.0f core-s, %.0f s "
+                   "per evaluation on %d cores") %
+                  (n_sample, wl.n_angles, n_sample, cores, wall, slab, t_ray, wl.H // slab, wl.H,
+                   wl.H, wl.W, t_frame, wl.n_angles, n_sample, core_s, t_eval, cores),
     }
+
+
+def fourier_bench(wl, u, q, amp, amp_ref, steps, joseph_rate, joseph_F):
+    """The same gradient with the Fourier-slice projector (gridding) in place
+    of Joseph's ray sums: evaluations per second and the time of its forward
+    and transpose kernels.  The two projectors are different discretisations
+    of R, so their objectives differ by the discretisation gap (reported)."""
+    import torch
+    from paper_2407_20304_amd import holo
+    plan = holo.Plan.for_workload(wl)
+    plan.set_projector("fourier")
+    dev = u.device
+    F = torch.empty((1,), dtype=torch.float64, device=dev)
+    g_u, g_q = torch.empty_like(u), torch.empty_like(q)
+    plan.workspace(dev)
+    plan.holo_grad(u, q, amp, amp_ref, F=F, g_u=g_u, g_q=g_q)
+    torch.cuda.synchronize()
+    plan.timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.holo_grad(u, q, amp, amp_ref, F=F, g_u=g_u, g_q=g_q)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    plan.timing(False)
+    kt = plan.kernel_times()
+    res = {"projector": "Fourier-slice gridding (2x oversampled grid, 8-tap kernel)",
+           "evals_per_s": steps / elapsed, "ms_per_step": 1000.0 * elapsed / steps,
+           "speedup_vs_joseph": (steps / elapsed) / joseph_rate,
+           "kernels_ms_per_step": {k: v[0] / steps for k, v in kt.items() if v[1] > 0},
+           "objective": F.item(),
+           "objective_rel_diff_vs_joseph": abs(F.item() - joseph_F) / abs(joseph_F)}
+    plan.close()
+    del g_u, g_q
+    torch.cuda.empty_cache()
+    return res
 
 
 def plain_bench(wl, u, q, amp, amp_ref, F, g_u, g_q, fused_rate):
@@ -278,7 +373,13 @@ def main():
                          "its own JSON line")
     ap.add_argument("--no-batch2d", action="store_true",
                     help="leave the batched single-angle workload out of the default line")
+    ap.add_argument("--no-fourier", action="store_true",
+                    help="leave the Fourier-slice projector's gradient out of the default line")
+    ap.add_argument("--cpu-baseline-child", metavar="DIR", help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_baseline_child:
+        cpu_baseline_child(args.cpu_baseline_child)
+        return
     if args.gpus != 1:
         print("bench.py measures one MI355X: the path runs on a single GPU "
               "(multi-GPU sharding is a design note only); use --gpus 1", file=sys.stderr)
@@ -405,6 +506,12 @@ def main():
     if not args.no_plain:
         result["plain"] = plain_bench(wl, u, q, amp, amp_ref, F, g_u, g_q, K / elapsed)
         result["vs_plain"] = result["plain"]["speedup"]
+    if not args.no_fourier and W <= 1024:
+        log("Fourier-slice projector")
+        plan.close()
+        del ws, plan
+        torch.cuda.empty_cache()
+        result["fourier_slice"] = fourier_bench(wl, u, q, amp, amp_ref, K, K / elapsed, Fv)
     if not args.no_batch2d:
         log("batched single-angle workload")
         result["batch2d"] = batch2d_bench()

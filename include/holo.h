@@ -140,6 +140,42 @@ holo_status holo_plan_autotune(holo_plan* plan, const holo_c64* u, const holo_c6
                                int32_t n_cand, void* ws, size_t ws_bytes,
                                int32_t* best_chunk, float* times_ms, void* stream);
 
+/* Launch-shape parameters ("tiles") that change the speed of a compute call
+ * but not its results (beyond the summation grouping of the cost):
+ *   CHUNK     angles per chunk (holo_plan_set_chunk);
+ *   COL_TILE  columns per workgroup of the fused column pass: 0 (the
+ *             default: 16 for H <= 512, 8 for H = 1024, 4 for H = 2048) or
+ *             half of the default;
+ *   FS_SLAB   slices per slab of the Fourier-slice projector: 1, 2, 4 or 8
+ *             (default 8);
+ *   FWD_BINS  bins per workgroup of the forward ray sums, 16 (default) or
+ *             8 (smaller staged windows, so more angles share one;
+ *             setting it regroups the angles, and it is refused if the chunk
+ *             is smaller than the new largest group).
+ * holo_plan_set_tile validates and sets one (the workspace size can change
+ * with CHUNK; query holo_workspace_bytes again); holo_plan_get_tile reads
+ * it.  holo_plan_autotune_tile is holo_plan_autotune for any of them: one
+ * untimed gradient, then one gradient per candidate value timed with HIP
+ * events on `stream`; the fastest becomes the plan's value.  Errors:
+ * INVALID_ARGUMENT (NULL, unknown parameter, a value outside the ones
+ * above), WORKSPACE_TOO_SMALL (autotune: the largest candidate's workspace
+ * does not fit).  Set and get are host-only; autotune synchronises
+ * `stream`. */
+typedef enum {
+  HOLO_TUNE_CHUNK = 0,
+  HOLO_TUNE_COL_TILE = 1,
+  HOLO_TUNE_FS_SLAB = 2,
+  HOLO_TUNE_FWD_BINS = 3
+} holo_tune_param;
+holo_status holo_plan_set_tile(holo_plan* plan, int32_t param, int32_t value);
+holo_status holo_plan_get_tile(const holo_plan* plan, int32_t param, int32_t* value);
+holo_status holo_plan_autotune_tile(holo_plan* plan, int32_t param, const holo_c64* u,
+                                    const holo_c64* q, const float* amp, const float* amp_ref,
+                                    double* F, holo_c64* g_u, holo_c64* g_q,
+                                    const int32_t* candidates, int32_t n_cand, void* ws,
+                                    size_t ws_bytes, int32_t* best, float* times_ms,
+                                    void* stream);
+
 /* The least-squares functional that holo_fwd, holo_adj, holo_objective,
  * holo_grad*, holo_cg (and the residual they form) evaluate on this plan.
  *   AMPLITUDE (default): F2 of Eq. (10),
@@ -196,8 +232,9 @@ holo_status holo_plan_set_padding(holo_plan* plan, int32_t pad);
  *     by gridding on a twice-oversampled frequency grid (8-tap kernel,
  *     approximation error a few 1e-8 relative) with O(W^2 log W + N_theta W)
  *     work per slice instead of O(N_theta W^2).  Its transpose is the exact
- *     transpose of the same computation.  Needs det_cols <= 1024; grows the
- *     workspace by 8 grids of (2W)^2 and 8 N_theta (W + 2) samples (query
+ *     transpose of the same computation.  Needs det_cols <= 1024; changes
+ *     the workspace (8 grids of (2W)^2 and 8 N_theta (W + 2) samples in
+ *     place of the ray sums' slice-blocked volume copies; query
  *     holo_workspace_bytes again).
  * Errors: INVALID_ARGUMENT (NULL plan, unknown value), UNSUPPORTED_SIZE
  * (FOURIER with det_cols above 1024).  Host-only. */
@@ -404,7 +441,7 @@ holo_status holo_timing_read(holo_plan* plan, int32_t kernel_class,
 
 /* The angle groups of the forward ray sums (diagnostics): consecutive
  * angles of one walk direction, at most 4, never crossing a chunk, whose
- * rays share one staged column window per (block of 16 bins, row); the
+ * rays share one staged column window per (block of FWD_BINS bins, row); the
  * plan forms them so that every tap of every row lies at least one column
  * inside its window.  Writes *n_groups and, for i < min(capacity,
  * *n_groups), the first angle and the angle count of group i.  Errors:

@@ -53,6 +53,8 @@ struct holo_plan {
   std::vector<float> shift;                 // empty = no shifts
   std::vector<float> pshift;                // probe shifts, empty = none
   bool pshift_dirty = false;                // device copy older than pshift
+  int fwd_nb = kFwdNB;                      // bins per forward workgroup (16 or 8)
+  bool groups_dirty = false;                // device copy older than groups
   std::vector<double> ang;                  // [n_angles][kAngleStride]
   std::vector<float2> twW, twH, chirpW, chirpH;
   // padded propagation (reading P1): 1 = periodic, 2 = padded; the tables
@@ -63,6 +65,10 @@ struct holo_plan {
   // (built when W <= 1024): 1 / kernel transform, angles sorted modulo pi,
   // first sorted position of every angle bin
   int projector = HOLO_PROJECTOR_JOSEPH;
+  // launch-shape choices (the autotuner's tiles): pass B's columns per
+  // workgroup (0 = default) and the Fourier-slice slab depth
+  int col_tile = 0;
+  int fs_slab = kFsSlab;
   std::vector<float> fs_dinv;
   std::vector<int> fs_sorted, fs_bins;
   size_t off_fsdinv = 0, off_fssorted = 0, off_fsbins = 0;
@@ -171,14 +177,14 @@ static void build_fs_tables(holo_plan* P) {
 // inside the staged kFwdSeg columns, and the kernel's clamp of the tap base
 // (to at most kFwdSeg - 1.01 for the highest tap) only ever acts on windows
 // moved into the zero padding.
-static bool fwd_group_fits(const holo_plan* P, int a, int b) {
+static bool fwd_group_fits(const holo_plan* P, int a, int b, int nb) {
   const int W = P->W;
-  for (int sb = 0; sb < W; sb += kFwdNB) {
+  for (int sb = 0; sb < W; sb += nb) {
     for (int r : {0, W - 1}) {
       double mn = 1e300, mx = -1e300;
       for (int k = a; k < b; ++k) {
         const double* g = &P->ang[(size_t)k * kAngleStride];
-        for (int bin : {sb, sb + kFwdNB - 1}) {
+        for (int bin : {sb, sb + nb - 1}) {
           const double f = g[kA] + (double)bin * g[kB] + (double)r * g[kD];
           mn = std::fmin(mn, f);
           mx = std::fmax(mx, f);
@@ -190,6 +196,33 @@ static bool fwd_group_fits(const holo_plan* P, int a, int b) {
   return true;
 }
 
+// Forward ray-sum groups for bin blocks of nb bins (never larger than a
+// chunk): consecutive angles of one walk direction whose windows fit.
+static void form_groups(holo_plan* P, int nb, std::vector<int2>& groups,
+                        std::vector<int>& group_of, int& max_group) {
+  const int na_max = std::min(kFwdNA, P->chunk);
+  groups.clear();
+  group_of.assign(P->n_angles, 0);
+  max_group = 1;
+  for (int a = 0; a < P->n_angles;) {
+    int b = a + 1;
+    while (b < P->n_angles && b - a < na_max &&
+           P->ang[(size_t)b * kAngleStride + kBranch] == P->ang[(size_t)a * kAngleStride + kBranch] &&
+           fwd_group_fits(P, a, b + 1, nb))
+      ++b;
+    for (int k = a; k < b; ++k) group_of[k] = (int)groups.size();
+    groups.push_back(make_int2(a, b - a));
+    max_group = std::max(max_group, b - a);
+    a = b;
+  }
+}
+
+static void set_fwd_bins(holo_plan* P, int nb) {
+  P->fwd_nb = nb;
+  form_groups(P, nb, P->groups, P->group_of, P->max_group);
+  P->groups_dirty = true;
+}
+
 // Workspace layout of a plan (depends on its chunk).
 static void layout_workspace(holo_plan* P) {
   const size_t fr = (size_t)P->H * P->W * sizeof(float2);
@@ -199,18 +232,22 @@ static void layout_workspace(holo_plan* P) {
   P->off_P = o;   o = align_up(o + fr);
   // z-blocked copies of the volume read by the ray sums (one per walk
   // direction), rows padded by kFwdPad zero columns on each side
-  const size_t vb = (size_t)P->H * P->W * vol_row(P->W) * sizeof(float2);
+  // (not used by the Fourier-slice projector)
+  const size_t vb = P->projector == HOLO_PROJECTOR_FOURIER
+                        ? 0 : (size_t)P->H * P->W * vol_row(P->W) * sizeof(float2);
   P->off_ub = o;  o = align_up(o + vb);
   P->off_uTb = o; o = align_up(o + (P->any_xwalk ? vb : 0));
   P->off_psi = o; o = align_up(o + fr * P->chunk);
   P->off_X = o;   o = align_up(o + fr * P->chunk * P->nd);
   // sinogram rows carry kAdjPad zero bins on each side
   P->off_S = o;   o = align_up(o + (size_t)P->H * sino_row(P->W) * sizeof(float2) * P->n_angles);
-  // column tiles per frame: the padded column pass has at least as many
-  // as the periodic one, so one size serves both
-  const size_t tiles = (size_t)std::max(P->W / cols_per_wg(P->H),
-                                        P->chirp2W.empty() ? 0 : pad_col_tiles(P->H, P->W));
-  P->n_fpart = tiles * (1 + (size_t)P->n_angles * P->nd);
+  // cost slots: the reference term's column tiles, then every frame's; sized
+  // for the most tiles any column pass of the plan can use (the padded pass,
+  // or pass B at half its default tile), so tuning never resizes them
+  const size_t pt = P->chirp2W.empty() ? 0 : (size_t)pad_col_tiles(P->H, P->W);
+  const size_t ref_tiles = std::max((size_t)(P->W / cols_per_wg(P->H)), pt);
+  const size_t tiles = std::max((size_t)(P->W / (cols_per_wg(P->H) / 2)), pt);
+  P->n_fpart = ref_tiles + tiles * (size_t)P->n_angles * P->nd;
   // cost partials, then the reduction's stage-one sums
   P->off_F = o;   o = align_up(o + (P->n_fpart + kReduceParts) * sizeof(double));
   // with probe shifts: conj(phi) w of every frame of a chunk
@@ -295,20 +332,9 @@ extern "C" holo_status holo_plan_create(const holo_geom* geom, holo_plan** out) 
       }
     }
 
-    // Forward ray-sum groups (never larger than a chunk).
-    const int na_max = std::min(kFwdNA, P->chunk);
-    P->group_of.resize(P->n_angles);
-    for (int a = 0; a < P->n_angles;) {
-      int b = a + 1;
-      while (b < P->n_angles && b - a < na_max &&
-             P->ang[(size_t)b * kAngleStride + kBranch] == P->ang[(size_t)a * kAngleStride + kBranch] &&
-             fwd_group_fits(P, a, b + 1))
-        ++b;
-      for (int k = a; k < b; ++k) P->group_of[k] = (int)P->groups.size();
-      P->groups.push_back(make_int2(a, b - a));
-      P->max_group = std::max(P->max_group, b - a);
-      a = b;
-    }
+    // Forward ray-sum groups for blocks of kFwdNB bins (8-bin blocks are a
+    // tuning choice, holo_plan_set_tile).
+    set_fwd_bins(P, kFwdNB);
 
     // Transfer-function tables: detector steps, probe steps, reference.
     std::vector<double> rhos(chirp_rows(P->nd));
@@ -342,7 +368,7 @@ extern "C" holo_status holo_plan_create(const holo_geom* geom, holo_plan** out) 
     P->off_chH = t;   t = align_up(t + P->chirpH.size() * sizeof(float2));
     P->off_ang = t;   t = align_up(t + P->ang.size() * sizeof(double));
     P->off_shift = t; t = align_up(t + P->shift.size() * sizeof(float));
-    P->off_groups = t; t = align_up(t + P->groups.size() * sizeof(int2));
+    P->off_groups = t; t = align_up(t + (size_t)P->n_angles * sizeof(int2));
     // probe shifts (room for all of them, filled when set)
     P->off_pshift = t; t = align_up(t + (size_t)P->n_angles * P->nd * 2 * sizeof(float));
     P->off_tw2W = t;  t = align_up(t + P->tw2W.size() * sizeof(float2));
@@ -452,6 +478,10 @@ holo_status ensure_tables(holo_plan* P) {
       HOLO_HIP(hipMemcpy((char*)P->d_tables + P->off_pshift, P->pshift.data(),
                          P->pshift.size() * sizeof(float), hipMemcpyHostToDevice));
     P->pshift_dirty = false;
+    if (P->groups_dirty)
+      HOLO_HIP(hipMemcpy((char*)P->d_tables + P->off_groups, P->groups.data(),
+                         P->groups.size() * sizeof(int2), hipMemcpyHostToDevice));
+    P->groups_dirty = false;
     return HOLO_OK;
   }
   const size_t bytes = P->table_bytes;
@@ -484,6 +514,7 @@ holo_status ensure_tables(holo_plan* P) {
   P->d_tables = d;
   P->device = dev;
   P->pshift_dirty = false;
+  P->groups_dirty = false;
   return HOLO_OK;
 }
 
@@ -511,6 +542,7 @@ DevGeom make_geom(const holo_plan* P) {
   g.tw2H = tabs ? (const float2*)(b + P->off_tw2H) : nullptr;
   g.chirp2W = tabs ? (const float2*)(b + P->off_ch2W) : nullptr;
   g.chirp2H = tabs ? (const float2*)(b + P->off_ch2H) : nullptr;
+  g.col_tile = P->col_tile;
   return g;
 }
 
@@ -548,7 +580,11 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
   float2* Pbuf = P->pshift.empty() ? nullptr : (float2*)(wsb + P->off_Pbuf);
   const double* d_ang = (const double*)((const char*)P->d_tables + P->off_ang);
   const bool padded = P->pad == 2;
-  const int tiles = padded ? pad_col_tiles(H, W) : W / cols_per_wg(H);
+  // cost slots: ref_tiles of the reference term (the probe-side column
+  // launch), then `tiles` per frame (the frame column launches)
+  const int ref_tiles = padded ? pad_col_tiles(H, W) : W / cols_per_wg(H);
+  const int tiles = padded ? pad_col_tiles(H, W)
+                           : W / (P->col_tile ? P->col_tile : cols_per_wg(H));
   // a padded propagation over `n` frames (see PadJob)
   auto pj = [&](const float2* src, float2* dst, long long step, int n, int chirp0, int cmod,
                 int conj, int pmode, const float* a, int fslot0) {
@@ -589,7 +625,7 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
     HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_rows_pad(g, rq, st); }));
     HOLO_HIP(timed(P, HOLO_K_PROBE, st, [&] { return launch_cols_pad(g, cq, Fpart, st); }));
     if (with_ref) {
-      // the reference field, its residual (cost slots 0 .. tiles - 1) and,
+      // the reference field, its residual (cost slots 0 .. ref_tiles - 1) and,
       // for the probe gradient, its adjoint propagation
       const PadJob rr = pj(q, Pref, 0, 1, cr, 1, 0, 0, nullptr, 0);
       const PadJob cr2 = pj(Pref, Pref, hw, 1, cr, 1, 0, want_gq ? 1 : 2, amp_ref, 0);
@@ -637,8 +673,8 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
     fa.ang = d_ang;
     fa.sorted_k = (const int*)(tb + P->off_fssorted);
     fa.bin_first = (const int*)(tb + P->off_fsbins);
-    for (int z0 = 0; z0 < H; z0 += kFsSlab) {
-      const int nz = std::min(kFsSlab, H - z0);
+    for (int z0 = 0; z0 < H; z0 += P->fs_slab) {
+      const int nz = std::min(P->fs_slab, H - z0);
       HOLO_HIP(timed(P, HOLO_K_RADON_FWD, st, [&] {
         return launch_fs_forward_slab(g, fa, u + (size_t)z0 * W * W, fsG, S, z0, nz, st);
       }));
@@ -675,10 +711,10 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
     } else {
       HOLO_HIP(timed(P, HOLO_K_RADON_FWD, st, [&] {
         return launch_radon_fwd(g, ub, uTb, psi, d_ang, d_groups, gfirst, glast - gfirst + 1, c0,
-                                c1, st);
+                                c1, P->fwd_nb, st);
       }));
     }
-    double* Fc = Fpart + (size_t)tiles * (1 + (size_t)(c0 - k0) * nd);
+    double* Fc = Fpart + ref_tiles + (size_t)tiles * (c0 - k0) * nd;
     if (padded) {
       // the unfused sequence: elementwise pass A, padded rows, padded
       // columns (with the residual and the adjoint columns), padded adjoint
@@ -760,8 +796,8 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
     }
   }
   if (want_gu && fs) {
-    for (int z0 = 0; z0 < H; z0 += kFsSlab) {
-      const int nz = std::min(kFsSlab, H - z0);
+    for (int z0 = 0; z0 < H; z0 += P->fs_slab) {
+      const int nz = std::min(P->fs_slab, H - z0);
       HOLO_HIP(timed(P, HOLO_K_RADON_ADJ, st, [&] {
         return launch_fs_adjoint_slab(g, fa, S, fsA, fsG, gu + (size_t)z0 * W * W, z0, nz, st);
       }));
@@ -792,9 +828,9 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
     }));
   }
   if (want_F) {
-    // the first `tiles` slots hold the reference term's cost
-    const size_t first = with_ref ? 0 : (size_t)tiles;
-    const size_t n = (size_t)tiles * (1 + (size_t)(k1 - k0) * nd) - first;
+    // the first ref_tiles slots hold the reference term's cost
+    const size_t first = with_ref ? 0 : (size_t)ref_tiles;
+    const size_t n = ref_tiles + (size_t)tiles * (k1 - k0) * nd - first;
     HOLO_HIP(timed(P, HOLO_K_OTHER, st, [&] {
       return launch_reduce_sum(Fpart + first, n, Fpart + P->n_fpart, F, st);
     }));
@@ -1083,32 +1119,109 @@ extern "C" holo_status holo_plan_get_chunk(const holo_plan* P, int32_t* chunk) {
   return HOLO_OK;
 }
 
+// The launch-shape parameters the tile autotuner can choose.
+static holo_status tile_check(const holo_plan* P, int param, int value, const char* fn) {
+  switch (param) {
+    case HOLO_TUNE_CHUNK:
+      if (value < P->max_group)
+        return fail(HOLO_ERR_INVALID_ARGUMENT, std::string(fn) + ": chunk " +
+                                                   std::to_string(value) + " is below " +
+                                                   std::to_string(P->max_group));
+      return HOLO_OK;
+    case HOLO_TUNE_COL_TILE:
+      if (value != 0 && !col_tile_supported(P->H, value))
+        return fail(HOLO_ERR_INVALID_ARGUMENT,
+                    std::string(fn) + ": column tile must be 0, " +
+                        std::to_string(cols_per_wg(P->H)) + " or " +
+                        std::to_string(cols_per_wg(P->H) / 2));
+      return HOLO_OK;
+    case HOLO_TUNE_FS_SLAB:
+      if (value != 1 && value != 2 && value != 4 && value != kFsSlab)
+        return fail(HOLO_ERR_INVALID_ARGUMENT, std::string(fn) + ": slab must be 1, 2, 4 or 8");
+      return HOLO_OK;
+    case HOLO_TUNE_FWD_BINS: {
+      if (value != kFwdNB && value != kFwdNB / 2)
+        return fail(HOLO_ERR_INVALID_ARGUMENT, std::string(fn) + ": forward bins must be 8 or 16");
+      // the chunk must still hold the largest angle group
+      std::vector<int2> g;
+      std::vector<int> go;
+      int mg = 1;
+      form_groups(const_cast<holo_plan*>(P), value, g, go, mg);
+      if (P->chunk < mg)
+        return fail(HOLO_ERR_INVALID_ARGUMENT, std::string(fn) + ": the chunk is smaller than "
+                                                                 "an angle group of that size");
+      return HOLO_OK;
+    }
+    default:
+      return fail(HOLO_ERR_INVALID_ARGUMENT, std::string(fn) + ": unknown parameter");
+  }
+}
+
+static int tile_get(const holo_plan* P, int param) {
+  return param == HOLO_TUNE_CHUNK ? P->chunk
+         : param == HOLO_TUNE_COL_TILE ? P->col_tile
+         : param == HOLO_TUNE_FS_SLAB ? P->fs_slab : P->fwd_nb;
+}
+
+static void tile_put(holo_plan* P, int param, int value) {
+  if (param == HOLO_TUNE_CHUNK) P->chunk = std::min<int>(value, P->n_angles);
+  else if (param == HOLO_TUNE_COL_TILE) P->col_tile = value;
+  else if (param == HOLO_TUNE_FS_SLAB) P->fs_slab = value;
+  else if (value != P->fwd_nb) set_fwd_bins(P, value);
+  layout_workspace(P);
+}
+
+extern "C" holo_status holo_plan_set_tile(holo_plan* P, int32_t param, int32_t value) {
+  if (!P) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_set_tile: plan is NULL");
+  holo_status s = tile_check(P, param, value, "holo_plan_set_tile");
+  if (s != HOLO_OK) return s;
+  tile_put(P, param, value);
+  return HOLO_OK;
+}
+
+extern "C" holo_status holo_plan_get_tile(const holo_plan* P, int32_t param, int32_t* value) {
+  if (!P || !value) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_get_tile: NULL argument");
+  if (param < HOLO_TUNE_CHUNK || param > HOLO_TUNE_FWD_BINS)
+    return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_get_tile: unknown parameter");
+  *value = tile_get(P, param);
+  return HOLO_OK;
+}
+
 extern "C" holo_status holo_plan_autotune(holo_plan* P, const holo_c64* u, const holo_c64* q,
                                           const float* amp, const float* amp_ref, double* F,
                                           holo_c64* g_u, holo_c64* g_q, const int32_t* candidates,
                                           int32_t n_cand, void* ws, size_t ws_bytes,
                                           int32_t* best_chunk, float* times_ms, void* stream) {
+  return holo_plan_autotune_tile(P, HOLO_TUNE_CHUNK, u, q, amp, amp_ref, F, g_u, g_q, candidates,
+                                 n_cand, ws, ws_bytes, best_chunk, times_ms, stream);
+}
+
+extern "C" holo_status holo_plan_autotune_tile(holo_plan* P, int32_t param, const holo_c64* u,
+                                               const holo_c64* q, const float* amp,
+                                               const float* amp_ref, double* F, holo_c64* g_u,
+                                               holo_c64* g_q, const int32_t* candidates,
+                                               int32_t n_cand, void* ws, size_t ws_bytes,
+                                               int32_t* best_chunk, float* times_ms,
+                                               void* stream) {
   holo_status s = check_common(P, u, q, "holo_plan_autotune");
   if (s != HOLO_OK) return s;
   if (!amp || !amp_ref || !F || !g_u || !g_q || !candidates || !best_chunk || !ws)
     return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_autotune: NULL argument");
   if (n_cand < 1) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_autotune: no candidates");
-  const int chunk0 = P->chunk;
+  if (param < HOLO_TUNE_CHUNK || param > HOLO_TUNE_FWD_BINS)
+    return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_autotune: unknown parameter");
+  const int chunk0 = tile_get(P, param);
   size_t need = 0;
   for (int i = 0; i < n_cand; ++i) {
-    if (candidates[i] < P->max_group) {
-      P->chunk = chunk0;
-      layout_workspace(P);
-      return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_autotune: candidate " +
-                                                 std::to_string(candidates[i]) + " is below " +
-                                                 std::to_string(P->max_group));
+    s = tile_check(P, param, candidates[i], "holo_plan_autotune");
+    if (s != HOLO_OK) {
+      tile_put(P, param, chunk0);
+      return s;
     }
-    P->chunk = std::min<int>(candidates[i], P->n_angles);
-    layout_workspace(P);
+    tile_put(P, param, candidates[i]);
     need = std::max(need, P->ws_bytes);
   }
-  P->chunk = chunk0;
-  layout_workspace(P);
+  tile_put(P, param, chunk0);
   if (ws_bytes < need)
     return fail(HOLO_ERR_WORKSPACE_TOO_SMALL, "holo_plan_autotune: workspace needs " +
                                                   std::to_string(need) + " bytes, got " +
@@ -1125,13 +1238,12 @@ extern "C" holo_status holo_plan_autotune(holo_plan* P, const holo_c64* u, const
                ws_bytes, stream);
   };
   // One untimed gradient first (device tables, code load), then one timed
-  // gradient per candidate; the fastest becomes the plan's chunk.
+  // gradient per candidate; the fastest becomes the plan's value.
   int best = chunk0;
   float best_ms = 0.f;
   s = grad();
   for (int i = 0; i < n_cand && s == HOLO_OK; ++i) {
-    P->chunk = std::min<int>(candidates[i], P->n_angles);
-    layout_workspace(P);
+    tile_put(P, param, candidates[i]);
     float ms = 0.f;
     if (hipEventRecord(e0, st) != hipSuccess) { s = fail(HOLO_ERR_HIP, "hipEventRecord"); break; }
     s = grad();
@@ -1144,13 +1256,12 @@ extern "C" holo_status holo_plan_autotune(holo_plan* P, const holo_c64* u, const
     if (times_ms) times_ms[i] = ms;
     if (i == 0 || ms < best_ms) {
       best_ms = ms;
-      best = P->chunk;
+      best = tile_get(P, param);
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  P->chunk = s == HOLO_OK ? best : chunk0;
-  layout_workspace(P);
+  tile_put(P, param, s == HOLO_OK ? best : chunk0);
   if (s == HOLO_OK) *best_chunk = best;
   return s;
 }

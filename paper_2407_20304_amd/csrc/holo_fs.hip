@@ -217,8 +217,10 @@ __global__ __launch_bounds__(kT) void k_fs_project(const float2* __restrict__ G,
 // inverse rows + deapodisation.
 // ---------------------------------------------------------------------------
 
-// A[z][k][m + W/2] = (-1)^m DFT(h)[m mod W] / W for m = -W/2 .. W/2, the two
-// Nyquist entries halved (the transpose of the forward's line step).
+// A[k][m + W/2][z] = (-1)^m DFT(h)[m mod W] / W for m = -W/2 .. W/2, the two
+// Nyquist entries halved (the transpose of the forward's line step); the
+// slab's slices are innermost (kFsSlab of them, 64 bytes), so the spread
+// reads all slices of a polar sample from one cache line.
 template <int W>
 __global__ __launch_bounds__(kT) void k_fs_line_T(const float2* __restrict__ S,
                                                   float2* __restrict__ A, FsArgs f,
@@ -240,7 +242,7 @@ __global__ __launch_bounds__(kT) void k_fs_line_T(const float2* __restrict__ S,
   for (int e = 0; e < E; ++e) Ln[fpi(lt + e * TL)] = in[lt + e * TL];
   if constexpr (fs_wave(TL)) __syncthreads();
   fft<W, TL, false, true, fs_wave(TL)>(Ln, s_tw, lt);
-  float2* out = A + (size_t)L * (W + 2);
+  float2* out = A + (size_t)k * (W + 1) * kFsSlab + z;
   if (!live) return;                                // after the last barrier
   const float sc = 1.0f / (float)W;
 #pragma unroll
@@ -251,97 +253,160 @@ __global__ __launch_bounds__(kT) void k_fs_line_T(const float2* __restrict__ S,
     float s = (m & 1) ? -sc : sc;
     if (mp == 0) s *= 0.5f;
     v = make_float2(s * v.x, s * v.y);
-    out[mp] = v;
-    if (mp == 0) out[W] = v;                        // m = +W/2 shares the halved value
+    out[(size_t)mp * kFsSlab] = v;
+    if (mp == 0) out[(size_t)W * kFsSlab] = v;      // m = +W/2 shares the halved value
   }
 }
 
-// Every grid point of the slab sums kernel-weighted polar samples within its
-// reach (the transpose of the gridding), for all kFsSlab slices at once.
+// Every grid point of the slab sums the kernel-weighted polar samples within
+// its reach (the transpose of the gridding), for all slices of the slab at
+// once.  A workgroup owns a 16 x 16 tile of grid points.  The lines that can
+// reach any point of the tile are those within d = 8 sqrt(2) + KW sqrt(2)/2
+// of the tile centre: an angle window around the centre's polar angle
+// (found through the table of angles sorted modulo pi), and on each line the
+// samples m with |2m - c.e| <= d (at most 18).  The window is taken in
+// batches of kSpBatch lines: the batch's samples (all slab slices, 64
+// contiguous bytes per sample) are copied into LDS, then every point gathers
+// from there.  Tiles near the grid edge also visit the periodic images of
+// the tile that polar samples (radius <= M/2) can reach.
+constexpr int kSpTile = 16, kSpBatch = 48, kSpM = 20;
+
 template <int W>
 __global__ __launch_bounds__(kT) void k_fs_spread(const float2* __restrict__ A,
                                                   float2* __restrict__ G, FsArgs f, int nz) {
-  constexpr int M = 2 * W;
-  const int idx = blockIdx.x * kT + threadIdx.x;
-  if (idx >= M * M) return;
-  const int lx = idx % M, ly = idx / M;
+  constexpr int M = 2 * W, NT = M / kSpTile;
+  __shared__ float4 s_a[kSpBatch * kSpM * 4];
+  __shared__ double s_c[kSpBatch], s_s[kSpBatch];
+  __shared__ float s_ih[kSpBatch];
+  __shared__ int s_m0[kSpBatch], s_nm[kSpBatch], s_kk[kSpBatch];
+  __shared__ int s_seg[2][2], s_nseg;
+  const int tx = blockIdx.x % NT, ty = blockIdx.x / NT;
+  const int lx = tx * kSpTile + (threadIdx.x & 15), ly = ty * kSpTile + (threadIdx.x >> 4);
+  const int idx = ly * M + lx;
+  // centred coordinates (a tile never straddles M/2, a multiple of 16)
   const int cx = lx < M / 2 ? lx : lx - M, cy = ly < M / 2 ? ly : ly - M;
-  // periodic images of the point that polar samples (radius <= M/2) can reach
-  const int ax = cx < -M / 2 + KW / 2 ? cx + M : (cx >= M / 2 - KW / 2 ? cx - M : cx);
-  const int ay = cy < -M / 2 + KW / 2 ? cy + M : (cy >= M / 2 - KW / 2 ? cy - M : cy);
+  const int tcx0 = tx * kSpTile < M / 2 ? tx * kSpTile : tx * kSpTile - M;
+  const int tcy0 = ty * kSpTile < M / 2 ? ty * kSpTile : ty * kSpTile - M;
+  const double ccx = tcx0 + 7.5, ccy = tcy0 + 7.5;             // tile centre
+  const double d = 8.0 * 1.4142135623730951 + 0.5 * KW * 1.4142135623730951 + 0.05;
   const float beta = f.beta;
-  constexpr float kReach = (float)KW * 0.70710678f + 0.05f;   // KW/2 * sqrt(2)
+  const float4* A4 = reinterpret_cast<const float4*>(A);
   float2 acc[kFsSlab];
 #pragma unroll
   for (int z = 0; z < kFsSlab; ++z) acc[z] = make_float2(0.f, 0.f);
-  const size_t zstride = (size_t)f.K * (W + 2);
-  for (int im = 0; im < 4; ++im) {
-    const int px = (im & 1) ? ax : cx, py = (im & 2) ? ay : cy;
-    if (((im & 1) && ax == cx) || ((im & 2) && ay == cy)) continue;
-    const float r = sqrtf((float)px * px + (float)py * py);
-    if (r > 0.5f * (float)M + (float)KW) continue;
-    // sorted positions of the angles whose line passes within reach
-    int seg_lo[2], seg_hi[2], nseg = 1;
-    if (r <= kReach) {
-      seg_lo[0] = 0;
-      seg_hi[0] = f.n_angles;
-    } else {
-      const float dl = asinf(fminf(1.0f, kReach / r));
-      float phi = atan2f((float)py, (float)px);
-      if (phi < 0.f) phi += 3.14159265358979f;
-      if (phi >= 3.14159265358979f) phi -= 3.14159265358979f;
-      const float sc = (float)kFsBins / 3.14159265358979f;
-      int b0 = (int)floorf((phi - dl) * sc) - 1, b1 = (int)floorf((phi + dl) * sc) + 1;
-      if (b1 - b0 + 1 >= kFsBins) {
-        seg_lo[0] = 0;
-        seg_hi[0] = f.n_angles;
-      } else if (b0 < 0) {
-        seg_lo[0] = f.bin_first[b0 + kFsBins];
-        seg_hi[0] = f.n_angles;
-        seg_lo[1] = 0;
-        seg_hi[1] = f.bin_first[b1 + 1];
-        nseg = 2;
-      } else if (b1 >= kFsBins) {
-        seg_lo[0] = f.bin_first[b0];
-        seg_hi[0] = f.n_angles;
-        seg_lo[1] = 0;
-        seg_hi[1] = f.bin_first[b1 - kFsBins + 1];
-        nseg = 2;
+
+  for (int im = 0; im < 9; ++im) {
+    const int ox = (im % 3 - 1) * M, oy = (im / 3 - 1) * M;
+    const double icx = ccx + ox, icy = ccy + oy;
+    const double rc = sqrt(icx * icx + icy * icy);
+    if (rc > 0.5 * M + d) continue;                              // uniform over the tile
+    // the tile's angle window: sorted positions, one or two segments
+    if (threadIdx.x == 0) {
+      int nseg = 1;
+      if (rc <= d) {
+        s_seg[0][0] = 0;
+        s_seg[0][1] = f.n_angles;
       } else {
-        seg_lo[0] = f.bin_first[b0];
-        seg_hi[0] = f.bin_first[b1 + 1];
+        const double dl = asin(fmin(1.0, d / rc));
+        double phi = atan2(icy, icx);
+        const double pi = 3.14159265358979323846;
+        if (phi < 0.0) phi += pi;
+        if (phi >= pi) phi -= pi;
+        const double sc = (double)kFsBins / pi;
+        const int b0 = (int)floor((phi - dl) * sc) - 1, b1 = (int)floor((phi + dl) * sc) + 1;
+        if (b1 - b0 + 1 >= kFsBins) {
+          s_seg[0][0] = 0;
+          s_seg[0][1] = f.n_angles;
+        } else if (b0 < 0) {
+          s_seg[0][0] = f.bin_first[b0 + kFsBins];
+          s_seg[0][1] = f.n_angles;
+          s_seg[1][0] = 0;
+          s_seg[1][1] = f.bin_first[b1 + 1];
+          nseg = 2;
+        } else if (b1 >= kFsBins) {
+          s_seg[0][0] = f.bin_first[b0];
+          s_seg[0][1] = f.n_angles;
+          s_seg[1][0] = 0;
+          s_seg[1][1] = f.bin_first[b1 - kFsBins + 1];
+          nseg = 2;
+        } else {
+          s_seg[0][0] = f.bin_first[b0];
+          s_seg[0][1] = f.bin_first[b1 + 1];
+        }
       }
+      s_nseg = nseg;
     }
-    for (int sgi = 0; sgi < nseg; ++sgi) {
-      for (int sp = seg_lo[sgi]; sp < seg_hi[sgi]; ++sp) {
-        const int kk = f.sorted_k[sp];
-        if (kk < f.k0 || kk >= f.k0 + f.K) continue;
-        const double* ap = f.ang + (size_t)kk * kAngleStride;
-        const double C = 2.0 * ap[kCos], Sn = 2.0 * ap[kSin];
-        // m range from the dominant axis of the line
-        const bool xd = fabs(C) >= fabs(Sn);
-        const double e = xd ? C : Sn, pd = xd ? (double)px : (double)py;
-        const double mc = pd / e, hw = 0.5 * (double)KW / fabs(e);
-        int m0 = (int)ceil(mc - hw), m1 = (int)floor(mc + hw);
-        m0 = max(m0, -W / 2);
-        m1 = min(m1, W / 2);
-        const float2* ak = A + (size_t)(kk - f.k0) * (W + 2) + W / 2;
-        for (int m = m0; m <= m1; ++m) {
-          const float dx = (float)((double)px - (double)m * C);
-          const float dy = (float)((double)py - (double)m * Sn);
-          if (fabsf(dx) >= 0.5f * (float)KW || fabsf(dy) >= 0.5f * (float)KW) continue;
-          const float w = es_kernel(dx, beta) * es_kernel(dy, beta);
+    __syncthreads();
+    const int nseg = s_nseg;
+    const double px = (double)(cx + ox), py = (double)(cy + oy);
+    for (int sg = 0; sg < nseg; ++sg) {
+      const int lo = s_seg[sg][0], hi = s_seg[sg][1];
+      for (int b0 = lo; b0 < hi; b0 += kSpBatch) {
+        const int nb = min(kSpBatch, hi - b0);
+        // the batch's lines: direction, the tile's sample range
+        if ((int)threadIdx.x < nb) {
+          const int t = threadIdx.x;
+          const int kk = f.sorted_k[b0 + t];
+          int m0 = 0, nm = 0;
+          double C = 0.0, Sn = 0.0;
+          float ih = 0.f;
+          if (kk >= f.k0 && kk < f.k0 + f.K) {
+            const double* ap = f.ang + (size_t)kk * kAngleStride;
+            C = 2.0 * ap[kCos];
+            Sn = 2.0 * ap[kSin];
+            ih = (float)ap[kInvH];
+            const double ce = 0.5 * (icx * C + icy * Sn);           // c.e in grid units
+            m0 = max((int)ceil(0.5 * (ce - d)), -W / 2);
+            const int m1 = min((int)floor(0.5 * (ce + d)), W / 2);
+            nm = max(0, m1 - m0 + 1);
+          }
+          s_c[t] = C;
+          s_s[t] = Sn;
+          s_ih[t] = ih;
+          s_m0[t] = m0;
+          s_nm[t] = nm;
+          s_kk[t] = kk - f.k0;
+        }
+        __syncthreads();
+        // copy the batch's samples into LDS: line t, sample j, quarter q
+        for (int i = threadIdx.x; i < nb * kSpM * 4; i += kT) {
+          const int q = i & 3, j = (i >> 2) % kSpM, t = (i >> 2) / kSpM;
+          if (j < s_nm[t])
+            s_a[i] = A4[((size_t)s_kk[t] * (W + 1) + (s_m0[t] + j + W / 2)) * 4 + q];
+        }
+        __syncthreads();
+        for (int t = 0; t < nb; ++t) {
+          const int nm = s_nm[t];
+          if (nm == 0) continue;
+          const double C = s_c[t], Sn = s_s[t];
+          const double ihd = (double)s_ih[t];
+          const bool xd = fabs(C) >= fabs(Sn);
+          const double e = xd ? C : Sn, pd = xd ? px : py;
+          const double mc = 0.5 * pd * (e >= 0.0 ? ihd : -ihd), hw = 0.25 * (double)KW * ihd;
+          const int m0 = s_m0[t];
+          const int ma = max((int)ceil(mc - hw), m0), mb = min((int)floor(mc + hw), m0 + nm - 1);
+          for (int m = ma; m <= mb; ++m) {
+            const float dx = (float)(px - (double)m * C);
+            const float dy = (float)(py - (double)m * Sn);
+            if (fabsf(dx) >= 0.5f * (float)KW || fabsf(dy) >= 0.5f * (float)KW) continue;
+            const float w = es_kernel(dx, beta) * es_kernel(dy, beta);
+            const float4* sa = s_a + (t * kSpM + (m - m0)) * 4;
 #pragma unroll
-          for (int z = 0; z < kFsSlab; ++z) {
-            if (z < nz) {
-              const float2 a = ak[z * zstride + m];
-              acc[z].x = fmaf(w, a.x, acc[z].x);
-              acc[z].y = fmaf(w, a.y, acc[z].y);
+            for (int z2 = 0; z2 < kFsSlab / 2; ++z2) {
+              if (2 * z2 < nz) {
+                const float4 a = sa[z2];
+                acc[2 * z2].x = fmaf(w, a.x, acc[2 * z2].x);
+                acc[2 * z2].y = fmaf(w, a.y, acc[2 * z2].y);
+                acc[2 * z2 + 1].x = fmaf(w, a.z, acc[2 * z2 + 1].x);
+                acc[2 * z2 + 1].y = fmaf(w, a.w, acc[2 * z2 + 1].y);
+              }
             }
           }
         }
+        __syncthreads();
       }
     }
+    __syncthreads();                 // every thread is done with s_seg before it changes
   }
 #pragma unroll
   for (int z = 0; z < kFsSlab; ++z)
@@ -432,7 +497,7 @@ hipError_t launch_fs_adjoint_slab(const DevGeom& g, const FsArgs& f, const float
     const unsigned nl = (unsigned)nz * (unsigned)f.K;                                        \
     k_fs_line_T<N><<<(nl + fs_lpw(N) - 1) / fs_lpw(N), kT, 0, st>>>(S, A, f, g.twW, g.H, z0,   \
                                                                    (int)nl);                  \
-    k_fs_spread<N><<<(unsigned)((M * M + kT - 1) / kT), kT, 0, st>>>(A, G, f, nz);          \
+    k_fs_spread<N><<<(unsigned)((M / kSpTile) * (M / kSpTile)), kT, 0, st>>>(A, G, f, nz);  \
     k_fs_cols<N, true><<<(unsigned)(nz * (M / fs_tc(M))), kColT, 0, st>>>(G, g.tw2W);        \
     k_fs_rows_T<N><<<(unsigned)(nz * N / fs_lpw(M)), kT, 0, st>>>(G, gu_slab, f, g.tw2W);    \
     break;                                                                                   \

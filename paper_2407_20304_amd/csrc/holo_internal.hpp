@@ -42,6 +42,7 @@ struct DevGeom {
   const float2* tw2H;        // [2H]
   const float2* chirp2W;     // [2 nd + 1][2W], times 1/(2W)
   const float2* chirp2H;     // [2 nd + 1][2H], times 1/(2H)
+  int col_tile;              // columns per pass-B workgroup (0: the default)
 };
 
 // Fourier-slice projector (holo_fs.hip): gridding kernel taps per axis,
@@ -102,6 +103,8 @@ enum ColMode { kColFwd = 0, kColObj = 1, kColGrad = 2, kColAdj = 3 };
 int rows_per_wg(int W);      // lines of W handled by one 256-thread workgroup
 int cols_per_wg(int H);      // columns of length H per workgroup
 bool fft_size_supported(int n);
+// Pass B's column tile: cols_per_wg(H) (the default) or half of it.
+bool col_tile_supported(int H, int tc);
 // Ray-sum tiling (see the kernels): forward angle-group size, slices and
 // bins per workgroup, staged rows per block and staged columns per row;
 // transpose slices per thread, angles per staged group and bins per staged
@@ -164,7 +167,7 @@ hipError_t launch_pass_d(const DevGeom& g, const float2* X, const float2* psi, f
                          int k_first, int Kc, hipStream_t st);
 hipError_t launch_radon_fwd(const DevGeom& g, const float2* ub, const float2* uTb, float2* psi,
                             const double* ang, const int2* groups, int g0, int ngroups, int c0,
-                            int c1, hipStream_t st);
+                            int c1, int nb, hipStream_t st);
 hipError_t launch_radon_adj(const DevGeom& g, const float2* S, float2* gu, const double* ang,
                             int K, hipStream_t st);
 hipError_t launch_block_volume(const DevGeom& g, const float2* u, float2* ub, float2* uTb,

@@ -379,13 +379,13 @@ __device__ __forceinline__ int xcd_logical(int h, int n) {
   return x * q + min(x, r) + loc;
 }
 
-template <int H, int MODE>
+template <int H, int MODE, int TC>
 __global__ __launch_bounds__(kColThreads) void k_pass_b(const float2* __restrict__ src,
                                                         float2* __restrict__ X,
                                                         const float* __restrict__ amp,
                                                         double* __restrict__ Fpart, DevGeom g,
                                                         int ntiles) {
-  constexpr int TC = cols_tc(H), TLc = kColThreads / TC;
+  constexpr int TLc = kColThreads / TC;
   constexpr int NPT = H * TC / kColThreads;       // tile elements per thread
   constexpr int RS = kColThreads / TC;            // tile rows between a thread's elements
   static_assert(H * TC % kColThreads == 0 && RS % 32 == 0, "column tile");
@@ -832,8 +832,9 @@ __global__ __launch_bounds__(kThreads) void k_block_volume(const float2* __restr
 // ---------------------------------------------------------------------------
 
 // Forward.  A workgroup owns up to kFwdNA consecutive angles of one walk
-// direction (one wave per angle), kFwdNB consecutive bins and kFwdZT slices.
-// Within a wave, 16 consecutive lanes cover the 64 slices of one group of 4
+// direction (one wave per angle), NB (16, or 8 for plans whose angle windows
+// spread too far for 16) consecutive bins and kFwdZT slices.
+// Within a wave, 16 consecutive lanes cover the 64 slices of one group of NB/4
 // consecutive bins: lane l takes the slice pairs (2 (l % 16), + 1) and
 // (32 + 2 (l % 16), + 1), so one tap position and weight serve 4 slices and
 // each tap of a pair is one 16-byte LDS read.  The workgroup walks the rows
@@ -845,19 +846,20 @@ __global__ __launch_bounds__(kThreads) void k_block_volume(const float2* __restr
 // one column: free of bank conflicts.  Angles that walk along x read the
 // x/y-transposed volume, so both walk directions use the same code.  The
 // host groups angles so that every window fits.
+template <int NB>
 __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restrict__ u,
                                                          const float2* __restrict__ uT,  // z-blocked
                                                          float2* __restrict__ psi, DevGeom g,
                                                          const double* __restrict__ ang,
                                                          const int2* __restrict__ groups,
                                                          int g0, int ngroups, int c0, int c1) {
-  constexpr int ZT = kFwdZT, NB = kFwdNB, SEG = kFwdSeg, ZB = kVolZB;
+  constexpr int ZT = kFwdZT, SEG = kFwdSeg, ZB = kVolZB;
   constexpr int BPT = NB / 4;                       // bins per thread
   constexpr int NBUF = 3;                           // row buffers (loads run 2 rows ahead)
   constexpr int ROWF2 = SEG * ZT;                   // float2 per staged row
   constexpr int LPW = ROWF2 / (4 * 128);            // LDS-direct loads (16 B per lane) per wave per row
   constexpr int C4 = ZT / 2;                        // float4 per staged column
-  static_assert(ZT == 64 && NB == 16 && LPW == 4 && kThreads == 256, "tiling");
+  static_assert(ZT == 64 && (NB == 16 || NB == 8) && LPW == 4 && kThreads == 256, "tiling");
   __shared__ float4 tile4[NBUF * ROWF2 / 2];
   __shared__ short s_xl[kMaxW];
   const int W = g.W, H = g.H;
@@ -1017,11 +1019,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
       const float mag = expf((float)(-kap * py));
       o[b] = make_float2(mag * cs, mag * sn);
     }
-    // the thread's 4 bins of one slice are 32 contiguous bytes
+    // the thread's BPT bins of one slice are 8 BPT contiguous bytes
     const int z = z0 + 32 * (e >> 1) + 2 * pz + (e & 1);
     float4* dst = reinterpret_cast<float4*>(psi + ((size_t)(k - c0) * H + z) * W + s0);
-    dst[0] = make_float4(o[0].x, o[0].y, o[1].x, o[1].y);
-    dst[1] = make_float4(o[2].x, o[2].y, o[3].x, o[3].y);
+#pragma unroll
+    for (int b = 0; b < BPT; b += 2) dst[b / 2] = make_float4(o[b].x, o[b].y, o[b + 1].x, o[b + 1].y);
   }
 }
 
@@ -1410,28 +1412,37 @@ hipError_t launch_pass_a(const DevGeom& g, const float2* psi, const float2* Q, f
   return hipGetLastError();
 }
 
+bool col_tile_supported(int H, int tc) { return tc == cols_tc(H) || tc == cols_tc(H) / 2; }
+
+template <int N, int TC>
+static void pass_b_mode(int mode, unsigned grid, const float2* src, float2* X, const float* amp,
+                        double* Fpart, const DevGeom& g, int ntiles, hipStream_t st) {
+  switch (mode) {
+    case kColFwd: k_pass_b<N, kColFwd, TC><<<grid, kColThreads, 0, st>>>(src, X, amp, Fpart, g, ntiles); break;
+    case kColObj: k_pass_b<N, kColObj, TC><<<grid, kColThreads, 0, st>>>(src, X, amp, Fpart, g, ntiles); break;
+    case kColGrad: k_pass_b<N, kColGrad, TC><<<grid, kColThreads, 0, st>>>(src, X, amp, Fpart, g, ntiles); break;
+    default: k_pass_b<N, kColAdj, TC><<<grid, kColThreads, 0, st>>>(src, X, amp, Fpart, g, ntiles); break;
+  }
+}
+
+// Pass B with g.col_tile columns per workgroup: the default cols_tc(H) or
+// half of it (a tuning choice; the results are the same, only the cost
+// partials are summed in a different grouping).
 hipError_t launch_pass_b(const DevGeom& g, int mode, const float2* src, float2* X,
                          const float* amp, double* Fpart, int Kc, hipStream_t st) {
-  const int ntiles = g.W / cols_per_wg(g.H);
+  if (mode != kColFwd && mode != kColObj && mode != kColGrad && mode != kColAdj)
+    return hipErrorInvalidValue;
+  const int tc = g.col_tile ? g.col_tile : cols_tc(g.H);
+  if (!col_tile_supported(g.H, tc)) return hipErrorInvalidValue;
+  const int ntiles = g.W / tc;
   const unsigned grid = (unsigned)ntiles * (unsigned)(Kc * g.nd);
   switch (g.H) {
-#define CASE(N)                                                                                 \
-  case N:                                                                                       \
-    switch (mode) {                                                                             \
-      case kColFwd:                                                                             \
-        k_pass_b<N, kColFwd><<<grid, kColThreads, 0, st>>>(src, X, amp, Fpart, g, ntiles);      \
-        break;                                                                                  \
-      case kColObj:                                                                             \
-        k_pass_b<N, kColObj><<<grid, kColThreads, 0, st>>>(src, X, amp, Fpart, g, ntiles);      \
-        break;                                                                                  \
-      case kColGrad:                                                                            \
-        k_pass_b<N, kColGrad><<<grid, kColThreads, 0, st>>>(src, X, amp, Fpart, g, ntiles);     \
-        break;                                                                                  \
-      case kColAdj:                                                                             \
-        k_pass_b<N, kColAdj><<<grid, kColThreads, 0, st>>>(src, X, amp, Fpart, g, ntiles);      \
-        break;                                                                                  \
-      default: return hipErrorInvalidValue;                                                     \
-    }                                                                                           \
+#define CASE(N)                                                                     \
+  case N:                                                                           \
+    if (tc == cols_tc(N))                                                           \
+      pass_b_mode<N, cols_tc(N)>(mode, grid, src, X, amp, Fpart, g, ntiles, st);    \
+    else                                                                            \
+      pass_b_mode<N, cols_tc(N) / 2>(mode, grid, src, X, amp, Fpart, g, ntiles, st); \
     break;
     HOLO_FOR_SIZES(CASE)
 #undef CASE
@@ -1500,9 +1511,15 @@ hipError_t launch_probe_shift_acc(const DevGeom& g, float2* G, const float2* Pbu
 
 hipError_t launch_radon_fwd(const DevGeom& g, const float2* ub, const float2* uTb, float2* psi,
                             const double* ang, const int2* groups, int g0, int ngroups, int c0,
-                            int c1, hipStream_t st) {
-  const unsigned n = (unsigned)(g.W / kFwdNB) * (unsigned)(g.H / kFwdZT) * (unsigned)ngroups;
-  k_radon_fwd<<<n, kThreads, 0, st>>>(ub, uTb, psi, g, ang, groups, g0, ngroups, c0, c1);
+                            int c1, int nb, hipStream_t st) {
+  const unsigned n = (unsigned)(g.W / nb) * (unsigned)(g.H / kFwdZT) * (unsigned)ngroups;
+  if (nb == kFwdNB)
+    k_radon_fwd<kFwdNB><<<n, kThreads, 0, st>>>(ub, uTb, psi, g, ang, groups, g0, ngroups, c0, c1);
+  else if (nb == kFwdNB / 2)
+    k_radon_fwd<kFwdNB / 2><<<n, kThreads, 0, st>>>(ub, uTb, psi, g, ang, groups, g0, ngroups, c0,
+                                                    c1);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

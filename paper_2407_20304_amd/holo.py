@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libholo.so")
 EXPORTS = (
     "holo_plan_create", "holo_plan_destroy", "holo_workspace_bytes", "holo_plan_set_functional",
     "holo_plan_set_chunk", "holo_plan_get_chunk", "holo_plan_autotune",
+    "holo_plan_set_tile", "holo_plan_get_tile", "holo_plan_autotune_tile",
     "holo_plan_set_probe_shifts", "holo_plan_set_padding", "holo_plan_set_projector",
     "holo_fwd", "holo_adj", "holo_objective", "holo_grad",
     "holo_grad_object", "holo_grad_probe",
@@ -78,6 +79,10 @@ def lib():
     L.holo_plan_set_projector.argtypes = [P, c_int32]
     L.holo_plan_get_chunk.argtypes = [P, POINTER(c_int32)]
     L.holo_plan_autotune.argtypes = [P, P, P, P, P, P, P, P, P, c_int32, P, c_size_t, P, P, P]
+    L.holo_plan_set_tile.argtypes = [P, c_int32, c_int32]
+    L.holo_plan_get_tile.argtypes = [P, c_int32, POINTER(c_int32)]
+    L.holo_plan_autotune_tile.argtypes = [P, c_int32, P, P, P, P, P, P, P, P, c_int32, P, c_size_t,
+                                          P, P, P]
     L.holo_fwd.argtypes = [P, P, P, c_int32, c_int32, P, P, c_size_t, P]
     L.holo_adj.argtypes = [P, P, P, c_int32, c_int32, P, P, P, P, c_size_t, P]
     L.holo_objective.argtypes = [P, P, P, P, P, P, P, c_size_t, P]
@@ -308,6 +313,95 @@ class Plan:
                 json.dump(data, f, indent=1, sort_keys=True)
             os.replace(tmp, cache)
         return int(best.value), result
+
+    TILES = {"chunk": 0, "col_tile": 1, "fs_slab": 2, "fwd_bins": 3}
+
+    def set_tile(self, name, value):
+        """Set a launch-shape parameter ("chunk", "col_tile", "fs_slab")."""
+        _check(lib().holo_plan_set_tile(self._h, c_int32(self.TILES[name]), c_int32(int(value))))
+        self._refresh_workspace_size()
+
+    def get_tile(self, name):
+        v = c_int32()
+        _check(lib().holo_plan_get_tile(self._h, c_int32(self.TILES[name]), ctypes.byref(v)))
+        return int(v.value)
+
+    def autotune_tile(self, name, u, q, amp, amp_ref, candidates, stream=None):
+        """Time one gradient per candidate value of a launch-shape parameter
+        (holo_plan_autotune_tile) and keep the fastest.  Returns
+        (value, {candidate: ms})."""
+        import torch
+        self._check_data(u, q, amp, amp_ref)
+        cands = [int(c) for c in candidates]
+        v0 = self.get_tile(name)
+        need = 0
+        for c in cands:
+            self.set_tile(name, c)
+            need = max(need, self.workspace_bytes)
+        self.set_tile(name, v0)
+        ws = torch.empty(need, dtype=torch.uint8, device=u.device)
+        F = torch.empty((1,), dtype=torch.float64, device=u.device)
+        g_u, g_q = torch.empty_like(u), torch.empty_like(q)
+        arr = (c_int32 * len(cands))(*cands)
+        times = (c_float * len(cands))()
+        best = c_int32()
+        _check(lib().holo_plan_autotune_tile(self._h, c_int32(self.TILES[name]), _ptr(u), _ptr(q),
+                                             _ptr(amp), _ptr(amp_ref), _ptr(F), _ptr(g_u),
+                                             _ptr(g_q), arr, c_int32(len(cands)), _ptr(ws),
+                                             c_size_t(ws.numel()), ctypes.byref(best), times,
+                                             _stream(stream)))
+        del ws, g_u, g_q
+        self._ws = None
+        self._refresh_workspace_size()
+        return int(best.value), {c: float(t) for c, t in zip(cands, times)}
+
+    def autotune_tiles(self, u, q, amp, amp_ref, chunks=(16, 32, 64, 128), cache=None):
+        """The chunk (autotune), then the column tile (default or half) and,
+        with the Fourier-slice projector, the slab depth (2, 4, 8), each
+        timed with the others fixed.  Returns {name: (value, times)}; with a
+        cache file the choices are stored and reused like the chunk's."""
+        import json
+        cache = cache or os.environ.get("HOLO_TUNE_CACHE")
+        key = self.tune_key(u.device) + ":tiles:" + self.projector
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                entry = json.load(f).get(key)
+            names = ("chunk", "col_tile", "fs_slab", "fwd_bins")
+            if entry is not None and all(n in entry for n in names):
+                for name in names:
+                    self.set_tile(name, int(entry[name]))
+                return {name: (int(entry[name]), None) for name in names}
+        out = {"chunk": self.autotune(u, q, amp, amp_ref, candidates=chunks)}
+        out["col_tile"] = self.autotune_tile("col_tile", u, q, amp, amp_ref,
+                                             [0, self.default_col_tile() // 2])
+        if self.projector == "fourier":
+            out["fs_slab"] = self.autotune_tile("fs_slab", u, q, amp, amp_ref, [2, 4, 8])
+            out["fwd_bins"] = (self.get_tile("fwd_bins"), None)
+        else:
+            out["fs_slab"] = (self.get_tile("fs_slab"), None)
+            bins = [b for b in (16, 8) if self._tile_ok("fwd_bins", b)]
+            out["fwd_bins"] = self.autotune_tile("fwd_bins", u, q, amp, amp_ref, bins)
+        if cache:
+            data = {}
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    data = json.load(f)
+            data[key] = {name: v[0] for name, v in out.items()}
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(data, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return out
+
+    def _tile_ok(self, name, value):
+        v0 = self.get_tile(name)
+        ok = lib().holo_plan_set_tile(self._h, c_int32(self.TILES[name]), c_int32(int(value))) == 0
+        lib().holo_plan_set_tile(self._h, c_int32(self.TILES[name]), c_int32(v0))
+        return ok
+
+    def default_col_tile(self):
+        """The column pass's default columns per workgroup for this H."""
+        return 4 if self.H >= 2048 else (8 if self.H >= 1024 else 16)
 
     FUNCTIONALS = {"amplitude": 0, "intensity": 1, "conventional": 2}
 

@@ -296,11 +296,41 @@ def test_projector_switch_validates_on_the_host():
     assert L.holo_plan_set_projector(p._h, 2) == 1
     n0 = p.workspace_bytes
     p.set_projector("fourier")
-    # 8 grids of (2W)^2 and 8 x n_angles x (W + 2) polar samples, complex64
-    assert p.workspace_bytes >= n0 + 8 * (2 * 64) ** 2 * 8 + 8 * 10 * 66 * 8
+    # 8 grids of (2W)^2 and 8 x n_angles x (W + 2) polar samples (complex64)
+    # in place of the two slice-blocked volume copies (64 rows of 64 + 64)
+    vol = 2 * 64 * 64 * (64 + 64) * 8
+    assert p.workspace_bytes >= n0 - vol + 8 * (2 * 64) ** 2 * 8 + 8 * 10 * 66 * 8
     p.set_projector("joseph")
     assert p.workspace_bytes == n0
     p.close()
     big = make_plan(W=2048)
     assert L.holo_plan_set_projector(big._h, 1) == 2
     big.close()
+
+
+def test_tile_parameters_validate_on_the_host():
+    L = holo.lib()
+    p = make_plan()          # 64 x 64: the column pass takes 16 columns, or 8
+    v = ctypes.c_int32()
+    assert L.holo_plan_set_tile(None, 1, 8) == 1
+    assert L.holo_plan_set_tile(p._h, 4, 8) == 1          # unknown parameter
+    assert L.holo_plan_set_tile(p._h, 3, 12) == 1         # forward bins are 16 or 8
+    assert L.holo_plan_set_tile(p._h, 3, 8) == 0
+    assert L.holo_plan_get_tile(p._h, 3, ctypes.byref(v)) == 0 and v.value == 8
+    assert L.holo_plan_set_tile(p._h, 3, 16) == 0
+    assert L.holo_plan_set_tile(p._h, 1, 4) == 1
+    assert L.holo_plan_set_tile(p._h, 1, 8) == 0
+    assert L.holo_plan_get_tile(p._h, 1, ctypes.byref(v)) == 0 and v.value == 8
+    assert L.holo_plan_set_tile(p._h, 1, 0) == 0
+    assert L.holo_plan_set_tile(p._h, 2, 3) == 1
+    assert L.holo_plan_set_tile(p._h, 2, 4) == 0
+    assert L.holo_plan_set_tile(p._h, 0, 2) == 0          # chunk 2 >= largest angle group
+    assert L.holo_plan_get_tile(p._h, 0, ctypes.byref(v)) == 0 and v.value == 2
+    assert p.default_col_tile() == 16
+    buf = ctypes.c_void_p(1)
+    cands = (ctypes.c_int32 * 2)(0, 3)
+    best = ctypes.c_int32()
+    # an invalid candidate is refused before any device work
+    assert L.holo_plan_autotune_tile(p._h, 1, buf, buf, buf, buf, buf, buf, buf, cands, 2, buf,
+                                     1 << 40, ctypes.byref(best), None, None) == 1
+    p.close()

@@ -270,6 +270,52 @@ def test_fourier_slice_projector_parity(H, W, angles, chunk):
     PB.assert_close_scalar(F1.item(), PB.oracle_grad(p)[0], "F with Joseph's sums")
 
 
+def test_tile_choices_and_their_autotuner(small):
+    """The launch-shape parameters change no field: the column pass at half
+    its default tile and the Fourier-slice projector at slab depths 2 and 8
+    give bitwise-equal gradients (F up to the grouping of its partial sums);
+    the tile autotuner picks a value among the candidates and the tuned plan
+    still matches the oracle."""
+    import torch
+    say("tile choices 64^3, 12 angles, shifts, chunk 5")
+    u, q, amp, amp_ref = PB.to_gpu(small)
+    plan = PB.gpu_plan(small)
+    F0, gu0, gq0 = [t.clone() for t in plan.holo_grad(u, q, amp, amp_ref)]
+    plan.set_tile("col_tile", plan.default_col_tile() // 2)
+    F1, gu1, gq1 = plan.holo_grad(u, q, amp, amp_ref)
+    assert bool(torch.equal(gu0, gu1)) and bool(torch.equal(gq0, gq1))
+    assert abs(F1.item() - F0.item()) <= 1e-12 * abs(F0.item())
+    plan.set_tile("col_tile", 0)
+    # the forward ray sums in 8-bin blocks (regrouped angles): the same sums
+    # to rounding
+    plan.set_tile("fwd_bins", 8)
+    F2, gu2, gq2 = plan.holo_grad(u, q, amp, amp_ref)
+    Fo, guo, gqo = PB.oracle_grad(small)
+    PB.assert_close_scalar(F2.item(), Fo, "F (8-bin forward)")
+    PB.assert_close(gu2.cpu().numpy(), guo, "g_u (8-bin forward)")
+    PB.assert_close(gq2.cpu().numpy(), gqo, "g_q (8-bin forward)")
+    plan.set_tile("fwd_bins", 16)
+    plan.set_projector("fourier")
+    plan.set_tile("fs_slab", 8)
+    _, guf8, gqf8 = [t.clone() for t in plan.holo_grad(u, q, amp, amp_ref)]
+    plan.set_tile("fs_slab", 2)
+    _, guf2, gqf2 = plan.holo_grad(u, q, amp, amp_ref)
+    assert bool(torch.equal(guf8, guf2)) and bool(torch.equal(gqf8, gqf2))
+    choice = plan.autotune_tiles(u, q, amp, amp_ref, chunks=(4, 6, 12))
+    say("  tuned: %s" % {k: v[0] for k, v in choice.items()})
+    assert choice["chunk"][0] in (4, 6, 12) and choice["col_tile"][0] in (0, plan.default_col_tile() // 2)
+    assert choice["fs_slab"][0] in (2, 4, 8)
+    F, g_u, g_q = plan.holo_grad(u, q, amp, amp_ref)
+    small.geom.projector = "fourier"
+    try:
+        Fo, guo, gqo = PB.oracle_grad(small)
+    finally:
+        small.geom.projector = "joseph"
+    PB.assert_close_scalar(F.item(), Fo)
+    PB.assert_close(g_u.cpu().numpy(), guo, "g_u")
+    PB.assert_close(g_q.cpu().numpy(), gqo, "g_q")
+
+
 def test_autotune_chunk_and_cache(small, tmp_path):
     """The chunk autotuner times one gradient per candidate, keeps the
     fastest, and the tuned plan's gradient still matches the oracle; a
