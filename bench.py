@@ -43,9 +43,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Sources the dominant kernel is built from (its body, the shared constants
-# and launch helpers, and the FFT header compiled into the same unit).
-KERNEL_SOURCES = ("holo_kernels.hip", "holo_internal.hpp", "fft_lds.hpp")
+# Sources the ray-sum kernels are built from (their bodies and launchers,
+# and the shared constants and geometry header).
+KERNEL_SOURCES = ("holo_radon.hip", "holo_internal.hpp")
 
 
 def csrc_sha256():

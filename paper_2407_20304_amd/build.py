@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libholo.so")
-SOURCES = ["holo_kernels.hip", "holo_api.cpp", "holo2d.hip", "holo2d_api.cpp", "holo_multires.hip",
+SOURCES = ["holo_kernels.hip", "holo_radon.hip", "holo_api.cpp", "holo2d.hip", "holo2d_api.cpp", "holo_multires.hip",
            "holo_fs.hip"]
 PLAIN_LIB = os.path.join(HERE, "libholo_plain.so")
 PLAIN_SOURCES = [os.path.join("plain", "plain_radon.hip")]

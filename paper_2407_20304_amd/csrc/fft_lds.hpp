@@ -268,6 +268,96 @@ __device__ __forceinline__ void fft_stage(float2* line, const float2* tw, int lt
   fft_sync<WAVE>();
 }
 
+// Register-chained form.  Thread lt holds the line elements e[m] =
+// x[lt + m TL] (m < N / TL).  When every stage of the plan gives each
+// thread the same number of butterflies (N / R a multiple of TL for every
+// radix R), those are exactly the inputs of its first-stage butterflies
+// (i = lt + it TL reads x[i + j N / R]) and the outputs of its last-stage
+// butterflies (written to i + j N / R, since the last stage has P = N / R).
+// The first stage then reads registers and the last writes them: a
+// transform costs one LDS round trip fewer than its stage count, and the
+// work between a forward and an inverse transform (a transfer-function
+// multiply, a residual) needs none.
+template <int N, int TL, int S = 0>
+__host__ __device__ constexpr bool fft_even_stages() {
+  if constexpr (S >= fft_nstages_tl(N, TL)) {
+    return true;
+  } else {
+    return (N / fft_radix_tl(N, TL, S)) % TL == 0 && fft_even_stages<N, TL, S + 1>();
+  }
+}
+
+template <int N, int TL, int R, int P, bool INV, bool PADDED, bool WAVE, bool IN_REG, bool OUT_REG,
+          int E>
+__device__ __forceinline__ void fft_stage_e(float2 (&e)[E], float2* line, const float2* tw,
+                                            int lt) {
+  constexpr int NB = N / R;
+  constexpr int IT = NB / TL;
+  static_assert(NB % TL == 0 && E == N / TL, "even stages");
+  constexpr bool RLIN = !PADDED || NB % 32 == 0 || 32 % NB == 0;
+  constexpr bool WLIN = !PADDED || P % 32 == 0 ||
+                        (32 % P == 0 && (32 % (P * R) == 0 || (P * R) % 32 == 0));
+  float2 v[IT][R];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int i = lt + it * TL;
+    if constexpr (IN_REG) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) v[it][j] = e[it + j * IT];
+    } else if constexpr (RLIN) {
+      const int rb = fidx<PADDED>(i);
+#pragma unroll
+      for (int j = 0; j < R; ++j) v[it][j] = line[rb + pstep<PADDED>(j * NB)];
+    } else {
+#pragma unroll
+      for (int j = 0; j < R; ++j) v[it][j] = line[fidx<PADDED>(i + j * NB)];
+    }
+  }
+  // every thread's reads of the line (this stage's, or the previous
+  // transform's last stage) are done before it is overwritten
+  if constexpr (!OUT_REG) fft_sync<WAVE>();
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int i = lt + it * TL;
+    const int k = i % P;
+    if (P > 1) {
+#pragma unroll
+      for (int j = 1; j < R; ++j) {
+        float2 w = tw[j * k * (N / (P * R))];
+        if (INV) w.y = -w.y;
+        v[it][j] = cmul(v[it][j], w);
+      }
+    }
+    Dft<R, INV>::run(v[it]);
+    if constexpr (OUT_REG) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) e[it + j * IT] = v[it][j];
+    } else {
+      const int base = (i - k) * R + k;
+      if constexpr (WLIN) {
+        const int wb = fidx<PADDED>(base);
+#pragma unroll
+        for (int j = 0; j < R; ++j) line[wb + pstep<PADDED>(j * P)] = v[it][j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < R; ++j) line[fidx<PADDED>(base + j * P)] = v[it][j];
+      }
+    }
+  }
+  if constexpr (!OUT_REG) fft_sync<WAVE>();
+}
+
+template <int N, int TL, bool INV, bool PADDED, bool WAVE, int S, int E>
+__device__ __forceinline__ void fft_stages_e(float2 (&e)[E], float2* line, const float2* tw,
+                                             int lt) {
+  constexpr int NS = fft_nstages_tl(N, TL);
+  if constexpr (S < NS) {
+    fft_stage_e<N, TL, fft_radix_tl(N, TL, S), fft_pstride_tl(N, TL, S), INV, PADDED, WAVE, S == 0,
+                S == NS - 1>(e, line, tw, lt);
+    fft_stages_e<N, TL, INV, PADDED, WAVE, S + 1>(e, line, tw, lt);
+  }
+}
+
 template <int N, int TL, bool INV, bool PADDED, bool WAVE, int S>
 __device__ __forceinline__ void fft_stages(float2* line, const float2* tw, int lt) {
   if constexpr (S < fft_nstages_tl(N, TL)) {
@@ -290,6 +380,31 @@ __device__ __forceinline__ void fft(float2* line, const float2* tw, int lt) {
   static_assert(!WAVE || (TL <= 64 && 64 % TL == 0), "wavefront-owned lines");
   fft_sync<WAVE>();
   fft_stages<N, TL, INV, PADDED, WAVE, 0>(line, tw, lt);
+}
+
+// Unnormalised DFT of the line whose elements x[lt + m TL] thread lt holds in
+// e[m]; on return e[m] holds X[lt + m TL].  `line` (fft_line_len(N) elements
+// if PADDED) is the exchange buffer of the line: its contents are
+// overwritten, and every thread of the line must call.  The twiddles obey
+// the rules of fft(); no other ordering is needed around the call: the
+// transform neither reads the line before writing it nor leaves anything
+// in it that the caller reads.  Plans whose stages are not even (lengths
+// 3 * 2^a for some thread counts) go through the line-based transform.
+template <int N, int TL, bool INV, bool PADDED = true, bool WAVE = false>
+__device__ __forceinline__ void fft_e(float2 (&e)[N / TL], float2* line, const float2* tw,
+                                      int lt) {
+  static_assert(!WAVE || (TL <= 64 && 64 % TL == 0), "wavefront-owned lines");
+  static_assert(N % TL == 0, "whole elements per thread");
+  if constexpr (fft_even_stages<N, TL>()) {
+    fft_stages_e<N, TL, INV, PADDED, WAVE, 0>(e, line, tw, lt);
+  } else {
+    fft_sync<WAVE>();
+#pragma unroll
+    for (int m = 0; m < N / TL; ++m) line[fidx<PADDED>(lt + m * TL)] = e[m];
+    fft<N, TL, INV, PADDED, WAVE>(line, tw, lt);
+#pragma unroll
+    for (int m = 0; m < N / TL; ++m) e[m] = line[fidx<PADDED>(lt + m * TL)];
+  }
 }
 
 }  // namespace holo

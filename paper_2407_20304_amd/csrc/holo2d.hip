@@ -6,12 +6,16 @@
 // lists one item per workgroup (instance, plane/job, first line), the kernel
 // switches on the instance's edge length to the FFT specialised for it.
 //   probe   rows+columns: Q_j = D_{rho_probe_j} q, P = D_1 q, reference cost
-//           and residual; rows+columns of D_{-1} on the residual
+//           and residual r_ref, the columns of D_{-1} on r_ref
 //   A       rows: phi = 1 + B_j(psi - 1), x = Q_j phi, row propagation
 //   B       columns: propagation, residual, cost, adjoint propagation
-//   C       rows: adjoint propagation -> w, G_j = conj(phi) w, X = conj(Q_j) w
-//   Gq      rows+columns of D_{-rho_probe_j} on G_j
-//   gather  g_psi = sum_j B_j^T X_j and g_q = sum_j G_j + D_{-1} r_ref
+//   C       rows: adjoint propagation -> w, X = conj(Q_j) w, G_j = conj(phi) w
+//           and at once the rows of D_{-rho_probe_j} on G_j; the rows of
+//           D_{-1} on r_ref
+//   Gq      per column tile: the columns of every D_{-rho_probe_j} G_j,
+//           summed over j before one inverse transform, plus D_{-1} r_ref:
+//           g_q = sum_j D_{-rho_probe_j} G_j + D_{-1} r_ref
+//   gather  g_psi = sum_j B_j^T X_j
 //   reduce  per-instance cost from double partials
 #include "holo2d_internal.hpp"
 #include "fft_lds.hpp"
@@ -32,8 +36,15 @@ __host__ __device__ constexpr int b_col_pitch(int n) { return fft_line_len(n) + 
 // LDS of one column workgroup of size n: twiddles plus the tile.
 __host__ __device__ constexpr int b_cols_lds(int n) { return n + b_cols_tc(n) * b_col_pitch(n); }
 
+// The probe-gradient column pass keeps every plane's spectrum sum in
+// registers next to the plane being transformed: 4 columns per workgroup
+// (64 threads per column) keep that to 2 x n / 64 elements per thread.
+__host__ __device__ constexpr int b_gq_tc(int) { return 4; }
+__host__ __device__ constexpr int b_gq_lds(int n) { return n + b_gq_tc(n) * b_col_pitch(n); }
+
 int b2_rows_per_wg(int n) { return b_rows_lpw(n); }
 int b2_cols_per_wg(int n) { return b_cols_tc(n); }
+int b2_gq_per_wg(int n) { return b_gq_tc(n); }
 bool b2_size_supported(int n) {
   switch (n) {
     case 64: case 128: case 192: case 256: case 384: case 512: case 1024: return true;
@@ -136,31 +147,28 @@ __device__ __forceinline__ void b_rows_body(const B2Args& A, const B2Item& it, f
       chirp = (j < nd) ? nd + j : 2 * nd;
       conj = false;
       break;
-    case kB2RowsRef:     // residual -> D_{-1}
-      src = A.P + in.off;
-      dst = A.P + in.off;
-      chirp = 2 * nd;
-      conj = true;
-      break;
     case kB2RowsA:
       src = nullptr;
       dst = A.X + in.off * nd + j * fr;
       chirp = j;
       conj = false;
       break;
-    case kB2RowsC:
-      src = A.X + in.off * nd + j * fr;
-      dst = A.X + in.off * nd + j * fr;
-      chirp = j;
-      conj = true;
-      break;
-    default:             // kB2RowsGq: G_j -> D_{-rho_probe_j}
-      src = A.G + in.off * nd + j * fr;
-      dst = A.G + in.off * nd + j * fr;
-      chirp = nd + j;
+    default:             // kB2RowsC, kB2RowsCGq
+      if (j < nd) {
+        src = A.X + in.off * nd + j * fr;
+        dst = A.X + in.off * nd + j * fr;
+        chirp = j;
+      } else {           // reference residual -> rows of D_{-1}
+        src = A.P + in.off;
+        dst = A.P + in.off;
+        chirp = 2 * nd;
+      }
       conj = true;
       break;
   }
+  // The thread's row elements s = lt + e TL stay in registers from load to
+  // store; the line in LDS is only the transforms' exchange buffer.
+  float2 v[E];
   if (A.mode == kB2RowsA) {
     const double m = A.mag[j];
     const BTaps ty = b_fwd_taps(c, m, z, N);
@@ -169,42 +177,57 @@ __device__ __forceinline__ void b_rows_body(const B2Args& A, const B2Item& it, f
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int s = lt + e * TL;
-      L[fpi(s)] = cmul(Qr[s], b_phi(psi, N, ty, b_fwd_taps(c, m, s, N)));
+      v[e] = cmul(Qr[s], b_phi(psi, N, ty, b_fwd_taps(c, m, s, N)));
     }
   } else {
     const float2* r = src + (size_t)z * N;
 #pragma unroll
-    for (int e = 0; e < E; ++e) L[fpi(lt + e * TL)] = r[lt + e * TL];
+    for (int e = 0; e < E; ++e) v[e] = r[lt + e * TL];
   }
   // A line within one wavefront synchronises only there (s_tw is behind
-  // the barrier).
+  // the barrier; otherwise the first stage's barrier covers it).
   constexpr bool WL = TL <= 64;
   if constexpr (WL) __syncthreads();
-  fft<N, TL, false, true, WL>(L, s_tw, lt);
+  fft_e<N, TL, false, true, WL>(v, L, s_tw, lt);
   const float2* ch = in.chirp + (size_t)chirp * N;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int s = lt + e * TL;
-    L[fpi(s)] = conj ? cmulc(L[fpi(s)], ch[s]) : cmul(L[fpi(s)], ch[s]);
+    v[e] = conj ? cmulc(v[e], ch[s]) : cmul(v[e], ch[s]);
   }
-  fft<N, TL, true, true, WL>(L, s_tw, lt);
+  fft_e<N, TL, true, true, WL>(v, L, s_tw, lt);
   float2* o = dst + (size_t)z * N;
-  if (A.mode == kB2RowsC) {
-    const double m = A.mag[j];
-    const BTaps ty = b_fwd_taps(c, m, z, N);
-    const float2* psi = A.psi + in.off;
+  if ((A.mode == kB2RowsC || A.mode == kB2RowsCGq) && j < nd) {
+    // X = conj(Q_j) w; with the probe gradient, G_j = conj(phi) w goes
+    // through the rows of D_{-rho_probe_j} at once
+    const bool gq = A.mode == kB2RowsCGq;
     const float2* Qr = A.Q + in.off * nd + j * fr + (size_t)z * N;
-    float2* Gr = A.G + in.off * nd + j * fr + (size_t)z * N;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int s = lt + e * TL;
-      const float2 w = L[fpi(s)];
-      Gr[s] = cmulc(w, b_phi(psi, N, ty, b_fwd_taps(c, m, s, N)));
-      o[s] = cmulc(w, Qr[s]);
+      o[s] = cmulc(v[e], Qr[s]);
+    }
+    if (gq) {
+      const double m = A.mag[j];
+      const BTaps ty = b_fwd_taps(c, m, z, N);
+      const float2* psi = A.psi + in.off;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int s = lt + e * TL;
+        v[e] = cmulc(v[e], b_phi(psi, N, ty, b_fwd_taps(c, m, s, N)));
+      }
+      fft_e<N, TL, false, true, WL>(v, L, s_tw, lt);
+      const float2* cq = in.chirp + (size_t)(nd + j) * N;
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = cmulc(v[e], cq[lt + e * TL]);
+      fft_e<N, TL, true, true, WL>(v, L, s_tw, lt);
+      float2* Gr = A.G + in.off * nd + j * fr + (size_t)z * N;
+#pragma unroll
+      for (int e = 0; e < E; ++e) Gr[lt + e * TL] = v[e];
     }
   } else {
 #pragma unroll
-    for (int e = 0; e < E; ++e) o[lt + e * TL] = L[fpi(lt + e * TL)];
+    for (int e = 0; e < E; ++e) o[lt + e * TL] = v[e];
   }
   (void)LPW;
 }
@@ -270,62 +293,65 @@ __device__ __forceinline__ void b_cols_body(const B2Args& A, const B2Item& it, f
   float2* frame;
   const float* amp = nullptr;
   int chirp;
-  bool conj = false, adj_after = false;
-  switch (A.mode) {
-    case kB2ColsProbe:
-      frame = (j < nd) ? A.Q + in.off * nd + j * fr : A.P + in.off;
-      chirp = (j < nd) ? nd + j : 2 * nd;
-      if (j == nd) amp = A.amp_ref + in.off;
-      break;
-    case kB2ColsRef:
-      frame = A.P + in.off;
-      chirp = 2 * nd;
-      conj = true;
-      break;
-    case kB2ColsB:
-      frame = A.X + in.off * nd + j * fr;
-      chirp = j;
-      amp = A.amp ? A.amp + in.off * nd + j * fr : nullptr;
-      adj_after = A.amp != nullptr && A.want_grad;
-      break;
-    default:  // kB2ColsGq
-      frame = A.G + in.off * nd + j * fr;
-      chirp = nd + j;
-      conj = true;
-      break;
+  bool adj_after = false;
+  if (A.mode == kB2ColsProbe) {
+    frame = (j < nd) ? A.Q + in.off * nd + j * fr : A.P + in.off;
+    chirp = (j < nd) ? nd + j : 2 * nd;
+    if (j == nd) {                 // reference: residual, then D_{-1} columns
+      amp = A.amp_ref + in.off;
+      adj_after = A.want_gq != 0;
+    }
+  } else {                         // kB2ColsB
+    frame = A.X + in.off * nd + j * fr;
+    chirp = j;
+    amp = A.amp ? A.amp + in.off * nd + j * fr : nullptr;
+    adj_after = A.amp != nullptr && A.want_grad;
   }
   for (int i = threadIdx.x; i < N * TC; i += kT2) {
     const int zz = i / TC, cc = i % TC;
     col0[cc * CP + fpi(zz)] = frame[(size_t)zz * N + s0 + cc];
   }
   const float2* ch = in.chirp + (size_t)chirp * N;
-  // Each column lies within one wavefront: the transforms synchronise only
-  // there, behind one barrier for the tile and s_tw.
+  // The thread's column elements zz = lt + e TLc stay in registers around
+  // the transforms; the tile is touched to load, to store and for the
+  // residual (amplitudes read in the coalesced tile order).
+  constexpr int EC = N / TLc;
   constexpr bool WL = TLc <= 64;
-  if constexpr (WL) __syncthreads();
-  fft<N, TLc, false, true, WL>(Lc, s_tw, lt);
-  for (int zz = lt; zz < N; zz += TLc)
-    Lc[fpi(zz)] = conj ? cmulc(Lc[fpi(zz)], ch[zz]) : cmul(Lc[fpi(zz)], ch[zz]);
-  fft<N, TLc, true, true, WL>(Lc, s_tw, lt);
-  __syncthreads();
+  float2 v[EC];
+  __syncthreads();   // tile and s_tw
+#pragma unroll
+  for (int e = 0; e < EC; ++e) v[e] = Lc[fpi(lt + e * TLc)];
+  fft_e<N, TLc, false, true, WL>(v, Lc, s_tw, lt);
+#pragma unroll
+  for (int e = 0; e < EC; ++e) v[e] = cmul(v[e], ch[lt + e * TLc]);
+  fft_e<N, TLc, true, true, WL>(v, Lc, s_tw, lt);
   if (amp) {
+    fft_sync<WL>();   // the column's exchange reads are done
+#pragma unroll
+    for (int e = 0; e < EC; ++e) Lc[fpi(lt + e * TLc)] = v[e];
+    __syncthreads();
     double acc = 0.0;
     for (int i = threadIdx.x; i < N * TC; i += kT2) {
       const int zz = i / TC, cc = i % TC;
-      float2 v = col0[cc * CP + fpi(zz)];
-      acc += b_residual(v, amp[(size_t)zz * N + s0 + cc], A.functional);
-      col0[cc * CP + fpi(zz)] = v;
+      float2 t = col0[cc * CP + fpi(zz)];
+      acc += b_residual(t, amp[(size_t)zz * N + s0 + cc], A.functional);
+      col0[cc * CP + fpi(zz)] = t;
     }
-    b_block_sum(acc, A.Fpart + it.slot);
-    __syncthreads();
+    b_block_sum(acc, A.Fpart + it.slot);   // (its barriers publish the residual)
+#pragma unroll
+    for (int e = 0; e < EC; ++e) v[e] = Lc[fpi(lt + e * TLc)];
   }
   if (adj_after) {
-    fft<N, TLc, false, true, WL>(Lc, s_tw, lt);
-    for (int zz = lt; zz < N; zz += TLc) Lc[fpi(zz)] = cmulc(Lc[fpi(zz)], ch[zz]);
-    fft<N, TLc, true, true, WL>(Lc, s_tw, lt);
-    __syncthreads();
+    fft_e<N, TLc, false, true, WL>(v, Lc, s_tw, lt);
+#pragma unroll
+    for (int e = 0; e < EC; ++e) v[e] = cmulc(v[e], ch[lt + e * TLc]);
+    fft_e<N, TLc, true, true, WL>(v, Lc, s_tw, lt);
   }
   if (A.mode == kB2ColsB && A.amp && !A.want_grad) return;  // objective only
+  __syncthreads();   // every column's exchange reads are done
+#pragma unroll
+  for (int e = 0; e < EC; ++e) Lc[fpi(lt + e * TLc)] = v[e];
+  __syncthreads();
   for (int i = threadIdx.x; i < N * TC; i += kT2) {
     const int zz = i / TC, cc = i % TC;
     frame[(size_t)zz * N + s0 + cc] = col0[cc * CP + fpi(zz)];
@@ -349,8 +375,80 @@ __global__ __launch_bounds__(kT2) void k2_cols(B2Args A, const B2Item* __restric
   }
 }
 
+// Probe gradient of one column tile: every plane's G_j (rows already
+// through D_{-rho_probe_j}) is loaded, its columns transformed and weighted
+// by the conjugate column transfer factors, and the spectra are summed in
+// registers (each thread keeps the column elements it owns); one inverse
+// transform of the sum, plus the reference term D_{-1} r_ref, is g_q.
+template <int N>
+__device__ __forceinline__ void b_cols_gq_sum(const B2Args& A, const B2Item& it, float2* lds) {
+  constexpr int TC = b_gq_tc(N), TLc = kT2 / TC, EC = N / TLc;
+  static_assert(N % TLc == 0, "column elements per thread");
+  float2* s_tw = lds;
+  const int cidx = threadIdx.x / TLc, lt = threadIdx.x % TLc;
+  constexpr int CP = b_col_pitch(N);
+  float2* col0 = lds + N;
+  float2* Lc = col0 + cidx * CP;
+  const B2Inst in = A.inst[it.inst];
+  for (int i = threadIdx.x; i < N; i += kT2) s_tw[i] = in.tw[i];
+  const size_t fr = (size_t)N * N;
+  const int nd = A.nd, s0 = it.line0;
+  constexpr bool WL = TLc <= 64;
+  float2 acc[EC];
+#pragma unroll
+  for (int e = 0; e < EC; ++e) acc[e] = make_float2(0.f, 0.f);
+  for (int j = 0; j < nd; ++j) {
+    const float2* frame = A.G + in.off * nd + j * fr;
+    __syncthreads();   // the previous plane's tile has been read
+    for (int i = threadIdx.x; i < N * TC; i += kT2) {
+      const int zz = i / TC, cc = i % TC;
+      col0[cc * CP + fpi(zz)] = frame[(size_t)zz * N + s0 + cc];
+    }
+    __syncthreads();
+    float2 v[EC];
+#pragma unroll
+    for (int e = 0; e < EC; ++e) v[e] = Lc[fpi(lt + e * TLc)];
+    fft_e<N, TLc, false, true, WL>(v, Lc, s_tw, lt);
+    const float2* ch = in.chirp + (size_t)(nd + j) * N;
+#pragma unroll
+    for (int e = 0; e < EC; ++e) {
+      const float2 t = cmulc(v[e], ch[lt + e * TLc]);
+      acc[e].x += t.x;
+      acc[e].y += t.y;
+    }
+  }
+  fft_e<N, TLc, true, true, WL>(acc, Lc, s_tw, lt);
+  __syncthreads();   // every column's exchange reads are done
+#pragma unroll
+  for (int e = 0; e < EC; ++e) Lc[fpi(lt + e * TLc)] = acc[e];
+  __syncthreads();
+  const float2* ref = A.P + in.off;
+  float2* gq = A.g_q + in.off;
+  for (int i = threadIdx.x; i < N * TC; i += kT2) {
+    const int zz = i / TC, cc = i % TC;
+    const size_t o = (size_t)zz * N + s0 + cc;
+    const float2 v = col0[cc * CP + fpi(zz)], r = ref[o];
+    gq[o] = make_float2(v.x + r.x, v.y + r.y);
+  }
+}
+
+template <int LDS>
+__global__ __launch_bounds__(kT2) __attribute__((amdgpu_waves_per_eu(4))) void k2_gq_sum(B2Args A, const B2Item* __restrict__ items) {
+  __shared__ float2 lds[LDS];
+  const B2Item it = items[blockIdx.x];
+  switch (A.inst[it.inst].n) {
+#define CASE(N) \
+  case N:       \
+    if constexpr (b_gq_lds(N) <= LDS) b_cols_gq_sum<N>(A, it, lds); \
+    break;
+    CASE(64) CASE(128) CASE(192) CASE(256) CASE(384) CASE(512) CASE(1024)
+#undef CASE
+    default: break;
+  }
+}
+
 // ---------------------------------------------------------------------------
-// Gather (B^T over planes, probe-gradient sum) and per-instance reduction
+// Gather (B^T over planes) and per-instance reduction
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kT2) void k2_gather(B2Args A, const B2Item* __restrict__ items) {
@@ -363,7 +461,6 @@ __global__ __launch_bounds__(kT2) void k2_gather(B2Args A, const B2Item* __restr
   const size_t fr = (size_t)n * n;
   const double c = n / 2.0;
   float ax = 0.f, ay = 0.f;
-  float2 gq = A.want_ref ? A.P[in.off + p] : make_float2(0.f, 0.f);
   for (int j = 0; j < A.nd; ++j) {
     const double m = A.mag[j];
     const BAdj rz = b_adj_taps(c, m, z, n), rs = b_adj_taps(c, m, s, n);
@@ -381,12 +478,8 @@ __global__ __launch_bounds__(kT2) void k2_gather(B2Args A, const B2Item* __restr
         ay += wt * v.y;
       }
     }
-    const float2 gj = A.G[in.off * A.nd + j * fr + p];
-    gq.x += gj.x;
-    gq.y += gj.y;
   }
-  if (A.g_psi) A.g_psi[in.off + p] = make_float2(ax, ay);
-  if (A.g_q) A.g_q[in.off + p] = gq;
+  A.g_psi[in.off + p] = make_float2(ax, ay);
 }
 
 __global__ __launch_bounds__(kT2) void k2_reduce(const double* __restrict__ parts,
@@ -413,8 +506,19 @@ hipError_t launch_b2_cols(const B2Args& A, const B2Item* items, int n, hipStream
   return hipGetLastError();
 }
 
+hipError_t launch_b2_gq_sum(const B2Args& A, const B2Item* items, int n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (!A.g_q || !A.P) return hipErrorInvalidValue;
+  if (A.max_n <= 512)
+    k2_gq_sum<b_gq_lds(512)><<<n, kT2, 0, st>>>(A, items);
+  else
+    k2_gq_sum<b_gq_lds(1024)><<<n, kT2, 0, st>>>(A, items);
+  return hipGetLastError();
+}
+
 hipError_t launch_b2_gather(const B2Args& A, const B2Item* items, int n, hipStream_t st) {
   if (n == 0) return hipSuccess;
+  if (!A.g_psi) return hipErrorInvalidValue;
   k2_gather<<<n, kT2, 0, st>>>(A, items);
   return hipGetLastError();
 }

@@ -38,8 +38,8 @@ struct holo2d_plan {
   long long total = 0;
   std::vector<int> dsizes;                // distinct sizes
   std::vector<std::vector<float2>> tw, chirp;
-  ItemList rows_probe, rows_probe_noref, rows_ref, rows_nd, cols_probe, cols_probe_noref,
-      cols_ref, cols_nd, gather;
+  ItemList rows_probe, rows_probe_noref, rows_nd, rows_cgq, cols_probe, cols_probe_noref,
+      cols_nd, cols_gq, gather;
   std::vector<int2> ranges;               // per-instance cost-partial slots
   int n_slots = 0;
   // device tables
@@ -142,15 +142,16 @@ extern "C" holo_status holo2d_plan_create(int32_t n_inst, const int32_t* sizes, 
     for (int i : order) {
       const int n = P->sizes[i];
       const int lpw = b2_rows_per_wg(n), tc = b2_cols_per_wg(n);
+      // job n_dist of the probe and pass-C rows is the reference term
       for (int j = 0; j <= n_dist; ++j)
         for (int z = 0; z < n; z += lpw) {
           P->rows_probe.items.push_back({i, j, z, 0});
+          P->rows_cgq.items.push_back({i, j, z, 0});
           if (j < n_dist) {
             P->rows_probe_noref.items.push_back({i, j, z, 0});
             P->rows_nd.items.push_back({i, j, z, 0});
           }
         }
-      for (int z = 0; z < n; z += lpw) P->rows_ref.items.push_back({i, 0, z, 0});
       for (int j = 0; j <= n_dist; ++j)
         for (int s = 0; s < n; s += tc) {
           // cost slots: plane j's column tiles, then the reference's
@@ -161,7 +162,7 @@ extern "C" holo_status holo2d_plan_create(int32_t n_inst, const int32_t* sizes, 
             P->cols_nd.items.push_back({i, j, s, slot});
           }
         }
-      for (int s = 0; s < n; s += tc) P->cols_ref.items.push_back({i, 0, s, 0});
+      for (int s = 0; s < n; s += b2_gq_per_wg(n)) P->cols_gq.items.push_back({i, 0, s, 0});
       for (int p = 0; p < n * n; p += 256) P->gather.items.push_back({i, 0, p, 0});
     }
     // device table layout
@@ -174,8 +175,8 @@ extern "C" holo_status holo2d_plan_create(int32_t n_inst, const int32_t* sizes, 
     }
     P->off_inst = t;
     t = al(t + sizeof(B2Inst) * n_inst);
-    for (ItemList* L : {&P->rows_probe, &P->rows_probe_noref, &P->rows_ref, &P->rows_nd,
-                        &P->cols_probe, &P->cols_probe_noref, &P->cols_ref, &P->cols_nd,
+    for (ItemList* L : {&P->rows_probe, &P->rows_probe_noref, &P->rows_nd, &P->rows_cgq,
+                        &P->cols_probe, &P->cols_probe_noref, &P->cols_nd, &P->cols_gq,
                         &P->gather}) {
       L->off = t;
       t = al(t + sizeof(B2Item) * L->items.size());
@@ -268,8 +269,8 @@ void b2_table_image(const holo2d_plan* P, const char* base, std::vector<char>& h
   }
   std::copy((const char*)inst.data(), (const char*)(inst.data() + inst.size()),
             h.data() + P->off_inst);
-  for (const ItemList* L : {&P->rows_probe, &P->rows_probe_noref, &P->rows_ref, &P->rows_nd,
-                            &P->cols_probe, &P->cols_probe_noref, &P->cols_ref, &P->cols_nd,
+  for (const ItemList* L : {&P->rows_probe, &P->rows_probe_noref, &P->rows_nd, &P->rows_cgq,
+                            &P->cols_probe, &P->cols_probe_noref, &P->cols_nd, &P->cols_gq,
                             &P->gather})
     std::copy((const char*)L->items.data(), (const char*)(L->items.data() + L->items.size()),
               h.data() + L->off);
@@ -330,7 +331,8 @@ holo_status b2_launch(holo2d_plan* P, B2Run run, const char* tb, char* w, const 
   const bool want_gq = grad && g_q && !conv;
   A.want_ref = want_ref ? 1 : 0;
   A.want_grad = grad ? 1 : 0;
-  A.g_psi = (float2*)g_psi;
+  A.want_gq = want_gq ? 1 : 0;
+  A.g_psi = grad ? (float2*)g_psi : nullptr;
   A.g_q = want_gq ? (float2*)g_q : nullptr;
 
   // probe stage
@@ -347,12 +349,6 @@ holo_status b2_launch(holo2d_plan* P, B2Run run, const char* tb, char* w, const 
     const ItemList& cp = want_ref ? P->cols_probe : P->cols_probe_noref;
     B2_HIP(launch_b2_cols(A, items(cp), (int)cp.items.size(), st));
   }
-  if (want_gq) {
-    A.mode = kB2RowsRef;
-    B2_HIP(launch_b2_rows(A, items(P->rows_ref), (int)P->rows_ref.items.size(), st));
-    A.mode = kB2ColsRef;
-    B2_HIP(launch_b2_cols(A, items(P->cols_ref), (int)P->cols_ref.items.size(), st));
-  }
   // pass A and pass B
   A.mode = kB2RowsA;
   B2_HIP(launch_b2_rows(A, items(P->rows_nd), (int)P->rows_nd.items.size(), st));
@@ -360,15 +356,16 @@ holo_status b2_launch(holo2d_plan* P, B2Run run, const char* tb, char* w, const 
   A.mode = kB2ColsB;
   B2_HIP(launch_b2_cols(A, items(P->cols_nd), (int)P->cols_nd.items.size(), st));
   if (grad) {
-    A.mode = kB2RowsC;
-    B2_HIP(launch_b2_rows(A, items(P->rows_nd), (int)P->rows_nd.items.size(), st));
+    // pass C (with the probe gradient's rows and the reference rows when
+    // g_q is wanted), then g_q per column tile and g_psi by the gather
+    A.mode = want_gq ? kB2RowsCGq : kB2RowsC;
+    const ItemList& rc = want_gq ? P->rows_cgq : P->rows_nd;
+    B2_HIP(launch_b2_rows(A, items(rc), (int)rc.items.size(), st));
     if (want_gq) {
-      A.mode = kB2RowsGq;
-      B2_HIP(launch_b2_rows(A, items(P->rows_nd), (int)P->rows_nd.items.size(), st));
-      A.mode = kB2ColsGq;
-      B2_HIP(launch_b2_cols(A, items(P->cols_nd), (int)P->cols_nd.items.size(), st));
+      A.mode = kB2ColsGqSum;
+      B2_HIP(launch_b2_gq_sum(A, items(P->cols_gq), (int)P->cols_gq.items.size(), st));
     }
-    B2_HIP(launch_b2_gather(A, items(P->gather), (int)P->gather.items.size(), st));
+    if (g_psi) B2_HIP(launch_b2_gather(A, items(P->gather), (int)P->gather.items.size(), st));
   }
   if (F && run != kB2Fwd)
     B2_HIP(launch_b2_reduce(A.Fpart, (const int2*)(tb + P->off_ranges), P->n_inst, F, st));

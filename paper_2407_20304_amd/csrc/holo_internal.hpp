@@ -1,5 +1,6 @@
 // Internal interface between the host runtime (holo_api.cpp) and the HIP
-// kernels (holo_kernels.hip).  Not part of the public ABI.
+// kernels (holo_kernels.hip, holo_radon.hip, holo_fs.hip).  Not part of the
+// public ABI.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstddef>
@@ -7,6 +8,7 @@
 
 namespace holo {
 
+constexpr int kThreads = 256;   // threads per workgroup of the 1-D kernels
 constexpr int kMaxDist = 8;
 // Per-angle constants (double): see AngleCols.
 constexpr int kAngleStride = 8;
@@ -191,5 +193,14 @@ hipError_t launch_axpy(const float2* x, const float2* e, float t, float2* out, s
 hipError_t launch_cg_dir(const float2* g, float2* eta, float beta, int restart, size_t n,
                          hipStream_t st);
 hipError_t launch_real_to_c64(const float* a, float2* out, size_t n, hipStream_t st);
+
+// The dispatcher hands workgroup h of a 1-D grid to XCD h mod 8.  Remap so
+// that each XCD walks a contiguous range of logical indices: neighbours in
+// logical order then share that XCD's L2.
+__device__ __forceinline__ int xcd_logical(int h, int n) {
+  const int q = n >> 3, r = n & 7;
+  const int x = h & 7, loc = h >> 3;
+  return x * q + min(x, r) + loc;
+}
 
 }  // namespace holo
