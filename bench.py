@@ -26,16 +26,20 @@ PEAK_FP32_VALU_TFLOPS = 157.3   # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0           # MI355X published HBM3E bandwidth
 FLOP_PER_LERP = 8               # 2 taps x (re, im) x fused multiply-add
 
-# HBM traffic per launch of the dominant kernel, from two rocprofv3 --pmc runs
+# HBM traffic per launch of the ray-sum kernels, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean over the launches of
 # one gradient evaluation), each scaled by what the same counter reads for a
 # 1 GiB device-to-device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  The
 # figures hold for the kernel sources they were taken on (SHA-256 over
-# KERNEL_SOURCES); after any change to those the field reports null.
+# KERNEL_SOURCES) and the workload they were taken on; after any change to
+# those sources, or on another workload, the field reports null.
 TRAFFIC = {
-    "k_radon_fwd": {"fetch_kib": 15932943.35, "write_kib": 1246930.94,
+    "k_radon_fwd": {"workload": "vol1024_a1800", "fetch_kib": 17812112.30, "write_kib": 508471.22,
                     "fetch_scale": 2.0, "write_scale": 1.0,
-                    "sources_sha256": "1be59e656a75ba7ecda887041f954fff4dcdb0a09b7cc439ddb7892aac786588"},
+                    "sources_sha256": "175d768c47cb273a7e69cb9e2bd630e902d129d9674391681679e3551952b995"},
+    "k_radon_adj": {"workload": "vol1024_a1800", "fetch_kib": 484253479.5, "write_kib": 8388608.0,
+                    "fetch_scale": 2.0, "write_scale": 1.0,
+                    "sources_sha256": "175d768c47cb273a7e69cb9e2bd630e902d129d9674391681679e3551952b995"},
 }
 
 
@@ -57,9 +61,9 @@ def csrc_sha256():
     return h.hexdigest()
 
 
-def traffic_bytes(kernel):
+def traffic_bytes(kernel, workload):
     t = TRAFFIC.get(kernel)
-    if t is None or t["sources_sha256"] != csrc_sha256():
+    if t is None or t["workload"] != workload or t["sources_sha256"] != csrc_sha256():
         return None
     return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
@@ -331,6 +335,29 @@ def batch2d_bench(steps=20, warmup=3):
     ms = e0.elapsed_time(e1) / steps
     if not bool(torch.isfinite(F).all()):
         raise RuntimeError("batched objective is not finite")
+    # the same call captured once in a HIP graph and replayed: the launch
+    # sequence without per-call host work; the replays must reproduce the
+    # eager results bit for bit
+    F_eager, gp_eager, gq_eager = F.clone(), g_psi.clone(), g_q.clone()
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            plan.holo2d_grad(psi, q, amp, amp_ref, F=F, g_psi=g_psi, g_q=g_q)
+    torch.cuda.current_stream().wait_stream(side)
+    graph.replay()
+    torch.cuda.synchronize()
+    if not (bool((F == F_eager).all()) and bool((g_psi == gp_eager).all())
+            and bool((g_q == gq_eager).all())):
+        raise RuntimeError("graph replay differs from the eager call")
+    e0.record()
+    for _ in range(steps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1) / steps
+    del graph
     T = plan.total
     compulsory = T * (8 + 8 + 4 * nd + 4 + 8 + 8)
     # FFT flops at 5 N log2 N per N-point transform: a propagation D is two
@@ -341,6 +368,7 @@ def batch2d_bench(steps=20, warmup=3):
     res = {"workload": "batch96_mixed", "instances": plan.n_inst,
            "sizes": {str(n): sizes.count(n) for n in sorted(set(sizes))}, "pixels": T,
            "n_dist": nd, "calls": steps, "ms_per_call": ms, "calls_per_s": 1e3 / ms,
+           "ms_per_call_graph": ms_graph,
            "compulsory_bytes": compulsory, "GBps": compulsory / (ms * 1e-3) / 1e9,
            "hbm_frac": compulsory / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
            "fft_flop": fft_flop, "fft_TFLOPs": fft_flop / (ms * 1e-3) / 1e12}
@@ -467,7 +495,8 @@ def main():
         ent = {"ms_per_step": ms / K, "launches_per_step": n / K, "avg_launch_ms": ms / n}
         if name in ("radon_fwd", "radon_adj"):
             tf = lerps * FLOP_PER_LERP / (ms * 1e-3) / 1e12
-            ent.update({"achieved": tf, "unit": "TFLOP/s", "frac": tf / PEAK_FP32_VALU_TFLOPS})
+            ent.update({"achieved": tf, "unit": "TFLOP/s", "frac": tf / PEAK_FP32_VALU_TFLOPS,
+                        "traffic_per_launch": traffic_bytes("k_" + name, wl.name)})
         kernels[name] = ent
     frame_ms = sum(kt[c][0] for c in ("pass_a", "pass_b", "pass_c", "pass_d"))
     frame_gbs = frame_bytes_model(wl, K) / (frame_ms * 1e-3) / 1e9 if frame_ms > 0 else None
@@ -477,7 +506,7 @@ def main():
     achieved = per_launch_flop / (dms / dn * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": "k_" + dom, "achieved": achieved,
                 "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": traffic_bytes("k_" + dom),
+                "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": traffic_bytes("k_" + dom, wl.name),
                 "per_launch_flop": per_launch_flop, "avg_launch_ms": dms / dn}
 
     result = {
