@@ -543,6 +543,8 @@ DevGeom make_geom(const holo_plan* P) {
   g.chirp2W = tabs ? (const float2*)(b + P->off_ch2W) : nullptr;
   g.chirp2H = tabs ? (const float2*)(b + P->off_ch2H) : nullptr;
   g.col_tile = P->col_tile;
+  g.ang = (const double*)(b + P->off_ang);
+  g.sino_mirror = P->projector == HOLO_PROJECTOR_JOSEPH ? 1 : 0;
   return g;
 }
 

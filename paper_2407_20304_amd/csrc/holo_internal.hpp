@@ -45,6 +45,11 @@ struct DevGeom {
   const float2* chirp2W;     // [2 nd + 1][2W], times 1/(2W)
   const float2* chirp2H;     // [2 nd + 1][2H], times 1/(2H)
   int col_tile;              // columns per pass-B workgroup (0: the default)
+  // Joseph plans store the sinogram rows of angles with cos < 0 with the
+  // bin axis reversed (as the angle theta - pi): pass D writes them so and
+  // the transpose reads them so, which makes cos >= 0 for every angle it sees
+  const double* ang;         // [n_angles][kAngleStride] plan angle table
+  int sino_mirror;
 };
 
 // Fourier-slice projector (holo_fs.hip): gridding kernel taps per axis,

@@ -692,7 +692,9 @@ __global__ __launch_bounds__(kThreads) void k_pass_d(const float2* __restrict__ 
                                                      int k_first, int Kc) {
   // A workgroup covers 16 rows x 16 padded bins, bins fastest, of the
   // sinogram S[k][z][kAdjPad + s] (rows padded by kAdjPad zero bins on each
-  // side) for kPassDAngles consecutive angles.  Workgroups over the padding
+  // side; with g.sino_mirror, rows of angles with cos < 0 are stored
+  // reversed, bin s at kAdjPad + W - 1 - s) for kPassDAngles consecutive
+  // angles.  Workgroups over the padding
   // write its zeros.  The transposed resampling is separable, so its taps
   // are formed once per workgroup (once per angle with shifts): per plane,
   // the row taps of each of the 16 rows and the column taps of each of the
@@ -742,7 +744,9 @@ __global__ __launch_bounds__(kThreads) void k_pass_d(const float2* __restrict__ 
       }
       __syncthreads();
     }
-    float2* out = S + ((size_t)k * H + z) * Wp + sp;
+    // rows of angles with cos < 0 reversed for the Joseph transpose
+    const bool mir = g.sino_mirror && g.ang[(size_t)(k_first + k) * kAngleStride + kCos] < 0.0;
+    float2* out = S + ((size_t)k * H + z) * Wp + (mir ? Wp - 1 - sp : sp);
     if (!inside) {
       *out = make_float2(0.f, 0.f);
       continue;

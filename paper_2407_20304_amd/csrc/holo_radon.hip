@@ -323,9 +323,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
     if (t < TW) {
       const int kk = min(w * TW + t, K - 1);
       const double* ap = ang + (size_t)kk * kAngleStride;
-      const double C = ap[kCos], Sn = ap[kSin], ih = ap[kInvH];
-      const double q0 = g.cW + X0 * C + Y0 * Sn;
-      int sl = (int)floor(g.cW + fmin(X0 * C, X1 * C) + fmin(Y0 * Sn, Y1 * Sn)) - 2;
+      // an angle with cos < 0 has its row stored reversed: it is the angle
+      // theta - pi, direction (-cos, -sin), positions W - 1 - q
+      const bool mir = ap[kCos] < 0.0;
+      const double C = mir ? -ap[kCos] : ap[kCos], Sn = mir ? -ap[kSin] : ap[kSin];
+      const double ih = ap[kInvH];
+      const double cq = mir ? (double)(W - 1) - g.cW : g.cW;
+      const double q0 = cq + X0 * C + Y0 * Sn;
+      int sl = (int)floor(cq + fmin(X0 * C, X1 * C) + fmin(Y0 * Sn, Y1 * Sn)) - 2;
       sl -= sl & 1;                                     // even: 16-byte aligned bin pairs
       sl = min(max(sl, -kAdjPad), W + kAdjPad - SEG);
       s_sl[slot][t] = sl;
@@ -394,24 +399,25 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
     const int slot = (k0 / TW) & 1, base = k0 % TW;
     const float2* gb = tile + (gi % NBUF) * GF2;
     for (int a = 0; a < na; ++a) {
-      // the pair's fractional bins q and q + cos; every bin with a nonzero
+      // The pair's fractional bins are q and q + cos, cos >= 0 (rows of
+      // angles with cos < 0 are stored reversed).  Every bin with a nonzero
       // weight for either voxel (|i - q| < h <= 1) is one of jm .. jm + 2,
-      // jm = floor(min of the two), and its weight is the footprint
-      // max(0, 1 - |i - q| / h) / h = max(0, 1/h - |i - q| / h^2)
+      // jm = floor(q), and its weight is the footprint
+      // max(0, 1 - |i - q| / h) / h = max(0, 1/h - |i - q| / h^2).  The
+      // first voxel's third bin lies more than one bin from it, so its
+      // weight is zero and is not formed.
       const float ih = s_ih[slot][base + a], ih2 = s_ih2[slot][base + a];
       const float c = s_c[slot][base + a];
       const float qa = fmaf((float)dy, s_s[slot][base + a],
                             fmaf((float)(2 * px), c, s_f0[slot][base + a]));
       const float qb = qa + c;
-      const float fl = floorf(fminf(qa, qb));
-      const int jm = min(max((int)fl, 0), SEG - 3);
-      float wt[2][3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const float bin = (float)(jm + k);        // the bins actually read
-        wt[0][k] = fmaxf(0.0f, fmaf(-fabsf(bin - qa), ih2, ih));
-        wt[1][k] = fmaxf(0.0f, fmaf(-fabsf(bin - qb), ih2, ih));
-      }
+      const int jm = min(max((int)floorf(qa), 0), SEG - 3);
+      const float dl = (float)jm - qa, dh = (float)jm - qb;   // bin jm relative to each voxel
+      const float wl0 = fmaxf(0.0f, fmaf(-fabsf(dl), ih2, ih));
+      const float wl1 = fmaxf(0.0f, fmaf(-fabsf(dl + 1.0f), ih2, ih));
+      const float wh0 = fmaxf(0.0f, fmaf(-fabsf(dh), ih2, ih));
+      const float wh1 = fmaxf(0.0f, fmaf(-fabsf(dh + 1.0f), ih2, ih));
+      const float wh2 = fmaxf(0.0f, fmaf(-fabsf(dh + 2.0f), ih2, ih));
       const float2* tp = gb + a * ZT * SEG + sg * ZS * SEG + jm;
       // software pipeline: the three bins of slice i + LA are requested
       // before slice i is accumulated
@@ -429,11 +435,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
 #pragma unroll
       for (int i = 0; i < ZS; ++i) {
         if (i + LA < ZS) fetch(i + LA);
-#pragma unroll
-        for (int v = 0; v < 2; ++v) {
-          ax[v][i] = fmaf(wt[v][2], r[i][2].x, fmaf(wt[v][1], r[i][1].x, fmaf(wt[v][0], r[i][0].x, ax[v][i])));
-          ay[v][i] = fmaf(wt[v][2], r[i][2].y, fmaf(wt[v][1], r[i][1].y, fmaf(wt[v][0], r[i][0].y, ay[v][i])));
-        }
+        ax[0][i] = fmaf(wl1, r[i][1].x, fmaf(wl0, r[i][0].x, ax[0][i]));
+        ay[0][i] = fmaf(wl1, r[i][1].y, fmaf(wl0, r[i][0].y, ay[0][i]));
+        ax[1][i] = fmaf(wh2, r[i][2].x, fmaf(wh1, r[i][1].x, fmaf(wh0, r[i][0].x, ax[1][i])));
+        ay[1][i] = fmaf(wh2, r[i][2].y, fmaf(wh1, r[i][1].y, fmaf(wh0, r[i][0].y, ay[1][i])));
       }
     }
     // two-level single-precision sums: partials of up to 8 NA angles are
@@ -477,6 +482,8 @@ hipError_t launch_radon_fwd(const DevGeom& g, const float2* ub, const float2* uT
 
 hipError_t launch_radon_adj(const DevGeom& g, const float2* S, float2* gu, const double* ang,
                             int K, hipStream_t st) {
+  // the kernel reads the rows of angles with cos < 0 reversed
+  if (!g.sino_mirror) return hipErrorInvalidValue;
   const unsigned n = (unsigned)(g.W / 16) * (unsigned)(g.W / 16) * (unsigned)(g.H / kAdjZT);
   k_radon_adj<<<n, kThreads, 0, st>>>(S, gu, g, ang, K);
   return hipGetLastError();
