@@ -12,7 +12,10 @@
 // Lengths are 2^a (radices 8, then 4 or 2; a plan ending in 4, 4 ends in
 // one radix-16 stage instead when the line has N / 16 threads) and 3 * 2^a
 // (one radix-3 stage first).  Twiddles come from a table tw[m] = exp(-2 pi i m / N) built in
-// double precision on the host and staged in LDS by the caller.
+// double precision on the host and staged in LDS by the caller in the padded
+// layout of the lines (tw[m] at fpi(m), fft_line_len(N) elements): a stage
+// reads the twiddles j k N / (P R) of its butterflies, strided by up to
+// N / 8 entries, which the plain layout puts on a few banks.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -248,7 +251,7 @@ __device__ __forceinline__ void fft_stage(float2* line, const float2* tw, int lt
       if (P > 1) {
 #pragma unroll
         for (int j = 1; j < R; ++j) {
-          float2 w = tw[j * k * (N / (P * R))];
+          float2 w = tw[fpi(j * k * (N / (P * R)))];
           if (INV) w.y = -w.y;
           v[it][j] = cmul(v[it][j], w);
         }
@@ -323,7 +326,7 @@ __device__ __forceinline__ void fft_stage_e(float2 (&e)[E], float2* line, const 
     if (P > 1) {
 #pragma unroll
       for (int j = 1; j < R; ++j) {
-        float2 w = tw[j * k * (N / (P * R))];
+        float2 w = tw[fpi(j * k * (N / (P * R)))];
         if (INV) w.y = -w.y;
         v[it][j] = cmul(v[it][j], w);
       }

@@ -34,13 +34,13 @@ __host__ __device__ constexpr int b_cols_tc(int n) { return n >= 384 ? 8 : 16; }
 // tile loads (columns of consecutive threads at one row) spread over banks.
 __host__ __device__ constexpr int b_col_pitch(int n) { return fft_line_len(n) + 4; }
 // LDS of one column workgroup of size n: twiddles plus the tile.
-__host__ __device__ constexpr int b_cols_lds(int n) { return n + b_cols_tc(n) * b_col_pitch(n); }
+__host__ __device__ constexpr int b_cols_lds(int n) { return fft_line_len(n) + b_cols_tc(n) * b_col_pitch(n); }
 
 // The probe-gradient column pass keeps every plane's spectrum sum in
 // registers next to the plane being transformed: 4 columns per workgroup
 // (64 threads per column) keep that to 2 x n / 64 elements per thread.
 __host__ __device__ constexpr int b_gq_tc(int) { return 4; }
-__host__ __device__ constexpr int b_gq_lds(int n) { return n + b_gq_tc(n) * b_col_pitch(n); }
+__host__ __device__ constexpr int b_gq_lds(int n) { return fft_line_len(n) + b_gq_tc(n) * b_col_pitch(n); }
 
 int b2_rows_per_wg(int n) { return b_rows_lpw(n); }
 int b2_cols_per_wg(int n) { return b_cols_tc(n); }
@@ -124,13 +124,13 @@ __device__ __forceinline__ BAdj b_adj_taps(double c, double m, int idx, int n) {
 template <int N>
 __device__ __forceinline__ void b_rows_body(const B2Args& A, const B2Item& it, float2* lds) {
   constexpr int TL = b_rows_tl(N), LPW = b_rows_lpw(N), E = N / TL;
-  static_assert(N + LPW * fft_line_len(N) <= kRowLds, "row lines fit the LDS");
+  static_assert((LPW + 1) * fft_line_len(N) <= kRowLds, "twiddles and row lines fit the LDS");
   float2* s_tw = lds;
   const int line = threadIdx.x / TL, lt = threadIdx.x % TL;
   // lines stored padded (element s at fpi(s)): conflict-free FFT stages
-  float2* L = lds + N + line * fft_line_len(N);
+  float2* L = lds + fft_line_len(N) + line * fft_line_len(N);
   const B2Inst in = A.inst[it.inst];
-  for (int i = threadIdx.x; i < N; i += kT2) s_tw[i] = in.tw[i];
+  for (int i = threadIdx.x; i < N; i += kT2) s_tw[fpi(i)] = in.tw[i];
   const int z = it.line0 + line;
   const size_t fr = (size_t)N * N;
   const int j = it.job;
@@ -232,7 +232,10 @@ __device__ __forceinline__ void b_rows_body(const B2Args& A, const B2Item& it, f
   (void)LPW;
 }
 
-__global__ __launch_bounds__(kT2) void k2_rows(B2Args A, const B2Item* __restrict__ items) {
+// (four waves per SIMD: the padded twiddle addresses would otherwise take
+// it just past 128 VGPRs)
+__global__ __launch_bounds__(kT2) __attribute__((amdgpu_waves_per_eu(4))) void k2_rows(
+    B2Args A, const B2Item* __restrict__ items) {
   __shared__ float2 lds[kRowLds];
   const B2Item it = items[blockIdx.x];
   switch (A.inst[it.inst].n) {
@@ -283,10 +286,10 @@ __device__ __forceinline__ void b_cols_body(const B2Args& A, const B2Item& it, f
   const int cidx = threadIdx.x / TLc, lt = threadIdx.x % TLc;
   // column lines stored padded (element zz at fpi(zz)), pitch b_col_pitch
   constexpr int CP = b_col_pitch(N);
-  float2* col0 = lds + N;
+  float2* col0 = lds + fft_line_len(N);
   float2* Lc = col0 + cidx * CP;
   const B2Inst in = A.inst[it.inst];
-  for (int i = threadIdx.x; i < N; i += kT2) s_tw[i] = in.tw[i];
+  for (int i = threadIdx.x; i < N; i += kT2) s_tw[fpi(i)] = in.tw[i];
   const size_t fr = (size_t)N * N;
   const int j = it.job, nd = A.nd;
   const int s0 = it.line0;
@@ -387,10 +390,10 @@ __device__ __forceinline__ void b_cols_gq_sum(const B2Args& A, const B2Item& it,
   float2* s_tw = lds;
   const int cidx = threadIdx.x / TLc, lt = threadIdx.x % TLc;
   constexpr int CP = b_col_pitch(N);
-  float2* col0 = lds + N;
+  float2* col0 = lds + fft_line_len(N);
   float2* Lc = col0 + cidx * CP;
   const B2Inst in = A.inst[it.inst];
-  for (int i = threadIdx.x; i < N; i += kT2) s_tw[i] = in.tw[i];
+  for (int i = threadIdx.x; i < N; i += kT2) s_tw[fpi(i)] = in.tw[i];
   const size_t fr = (size_t)N * N;
   const int nd = A.nd, s0 = it.line0;
   constexpr bool WL = TLc <= 64;

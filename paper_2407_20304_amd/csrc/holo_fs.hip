@@ -63,12 +63,12 @@ __global__ __launch_bounds__(kT) void k_fs_rows(const float2* __restrict__ u,
                                                 float2* __restrict__ G, FsArgs f,
                                                 const float2* __restrict__ tw) {
   constexpr int M = 2 * W, TL = fs_tl(M), LPW = fs_lpw(M), E = M / TL;
-  __shared__ float2 s_tw[M];
+  __shared__ float2 s_tw[fft_line_len(M)];
   __shared__ float2 s_line[LPW][fft_line_len(M)];
   const int line = threadIdx.x / TL, lt = threadIdx.x % TL;
   const int L = blockIdx.x * LPW + line;            // z * W + y
   const int z = L / W, y = L % W;
-  for (int i = threadIdx.x; i < M; i += kT) s_tw[i] = tw[i];
+  for (int i = threadIdx.x; i < M; i += kT) s_tw[fpi(i)] = tw[i];
   const float2* row = u + (size_t)L * W;
   const float dy = f.dinv[y];
   float2* Ln = s_line[line];
@@ -103,13 +103,13 @@ template <int W, bool INV>
 __global__ __launch_bounds__(kColT) void k_fs_cols(float2* __restrict__ G,
                                                    const float2* __restrict__ tw) {
   constexpr int M = 2 * W, TC = fs_tc(M), TLc = kColT / TC;
-  __shared__ float2 s_tw[M];
+  __shared__ float2 s_tw[fft_line_len(M)];
   __shared__ float2 s_col[TC][fs_pitch(M)];
   const int c = threadIdx.x / TLc, lt = threadIdx.x % TLc;
   constexpr int ntiles = M / TC;
   const int z = blockIdx.x / ntiles, s0 = (blockIdx.x % ntiles) * TC;
   float2* g = G + (size_t)z * M * M + s0;
-  for (int i = threadIdx.x; i < M; i += kColT) s_tw[i] = tw[i];
+  for (int i = threadIdx.x; i < M; i += kColT) s_tw[fpi(i)] = tw[i];
   for (int i = threadIdx.x; i < M * TC; i += kColT) {
     const int r = i / TC, cc = i % TC;
     const bool data = INV || r < W / 2 || r >= M - W / 2;
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(kT) void k_fs_project(const float2* __restrict__ G,
                                                    const float2* __restrict__ twW, int H,
                                                    int z0, int nlines, float kappa) {
   constexpr int M = 2 * W, TL = fs_tl(W), LPW = fs_lpw(W), E = W / TL;
-  __shared__ float2 s_tw[W];
+  __shared__ float2 s_tw[fft_line_len(W)];
   __shared__ float2 s_line[LPW][fft_line_len(W)];
   const int line = threadIdx.x / TL, lt = threadIdx.x % TL;
   // z * K + k, angles fastest; lines past the last only join the transforms
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(kT) void k_fs_project(const float2* __restrict__ G,
   const bool live = L0 < nlines;
   const int L = live ? L0 : nlines - 1;
   const int z = L / f.K, k = L % f.K;
-  for (int i = threadIdx.x; i < W; i += kT) s_tw[i] = twW[i];
+  for (int i = threadIdx.x; i < W; i += kT) s_tw[fpi(i)] = twW[i];
   const double* ap = f.ang + (size_t)(f.k0 + k) * kAngleStride;
   const double C = 2.0 * ap[kCos], Sn = 2.0 * ap[kSin];    // grid units per m
   const float2* g = G + (size_t)z * M * M;
@@ -227,14 +227,14 @@ __global__ __launch_bounds__(kT) void k_fs_line_T(const float2* __restrict__ S,
                                                   const float2* __restrict__ twW, int H,
                                                   int z0, int nlines) {
   constexpr int TL = fs_tl(W), LPW = fs_lpw(W), E = W / TL;
-  __shared__ float2 s_tw[W];
+  __shared__ float2 s_tw[fft_line_len(W)];
   __shared__ float2 s_line[LPW][fft_line_len(W)];
   const int line = threadIdx.x / TL, lt = threadIdx.x % TL;
   const int L0 = blockIdx.x * LPW + line;
   const bool live = L0 < nlines;
   const int L = live ? L0 : nlines - 1;
   const int z = L / f.K, k = L % f.K;
-  for (int i = threadIdx.x; i < W; i += kT) s_tw[i] = twW[i];
+  for (int i = threadIdx.x; i < W; i += kT) s_tw[fpi(i)] = twW[i];
   const int Wp = W + 2 * kAdjPad;
   const float2* in = S + ((size_t)k * H + z0 + z) * Wp + kAdjPad;
   float2* Ln = s_line[line];
@@ -420,12 +420,12 @@ __global__ __launch_bounds__(kT) void k_fs_rows_T(const float2* __restrict__ G,
                                                   float2* __restrict__ gu, FsArgs f,
                                                   const float2* __restrict__ tw) {
   constexpr int M = 2 * W, TL = fs_tl(M), LPW = fs_lpw(M), E = M / TL;
-  __shared__ float2 s_tw[M];
+  __shared__ float2 s_tw[fft_line_len(M)];
   __shared__ float2 s_line[LPW][fft_line_len(M)];
   const int line = threadIdx.x / TL, lt = threadIdx.x % TL;
   const int L = blockIdx.x * LPW + line;
   const int z = L / W, y = L % W;
-  for (int i = threadIdx.x; i < M; i += kT) s_tw[i] = tw[i];
+  for (int i = threadIdx.x; i < M; i += kT) s_tw[fpi(i)] = tw[i];
   const int yp = y - W / 2;
   const float2* in = G + ((size_t)z * M + (yp < 0 ? yp + M : yp)) * M;
   float2* Ln = s_line[line];

@@ -167,13 +167,13 @@ __global__ __launch_bounds__(kThreads) void k_pass_a(const float2* __restrict__ 
                                                      int k_first) {
   constexpr int TL = rows_tl(W), LPW = rows_lpw(W), E = W / TL;
   constexpr bool WL = wave_lines(TL);
-  __shared__ float2 s_tw[W];
+  __shared__ float2 s_tw[fft_line_len(W)];
   __shared__ float2 s_line[LPW][fft_line_len(W)];
   const int line = threadIdx.x / TL, lt = threadIdx.x % TL;
   const int z = blockIdx.x * LPW + line;
   const int f = blockIdx.y;
   const int k = f / g.nd, j = f % g.nd;
-  for (int i = threadIdx.x; i < W; i += kThreads) s_tw[i] = g.twW[i];
+  for (int i = threadIdx.x; i < W; i += kThreads) s_tw[fpi(i)] = g.twW[i];
 
   double ty, tx;
   shift_of(g, k_first + k, j, ty, tx);
@@ -217,13 +217,13 @@ __global__ __launch_bounds__(kThreads) void k_pass_c(float2* __restrict__ X,
                                                      float2* __restrict__ Pbuf, DevGeom g,
                                                      int accumulate, int k_first, int Kc) {
   constexpr int TL = rows_tl(W), LPW = rows_lpw(W), E = W / TL;
-  __shared__ float2 s_tw[W];
+  __shared__ float2 s_tw[fft_line_len(W)];
   __shared__ float2 s_line[LPW][fft_line_len(W)];
   const int line = threadIdx.x / TL, lt = threadIdx.x % TL;
   const int lp = fpi(lt);   // padded position of the thread's first element
   const int z = blockIdx.x * LPW + line;
   const int j = blockIdx.y;
-  for (int i = threadIdx.x; i < W; i += kThreads) s_tw[i] = g.twW[i];
+  for (int i = threadIdx.x; i < W; i += kThreads) s_tw[fpi(i)] = g.twW[i];
   const double m = g.mag[j];
   const float2* Qrow = Q + ((size_t)j * g.H + z) * W;
   const float2* ch = g.chirpW + (size_t)chirp_det(j) * W;
@@ -286,13 +286,13 @@ __global__ __launch_bounds__(kThreads) void k_pass_c(float2* __restrict__ X,
 template <int W>
 __global__ __launch_bounds__(kThreads) void k_rows_prop(PropJobs jobs, DevGeom g) {
   constexpr int TL = rows_tl(W), LPW = rows_lpw(W), E = W / TL;
-  __shared__ float2 s_tw[W];
+  __shared__ float2 s_tw[fft_line_len(W)];
   __shared__ float2 s_line[LPW][fft_line_len(W)];
   const int line = threadIdx.x / TL, lt = threadIdx.x % TL;
   const int lp = fpi(lt);   // padded position of the thread's first element
   const int z = blockIdx.x * LPW + line;
   const PropJob& jb = jobs.job[blockIdx.y];
-  for (int i = threadIdx.x; i < W; i += kThreads) s_tw[i] = g.twW[i];
+  for (int i = threadIdx.x; i < W; i += kThreads) s_tw[fpi(i)] = g.twW[i];
   const float2* in = jb.src + (size_t)z * W;
   float2* L = s_line[line];
 #pragma unroll
@@ -367,7 +367,7 @@ __global__ __launch_bounds__(kColThreads) void k_pass_b(const float2* __restrict
   constexpr int RS = kColThreads / TC;            // tile rows between a thread's elements
   static_assert(H * TC % kColThreads == 0 && RS % 32 == 0, "column tile");
   constexpr bool kResidual = MODE == kColObj || MODE == kColGrad;
-  __shared__ float2 s_tw[H];
+  __shared__ float2 s_tw[fft_line_len(H)];
   __shared__ float2 s_col[TC][col_pitch(H)];
   const int c = threadIdx.x / TLc, lt = threadIdx.x % TLc;
   const int W = g.W;
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(kColThreads) void k_pass_b(const float2* __restrict
 #pragma unroll
   for (int r = 0; r < (H + kColThreads - 1) / kColThreads; ++r) {
     const int i = threadIdx.x + r * kColThreads;
-    if (i < H) s_tw[i] = g.twH[i];
+    if (i < H) s_tw[fpi(i)] = g.twH[i];
   }
 #pragma unroll
   for (int r = 0; r < NPT; ++r) l0[r * LSTEP] = t[r];
@@ -461,13 +461,13 @@ template <int H>
 __global__ __launch_bounds__(kColThreads) void k_cols_prop(PropJobs jobs, double* __restrict__ Fpart,
                                                            DevGeom g) {
   constexpr int TC = cols_tc(H), TLc = kColThreads / TC;
-  __shared__ float2 s_tw[H];
+  __shared__ float2 s_tw[fft_line_len(H)];
   __shared__ float2 s_col[TC][col_pitch(H)];
   const int c = threadIdx.x / TLc, lt = threadIdx.x % TLc;
   const int W = g.W;
   const int s0 = blockIdx.x * TC;
   const PropJob& jb = jobs.job[blockIdx.y];
-  for (int i = threadIdx.x; i < H; i += kColThreads) s_tw[i] = g.twH[i];
+  for (int i = threadIdx.x; i < H; i += kColThreads) s_tw[fpi(i)] = g.twH[i];
   const float2* in = jb.src + s0;
   for (int i = threadIdx.x; i < H * TC; i += kColThreads) {
     const int zz = i / TC, cc = i % TC;
@@ -515,12 +515,12 @@ template <int W>
 __global__ __launch_bounds__(kThreads) void k_rows_pad(PadJob jb, DevGeom g) {
   constexpr int N2 = 2 * W, TL = rows_tl(N2), LPW = rows_lpw(N2), E = N2 / TL;
   constexpr int OFF = W / 2;
-  __shared__ float2 s_tw[N2];
+  __shared__ float2 s_tw[fft_line_len(N2)];
   __shared__ float2 s_line[LPW][fft_line_len(N2)];
   const int line = threadIdx.x / TL, lt = threadIdx.x % TL;
   const int z = blockIdx.x * LPW + line;
   const int f = blockIdx.y;
-  for (int i = threadIdx.x; i < N2; i += kThreads) s_tw[i] = g.tw2W[i];
+  for (int i = threadIdx.x; i < N2; i += kThreads) s_tw[fpi(i)] = g.tw2W[i];
   const float2* in = jb.src + (size_t)f * jb.src_step + (size_t)z * W;
   float2* L = s_line[line];
 #pragma unroll
@@ -550,14 +550,14 @@ __global__ __launch_bounds__(kColThreads) void k_cols_pad(PadJob jb, double* __r
                                                           DevGeom g, int ntiles) {
   constexpr int N2 = 2 * H, TC = cols_tc(N2), TLc = kColThreads / TC;
   constexpr int OFF = H / 2;
-  __shared__ float2 s_tw[N2];
+  __shared__ float2 s_tw[fft_line_len(N2)];
   __shared__ float2 s_col[TC][col_pitch(N2)];
   const int c = threadIdx.x / TLc, lt = threadIdx.x % TLc;
   const int W = g.W;
   const int tile = blockIdx.x % ntiles, f = blockIdx.x / ntiles;
   const int s0 = tile * TC;
   const size_t HW = (size_t)H * W;
-  for (int i = threadIdx.x; i < N2; i += kColThreads) s_tw[i] = g.tw2H[i];
+  for (int i = threadIdx.x; i < N2; i += kColThreads) s_tw[fpi(i)] = g.tw2H[i];
   const float2* in = jb.src + (size_t)f * jb.src_step + s0;
   for (int i = threadIdx.x; i < N2 * TC; i += kColThreads) {
     const int zz = i / TC, cc = i % TC;

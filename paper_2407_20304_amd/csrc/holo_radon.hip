@@ -26,7 +26,13 @@ __global__ __launch_bounds__(kThreads) void k_block_volume(const float2* __restr
                                                            float2* __restrict__ ub,
                                                            float2* __restrict__ uTb, int W) {
   constexpr int ZT = kVolZB, P = kFwdPad;
-  __shared__ float2 brick[ZT][16][17];
+  // one 16 x 17 plane per slice, planes 274 elements apart: the write phase
+  // reads down the slices (the 16 lanes of consecutive z at one position,
+  // the next 16 at the neighbouring one), which a plane stride of 272 put
+  // on two bank pairs; 274 = 18 (mod 32) spreads the 16 slices over the
+  // even bank pairs and their neighbours over the odd ones
+  constexpr int PL = 16 * 17 + 2;
+  __shared__ float2 brick[ZT * PL];
   const int nt = W / 16, Wf = vol_row(W);
   const int x0 = (blockIdx.x % nt) * 16, y0 = (blockIdx.x / nt) * 16;
   const int zb = blockIdx.y;
@@ -34,7 +40,7 @@ __global__ __launch_bounds__(kThreads) void k_block_volume(const float2* __restr
   // read along x (contiguous)
   for (int i = threadIdx.x; i < ZT * 256; i += kThreads) {
     const int xx = i & 15, yy = (i >> 4) & 15, zz = i >> 8;
-    brick[zz][yy][xx] = u[(size_t)(zb * ZT + zz) * WW + (size_t)(y0 + yy) * W + x0 + xx];
+    brick[zz * PL + yy * 17 + xx] = u[(size_t)(zb * ZT + zz) * WW + (size_t)(y0 + yy) * W + x0 + xx];
   }
   __syncthreads();
   float2* bb = ub + (size_t)zb * WWf * ZT;
@@ -43,8 +49,8 @@ __global__ __launch_bounds__(kThreads) void k_block_volume(const float2* __restr
   for (int i = threadIdx.x; i < ZT * 256; i += kThreads) {
     const int zz = i % ZT, p = i / ZT;
     const int a = p & 15, b = p >> 4;
-    bb[((size_t)(y0 + b) * Wf + P + x0 + a) * ZT + zz] = brick[zz][b][a];
-    if (tb) tb[((size_t)(x0 + b) * Wf + P + y0 + a) * ZT + zz] = brick[zz][a][b];
+    bb[((size_t)(y0 + b) * Wf + P + x0 + a) * ZT + zz] = brick[zz * PL + b * 17 + a];
+    if (tb) tb[((size_t)(x0 + b) * Wf + P + y0 + a) * ZT + zz] = brick[zz * PL + a * 17 + b];
   }
   // padding: rows y0..y0+15 of ub (brick column 0 / last) and rows
   // x0..x0+15 of uTb (brick row 0 / last)

@@ -102,6 +102,16 @@ def plan(n, tl):
     return r
 
 
+def test_padded_twiddles_spread_the_strided_reads():
+    # the twiddle reads j k N / (P R) of a stage with P = 8 land on two bank
+    # pairs in the plain layout, on distinct ones in the padded layout
+    N = 1024
+    for j in range(1, 8):
+        idx = [j * (lane % 8) * (N // 64) for lane in range(32)]
+        assert len({a % 32 for a in set(idx)}) <= 2
+        assert len({fpi(a) % 32 for a in set(idx)}) == len(set(idx))
+
+
 def stockham(x, radices, inverse=False):
     """The kernels' Stockham stages in NumPy: butterfly i reads
     x[i + j N/R], multiplies input j by W_{PR}^{j (i mod P)}, takes an
