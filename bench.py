@@ -34,12 +34,12 @@ FLOP_PER_LERP = 8               # 2 taps x (re, im) x fused multiply-add
 # KERNEL_SOURCES) and the workload they were taken on; after any change to
 # those sources, or on another workload, the field reports null.
 TRAFFIC = {
-    "k_radon_fwd": {"workload": "vol1024_a1800", "fetch_kib": 17812112.30, "write_kib": 508471.22,
+    "k_radon_fwd": {"workload": "vol1024_a1800", "fetch_kib": 17724291.99, "write_kib": 508471.60,
                     "fetch_scale": 2.0, "write_scale": 1.0,
-                    "sources_sha256": "175d768c47cb273a7e69cb9e2bd630e902d129d9674391681679e3551952b995"},
-    "k_radon_adj": {"workload": "vol1024_a1800", "fetch_kib": 484253479.5, "write_kib": 8388608.0,
+                    "sources_sha256": "04f85a637bfcad1aa6dc0e2c77c8b072d67a1b26bba52ebdf87018f890c13865"},
+    "k_radon_adj": {"workload": "vol1024_a1800", "fetch_kib": 464191778.8, "write_kib": 8388608.0,
                     "fetch_scale": 2.0, "write_scale": 1.0,
-                    "sources_sha256": "175d768c47cb273a7e69cb9e2bd630e902d129d9674391681679e3551952b995"},
+                    "sources_sha256": "04f85a637bfcad1aa6dc0e2c77c8b072d67a1b26bba52ebdf87018f890c13865"},
 }
 
 
