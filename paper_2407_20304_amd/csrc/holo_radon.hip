@@ -78,8 +78,8 @@ __global__ __launch_bounds__(kThreads) void k_block_volume(const float2* __restr
 // ---------------------------------------------------------------------------
 
 // Forward.  A workgroup owns up to kFwdNA consecutive angles of one walk
-// direction (one wave per angle), NB (16, or 8 for plans whose angle windows
-// spread too far for 16) consecutive bins and kFwdZT slices.
+// direction (one wave per angle), NB (16 by default, or 8: a tuning choice)
+// consecutive bins and kFwdZT slices.
 // Within a wave, 16 consecutive lanes cover the 64 slices of one group of NB/4
 // consecutive bins: lane l takes the slice pairs (2 (l % 16), + 1) and
 // (32 + 2 (l % 16), + 1), so one tap position and weight serve 4 slices and
