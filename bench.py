@@ -395,6 +395,9 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy before the timed region "
                          "(a known-size reference for HBM traffic counters)")
+    ap.add_argument("--overlap", type=int, choices=(0, 1), default=None,
+                    help="run the next chunk's forward ray sums on a second stream during the "
+                         "current chunk's frame passes (1) or not (0); default: the plan's")
     ap.add_argument("--tune", action="store_true",
                     help="choose the chunk size with the autotuner (candidates 16, 32, 64, 128) "
                          "before timing; the default keeps the workload's chunk of 64")
@@ -460,6 +463,8 @@ def main():
         log("calibration copy: 1 GiB read + 1 GiB written")
 
     plan = holo.Plan.for_workload(wl)
+    if args.overlap is not None:
+        plan.set_tile("overlap", args.overlap)
     tuned = None
     if args.tune:
         best, times = plan.autotune(u, q, amp, amp_ref, candidates=(16, 32, 64, 128))
@@ -531,6 +536,7 @@ def main():
         "dtype": "c64",
         "data": "synthetic",
         "config": {"workload": wl.name, "volume": [H, W, W], "n_angles": N, "chunk": plan.chunk,
+                   "overlap": plan.get_tile("overlap"),
                    "n_dist": nd, "detector": [H, W], "parallelism": "single GPU"},
         "objective": Fv,
         "frame_stage_GBps": frame_gbs,

@@ -152,8 +152,14 @@ holo_status holo_plan_autotune(holo_plan* plan, const holo_c64* u, const holo_c6
  *             8 (smaller staged windows, so more angles share one;
  *             setting it regroups the angles, and it is refused if the chunk
  *             is smaller than the new largest group).
+ *   OVERLAP   1: Joseph's forward ray sums of the next chunk run on a second
+ *             stream of the library's, concurrently with the current chunk's
+ *             frame passes (two psi buffers in the workspace; the calls still
+ *             order all their work after the caller's stream's earlier work
+ *             and before its later work, also under graph capture); 0
+ *             (default): one stream.  The results are the same.
  * holo_plan_set_tile validates and sets one (the workspace size can change
- * with CHUNK; query holo_workspace_bytes again); holo_plan_get_tile reads
+ * with CHUNK and OVERLAP; query holo_workspace_bytes again); holo_plan_get_tile reads
  * it.  holo_plan_autotune_tile is holo_plan_autotune for any of them: one
  * untimed gradient, then one gradient per candidate value timed with HIP
  * events on `stream`; the fastest becomes the plan's value.  Errors:
@@ -165,7 +171,8 @@ typedef enum {
   HOLO_TUNE_CHUNK = 0,
   HOLO_TUNE_COL_TILE = 1,
   HOLO_TUNE_FS_SLAB = 2,
-  HOLO_TUNE_FWD_BINS = 3
+  HOLO_TUNE_FWD_BINS = 3,
+  HOLO_TUNE_OVERLAP = 4
 } holo_tune_param;
 holo_status holo_plan_set_tile(holo_plan* plan, int32_t param, int32_t value);
 holo_status holo_plan_get_tile(const holo_plan* plan, int32_t param, int32_t* value);

@@ -69,6 +69,12 @@ struct holo_plan {
   // workgroup (0 = default) and the Fourier-slice slab depth
   int col_tile = 0;
   int fs_slab = kFsSlab;
+  // Joseph's forward of the next chunk on a second stream, concurrent with
+  // the current chunk's frame passes (two psi buffers); the stream and its
+  // fork/join events are made on the first call that needs them
+  int overlap = 0;
+  hipStream_t side = nullptr;
+  hipEvent_t ov_ev[5] = {};
   std::vector<float> fs_dinv;
   std::vector<int> fs_sorted, fs_bins;
   size_t off_fsdinv = 0, off_fssorted = 0, off_fsbins = 0;
@@ -80,7 +86,7 @@ struct holo_plan {
   std::vector<int> group_of;
   // workspace layout (byte offsets)
   size_t off_Q = 0, off_G = 0, off_P = 0, off_ub = 0, off_uTb = 0, off_psi = 0, off_X = 0, off_S = 0,
-         off_F = 0, ws_bytes = 0, n_fpart = 0;
+         off_F = 0, ws_bytes = 0, n_fpart = 0, off_psi2 = 0;
   // device tables (lazily uploaded on the first compute call)
   void* d_tables = nullptr;
   int device = -1;
@@ -238,6 +244,9 @@ static void layout_workspace(holo_plan* P) {
   P->off_ub = o;  o = align_up(o + vb);
   P->off_uTb = o; o = align_up(o + (P->any_xwalk ? vb : 0));
   P->off_psi = o; o = align_up(o + fr * P->chunk);
+  // the second psi buffer of the overlapped forward (Joseph's ray sums only)
+  const bool two_psi = P->overlap && P->projector == HOLO_PROJECTOR_JOSEPH;
+  P->off_psi2 = o; o = align_up(o + (two_psi ? fr * P->chunk : 0));
   P->off_X = o;   o = align_up(o + fr * P->chunk * P->nd);
   // sinogram rows carry kAdjPad zero bins on each side
   P->off_S = o;   o = align_up(o + (size_t)P->H * sino_row(P->W) * sizeof(float2) * P->n_angles);
@@ -395,6 +404,16 @@ extern "C" holo_status holo_plan_destroy(holo_plan* P) {
     (void)hipEventDestroy(pe.second.second);
   }
   for (hipEvent_t e : P->ev_free) (void)hipEventDestroy(e);
+  if (P->side) {
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (cur != P->device) (void)hipSetDevice(P->device);
+    (void)hipStreamSynchronize(P->side);
+    for (hipEvent_t& e : P->ov_ev)
+      if (e) (void)hipEventDestroy(e);
+    (void)hipStreamDestroy(P->side);
+    if (cur != P->device && cur >= 0) (void)hipSetDevice(cur);
+  }
   if (P->d_tables) {
     int cur = -1;
     (void)hipGetDevice(&cur);
@@ -692,9 +711,10 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
 
   const bool frames_back = want_gq || want_gu;
   const int2* d_groups = (const int2*)((const char*)P->d_tables + P->off_groups);
+  // Chunks [c0, c1): whole ray-sum groups (clipped to [k0, k1)), at most
+  // `chunk` angles.
+  std::vector<int2> chunks;
   for (int c0 = k0, c1 = k0; c0 < k1; c0 = c1) {
-    // Chunk [c0, c1): whole ray-sum groups (clipped to [k0, k1)), at most
-    // `chunk` angles.
     c1 = c0;
     while (c1 < k1) {
       const int2 gr = P->groups[P->group_of[c1]];
@@ -703,18 +723,56 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
       c1 = end;
     }
     if (c1 == c0) c1 = std::min(c0 + P->chunk, k1);
-    const int Kc = c1 - c0;
+    chunks.push_back(make_int2(c0, c1));
+  }
+  // With the overlap on, chunk i + 1's forward runs on the side stream
+  // (into the other psi buffer) while chunk i's frame passes run on the
+  // caller's stream: the forward waits for the frames that last read its
+  // buffer (chunk i - 1), the frames for their own forward.
+  const bool ovl = P->overlap && !fs && chunks.size() > 1;
+  float2* psib[2] = {psi, ovl ? (float2*)(wsb + P->off_psi2) : psi};
+  hipStream_t sf = st;
+  if (ovl) {
+    if (!P->side) {
+      HOLO_HIP(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
+      for (hipEvent_t& e : P->ov_ev) HOLO_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    sf = P->side;
+    // the side stream starts after everything so far on the caller's
+    // stream (the volume copies, the probe stage)
+    HOLO_HIP(hipEventRecord(P->ov_ev[0], st));
+    HOLO_HIP(hipStreamWaitEvent(sf, P->ov_ev[0], 0));
+  }
+  hipEvent_t* ev_fwd = P->ov_ev + 1;      // [chunk parity]: forward done
+  hipEvent_t* ev_frames = P->ov_ev + 3;   // [chunk parity]: its frames done
+  auto forward = [&](size_t ci) -> hipError_t {
+    const int c0 = chunks[ci].x, c1 = chunks[ci].y;
     const int gfirst = P->group_of[c0], glast = P->group_of[c1 - 1];
+    hipError_t e = timed(P, HOLO_K_RADON_FWD, sf, [&] {
+      return launch_radon_fwd(g, ub, uTb, psib[ci & 1], d_ang, d_groups, gfirst,
+                              glast - gfirst + 1, c0, c1, P->fwd_nb, sf);
+    });
+    if (e == hipSuccess && ovl) e = hipEventRecord(ev_fwd[ci & 1], sf);
+    return e;
+  };
+  if (ovl) HOLO_HIP(forward(0));
+  for (size_t ci = 0; ci < chunks.size(); ++ci) {
+    const int c0 = chunks[ci].x, c1 = chunks[ci].y;
+    const int Kc = c1 - c0;
+    float2* const psi_c = psib[ci & 1];
     if (fs) {
       HOLO_HIP(timed(P, HOLO_K_OTHER, st, [&] {
-        return launch_copy_rows(S + (size_t)(c0 - k0) * H * Wp + kAdjPad, Wp, psi, (size_t)Kc * H,
-                                W, st);
+        return launch_copy_rows(S + (size_t)(c0 - k0) * H * Wp + kAdjPad, Wp, psi_c,
+                                (size_t)Kc * H, W, st);
       }));
+    } else if (ovl) {
+      HOLO_HIP(hipStreamWaitEvent(st, ev_fwd[ci & 1], 0));
+      if (ci + 1 < chunks.size()) {
+        if (ci >= 1) HOLO_HIP(hipStreamWaitEvent(sf, ev_frames[(ci + 1) & 1], 0));
+        HOLO_HIP(forward(ci + 1));
+      }
     } else {
-      HOLO_HIP(timed(P, HOLO_K_RADON_FWD, st, [&] {
-        return launch_radon_fwd(g, ub, uTb, psi, d_ang, d_groups, gfirst, glast - gfirst + 1, c0,
-                                c1, P->fwd_nb, st);
-      }));
+      HOLO_HIP(forward(ci));
     }
     double* Fc = Fpart + ref_tiles + (size_t)tiles * (c0 - k0) * nd;
     if (padded) {
@@ -725,7 +783,7 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
       float2* F0 = mode == kFwd ? v_out + (size_t)(c0 - k0) * nd * HW : X;
       if (mode != kAdj) {
         HOLO_HIP(timed(P, HOLO_K_PASS_A, st, [&] {
-          return launch_frames_x(g, psi, Q, F0, c0, Kc, st);
+          return launch_frames_x(g, psi_c, Q, F0, c0, Kc, st);
         }));
         const PadJob rf = pj(F0, F0, hw, nf, chirp_det(0), nd, 0, 0, nullptr, 0);
         HOLO_HIP(timed(P, HOLO_K_PASS_A, st, [&] { return launch_rows_pad(g, rf, st); }));
@@ -744,7 +802,7 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
         const PadJob ra = pj(X, X, hw, nf, chirp_det(0), nd, 1, 0, nullptr, 0);
         HOLO_HIP(timed(P, HOLO_K_PASS_C, st, [&] { return launch_rows_pad(g, ra, st); }));
         HOLO_HIP(timed(P, HOLO_K_PASS_C, st, [&] {
-          return launch_frames_c(g, X, psi, Q, Gacc, Pbuf, want_gq ? 1 : 0, c0, Kc, st);
+          return launch_frames_c(g, X, psi_c, Q, Gacc, Pbuf, want_gq ? 1 : 0, c0, Kc, st);
         }));
         if (want_gq && Pbuf)
           HOLO_HIP(timed(P, HOLO_K_PASS_C, st, [&] {
@@ -752,15 +810,16 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
           }));
         if (want_gu)
           HOLO_HIP(timed(P, HOLO_K_PASS_D, st, [&] {
-            return launch_pass_d(g, X, psi, S + (size_t)(c0 - k0) * H * sino_row(W), c0, Kc, st);
+            return launch_pass_d(g, X, psi_c, S + (size_t)(c0 - k0) * H * sino_row(W), c0, Kc, st);
           }));
       }
+      if (ovl) HOLO_HIP(hipEventRecord(ev_frames[ci & 1], st));
       continue;
     }
     switch (mode) {
       case kFwd: {
         float2* v = v_out + (size_t)(c0 - k0) * nd * HW;
-        HOLO_HIP(timed(P, HOLO_K_PASS_A, st, [&] { return launch_pass_a(g, psi, Q, v, c0, Kc, st); }));
+        HOLO_HIP(timed(P, HOLO_K_PASS_A, st, [&] { return launch_pass_a(g, psi_c, Q, v, c0, Kc, st); }));
         HOLO_HIP(timed(P, HOLO_K_PASS_B, st, [&] {
           return launch_pass_b(g, kColFwd, nullptr, v, nullptr, nullptr, Kc, st);
         }));
@@ -768,7 +827,7 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
       }
       case kObj:
       case kGrad: {
-        HOLO_HIP(timed(P, HOLO_K_PASS_A, st, [&] { return launch_pass_a(g, psi, Q, X, c0, Kc, st); }));
+        HOLO_HIP(timed(P, HOLO_K_PASS_A, st, [&] { return launch_pass_a(g, psi_c, Q, X, c0, Kc, st); }));
         const float* a = amp + (size_t)c0 * nd * HW;
         HOLO_HIP(timed(P, HOLO_K_PASS_B, st, [&] {
           return launch_pass_b(g, frames_back ? kColGrad : kColObj, nullptr, X, a, Fc, Kc, st);
@@ -785,7 +844,7 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
     }
     if ((mode == kGrad || mode == kAdj) && frames_back) {
       HOLO_HIP(timed(P, HOLO_K_PASS_C, st, [&] {
-        return launch_pass_c(g, X, psi, Q, Gacc, Pbuf, want_gq ? 1 : 0, c0, Kc, st);
+        return launch_pass_c(g, X, psi_c, Q, Gacc, Pbuf, want_gq ? 1 : 0, c0, Kc, st);
       }));
       if (want_gq && Pbuf)
         HOLO_HIP(timed(P, HOLO_K_PASS_C, st, [&] {
@@ -793,9 +852,10 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
         }));
       if (want_gu)
         HOLO_HIP(timed(P, HOLO_K_PASS_D, st, [&] {
-          return launch_pass_d(g, X, psi, S + (size_t)(c0 - k0) * H * sino_row(W), c0, Kc, st);
+          return launch_pass_d(g, X, psi_c, S + (size_t)(c0 - k0) * H * sino_row(W), c0, Kc, st);
         }));
     }
+    if (ovl) HOLO_HIP(hipEventRecord(ev_frames[ci & 1], st));
   }
   if (want_gu && fs) {
     for (int z0 = 0; z0 < H; z0 += P->fs_slab) {
@@ -1141,6 +1201,10 @@ static holo_status tile_check(const holo_plan* P, int param, int value, const ch
       if (value != 1 && value != 2 && value != 4 && value != kFsSlab)
         return fail(HOLO_ERR_INVALID_ARGUMENT, std::string(fn) + ": slab must be 1, 2, 4 or 8");
       return HOLO_OK;
+    case HOLO_TUNE_OVERLAP:
+      if (value != 0 && value != 1)
+        return fail(HOLO_ERR_INVALID_ARGUMENT, std::string(fn) + ": overlap must be 0 or 1");
+      return HOLO_OK;
     case HOLO_TUNE_FWD_BINS: {
       if (value != kFwdNB && value != kFwdNB / 2)
         return fail(HOLO_ERR_INVALID_ARGUMENT, std::string(fn) + ": forward bins must be 8 or 16");
@@ -1162,13 +1226,15 @@ static holo_status tile_check(const holo_plan* P, int param, int value, const ch
 static int tile_get(const holo_plan* P, int param) {
   return param == HOLO_TUNE_CHUNK ? P->chunk
          : param == HOLO_TUNE_COL_TILE ? P->col_tile
-         : param == HOLO_TUNE_FS_SLAB ? P->fs_slab : P->fwd_nb;
+         : param == HOLO_TUNE_FS_SLAB ? P->fs_slab
+         : param == HOLO_TUNE_OVERLAP ? P->overlap : P->fwd_nb;
 }
 
 static void tile_put(holo_plan* P, int param, int value) {
   if (param == HOLO_TUNE_CHUNK) P->chunk = std::min<int>(value, P->n_angles);
   else if (param == HOLO_TUNE_COL_TILE) P->col_tile = value;
   else if (param == HOLO_TUNE_FS_SLAB) P->fs_slab = value;
+  else if (param == HOLO_TUNE_OVERLAP) P->overlap = value;
   else if (value != P->fwd_nb) set_fwd_bins(P, value);
   layout_workspace(P);
 }
@@ -1183,7 +1249,7 @@ extern "C" holo_status holo_plan_set_tile(holo_plan* P, int32_t param, int32_t v
 
 extern "C" holo_status holo_plan_get_tile(const holo_plan* P, int32_t param, int32_t* value) {
   if (!P || !value) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_get_tile: NULL argument");
-  if (param < HOLO_TUNE_CHUNK || param > HOLO_TUNE_FWD_BINS)
+  if (param < HOLO_TUNE_CHUNK || param > HOLO_TUNE_OVERLAP)
     return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_get_tile: unknown parameter");
   *value = tile_get(P, param);
   return HOLO_OK;
@@ -1210,7 +1276,7 @@ extern "C" holo_status holo_plan_autotune_tile(holo_plan* P, int32_t param, cons
   if (!amp || !amp_ref || !F || !g_u || !g_q || !candidates || !best_chunk || !ws)
     return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_autotune: NULL argument");
   if (n_cand < 1) return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_autotune: no candidates");
-  if (param < HOLO_TUNE_CHUNK || param > HOLO_TUNE_FWD_BINS)
+  if (param < HOLO_TUNE_CHUNK || param > HOLO_TUNE_OVERLAP)
     return fail(HOLO_ERR_INVALID_ARGUMENT, "holo_plan_autotune: unknown parameter");
   const int chunk0 = tile_get(P, param);
   size_t need = 0;

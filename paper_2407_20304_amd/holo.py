@@ -314,10 +314,11 @@ class Plan:
             os.replace(tmp, cache)
         return int(best.value), result
 
-    TILES = {"chunk": 0, "col_tile": 1, "fs_slab": 2, "fwd_bins": 3}
+    TILES = {"chunk": 0, "col_tile": 1, "fs_slab": 2, "fwd_bins": 3, "overlap": 4}
 
     def set_tile(self, name, value):
-        """Set a launch-shape parameter ("chunk", "col_tile", "fs_slab")."""
+        """Set a launch-shape parameter ("chunk", "col_tile", "fs_slab",
+        "fwd_bins", "overlap")."""
         _check(lib().holo_plan_set_tile(self._h, c_int32(self.TILES[name]), c_int32(int(value))))
         self._refresh_workspace_size()
 
@@ -356,9 +357,10 @@ class Plan:
         return int(best.value), {c: float(t) for c, t in zip(cands, times)}
 
     def autotune_tiles(self, u, q, amp, amp_ref, chunks=(16, 32, 64, 128), cache=None):
-        """The chunk (autotune), then the column tile (default or half) and,
-        with the Fourier-slice projector, the slab depth (2, 4, 8), each
-        timed with the others fixed.  Returns {name: (value, times)}; with a
+        """The chunk (autotune), then the column tile (default or half), the
+        forward bin block (Joseph) or the slab depth (Fourier-slice, 2, 4,
+        8), and the overlapped forward (Joseph), each timed with the others
+        fixed.  Returns {name: (value, times)}; with a
         cache file the choices are stored and reused like the chunk's."""
         import json
         cache = cache or os.environ.get("HOLO_TUNE_CACHE")
@@ -366,7 +368,7 @@ class Plan:
         if cache and os.path.exists(cache):
             with open(cache) as f:
                 entry = json.load(f).get(key)
-            names = ("chunk", "col_tile", "fs_slab", "fwd_bins")
+            names = ("chunk", "col_tile", "fs_slab", "fwd_bins", "overlap")
             if entry is not None and all(n in entry for n in names):
                 for name in names:
                     self.set_tile(name, int(entry[name]))
@@ -381,6 +383,8 @@ class Plan:
             out["fs_slab"] = (self.get_tile("fs_slab"), None)
             bins = [b for b in (16, 8) if self._tile_ok("fwd_bins", b)]
             out["fwd_bins"] = self.autotune_tile("fwd_bins", u, q, amp, amp_ref, bins)
+        out["overlap"] = (self.autotune_tile("overlap", u, q, amp, amp_ref, [0, 1])
+                          if self.projector != "fourier" else (self.get_tile("overlap"), None))
         if cache:
             data = {}
             if os.path.exists(cache):

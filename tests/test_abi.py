@@ -313,7 +313,16 @@ def test_tile_parameters_validate_on_the_host():
     p = make_plan()          # 64 x 64: the column pass takes 16 columns, or 8
     v = ctypes.c_int32()
     assert L.holo_plan_set_tile(None, 1, 8) == 1
-    assert L.holo_plan_set_tile(p._h, 4, 8) == 1          # unknown parameter
+    assert L.holo_plan_set_tile(p._h, 5, 8) == 1          # unknown parameter
+    # the overlapped forward: 0 or 1, and a second psi buffer (one chunk of
+    # 64 x 64 frames) in the workspace when on
+    n0 = p.workspace_bytes
+    assert L.holo_plan_set_tile(p._h, 4, 2) == 1
+    p.set_tile("overlap", 1)
+    assert p.get_tile("overlap") == 1
+    assert p.workspace_bytes >= n0 + p.get_tile("chunk") * 64 * 64 * 8
+    p.set_tile("overlap", 0)
+    assert p.workspace_bytes == n0
     assert L.holo_plan_set_tile(p._h, 3, 12) == 1         # forward bins are 16 or 8
     assert L.holo_plan_set_tile(p._h, 3, 8) == 0
     assert L.holo_plan_get_tile(p._h, 3, ctypes.byref(v)) == 0 and v.value == 8

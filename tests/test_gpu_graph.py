@@ -54,6 +54,49 @@ def test_joint_gradient_graph_replay():
         torch.cuda.synchronize()
 
 
+def test_overlapped_forward_is_bitwise_the_serial_one_and_replays():
+    """The overlapped forward (the next chunk's ray sums on the library's
+    second stream) computes the same gradient bit for bit, eagerly and as a
+    captured graph (the fork and join through events are part of the
+    capture), over several chunks, with and without object shifts."""
+    import torch
+    for shifts in (False, True):
+        say("overlapped forward: 64^3, 12 angles, chunk 3, shifts", shifts)
+        p = PB.make_problem(64, 64, 12, config=0, shifts=shifts, chunk=3)
+        u, q, amp, amp_ref = PB.to_gpu(p)
+        plan = PB.gpu_plan(p)
+        F = torch.empty(1, dtype=torch.float64, device="cuda")
+        gu, gq = torch.empty_like(u), torch.empty_like(q)
+        plan.holo_grad(u, q, amp, amp_ref, F=F, g_u=gu, g_q=gq)
+        torch.cuda.synchronize()
+        ref = (F.clone(), gu.clone(), gq.clone())
+        plan.set_tile("overlap", 1)
+        for r in range(2):
+            F.zero_(), gu.zero_(), gq.zero_()
+            plan.holo_grad(u, q, amp, amp_ref, F=F, g_u=gu, g_q=gq)
+            torch.cuda.synchronize()
+            assert F.item() == ref[0].item(), r
+            assert bool((gu == ref[1]).all()) and bool((gq == ref[2]).all()), r
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                plan.holo_grad(u, q, amp, amp_ref, F=F, g_u=gu, g_q=gq)
+        torch.cuda.current_stream().wait_stream(s)
+        for r in range(3):
+            F.zero_(), gu.zero_(), gq.zero_()
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert F.item() == ref[0].item(), r
+            assert bool((gu == ref[1]).all()) and bool((gq == ref[2]).all()), r
+            plan.holo_objective(u, q, amp, amp_ref)
+            torch.cuda.synchronize()
+        del g
+        plan.close()
+
+
 def test_batch_gradient_graph_replay():
     import torch
     from paper_2407_20304_amd import holo
