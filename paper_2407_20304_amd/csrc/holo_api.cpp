@@ -734,8 +734,20 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
   hipStream_t sf = st;
   if (ovl) {
     if (!P->side) {
-      HOLO_HIP(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
-      for (hipEvent_t& e : P->ov_ev) HOLO_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      // made all together or not at all
+      hipStream_t side = nullptr;
+      hipEvent_t ev[5] = {};
+      hipError_t e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
+      for (int i = 0; i < 5 && e == hipSuccess; ++i)
+        e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+      if (e != hipSuccess) {
+        for (hipEvent_t x : ev)
+          if (x) (void)hipEventDestroy(x);
+        if (side) (void)hipStreamDestroy(side);
+        return fail(HOLO_ERR_HIP, std::string("overlapped forward: ") + hipGetErrorString(e));
+      }
+      P->side = side;
+      for (int i = 0; i < 5; ++i) P->ov_ev[i] = ev[i];
     }
     sf = P->side;
     // the side stream starts after everything so far on the caller's
