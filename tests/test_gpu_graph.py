@@ -70,7 +70,19 @@ def test_overlapped_forward_is_bitwise_the_serial_one_and_replays():
         plan.holo_grad(u, q, amp, amp_ref, F=F, g_u=gu, g_q=gq)
         torch.cuda.synchronize()
         ref = (F.clone(), gu.clone(), gq.clone())
+        v_ref = plan.holo_fwd(u, q).clone()
+        w = torch.randn_like(v_ref)
+        a_ref = [t.clone() for t in plan.holo_adj(u, q, w)]
+        F1_ref = plan.holo_objective(u, q, amp, amp_ref).clone()
         plan.set_tile("overlap", 1)
+        # the forward fields, the adjoint, the objective and the one-sided
+        # gradients take the overlapped path too
+        assert bool((plan.holo_fwd(u, q) == v_ref).all())
+        assert all(bool((x == y).all()) for x, y in zip(plan.holo_adj(u, q, w), a_ref))
+        assert bool((plan.holo_objective(u, q, amp, amp_ref) == F1_ref).all())
+        _, gu1 = plan.holo_grad_object(u, q, amp, amp_ref)
+        _, gq1 = plan.holo_grad_probe(u, q, amp, amp_ref)
+        assert bool((gu1 == ref[1]).all()) and bool((gq1 == ref[2]).all())
         for r in range(2):
             F.zero_(), gu.zero_(), gq.zero_()
             plan.holo_grad(u, q, amp, amp_ref, F=F, g_u=gu, g_q=gq)
