@@ -398,6 +398,9 @@ def main():
     ap.add_argument("--overlap", type=int, choices=(0, 1), default=None,
                     help="run the next chunk's forward ray sums on a second stream during the "
                          "current chunk's frame passes (1) or not (0); default: the plan's")
+    ap.add_argument("--fwd-bins", type=int, choices=(8, 16), default=None,
+                    help="bins per workgroup of Joseph's forward ray sums (16: 4 angles per "
+                         "workgroup, 8: 8 angles); default: the plan's")
     ap.add_argument("--tune", action="store_true",
                     help="choose the chunk size with the autotuner (candidates 16, 32, 64, 128) "
                          "before timing; the default keeps the workload's chunk of 64")
@@ -465,6 +468,8 @@ def main():
     plan = holo.Plan.for_workload(wl)
     if args.overlap is not None:
         plan.set_tile("overlap", args.overlap)
+    if args.fwd_bins is not None:
+        plan.set_tile("fwd_bins", args.fwd_bins)
     tuned = None
     if args.tune:
         best, times = plan.autotune(u, q, amp, amp_ref, candidates=(16, 32, 64, 128))
@@ -537,6 +542,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "volume": [H, W, W], "n_angles": N, "chunk": plan.chunk,
                    "overlap": plan.get_tile("overlap"),
+                   "fwd_bins": plan.get_tile("fwd_bins"),
                    "n_dist": nd, "detector": [H, W], "parallelism": "single GPU"},
         "objective": Fv,
         "frame_stage_GBps": frame_gbs,
