@@ -84,6 +84,10 @@ struct holo_plan {
   // whose staged row windows fit (first, count); group_of[k] = group index
   std::vector<int2> groups;
   std::vector<int> group_of;
+  // transpose angle classes (sin >= 0 / < 0 once rows with cos < 0 are
+  // reversed): class 0's angles in ascending order, then class 1's
+  std::vector<int> adj_order;
+  int adj_n0 = 0;
   // workspace layout (byte offsets)
   size_t off_Q = 0, off_G = 0, off_P = 0, off_ub = 0, off_uTb = 0, off_psi = 0, off_X = 0, off_S = 0,
          off_F = 0, ws_bytes = 0, n_fpart = 0, off_psi2 = 0;
@@ -91,7 +95,7 @@ struct holo_plan {
   void* d_tables = nullptr;
   int device = -1;
   size_t off_twW = 0, off_twH = 0, off_chW = 0, off_chH = 0, off_ang = 0, off_shift = 0,
-         off_groups = 0, off_pshift = 0, table_bytes = 0, off_Pbuf = 0;
+         off_groups = 0, off_pshift = 0, table_bytes = 0, off_Pbuf = 0, off_adjord = 0;
   size_t off_tw2W = 0, off_tw2H = 0, off_ch2W = 0, off_ch2H = 0;
   // timing diagnostics
   bool timing = false;
@@ -344,6 +348,13 @@ extern "C" holo_status holo_plan_create(const holo_geom* geom, holo_plan** out) 
     // Forward ray-sum groups for blocks of kFwdNB bins (8-bin blocks are a
     // tuning choice, holo_plan_set_tile).
     set_fwd_bins(P, kFwdNB);
+    // Transpose angle classes.
+    for (int cls = 0; cls < 2; ++cls)
+      for (int k = 0; k < P->n_angles; ++k)
+        if (adj_class(&P->ang[(size_t)k * kAngleStride]) == cls) P->adj_order.push_back(k);
+    P->adj_n0 = (int)(std::count_if(P->adj_order.begin(), P->adj_order.end(), [&](int k) {
+      return adj_class(&P->ang[(size_t)k * kAngleStride]) == 0;
+    }));
 
     // Transfer-function tables: detector steps, probe steps, reference.
     std::vector<double> rhos(chirp_rows(P->nd));
@@ -378,6 +389,7 @@ extern "C" holo_status holo_plan_create(const holo_geom* geom, holo_plan** out) 
     P->off_ang = t;   t = align_up(t + P->ang.size() * sizeof(double));
     P->off_shift = t; t = align_up(t + P->shift.size() * sizeof(float));
     P->off_groups = t; t = align_up(t + (size_t)P->n_angles * sizeof(int2));
+    P->off_adjord = t; t = align_up(t + (size_t)P->n_angles * sizeof(int));
     // probe shifts (room for all of them, filled when set)
     P->off_pshift = t; t = align_up(t + (size_t)P->n_angles * P->nd * 2 * sizeof(float));
     P->off_tw2W = t;  t = align_up(t + P->tw2W.size() * sizeof(float2));
@@ -518,6 +530,7 @@ holo_status ensure_tables(holo_plan* P) {
   if (e == hipSuccess) e = put(P->off_ang, P->ang.data(), P->ang.size() * sizeof(double));
   if (e == hipSuccess) e = put(P->off_shift, P->shift.data(), P->shift.size() * sizeof(float));
   if (e == hipSuccess) e = put(P->off_groups, P->groups.data(), P->groups.size() * sizeof(int2));
+  if (e == hipSuccess) e = put(P->off_adjord, P->adj_order.data(), P->adj_order.size() * sizeof(int));
   if (e == hipSuccess) e = put(P->off_pshift, P->pshift.data(), P->pshift.size() * sizeof(float));
   if (e == hipSuccess) e = put(P->off_tw2W, P->tw2W.data(), P->tw2W.size() * sizeof(float2));
   if (e == hipSuccess) e = put(P->off_tw2H, P->tw2H.data(), P->tw2H.size() * sizeof(float2));
@@ -877,8 +890,15 @@ holo_status run(holo_plan* P, Mode mode, const holo_c64* u_, const holo_c64* q_,
       }));
     }
   } else if (want_gu) {
+    // each class's angles within [k0, k1): a contiguous run of its list
+    const int* ord = (const int*)((const char*)P->d_tables + P->off_adjord);
+    const auto b0 = P->adj_order.begin(), e0 = b0 + P->adj_n0, e1 = P->adj_order.end();
+    const int lo0 = (int)(std::lower_bound(b0, e0, k0) - b0);
+    const int hi0 = (int)(std::lower_bound(b0, e0, k1) - b0);
+    const int lo1 = (int)(std::lower_bound(e0, e1, k0) - b0);
+    const int hi1 = (int)(std::lower_bound(e0, e1, k1) - b0);
     HOLO_HIP(timed(P, HOLO_K_RADON_ADJ, st, [&] {
-      return launch_radon_adj(g, S, gu, d_ang + (size_t)k0 * kAngleStride, k1 - k0, st);
+      return launch_radon_adj(g, S, gu, d_ang, k0, ord + lo0, hi0 - lo0, ord + lo1, hi1 - lo1, st);
     }));
   }
   if (want_gq) {

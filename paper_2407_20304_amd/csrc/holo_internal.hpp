@@ -22,6 +22,13 @@ enum AngleCols {
   kD = 6,
   kScale = 7    // path length per step, 1 / max(|cos|, |sin|)
 };
+// Class of an angle in the transpose: its direction, taken as theta - pi
+// (-cos, -sin) when cos < 0 (the rows the transpose reads reversed), has
+// sin >= 0 (class 0) or sin < 0 (class 1).
+inline int adj_class(const double* a) {
+  const double s = a[kCos] < 0.0 ? -a[kSin] : a[kSin];
+  return s < 0.0 ? 1 : 0;
+}
 
 // Geometry and device tables as the kernels see them.
 struct DevGeom {
@@ -175,8 +182,13 @@ hipError_t launch_pass_d(const DevGeom& g, const float2* X, const float2* psi, f
 hipError_t launch_radon_fwd(const DevGeom& g, const float2* ub, const float2* uTb, float2* psi,
                             const double* ang, const int2* groups, int g0, int ngroups, int c0,
                             int c1, int nb, hipStream_t st);
+// Transpose of the ray sums over angles k0 + [0, n0 + n1): S holds their rows
+// (row k - k0), ang the plan's whole angle table; ord0 / ord1 list the angles
+// of class 0 / 1 (sin >= 0 / < 0 once rows with cos < 0 are reversed) in
+// ascending order.
 hipError_t launch_radon_adj(const DevGeom& g, const float2* S, float2* gu, const double* ang,
-                            int K, hipStream_t st);
+                            int k0, const int* ord0, int n0, const int* ord1, int n1,
+                            hipStream_t st);
 hipError_t launch_block_volume(const DevGeom& g, const float2* u, float2* ub, float2* uTb,
                                hipStream_t st);
 hipError_t launch_fill_zero(float2* p, size_t n, hipStream_t st);

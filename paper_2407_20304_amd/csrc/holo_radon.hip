@@ -13,6 +13,8 @@
 //                 LDS-direct loads
 // Both are bound by VALU issue and LDS operand delivery, not by HBM: every
 // voxel is revisited once per angle.
+#include <type_traits>
+
 #include "holo_internal.hpp"
 
 namespace holo {
@@ -274,21 +276,30 @@ __global__ __launch_bounds__(kThreads, 2) void k_radon_fwd(const float2* __restr
 }
 
 // Transpose.  A workgroup owns a 16 x 16 voxel tile and kAdjZT slices; a
-// thread owns a voxel pair along x and half of the slices (kAdjZT / 2).  It
-// loops over all angles in groups of kAdjNA (one wave loads each angle of a
+// thread owns a 2 x 2 voxel block (an x pair in two neighbouring rows) and
+// a quarter of the slices (kAdjZT / 4, one slice group per wave).  It loops
+// over all angles in groups of kAdjNA (one wave loads each angle of a
 // group): the kAdjSeg bins of each slice that the tile projects onto are
 // copied straight from the sinogram into LDS, [angle][slice][bin], by
 // LDS-direct loads one group ahead of use (two group buffers); per slice a
-// thread then reads the three consecutive bins that carry both voxels'
-// weights.  The lanes of a wave read different bins of one 256-byte bin
-// row: no bank conflicts.  Sinogram rows are zero-padded by kAdjPad bins, so a segment
+// thread then reads the four consecutive bins that carry its four voxels'
+// weights (8 bytes of LDS per voxel and slice).  The lanes of a wave read
+// bins of one 256-byte bin row: no bank conflicts.  The angles come in two
+// classes, each in a list of its own (ascending angle indices): after the
+// reversal of the rows with cos < 0, sin >= 0 (class 0) or sin < 0 (class
+// 1).  Within a class the lowest-projecting voxel of every block is the
+// same one, so each class runs a loop specialised for it; each class is
+// padded to whole groups with dummy angles whose segment is the zero
+// padding of a row.  Sinogram rows are zero-padded by kAdjPad bins, so a segment
 // is read without bounds checks.  A voxel projecting to fractional bin q
 // takes max(0, 1 - |i - q| / h) / h of bin i (h = max(|cos|, |sin|)) --
 // exactly the weight Joseph's interpolation gave it.
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_radon_adj(const float2* __restrict__ S,
                                                          float2* __restrict__ gu, DevGeom g,
                                                          const double* __restrict__ ang,
-                                                         int K) {
+                                                         int k0, const int* __restrict__ ord0,
+                                                         int n0, const int* __restrict__ ord1,
+                                                         int n1) {
   constexpr int ZT = kAdjZT, NA = kAdjNA, SEG = kAdjSeg, TW = kAdjWin;
   constexpr int NBUF = 2;                           // group buffers (loads run 1 group ahead)
   constexpr int GF2 = NA * ZT * SEG;                // float2 per staged group
@@ -299,7 +310,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
   // Per-angle set-up for a window of TW angles, double-buffered by window
   // parity: first staged bin, fractional bin of the tile corner relative to
   // it, cos, sin, 1/h and 1/h^2.
-  __shared__ int s_sl[2][TW];
+  __shared__ int s_sl[2][TW], s_row[2][TW];
   __shared__ float s_f0[2][TW], s_c[2][TW], s_s[2][TW], s_ih[2][TW], s_ih2[2][TW];
   const float2* tile = reinterpret_cast<const float2*>(tile4);
   const int W = g.W, H = g.H, Wp = sino_row(W);
@@ -308,15 +319,31 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
   const int L = xcd_logical(blockIdx.x, gridDim.x);
   const int nt = W / 16;
   const int x0 = (L % nt) * 16, y0 = ((L / nt) % nt) * 16;
-  // thread: voxel pair (x, x + 1), x = x0 + 2 px, row y0 + dy, and the 8
-  // slices of slice group sg of the block
-  const int px = threadIdx.x & 7, dy = (threadIdx.x >> 3) & 15, sg = threadIdx.x >> 7;
-  const int x = x0 + 2 * px, y = y0 + dy;
+  // thread: voxels (x, y), (x + 1, y), (x, y + 1), (x + 1, y + 1),
+  // x = x0 + 2 px, y = y0 + 2 py, and the 4 slices of slice group sg (its
+  // wave) of the block
+  const int px = threadIdx.x & 7, py = (threadIdx.x >> 3) & 7, sg = threadIdx.x >> 6;
+  const int x = x0 + 2 * px, y = y0 + 2 * py;
   const int z0 = (L / (nt * nt)) * ZT;
   const double X0 = (double)x0 - g.cW, X1 = X0 + 15.0;
   const double Y0 = (double)y0 - g.cW, Y1 = Y0 + 15.0;
 
-  // Set-up of angle w * TW + t for threads t < TW, in double precision: the
+  // Position p of the angle sequence: class 0's list padded to a multiple of
+  // NA, then class 1's.  Returns the angle (a dummy repeats its class's last
+  // angle) and whether it is a dummy.
+  const int G0 = (n0 + NA - 1) / NA, G1 = (n1 + NA - 1) / NA;
+  const int ng = G0 + G1, Kp = ng * NA;
+  auto angle_at = [&](int p, bool& dummy) {
+    if (p < G0 * NA) {
+      dummy = p >= n0;
+      return ord0[min(p, n0 - 1)];
+    }
+    p -= G0 * NA;
+    dummy = p >= n1;
+    return ord1[min(p, n1 - 1)];
+  };
+
+  // Set-up of position w * TW + t for threads t < TW, in double precision: the
   // first staged bin is the lowest projection of the tile's corners minus two
   // or three bins of margin (even, so each lane's bin pair is 16-byte
   // aligned), moved into [-kAdjPad, W + kAdjPad - SEG] (a segment
@@ -327,7 +354,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
   auto setup_window = [&](int w) {
     const int slot = w & 1, t = threadIdx.x;
     if (t < TW) {
-      const int kk = min(w * TW + t, K - 1);
+      bool dummy;
+      const int kk = angle_at(min(w * TW + t, Kp - 1), dummy);
       const double* ap = ang + (size_t)kk * kAngleStride;
       // an angle with cos < 0 has its row stored reversed: it is the angle
       // theta - pi, direction (-cos, -sin), positions W - 1 - q
@@ -339,7 +367,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
       int sl = (int)floor(cq + fmin(X0 * C, X1 * C) + fmin(Y0 * Sn, Y1 * Sn)) - 2;
       sl -= sl & 1;                                     // even: 16-byte aligned bin pairs
       sl = min(max(sl, -kAdjPad), W + kAdjPad - SEG);
+      // a dummy reads the zero padding left of its row; its weights are
+      // zero there too (its taps fall far right of the segment)
+      if (dummy) sl = -kAdjPad;
       s_sl[slot][t] = sl;
+      s_row[slot][t] = kk - k0;
       s_f0[slot][t] = (float)(q0 - (double)sl);
       s_c[slot][t] = (float)C;
       s_s[slot][t] = (float)Sn;
@@ -358,10 +390,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
   const float2* Sl = S + (size_t)(z0 + (lane >> 4)) * Wp + kAdjPad + 2 * (lane & 15);
   const unsigned lds0 = (unsigned)(uintptr_t)(__attribute__((address_space(3))) float4*)tile4;
   auto issue = [&](int gidx) {
-    const int k0 = gidx * NA;
-    const int kk = min(k0 + wave, K - 1);                // past the end: never read back
-    const int sl = __builtin_amdgcn_readfirstlane(s_sl[(k0 / TW) & 1][k0 % TW + wave]);
-    const float2* src = Sl + (size_t)kk * HWp + sl;
+    const int p0 = gidx * NA;
+    const int sl = __builtin_amdgcn_readfirstlane(s_sl[(p0 / TW) & 1][p0 % TW + wave]);
+    const int row = __builtin_amdgcn_readfirstlane(s_row[(p0 / TW) & 1][p0 % TW + wave]);
+    const float2* src = Sl + (size_t)row * HWp + sl;
     const unsigned dst = __builtin_amdgcn_readfirstlane(
         lds0 + (unsigned)((((gidx % NBUF) * GF2) + wave * ZT * SEG) * 8));
 #pragma unroll
@@ -375,22 +407,24 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
           : "memory", "m0");
   };
 
-  constexpr int ZS = ZT / 2;                        // slices per thread
-  float ax[2][ZS], ay[2][ZS];
-  float ox[2][ZS], oy[2][ZS];
+  constexpr int ZS = ZT / 4;                        // slices per thread
+  static_assert(ZS == 4 && NA == 4, "slice group per wave");
+  // accumulators [voxel v = dx + 2 dy][slice]
+  float ax[4][ZS], ay[4][ZS];
+  float ox[4][ZS], oy[4][ZS];
 #pragma unroll
-  for (int v = 0; v < 2; ++v)
+  for (int v = 0; v < 4; ++v)
 #pragma unroll
     for (int i = 0; i < ZS; ++i) { ax[v][i] = ay[v][i] = 0.f; ox[v][i] = oy[v][i] = 0.f; }
 
-  const int ng = (K + NA - 1) / NA;
   constexpr int GPW = TW / NA;                      // groups per set-up window
   setup_window(0);
   __syncthreads();
   issue(0);
-  for (int gi = 0; gi < ng; ++gi) {
-    const int k0 = gi * NA;
-    const int na = min(NA, K - k0);
+  // One group of NA angles of one class.
+  auto group = [&](int gi, auto sneg) {
+    constexpr bool SNEG = decltype(sneg)::value;
+    const int p0 = gi * NA;
     // this wave's loads of group gi are complete and its LDS reads of group
     // gi - 1 have returned; the barrier publishes group gi of every wave,
     // retires group gi - 1 (whose buffer the loads of gi + 1 reuse) and the
@@ -401,57 +435,66 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
     if (gi + 1 < ng) issue(gi + 1);
     // the next window's set-up, written two groups before its first group
     // is issued, into the slot of the window before the current one
-    if ((gi + 2) % GPW == 0 && (gi + 2) * NA < K) setup_window((gi + 2) / GPW);
-    const int slot = (k0 / TW) & 1, base = k0 % TW;
+    if ((gi + 2) % GPW == 0 && (gi + 2) * NA < Kp) setup_window((gi + 2) / GPW);
+    const int slot = (p0 / TW) & 1, base = p0 % TW;
     const float2* gb = tile + (gi % NBUF) * GF2;
-    for (int a = 0; a < na; ++a) {
-      // The pair's fractional bins are q and q + cos, cos >= 0 (rows of
-      // angles with cos < 0 are stored reversed).  Every bin with a nonzero
-      // weight for either voxel (|i - q| < h <= 1) is one of jm .. jm + 2,
-      // jm = floor(q), and its weight is the footprint
-      // max(0, 1 - |i - q| / h) / h = max(0, 1/h - |i - q| / h^2).  The
-      // first voxel's third bin lies more than one bin from it, so its
-      // weight is zero and is not formed.
+    // One angle.  Its row has cos >= 0 (rows of angles with cos < 0 are
+    // stored reversed), so the block's lowest fractional bin q belongs to
+    // voxel (x, y) in class 0 and to (x, y + 1) in class 1 (SNEG); the
+    // others lie at q + cos (the x neighbour of the lowest), q + |sin| (its
+    // y neighbour) and q + cos + |sin| (the opposite corner), with
+    // 1 <= cos + |sin| <= sqrt(2).  Every bin with a nonzero weight
+    // (|i - q'| < h <= 1) is one of jm .. jm + 3, jm = floor(q): bins jm,
+    // jm + 1 for the lowest voxel, jm .. jm + 2 for its two neighbours and
+    // jm + 1 .. jm + 3 for the opposite corner; the weight is the footprint
+    // max(0, 1/h - |i - q'| / h^2).
+    constexpr int VL = SNEG ? 2 : 0, VX = SNEG ? 3 : 1, VY = SNEG ? 0 : 2, VXY = SNEG ? 1 : 3;
+#pragma unroll 1
+    for (int a = 0; a < NA; ++a) {
       const float ih = s_ih[slot][base + a], ih2 = s_ih2[slot][base + a];
-      const float c = s_c[slot][base + a];
-      const float qa = fmaf((float)dy, s_s[slot][base + a],
-                            fmaf((float)(2 * px), c, s_f0[slot][base + a]));
-      const float qb = qa + c;
-      const int jm = min(max((int)floorf(qa), 0), SEG - 3);
-      const float dl = (float)jm - qa, dh = (float)jm - qb;   // bin jm relative to each voxel
-      const float wl0 = fmaxf(0.0f, fmaf(-fabsf(dl), ih2, ih));
-      const float wl1 = fmaxf(0.0f, fmaf(-fabsf(dl + 1.0f), ih2, ih));
-      const float wh0 = fmaxf(0.0f, fmaf(-fabsf(dh), ih2, ih));
-      const float wh1 = fmaxf(0.0f, fmaf(-fabsf(dh + 1.0f), ih2, ih));
-      const float wh2 = fmaxf(0.0f, fmaf(-fabsf(dh + 2.0f), ih2, ih));
+      const float c = s_c[slot][base + a], sn = s_s[slot][base + a];
+      const float as = SNEG ? -sn : sn;
+      const float q = fmaf((float)(2 * py + (SNEG ? 1 : 0)), sn,
+                           fmaf((float)(2 * px), c, s_f0[slot][base + a]));
+      const int jm = min(max((int)floorf(q), 0), SEG - 4);
+      const float d = q - (float)jm;                   // lowest voxel relative to bin jm
+      auto wt = [&](float dist) { return fmaxf(0.0f, fmaf(-fabsf(dist), ih2, ih)); };
+      const float dX = d + c, dY = d + as, dXY = dX + as;
+      const float wL0 = wt(d), wL1 = wt(1.0f - d);
+      const float wX0 = wt(dX), wX1 = wt(1.0f - dX), wX2 = wt(2.0f - dX);
+      const float wY0 = wt(dY), wY1 = wt(1.0f - dY), wY2 = wt(2.0f - dY);
+      const float wXY1 = wt(1.0f - dXY), wXY2 = wt(2.0f - dXY), wXY3 = wt(3.0f - dXY);
       const float2* tp = gb + a * ZT * SEG + sg * ZS * SEG + jm;
-      // software pipeline: the three bins of slice i + LA are requested
+      // software pipeline: the four bins of slice i + LA are requested
       // before slice i is accumulated
-      constexpr int LA = 3;
-      static_assert(ZS == 8, "slice group");
-      float2 r[ZS][3];
+      constexpr int LA = 1;
+      float2 r[ZS][4];
       auto fetch = [&](int i) {
         const float2* t = tp + i * SEG;
-        r[i][0] = t[0];
-        r[i][1] = t[1];
-        r[i][2] = t[2];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) r[i][b] = t[b];
       };
 #pragma unroll
       for (int i = 0; i < LA; ++i) fetch(i);
 #pragma unroll
       for (int i = 0; i < ZS; ++i) {
         if (i + LA < ZS) fetch(i + LA);
-        ax[0][i] = fmaf(wl1, r[i][1].x, fmaf(wl0, r[i][0].x, ax[0][i]));
-        ay[0][i] = fmaf(wl1, r[i][1].y, fmaf(wl0, r[i][0].y, ay[0][i]));
-        ax[1][i] = fmaf(wh2, r[i][2].x, fmaf(wh1, r[i][1].x, fmaf(wh0, r[i][0].x, ax[1][i])));
-        ay[1][i] = fmaf(wh2, r[i][2].y, fmaf(wh1, r[i][1].y, fmaf(wh0, r[i][0].y, ay[1][i])));
+        const float2 r0 = r[i][0], r1 = r[i][1], r2 = r[i][2], r3 = r[i][3];
+        ax[VL][i] = fmaf(wL1, r1.x, fmaf(wL0, r0.x, ax[VL][i]));
+        ay[VL][i] = fmaf(wL1, r1.y, fmaf(wL0, r0.y, ay[VL][i]));
+        ax[VX][i] = fmaf(wX2, r2.x, fmaf(wX1, r1.x, fmaf(wX0, r0.x, ax[VX][i])));
+        ay[VX][i] = fmaf(wX2, r2.y, fmaf(wX1, r1.y, fmaf(wX0, r0.y, ay[VX][i])));
+        ax[VY][i] = fmaf(wY2, r2.x, fmaf(wY1, r1.x, fmaf(wY0, r0.x, ax[VY][i])));
+        ay[VY][i] = fmaf(wY2, r2.y, fmaf(wY1, r1.y, fmaf(wY0, r0.y, ay[VY][i])));
+        ax[VXY][i] = fmaf(wXY3, r3.x, fmaf(wXY2, r2.x, fmaf(wXY1, r1.x, ax[VXY][i])));
+        ay[VXY][i] = fmaf(wXY3, r3.y, fmaf(wXY2, r2.y, fmaf(wXY1, r1.y, ay[VXY][i])));
       }
     }
     // two-level single-precision sums: partials of up to 8 NA angles are
     // added into the outer sums
     if ((gi & 7) == 7 || gi + 1 >= ng) {
 #pragma unroll
-      for (int v = 0; v < 2; ++v)
+      for (int v = 0; v < 4; ++v)
 #pragma unroll
         for (int i = 0; i < ZS; ++i) {
           ox[v][i] += ax[v][i];
@@ -459,12 +502,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
           ax[v][i] = ay[v][i] = 0.f;
         }
     }
-  }
+  };
+  for (int gi = 0; gi < G0; ++gi) group(gi, std::integral_constant<bool, false>());
+  for (int gi = G0; gi < ng; ++gi) group(gi, std::integral_constant<bool, true>());
   const size_t WW = (size_t)W * W;
 #pragma unroll
   for (int i = 0; i < ZS; ++i) {
-    float4* o = reinterpret_cast<float4*>(gu + (size_t)(z0 + sg * ZS + i) * WW + (size_t)y * W + x);
-    *o = make_float4(ox[0][i], oy[0][i], ox[1][i], oy[1][i]);
+    float2* o = gu + (size_t)(z0 + sg * ZS + i) * WW + (size_t)y * W + x;
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+      *reinterpret_cast<float4*>(o + (size_t)dy * W) =
+          make_float4(ox[2 * dy][i], oy[2 * dy][i], ox[2 * dy + 1][i], oy[2 * dy + 1][i]);
   }
 }
 
@@ -487,11 +535,12 @@ hipError_t launch_radon_fwd(const DevGeom& g, const float2* ub, const float2* uT
 }
 
 hipError_t launch_radon_adj(const DevGeom& g, const float2* S, float2* gu, const double* ang,
-                            int K, hipStream_t st) {
+                            int k0, const int* ord0, int n0, const int* ord1, int n1,
+                            hipStream_t st) {
   // the kernel reads the rows of angles with cos < 0 reversed
-  if (!g.sino_mirror) return hipErrorInvalidValue;
+  if (!g.sino_mirror || n0 < 0 || n1 < 0 || n0 + n1 < 1) return hipErrorInvalidValue;
   const unsigned n = (unsigned)(g.W / 16) * (unsigned)(g.W / 16) * (unsigned)(g.H / kAdjZT);
-  k_radon_adj<<<n, kThreads, 0, st>>>(S, gu, g, ang, K);
+  k_radon_adj<<<n, kThreads, 0, st>>>(S, gu, g, ang, k0, ord0, n0, ord1, n1);
   return hipGetLastError();
 }
 

@@ -91,6 +91,37 @@ def test_adj_parity(small):
     PB.assert_close(gq.cpu().numpy(), rq, "gq")
 
 
+def test_adj_parity_angle_classes():
+    """The transpose visits a call's angles in two classes (sin >= 0 or < 0
+    once the rows of angles with cos < 0 are reversed), each padded to whole
+    angle groups with dummies: shuffled angles over the whole circle, with
+    the class boundaries 0, pi/2, pi and 3 pi/2 among them, over more than two
+    set-up windows, a sub-range whose classes end mid-group and a single
+    angle."""
+    import torch
+    from paper_2407_20304_amd import holo, synth
+    say("adj parity 64^3, 150 shuffled angles over the circle")
+    H = W = 64
+    rng = np.random.default_rng(11)
+    theta = rng.uniform(0.0, 2.0 * np.pi, 150)
+    theta[[0, 17, 40, 77, 101]] = [0.0, np.pi / 2, np.pi, 1.5 * np.pi, np.pi / 4]
+    geom = O.Geometry(H=H, W=W, theta=theta, mag_rel=synth.MAG_REL, m0=synth.M0,
+                      fresnel0=synth.FRESNEL0, kappa=synth.KAPPA, shift=None)
+    u = synth.ellipsoid_volume(W, H, 901).numpy()
+    q = synth.probe(H, W, 902)
+    plan = holo.Plan(H, W, theta, synth.MAG_REL, synth.M0, synth.FRESNEL0, synth.KAPPA, chunk=32)
+    ug = torch.from_numpy(u).cuda()
+    qg = torch.from_numpy(q).cuda()
+    for k0, k1 in ((0, 150), (5, 14), (40, 41)):
+        say("  angles [%d, %d)" % (k0, k1))
+        w = (rng.standard_normal((k1 - k0, 4, H, W)) +
+             1j * rng.standard_normal((k1 - k0, 4, H, W))).astype(np.complex64)
+        gu, gq = plan.holo_adj(ug, qg, torch.from_numpy(w).cuda(), k0, k1)
+        ru, rq = O.adjoint(PB.c128(u), PB.c128(q), PB.c128(w), geom, ks=range(k0, k1))
+        PB.assert_close(gu.cpu().numpy(), ru, "gu [%d, %d)" % (k0, k1))
+        PB.assert_close(gq.cpu().numpy(), rq, "gq [%d, %d)" % (k0, k1))
+
+
 def test_objective_and_grad_parity(small):
     say("objective/grad parity 64^3")
     u, q, amp, amp_ref = PB.to_gpu(small)
