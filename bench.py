@@ -34,12 +34,12 @@ FLOP_PER_LERP = 8               # 2 taps x (re, im) x fused multiply-add
 # KERNEL_SOURCES) and the workload they were taken on; after any change to
 # those sources, or on another workload, the field reports null.
 TRAFFIC = {
-    "k_radon_fwd": {"workload": "vol1024_a1800", "fetch_kib": 17724291.99, "write_kib": 508471.60,
+    "k_radon_fwd": {"workload": "vol1024_a1800", "fetch_kib": 18071319.02, "write_kib": 508470.90,
                     "fetch_scale": 2.0, "write_scale": 1.0,
-                    "sources_sha256": "a50ec36d5a7be007e4784a9f4e840ae639b5fd02babfde35e690092e2571870d"},
-    "k_radon_adj": {"workload": "vol1024_a1800", "fetch_kib": 464191778.8, "write_kib": 8388608.0,
+                    "sources_sha256": "3380b6fee8dbbf935951ce52edc6390c77dadd284769f003d904770488bae122"},
+    "k_radon_adj": {"workload": "vol1024_a1800", "fetch_kib": 707326934.5, "write_kib": 8388608.0,
                     "fetch_scale": 2.0, "write_scale": 1.0,
-                    "sources_sha256": "a50ec36d5a7be007e4784a9f4e840ae639b5fd02babfde35e690092e2571870d"},
+                    "sources_sha256": "3380b6fee8dbbf935951ce52edc6390c77dadd284769f003d904770488bae122"},
 }
 
 
