@@ -62,7 +62,7 @@ static_assert(b_cols_lds(384) <= kColLdsSmall && b_cols_lds(256) <= kColLdsSmall
               "small column LDS covers every size up to 512");
 
 __device__ __forceinline__ double b_src_pos(double c, double m, int idx) {
-  return c + m * ((double)idx - c);
+  return fma(m, (double)idx - c, c);
 }
 
 struct BTaps {
@@ -91,30 +91,6 @@ __device__ __forceinline__ float2 b_phi(const float2* __restrict__ psi, int n, c
   const float w00 = ty.w0 * tx.w0, w01 = ty.w0 * tx.w1, w10 = ty.w1 * tx.w0, w11 = ty.w1 * tx.w1;
   return make_float2(1.0f + w00 * (a.x - 1.f) + w01 * (b.x - 1.f) + w10 * (c.x - 1.f) + w11 * (d.x - 1.f),
                      w00 * a.y + w01 * b.y + w10 * c.y + w11 * d.y);
-}
-
-struct BAdj {
-  int d[3];
-  float w[3];
-};
-
-__device__ __forceinline__ BAdj b_adj_taps(double c, double m, int idx, int n) {
-  const double pre = ((double)idx - c) / m + c;
-  const int d0 = (int)floor(pre) - 1;
-  BAdj a;
-#pragma unroll
-  for (int e = 0; e < 3; ++e) {
-    const int d = d0 + e;
-    const bool ok = d >= 0 && d < n;
-    const double sp = b_src_pos(c, m, d);
-    const double fl = floor(sp);
-    const int i0 = (int)fl;
-    const float w = (float)(sp - fl);
-    const float wt = (i0 == idx) ? 1.0f - w : ((i0 + 1 == idx) ? w : 0.0f);
-    a.d[e] = ok ? d : 0;
-    a.w[e] = ok ? wt : 0.0f;
-  }
-  return a;
 }
 
 // ---------------------------------------------------------------------------
@@ -462,21 +438,20 @@ __global__ __launch_bounds__(kT2) void k2_gather(B2Args A, const B2Item* __restr
   if (p >= n * n) return;
   const int z = p / n, s = p % n;
   const size_t fr = (size_t)n * n;
-  const double c = n / 2.0;
   float ax = 0.f, ay = 0.f;
   for (int j = 0; j < A.nd; ++j) {
-    const double m = A.mag[j];
-    const BAdj rz = b_adj_taps(c, m, z, n), rs = b_adj_taps(c, m, s, n);
-    // With m >= 1 at most two adjacent candidates of an axis carry weight:
-    // (0, 1) if candidate 0 does, else (1, 2).  Four unconditional loads.
-    const int az = rz.w[0] != 0.0f ? 0 : 1, as = rs.w[0] != 0.0f ? 0 : 1;
+    // the two weighted taps of each axis (from the plan's table): four
+    // unconditional loads
+    const B2AdjTap tz = in.adj[j * n + z], ts = in.adj[j * n + s];
     const float2* Xj = A.X + in.off * A.nd + j * fr;
+    const int rz[2] = {tz.d0, tz.d1}, rs[2] = {ts.d0, ts.d1};
+    const float wz[2] = {tz.w0, tz.w1}, ws[2] = {ts.w0, ts.w1};
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        const float wt = rz.w[az + a] * rs.w[as + b];
-        const float2 v = Xj[(size_t)rz.d[az + a] * n + rs.d[as + b]];   // in range
+        const float wt = wz[a] * ws[b];
+        const float2 v = Xj[(size_t)rz[a] * n + rs[b]];   // in range
         ax += wt * v.x;
         ay += wt * v.y;
       }

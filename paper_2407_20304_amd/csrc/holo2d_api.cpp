@@ -38,13 +38,14 @@ struct holo2d_plan {
   long long total = 0;
   std::vector<int> dsizes;                // distinct sizes
   std::vector<std::vector<float2>> tw, chirp;
+  std::vector<std::vector<B2AdjTap>> adj;  // per distinct size: [nd][n]
   ItemList rows_probe, rows_probe_noref, rows_nd, rows_cgq, cols_probe, cols_probe_noref,
       cols_nd, cols_gq, gather;
   std::vector<int2> ranges;               // per-instance cost-partial slots
   int n_slots = 0;
   // device tables
   size_t off_inst = 0, off_ranges = 0, table_bytes = 0;
-  std::vector<size_t> off_tw, off_chirp;
+  std::vector<size_t> off_tw, off_chirp, off_adj;
   void* d_tables = nullptr;
   int device = -1;
   // workspace (bytes)
@@ -55,6 +56,33 @@ struct holo2d_plan {
 };
 
 static holo_status fail2(holo_status s, const std::string& m) { return holo::set_last_error(s, m); }
+
+// Transposed demagnification taps of one axis of an n-point frame for
+// magnification m (Eq. 8's resampling B_j, bilinear, free space outside):
+// the forward samples destination d at c + m (d - c) from the two pixels
+// around it, so source pixel idx receives weight from the destinations
+// whose sample lies within one pixel of it -- at most two adjacent ones,
+// as m >= 1, among the three candidates around (idx - c) / m + c.  The
+// arithmetic is the forward's (the sample position as one fused
+// multiply-add), so each weight is the forward's own.
+static B2AdjTap adj_tap(double c, double m, int idx, int n) {
+  const int d0 = (int)std::floor(((double)idx - c) / m + c) - 1;
+  int d[3];
+  float w[3];
+  for (int e = 0; e < 3; ++e) {
+    const int dd = d0 + e;
+    const double sp = std::fma(m, (double)dd - c, c);
+    const double fl = std::floor(sp);
+    const int i0 = (int)fl;
+    const float f = (float)(sp - fl);
+    const float wt = i0 == idx ? 1.0f - f : (i0 + 1 == idx ? f : 0.0f);
+    const bool ok = dd >= 0 && dd < n;
+    d[e] = ok ? dd : 0;
+    w[e] = ok ? wt : 0.0f;
+  }
+  const int e0 = w[0] != 0.0f ? 0 : 1;
+  return {d[e0], d[e0 + 1], w[e0], w[e0 + 1]};
+}
 
 static void chirp_rows(std::vector<float2>& out, int n, const std::vector<double>& rhos,
                        double nf) {
@@ -122,6 +150,10 @@ extern "C" holo_status holo2d_plan_create(int32_t n_inst, const int32_t* sizes, 
       std::vector<float2> c;
       chirp_rows(c, n, rhos, fresnel0);
       P->chirp.push_back(c);
+      std::vector<B2AdjTap> a((size_t)n_dist * n);
+      for (int j = 0; j < n_dist; ++j)
+        for (int idx = 0; idx < n; ++idx) a[(size_t)j * n + idx] = adj_tap(n / 2.0, P->mag[j], idx, n);
+      P->adj.push_back(a);
     }
     // work items, largest instances first
     std::vector<int> order(n_inst);
@@ -172,6 +204,8 @@ extern "C" holo_status holo2d_plan_create(int32_t n_inst, const int32_t* sizes, 
       t = al(t + P->tw[d].size() * sizeof(float2));
       P->off_chirp.push_back(t);
       t = al(t + P->chirp[d].size() * sizeof(float2));
+      P->off_adj.push_back(t);
+      t = al(t + P->adj[d].size() * sizeof(B2AdjTap));
     }
     P->off_inst = t;
     t = al(t + sizeof(B2Inst) * n_inst);
@@ -257,6 +291,8 @@ void b2_table_image(const holo2d_plan* P, const char* base, std::vector<char>& h
               h.data() + P->off_tw[d]);
     std::copy((const char*)P->chirp[d].data(),
               (const char*)(P->chirp[d].data() + P->chirp[d].size()), h.data() + P->off_chirp[d]);
+    std::copy((const char*)P->adj[d].data(), (const char*)(P->adj[d].data() + P->adj[d].size()),
+              h.data() + P->off_adj[d]);
   }
   std::vector<B2Inst> inst(P->n_inst);
   for (int i = 0; i < P->n_inst; ++i) {
@@ -266,6 +302,7 @@ void b2_table_image(const holo2d_plan* P, const char* base, std::vector<char>& h
     inst[i].off = P->off[i];
     inst[i].tw = (const float2*)(base + P->off_tw[k]);
     inst[i].chirp = (const float2*)(base + P->off_chirp[k]);
+    inst[i].adj = (const B2AdjTap*)(base + P->off_adj[k]);
   }
   std::copy((const char*)inst.data(), (const char*)(inst.data() + inst.size()),
             h.data() + P->off_inst);

@@ -6,11 +6,20 @@
 
 namespace holo {
 
+// Transpose of the bilinear demagnification along one axis: the two source
+// indices that give destination index idx a weight, and those weights
+// (unused entries have index 0 and weight 0).
+struct B2AdjTap {
+  int d0, d1;
+  float w0, w1;
+};
+
 struct B2Inst {
   int n;                   // square edge
   long long off;           // element offset of the instance's frame
   const float2* tw;        // [n] twiddles
   const float2* chirp;     // [2 nd + 1][n] transfer rows (det_j, probe_j, ref), times 1/n
+  const B2AdjTap* adj;     // [nd][n] transposed demagnification taps of an axis
 };
 
 struct B2Item {
