@@ -337,12 +337,26 @@ __device__ __forceinline__ void b_cols_body(const B2Args& A, const B2Item& it, f
   }
 }
 
+// Work item of workgroup h in a launch of n items for the column kernels.
+// The dispatcher hands workgroup h to XCD h mod 8; here each XCD takes runs
+// of kXcdRun consecutive items (neighbouring column tiles, whose row pieces
+// share cache lines, then share that XCD's L2), and the runs of the eight
+// XCDs interleave over the item list, so every XCD gets a mix of the
+// instance sizes.  Items past the last whole round keep their own index.
+constexpr int kXcdRun = 8;
+__device__ __forceinline__ int xcd_runs(int h, int n) {
+  constexpr int R = 8 * kXcdRun;
+  if (h >= (n / R) * R) return h;
+  const int x = h & 7, l = h >> 3;
+  return (l / kXcdRun) * R + x * kXcdRun + l % kXcdRun;
+}
+
 // LDS: the host launches the small instantiation only for batches whose
 // largest instance is at most 512 px.
 template <int LDS>
 __global__ __launch_bounds__(kT2) void k2_cols(B2Args A, const B2Item* __restrict__ items) {
   __shared__ float2 lds[LDS];
-  const B2Item it = items[blockIdx.x];
+  const B2Item it = items[xcd_runs(blockIdx.x, gridDim.x)];
   switch (A.inst[it.inst].n) {
 #define CASE(N) \
   case N:       \
@@ -414,7 +428,7 @@ __device__ __forceinline__ void b_cols_gq_sum(const B2Args& A, const B2Item& it,
 template <int LDS>
 __global__ __launch_bounds__(kT2) __attribute__((amdgpu_waves_per_eu(4))) void k2_gq_sum(B2Args A, const B2Item* __restrict__ items) {
   __shared__ float2 lds[LDS];
-  const B2Item it = items[blockIdx.x];
+  const B2Item it = items[xcd_runs(blockIdx.x, gridDim.x)];
   switch (A.inst[it.inst].n) {
 #define CASE(N) \
   case N:       \
