@@ -8,9 +8,9 @@
 //                 exp(i kappa p) epilogue
 //   radon_adj     transpose as a triangle-footprint gather over all angles
 //                 (a workgroup per 16 x 16 voxel tile and kAdjZT slices,
-//                 each thread a voxel pair along x and kAdjZT / 2 slices),
-//                 sinogram segments staged in LDS per angle group by
-//                 LDS-direct loads
+//                 each thread a 2 x 2 voxel block and kAdjZT / 4 slices,
+//                 angles in two classes by the sign of sin), sinogram
+//                 segments staged in LDS per angle group by LDS-direct loads
 // Both are bound by VALU issue and LDS operand delivery, not by HBM: every
 // voxel is revisited once per angle.
 #include <type_traits>
