@@ -315,10 +315,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
   const float2* tile = reinterpret_cast<const float2*>(tile4);
   const int W = g.W, H = g.H, Wp = sino_row(W);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // logical order: tile x fastest, then tile y, then slice block
+  // logical order: slice blocks slowest; within one, the tiles in square
+  // groups of GS x GS (x fastest within a group, groups in rows), so the
+  // workgroups resident on one XCD cover a compact patch of the slice block
+  // whose sinogram segments, per angle, are few and stay in that XCD's L2
   const int L = xcd_logical(blockIdx.x, gridDim.x);
   const int nt = W / 16;
-  const int x0 = (L % nt) * 16, y0 = ((L / nt) % nt) * 16;
+  const int GS = (nt % 8 == 0) ? 8 : (nt % 4 == 0) ? 4 : (nt % 2 == 0) ? 2 : 1;
+  const int tl = L % (nt * nt), grp = tl / (GS * GS), in_grp = tl % (GS * GS);
+  const int x0 = ((grp % (nt / GS)) * GS + in_grp % GS) * 16;
+  const int y0 = ((grp / (nt / GS)) * GS + in_grp / GS) * 16;
   // thread: voxels (x, y), (x + 1, y), (x, y + 1), (x + 1, y + 1),
   // x = x0 + 2 px, y = y0 + 2 py, and the 4 slices of slice group sg (its
   // wave) of the block
