@@ -34,12 +34,12 @@ FLOP_PER_LERP = 8               # 2 taps x (re, im) x fused multiply-add
 # KERNEL_SOURCES) and the workload they were taken on; after any change to
 # those sources, or on another workload, the field reports null.
 TRAFFIC = {
-    "k_radon_fwd": {"workload": "vol1024_a1800", "fetch_kib": 18071319.02, "write_kib": 508470.90,
+    "k_radon_fwd": {"workload": "vol1024_a1800", "fetch_kib": 17815383.81, "write_kib": 508471.91,
                     "fetch_scale": 2.0, "write_scale": 1.0,
-                    "sources_sha256": "3380b6fee8dbbf935951ce52edc6390c77dadd284769f003d904770488bae122"},
-    "k_radon_adj": {"workload": "vol1024_a1800", "fetch_kib": 707326934.5, "write_kib": 8388608.0,
+                    "sources_sha256": "6b32a6c8213a1a15bec205f27aa2afc6b8740ccca556363f00ff598746146a47"},
+    "k_radon_adj": {"workload": "vol1024_a1800", "fetch_kib": 136143410.9, "write_kib": 8388608.0,
                     "fetch_scale": 2.0, "write_scale": 1.0,
-                    "sources_sha256": "3380b6fee8dbbf935951ce52edc6390c77dadd284769f003d904770488bae122"},
+                    "sources_sha256": "6b32a6c8213a1a15bec205f27aa2afc6b8740ccca556363f00ff598746146a47"},
 }
 
 
