@@ -401,6 +401,9 @@ def main():
     ap.add_argument("--fwd-bins", type=int, choices=(8, 16), default=None,
                     help="bins per workgroup of Joseph's forward ray sums (16: 4 angles per "
                          "workgroup, 8: 8 angles); default: the plan's")
+    ap.add_argument("--col-tile", type=int, default=None,
+                    help="columns per workgroup of the fused column pass (0: the default for "
+                         "the detector height, or half of it); default: the plan's")
     ap.add_argument("--tune", action="store_true",
                     help="choose the chunk size with the autotuner (candidates 16, 32, 64, 128) "
                          "before timing; the default keeps the workload's chunk of 64")
@@ -470,6 +473,8 @@ def main():
         plan.set_tile("overlap", args.overlap)
     if args.fwd_bins is not None:
         plan.set_tile("fwd_bins", args.fwd_bins)
+    if args.col_tile is not None:
+        plan.set_tile("col_tile", args.col_tile)
     tuned = None
     if args.tune:
         best, times = plan.autotune(u, q, amp, amp_ref, candidates=(16, 32, 64, 128))
@@ -543,6 +548,7 @@ def main():
         "config": {"workload": wl.name, "volume": [H, W, W], "n_angles": N, "chunk": plan.chunk,
                    "overlap": plan.get_tile("overlap"),
                    "fwd_bins": plan.get_tile("fwd_bins"),
+                   "col_tile": plan.get_tile("col_tile"),
                    "n_dist": nd, "detector": [H, W], "parallelism": "single GPU"},
         "objective": Fv,
         "frame_stage_GBps": frame_gbs,
